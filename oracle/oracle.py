@@ -1,0 +1,263 @@
+"""ctypes wrapper of the FP64 CPU oracle (liboracle_bdem.so).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg.  The GPU library never loads it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_bdem.so")
+
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_u8p = C.POINTER(C.c_uint8)
+_i64p = C.POINTER(C.c_int64)
+
+MAT_STRIDE = 11
+ENV_LEN = 8
+
+
+class Options(C.Structure):
+    _fields_ = [("tol_abs", C.c_double), ("tol_rel", C.c_double), ("cg_rtol", C.c_double),
+                ("armijo_c", C.c_double), ("max_newton", C.c_int32), ("max_cg", C.c_int32),
+                ("max_ls", C.c_int32), ("break_bonds", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("cg_iters", C.c_int32),
+                ("ls_backtracks", C.c_int32), ("status", C.c_int32),
+                ("bonds_broken", C.c_int64), ("grad0", C.c_double),
+                ("grad_final", C.c_double), ("phi", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle import build_oracle  # noqa: WPS433
+            build_oracle.build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.c_int32, _dp, _dp, _dp, _dp, _dp, _i32p, _u8p, C.c_int64,
+                                 _i32p, _i32p, C.c_int32, _dp, _dp]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_last_error.restype = C.c_char_p
+        for name in ("orc_get_state", "orc_set_state"):
+            getattr(L, name).argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _u8p]
+        L.orc_bond_eval.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_bond_energy_parts.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp, _dp]
+        L.orc_bond_reduced.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp, C.c_int,
+                                       _dp, _dp]
+        L.orc_bond_stress.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp]
+        L.orc_predict.argtypes = [C.c_void_p, C.c_double, _dp, _dp]
+        L.orc_energy.argtypes = [C.c_void_p, C.c_double, _dp, _dp, C.c_int, _dp]
+        L.orc_energy_grad_hess.argtypes = [C.c_void_p, C.c_double, _dp, _dp, C.c_int, _dp,
+                                           _dp, _dp, _dp]
+        L.orc_hess_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+        L.orc_pcg.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp]
+        L.orc_psd_project.argtypes = [C.c_int, _dp, _dp]
+        L.orc_quat_matrices.argtypes = [_dp, _dp, _dp, _dp]
+        L.orc_quat_mul.argtypes = [_dp, _dp, _dp]
+        L.orc_quat_rotate.argtypes = [_dp, _dp, _dp]
+        L.orc_quat_exp_step.argtypes = [_dp, _dp, C.c_double, _dp]
+        L.orc_default_options.argtypes = [C.POINTER(Options)]
+        L.orc_step.argtypes = [C.c_void_p, C.c_double, C.POINTER(Options), C.POINTER(Stats)]
+        L.orc_break_bonds.argtypes = [C.c_void_p, _i64p]
+        _lib = L
+    return _lib
+
+
+def _p(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def material_table(materials):
+    rows = []
+    for m in materials:
+        rows.append([m["young"], m["poisson"], m["density"], m["sigma_c"], m["tau_c"],
+                     *m["stiff_scale"], float(m["shear_mode"]), float(m["tension_only"])])
+    return np.ascontiguousarray(rows, dtype=np.float64)
+
+
+def env_vector(scene):
+    return np.array([*scene.gravity, *scene.ground_normal, scene.ground_offset,
+                     scene.k_contact], dtype=np.float64)
+
+
+def default_options(**kw):
+    o = Options()
+    lib().orc_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Oracle:
+    """One oracle system built from a scene (see paper_2308_10459_amd.scenes)."""
+
+    def __init__(self, scene):
+        L = lib()
+        self.scene = scene
+        self.n, self.nb = scene.n, scene.nb
+        self._keep = [_f64(scene.pos), _f64(scene.quat), _f64(scene.vel), _f64(scene.qvel),
+                      _f64(scene.radius), np.ascontiguousarray(scene.pmat, dtype=np.int32),
+                      np.ascontiguousarray(scene.flags, dtype=np.uint8),
+                      np.ascontiguousarray(scene.ij, dtype=np.int32),
+                      None if scene.bmat is None else np.ascontiguousarray(scene.bmat, np.int32),
+                      material_table(scene.materials), env_vector(scene)]
+        pos, quat, vel, qvel, rad, pmat, flags, ij, bmat, mat, env = self._keep
+        h = L.orc_create(self.n, _p(pos), _p(quat), _p(vel), _p(qvel), _p(rad), _p(pmat, _i32p),
+                         _p(flags, _u8p), self.nb, _p(ij, _i32p), _p(bmat, _i32p),
+                         len(scene.materials), _p(mat), _p(env))
+        if not h:
+            raise ValueError("oracle create failed: " + L.orc_last_error().decode())
+        self.h = C.c_void_p(h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_destroy(h)
+            self.h = None
+
+    # ---- state ----
+    def get_state(self):
+        pos, quat = np.empty((self.n, 3)), np.empty((self.n, 4))
+        vel, qvel = np.empty((self.n, 3)), np.empty((self.n, 4))
+        alive = np.empty(max(self.nb, 1), dtype=np.uint8)
+        lib().orc_get_state(self.h, _p(pos), _p(quat), _p(vel), _p(qvel), _p(alive, _u8p))
+        return dict(pos=pos, quat=quat, vel=vel, qvel=qvel, alive=alive[:self.nb].copy())
+
+    def set_state(self, pos=None, quat=None, vel=None, qvel=None, alive=None):
+        a = [None if x is None else _f64(x) for x in (pos, quat, vel, qvel)]
+        al = None if alive is None else np.ascontiguousarray(alive, dtype=np.uint8)
+        lib().orc_set_state(self.h, _p(a[0]), _p(a[1]), _p(a[2]), _p(a[3]), _p(al, _u8p))
+
+    # ---- per bond ----
+    def bond_eval(self, b, pi, qi, pj, qj):
+        E, g, H = C.c_double(), np.empty(14), np.empty((14, 14))
+        args = [_f64(x) for x in (pi, qi, pj, qj)]
+        lib().orc_bond_eval(self.h, b, *[_p(x) for x in args], C.byref(E), _p(g), _p(H))
+        return E.value, g, H
+
+    def bond_energy_parts(self, b, pi, qi, pj, qj):
+        out = np.empty(3)
+        args = [_f64(x) for x in (pi, qi, pj, qj)]
+        lib().orc_bond_energy_parts(self.h, b, *[_p(x) for x in args], _p(out))
+        return out
+
+    def bond_reduced(self, b, pi, qi, pj, qj, psd=True):
+        g, H = np.empty(12), np.empty((12, 12))
+        args = [_f64(x) for x in (pi, qi, pj, qj)]
+        lib().orc_bond_reduced(self.h, b, *[_p(x) for x in args], int(psd), _p(g), _p(H))
+        return g, H
+
+    def bond_stress(self, b, pos, quat):
+        s, t = C.c_double(), C.c_double()
+        pos, quat = _f64(pos), _f64(quat)
+        lib().orc_bond_stress(self.h, b, _p(pos), _p(quat), C.byref(s), C.byref(t))
+        return s.value, t.value
+
+    # ---- whole system ----
+    def predict(self, dt):
+        ph, qh = np.empty((self.n, 3)), np.empty((self.n, 4))
+        lib().orc_predict(self.h, dt, _p(ph), _p(qh))
+        return ph, qh
+
+    def energy(self, dt, pos=None, quat=None, potential_only=False):
+        st = None
+        if pos is None or quat is None:
+            st = self.get_state()
+        pos = _f64(st["pos"] if pos is None else pos)
+        quat = _f64(st["quat"] if quat is None else quat)
+        phi = C.c_double()
+        lib().orc_energy(self.h, dt, _p(pos), _p(quat), int(potential_only), C.byref(phi))
+        return phi.value
+
+    def energy_grad_hess(self, dt, pos=None, quat=None, psd=True, hess=True):
+        if pos is None or quat is None:
+            st = self.get_state()
+            pos = st["pos"] if pos is None else pos
+            quat = st["quat"] if quat is None else quat
+        pos, quat = _f64(pos), _f64(quat)
+        phi, z = C.c_double(), np.empty((self.n, 6))
+        hd = np.empty((self.n, 6, 6)) if hess else None
+        ho = np.empty((max(self.nb, 1), 6, 6)) if hess else None
+        lib().orc_energy_grad_hess(self.h, dt, _p(pos), _p(quat), int(psd), C.byref(phi),
+                                   _p(z), _p(hd), _p(ho))
+        return phi.value, z, hd, (None if ho is None else ho[:self.nb])
+
+    def hess_apply(self, hdiag, hoff, x):
+        y = np.empty((self.n, 6))
+        hd, ho, xx = _f64(hdiag), _f64(hoff if self.nb else np.zeros((1, 6, 6))), _f64(x)
+        lib().orc_hess_apply(self.h, _p(hd), _p(ho), _p(xx), _p(y))
+        return y
+
+    def pcg(self, hdiag, hoff, b, rtol=1e-12, max_iter=100000):
+        y, res = np.empty((self.n, 6)), C.c_double()
+        hd, ho, bb = _f64(hdiag), _f64(hoff if self.nb else np.zeros((1, 6, 6))), _f64(b)
+        it = lib().orc_pcg(self.h, _p(hd), _p(ho), _p(bb), rtol, max_iter, _p(y), C.byref(res))
+        return y, it, res.value
+
+    def step(self, dt, **opts):
+        o = default_options(**opts)
+        st = Stats()
+        rc = lib().orc_step(self.h, dt, C.byref(o), C.byref(st))
+        d = st.as_dict()
+        d["rc"] = rc
+        return d
+
+    def break_bonds(self):
+        n = C.c_int64()
+        lib().orc_break_bonds(self.h, C.byref(n))
+        return n.value
+
+
+def psd_project(a):
+    a = _f64(a)
+    k = a.shape[0]
+    out = np.empty_like(a)
+    lib().orc_psd_project(k, _p(a), _p(out))
+    return out
+
+
+def quat_matrices(q):
+    q = _f64(q)
+    Ql, Qr, Gl = np.empty((4, 4)), np.empty((4, 4)), np.empty((3, 4))
+    lib().orc_quat_matrices(_p(q), _p(Ql), _p(Qr), _p(Gl))
+    return Ql, Qr, Gl
+
+
+def quat_mul(a, b):
+    a, b = _f64(a), _f64(b)
+    c = np.empty(4)
+    lib().orc_quat_mul(_p(a), _p(b), _p(c))
+    return c
+
+
+def quat_rotate(q, d0):
+    q, d0 = _f64(q), _f64(d0)
+    d = np.empty(3)
+    lib().orc_quat_rotate(_p(q), _p(d0), _p(d))
+    return d
+
+
+def quat_exp_step(q, dq, alpha):
+    q, dq = _f64(q), _f64(dq)
+    out = np.empty(4)
+    lib().orc_quat_exp_step(_p(q), _p(dq), alpha, _p(out))
+    return out
