@@ -1,0 +1,196 @@
+/*
+ * bdem.h -- C ABI of the MI355X implicit bonded-DEM library.
+ *
+ * One implicit time step of bonded DEM with manifold optimization (Lu, Cao,
+ * Li, Hu, "Implicit Bonded Discrete Element Method with Manifold
+ * Optimization"): minimise the incremental potential of Section 3.1
+ * (implicit-Euler form, equation "eq:optimization form") over particle
+ * positions p in R^3 and unit quaternions q in S^3 by the manifold Newton
+ * method of Section 4.2 / Algorithm 2, inside the stable integrator of
+ * Algorithm 3 (SPD-projected Hessian, PCG with relative tolerance
+ * eps_r = min(0.5, sqrt|grad f|), exp-map line search, projection, velocity
+ * update, bond update).  Bond potentials: Section 3.2 (stretch, shear,
+ * bend/twist).  Fracture: Section 3.3.  Ground repulsion: Section 5.4.
+ *
+ * Conventions
+ *   - quaternions are (x, y, z, w), scalar last (Appendix A); the rest
+ *     orientation of every particle is the identity, rest bond data (l0, d0)
+ *     come from the positions passed to bdem_create;
+ *   - reduced tangent coordinates: 6 per particle, (dp, y) with
+ *     dq = G_l(q)^T y, G_l the nullspace operator of Appendix A;
+ *   - all host arrays are row-major, tightly packed, in the caller's particle
+ *     and bond order.
+ *
+ * Ownership and streams
+ *   - bdem_create copies every host input; the caller may free them on return.
+ *   - device memory comes from the caller's workspace (workspace_dev, sized by
+ *     bdem_workspace_bytes, >= 256-byte aligned) or, if workspace_dev is NULL,
+ *     from hipMalloc inside the library (freed by bdem_destroy).
+ *   - all work is enqueued on hip_stream (a hipStream_t; NULL = the null
+ *     stream).  Calls that return host data synchronise that stream.
+ *   - calls on one handle are not thread safe; distinct handles are
+ *     independent.
+ *
+ * Errors
+ *   - every call returns a status; < 0 is an error (state unchanged),
+ *     > 0 a warning (step taken with the last accepted iterate, as in
+ *     Algorithm 3).  bdem_last_error() gives a message.
+ */
+#ifndef BDEM_H
+#define BDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bdem_ctx bdem_ctx;
+
+enum {
+  BDEM_OK = 0,
+  BDEM_W_NOT_CONVERGED = 1, /* Newton cap reached in some scene */
+  BDEM_W_LS_FAILED = 2,     /* line search exhausted in some scene */
+  BDEM_E_INVALID = -1,      /* bad argument (index, i==j, duplicate bond, non-unit q, dt<=0, ...) */
+  BDEM_E_HIP = -2,          /* HIP runtime error */
+  BDEM_E_NOMEM = -3,        /* workspace too small / allocation failed */
+  BDEM_E_NONFINITE = -4,    /* NaN / Inf in the state or the objective */
+  BDEM_E_DEGENERATE = -5,   /* |q_i + q_j| < 1e-6: shear frame undefined */
+  BDEM_E_STATE = -6         /* call not valid in the handle's state */
+};
+
+enum { BDEM_FREE = 0, BDEM_FIXED = 1, BDEM_KINEMATIC = 2 };  /* per-particle flags */
+enum { BDEM_PREC_FP64 = 0, BDEM_PREC_MIXED = 1 };
+enum { BDEM_SHEAR_LENGTH_SCALED = 0, BDEM_SHEAR_LITERAL = 1 };
+enum {
+  BDEM_EGH_E = 1,              /* energy */
+  BDEM_EGH_G = 2,              /* reduced gradient */
+  BDEM_EGH_H = 4,              /* reduced Hessian blocks */
+  BDEM_EGH_PSD = 8,            /* PSD-project the Hessian (Section 5.2) */
+  BDEM_EGH_POTENTIAL_ONLY = 16 /* V only: no inertia term */
+};
+
+/* Particles (Section 3.1: state x = {p, q}, extended mass from m and r). */
+typedef struct {
+  int32_t n;
+  const double *pos;       /* 3n, m */
+  const double *quat;      /* 4n, unit, scalar last; initial state (rest = identity) */
+  const double *vel;       /* 3n or NULL (= 0) */
+  const double *qvel;      /* 4n quaternion rate dq/dt or NULL (= 0) */
+  const double *radius;    /* n, m */
+  const int32_t *material; /* n, index into the material table */
+  const uint8_t *flags;    /* n or NULL (= FREE); KINEMATIC moves with its own velocity */
+  const int32_t *scene;    /* n or NULL (= one scene); non-decreasing ids 0..S-1 */
+} bdem_particles;
+
+/* Bonds (Section 3.2): unordered pairs, i != j, unique, within one scene. */
+typedef struct {
+  int64_t nb;
+  const int32_t *ij;       /* 2nb */
+  const int32_t *material; /* nb or NULL (= material of particle i) */
+} bdem_bonds;
+
+/* Material (Section 3.2 stiffnesses, Section 3.3 strengths).  G = E/(2(1+nu)). */
+typedef struct {
+  double young, poisson, density;
+  double sigma_c, tau_c;   /* tensile / shear strength, <= 0: unbreakable */
+  double stiff_scale[4];   /* multipliers of stretch, shear, twist, bend stiffness */
+  int32_t shear_mode;      /* BDEM_SHEAR_LENGTH_SCALED: 1/2 k_t (l0 theta)^2; LITERAL: 1/2 k_t theta^2 */
+  int32_t tension_only;    /* 1: compression does not count in sigma */
+} bdem_material;
+
+typedef struct {
+  double gravity[3];
+  double ground_normal[3], ground_offset; /* plane n.p = h; gap = n.p - h - r */
+  double k_contact;        /* < 0: E_max * r_max (Section 5.4), 0: no ground, > 0: value */
+  double mu_s, mu_r;       /* friction hook of Algorithm 3; must be 0 (not implemented) */
+  double newton_tol;       /* absolute stop |z|_2 <= newton_tol */
+  double newton_rtol;      /* relative stop |z|_2 <= newton_rtol |z0|_2 */
+  double armijo_c;         /* sufficient-decrease constant */
+  double cg_rtol_max;      /* PCG stops at |r| <= min(cg_rtol_max, sqrt|z|) |z| (Section 5.3) */
+  int32_t max_newton, max_cg, max_ls;
+  int32_t precision;       /* BDEM_PREC_FP64 or BDEM_PREC_MIXED */
+  int32_t break_each_step; /* apply the fracture test at the end of every step */
+  int32_t cg_chunk;        /* PCG iterations between host convergence checks */
+  int32_t use_graph;       /* replay the PCG chunk as a captured HIP graph */
+} bdem_options;
+
+typedef struct {
+  int32_t newton_iters, cg_iters, ls_backtracks, status;
+  int64_t bonds_broken;
+  double grad0, grad_final, phi;
+  /* milliseconds: 0 setup, 1 bond+particle evaluation, 2 PCG, 3 line search,
+   * 4 fracture + velocity, 5 total, 6 bond-kernel time (events), 7 SpMV-kernel time */
+  double t_ms[8];
+} bdem_step_stats;
+
+/* Defaults: gravity (0,0,-9.81), no ground, newton_tol 0, newton_rtol 1e-8,
+ * armijo_c 1e-4, cg_rtol_max 0.5, max_newton 50, max_cg 2000, max_ls 30,
+ * FP64, fracture on, cg_chunk 16, no graph. */
+void bdem_default_options(bdem_options *opt);
+
+/* Device bytes bdem_create needs for this problem (0 on invalid input). */
+size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
+                            const bdem_options *opt);
+
+/* Build a handle: validates the inputs, computes per-bond rest data (l0, d0,
+ * stiffnesses; Section 3.2), the block-sparse pattern of the reduced Hessian
+ * and uploads everything.  Errors: INVALID, NOMEM, HIP. */
+int bdem_create(const bdem_particles *p, const bdem_bonds *b, const bdem_material *mats,
+                int32_t n_mats, const bdem_options *opt, void *hip_stream,
+                void *workspace_dev, size_t workspace_bytes, bdem_ctx **out);
+
+/* One implicit step of every scene with the same dt (Algorithm 3).  stats
+ * (nullable) receives the totals over scenes.  Errors: INVALID (dt <= 0),
+ * NONFINITE, DEGENERATE, HIP; warnings NOT_CONVERGED, LS_FAILED. */
+int bdem_step(bdem_ctx *ctx, double dt, bdem_step_stats *stats);
+
+/* One implicit step with a time step per scene; stats_per_scene (nullable)
+ * has one entry per scene. */
+int bdem_step_batched(bdem_ctx *ctx, const double *dt_per_scene,
+                      bdem_step_stats *stats_per_scene);
+
+/* Objective at an evaluation state without solving (Section 3.1 Phi with the
+ * prediction x_hat = x_n + dt v_n of the current state; Sections 4.1-4.2
+ * reduced Riemannian gradient and Hessian; Section 5.2 projection when
+ * BDEM_EGH_PSD).  pos_eval / quat_eval NULL: the current state.  Outputs
+ * (host, nullable): energy (1), grad6 (6n), hdiag36 (36n: the 6x6 diagonal
+ * blocks), hoff36 (36nb: for bond (i,j) the block with rows of i and columns
+ * of j).  Fixed / kinematic particles: zero gradient, identity diagonal
+ * block, zero off-diagonal blocks. */
+int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, const double *pos_eval,
+                          const double *quat_eval, double *energy, double *grad6,
+                          double *hdiag36, double *hoff36);
+
+/* Section 3.3 stress test of every alive bond at the current state; bonds
+ * with sigma > sigma_c or tau > tau_c break permanently.  n_broken (nullable)
+ * = newly broken; alive_out (nb, nullable) = the alive mask after the test. */
+int bdem_break_bonds(bdem_ctx *ctx, int64_t *n_broken, uint8_t *alive_out);
+
+/* Checkpoint / restore of the mutable state (host arrays, nullable). */
+int bdem_get_state(const bdem_ctx *ctx, double *pos, double *quat, double *vel, double *qvel,
+                   uint8_t *alive);
+int bdem_set_state(bdem_ctx *ctx, const double *pos, const double *quat, const double *vel,
+                   const double *qvel, const uint8_t *alive);
+
+/* Sizes of the handle's problem. */
+int bdem_sizes(const bdem_ctx *ctx, int32_t *n, int64_t *nb, int32_t *n_scenes);
+
+/* Measurement hook: when enabled, HIP events bracket every bond-evaluation
+ * and SpMV launch of bdem_step (graphs are not used meanwhile); the summed
+ * kernel milliseconds land in bdem_step_stats.t_ms[6] (bond) and t_ms[7]
+ * (SpMV) and the launch counts of the last step in bdem_profile_counts. */
+int bdem_set_profiling(bdem_ctx *ctx, int32_t enable);
+int bdem_profile_counts(const bdem_ctx *ctx, int32_t *bond_launches, int32_t *spmv_launches);
+
+void bdem_destroy(bdem_ctx *ctx); /* NULL-safe */
+
+/* Message of the last failed call on ctx; NULL ctx: of the last failed create
+ * on this thread. */
+const char *bdem_last_error(const bdem_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDEM_H */

@@ -371,6 +371,7 @@ int orc_bond_eval(const orc_sys *s, int64_t b, const double *pi, const double *q
   orc_bond_energy_parts(s, b, pi, qi, pj, qj, parts);
   if (energy) *energy = parts[0] + parts[1] + parts[2];
   double gl[14] = {0}, Hl[196] = {0};
+  const int want_h = H != NULL;
 
   double u[3] = {pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2]};
   double l = sqrt(dot3(u, u));
@@ -390,6 +391,7 @@ int orc_bond_eval(const orc_sys *s, int64_t b, const double *pi, const double *q
     for (int r = 0; r < 3; ++r) {
       gl[PI_ + r] -= gu[r];
       gl[PJ_ + r] += gu[r];
+      if (want_h)
       for (int c = 0; c < 3; ++c) {
         Hl[(PI_ + r) * 14 + PI_ + c] += Huu[r * 3 + c];
         Hl[(PJ_ + r) * 14 + PJ_ + c] += Huu[r * 3 + c];
@@ -483,10 +485,12 @@ int orc_bond_eval(const orc_sys *s, int64_t b, const double *pi, const double *q
     for (int r = 0; r < 4; ++r) { A[(3 + r) * 14 + QI_ + r] = 1.0; A[(3 + r) * 14 + QJ_ + r] = 1.0; }
     double ga[14], T[98], Ha[196];
     mtm(7, 14, 1, A, g7, ga);
-    mm(7, 7, 14, H7, A, T);
-    mtm(7, 14, 14, A, T, Ha);
     for (int r = 0; r < 14; ++r) gl[r] += ga[r];
-    for (int r = 0; r < 196; ++r) Hl[r] += Ha[r];
+    if (want_h) {
+      mm(7, 7, 14, H7, A, T);
+      mtm(7, 14, 14, A, T, Ha);
+      for (int r = 0; r < 196; ++r) Hl[r] += Ha[r];
+    }
   }
 
   /* ---- bend / twist: t' = G_l(q_j) q_i (bilinear), t = R_0 t', V = 1/2 t^T K t ---- */
@@ -529,6 +533,7 @@ int orc_bond_eval(const orc_sys *s, int64_t b, const double *pi, const double *q
     for (int r = 0; r < 4; ++r) {
       gl[QI_ + r] += gqi[r];
       gl[QJ_ + r] += gqj[r];
+      if (want_h)
       for (int c = 0; c < 4; ++c) {
         Hl[(QI_ + r) * 14 + QI_ + c] += Hii[r * 4 + c];
         Hl[(QJ_ + r) * 14 + QJ_ + c] += Hjj[r * 4 + c];
@@ -951,6 +956,13 @@ int orc_bond_stress(const orc_sys *s, int64_t b, const double *pos, const double
   double Mb = sqrt(K[1] * t[1] * K[1] * t[1] + K[2] * t[2] * K[2] * t[2]);
   *sigma = Fn / s->S[b] + Mb * s->r0[b] / s->I[b];
   *tau = Fs / s->S[b] + Mt * s->r0[b] / s->J[b];
+  return 0;
+}
+
+int orc_stresses(const orc_sys *s, const double *pos, const double *quat, double *sigma,
+                 double *tau) {
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < s->nb; ++b) orc_bond_stress(s, b, pos, quat, sigma + b, tau + b);
   return 0;
 }
 

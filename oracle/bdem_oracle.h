@@ -58,6 +58,10 @@ int orc_bond_reduced(const orc_sys *s, int64_t b, const double *pi, const double
 int orc_bond_stress(const orc_sys *s, int64_t b, const double *pos, const double *quat,
                     double *sigma, double *tau);
 
+/* stresses of every bond (alive or not) at the given state */
+int orc_stresses(const orc_sys *s, const double *pos, const double *quat, double *sigma,
+                 double *tau);
+
 /* predicted state of a step: p_hat (3n), q_hat (4n) */
 int orc_predict(const orc_sys *s, double dt, double *p_hat, double *q_hat);
 

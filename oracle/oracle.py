@@ -60,6 +60,7 @@ def lib():
         L.orc_bond_reduced.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp, C.c_int,
                                        _dp, _dp]
         L.orc_bond_stress.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp]
+        L.orc_stresses.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_predict.argtypes = [C.c_void_p, C.c_double, _dp, _dp]
         L.orc_energy.argtypes = [C.c_void_p, C.c_double, _dp, _dp, C.c_int, _dp]
         L.orc_energy_grad_hess.argtypes = [C.c_void_p, C.c_double, _dp, _dp, C.c_int, _dp,
@@ -171,6 +172,12 @@ class Oracle:
         pos, quat = _f64(pos), _f64(quat)
         lib().orc_bond_stress(self.h, b, _p(pos), _p(quat), C.byref(s), C.byref(t))
         return s.value, t.value
+
+    def stresses(self, pos, quat):
+        sig, tau = np.empty(max(self.nb, 1)), np.empty(max(self.nb, 1))
+        pos, quat = _f64(pos), _f64(quat)
+        lib().orc_stresses(self.h, _p(pos), _p(quat), _p(sig), _p(tau))
+        return sig[:self.nb], tau[:self.nb]
 
     # ---- whole system ----
     def predict(self, dt):

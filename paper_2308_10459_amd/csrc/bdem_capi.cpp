@@ -1,0 +1,995 @@
+// Host side of the C ABI declared in include/bdem.h: validation, rest data
+// (Section 3.2), the block-sparse pattern of the reduced Hessian, workspace
+// layout, and the driver of one implicit step (Algorithm 3 with Algorithm 2
+// inside).  Every numeric decision of the Newton / PCG / line-search loops is
+// taken by device kernels from per-scene control blocks; the host only polls
+// how many scenes are still iterating.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/bdem.h"
+#include "bdem_internal.hpp"
+
+using namespace bdem;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Sizes {
+  int n = 0, n_pad = 0, n_scenes = 1;
+  int64_t nb = 0;
+  int nb_pad = 0, n_slots = 0;
+  bool mixed = false;
+};
+
+// ordered list of device buffers carved out of one allocation
+struct Layout {
+  size_t total = 0;
+  std::vector<std::pair<void **, size_t>> items;
+  void add(void **p, size_t bytes) { items.push_back({p, bytes}); total += align_up(bytes); }
+  void bind(char *base) const {
+    size_t off = 0;
+    for (auto &it : items) {
+      *it.first = base + off;
+      off += align_up(it.second);
+    }
+  }
+};
+
+void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
+  const size_t np = S.n_pad, nbp = S.nb_pad, ns = std::max(S.n_slots, 1);
+  const size_t T = S.mixed ? 4 : 8;
+  const size_t ntile_p = np / TILE, ntile_b = std::max<size_t>(nbp / TILE, 1);
+  const size_t nspmv = np / SPMV_ROWS;
+  const size_t npart = std::max(std::max(ntile_p, ntile_b), nspmv);
+  for (double4 **p : {&d.pn, &d.qn, &d.vn, &d.wn, &d.ph, &d.qh, &d.px, &d.qx, &d.pt, &d.qt, &d.pconst})
+    L.add(reinterpret_cast<void **>(p), np * sizeof(double4));
+  L.add(reinterpret_cast<void **>(&d.flags), np);
+  L.add(reinterpret_cast<void **>(&d.psid), np * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.row_ptr), (np + 1) * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.col), ns * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.bij), std::max<size_t>(nbp, 1) * sizeof(int2));
+  for (double4 **p : {&d.brest_a, &d.brest_b, &d.brest_c})
+    L.add(reinterpret_cast<void **>(p), std::max<size_t>(nbp, 1) * sizeof(double4));
+  L.add(reinterpret_cast<void **>(&d.bstrength), std::max<size_t>(nbp, 1) * sizeof(double2));
+  L.add(reinterpret_cast<void **>(&d.alive), std::max<size_t>(nbp, 1));
+  L.add(reinterpret_cast<void **>(&d.bslot), std::max<size_t>(nbp, 1) * sizeof(int2));
+  L.add(reinterpret_cast<void **>(&d.bsid), std::max<size_t>(nbp, 1) * sizeof(int));
+  L.add(&d.hdiag, np * 21 * T);
+  L.add(&d.hoff, ns * 36 * T);
+  L.add(&d.hhalf, ns * 21 * T);
+  L.add(&d.h9, std::max<size_t>(nbp, 1) * 45 * T);
+  L.add(reinterpret_cast<void **>(&d.ghalf), ns * 6 * sizeof(double));
+  L.add(&d.dinv, np * 21 * T);
+  for (double **p : {&d.z, &d.cx, &d.cr, &d.cs, &d.cp, &d.cAp})
+    L.add(reinterpret_cast<void **>(p), np * 6 * sizeof(double));
+  for (double2 **p : {&d.part_a, &d.part_b, &d.part_c})
+    L.add(reinterpret_cast<void **>(p), npart * sizeof(double2));
+  L.add(reinterpret_cast<void **>(&d.part_max), 2 * npart * sizeof(double));
+  L.add(reinterpret_cast<void **>(&d.part_cnt), npart * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.ctl), S.n_scenes * sizeof(SceneCtl));
+  L.add(reinterpret_cast<void **>(&d.scene_pbeg), (S.n_scenes + 1) * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.scene_bbeg), (S.n_scenes + 1) * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.counters), 4 * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.degenerate), sizeof(int));
+}
+
+// scene sizes from the particle and bond arrays (no validation beyond what
+// sizing needs)
+bool scene_sizes(const bdem_particles *p, const bdem_bonds *b, std::vector<int> &pcnt,
+                 std::vector<int64_t> &bcnt, std::string &err) {
+  const int n = p->n;
+  int S = 1;
+  if (p->scene) {
+    for (int i = 0; i < n; ++i) {
+      if (p->scene[i] < 0 || (i > 0 && p->scene[i] < p->scene[i - 1])) {
+        err = "scene ids must be non-negative and non-decreasing";
+        return false;
+      }
+    }
+    S = p->scene[n - 1] + 1;
+  }
+  pcnt.assign(S, 0);
+  bcnt.assign(S, 0);
+  for (int i = 0; i < n; ++i) pcnt[p->scene ? p->scene[i] : 0]++;
+  for (int s = 0; s < S; ++s)
+    if (pcnt[s] == 0) { err = "empty scene id"; return false; }
+  for (int64_t k = 0; k < b->nb; ++k) {
+    const int i = b->ij[2 * k], j = b->ij[2 * k + 1];
+    if (i < 0 || j < 0 || i >= n || j >= n) { err = "bond index out of range"; return false; }
+    const int si = p->scene ? p->scene[i] : 0, sj = p->scene ? p->scene[j] : 0;
+    if (si != sj) { err = "bond joins two scenes"; return false; }
+    bcnt[si]++;
+  }
+  return true;
+}
+
+Sizes compute_sizes(const std::vector<int> &pcnt, const std::vector<int64_t> &bcnt, int n,
+                    int64_t nb, bool mixed) {
+  Sizes S;
+  S.n = n;
+  S.nb = nb;
+  S.n_scenes = (int)pcnt.size();
+  S.mixed = mixed;
+  int64_t np = 0, nbp = 0;
+  for (size_t s = 0; s < pcnt.size(); ++s) {
+    np += (pcnt[s] + TILE - 1) / TILE * TILE;
+    nbp += (bcnt[s] + TILE - 1) / TILE * TILE;
+  }
+  S.n_pad = (int)np;
+  S.nb_pad = (int)nbp;
+  S.n_slots = (int)(2 * nb);
+  return S;
+}
+
+}  // namespace
+
+struct bdem_ctx {
+  hipStream_t stream = nullptr;
+  void *mem = nullptr;
+  bool own_mem = false;
+  Sizes S;
+  DevPtrs d{};
+  Params P{};
+  bdem_options opt{};
+  std::string err;
+  // host copies of the mapping
+  std::vector<int> p_int;        // user particle -> internal row
+  std::vector<int64_t> b_int;    // user bond -> internal bond
+  std::vector<int2> bslot_h;     // internal bond -> slots
+  std::vector<int> scene_pbeg, scene_bbeg;
+  // pinned host mirrors
+  int *h_counters = nullptr;     // 2 polling slots x 4
+  int prof_cnt[2] = {0, 0};      // profiled launches in the last step (bond, SpMV)
+  SceneCtl *h_ctl = nullptr;
+  hipEvent_t ev_slot[2] = {nullptr, nullptr};
+  // graph of one CG iteration (+ counter copy), one per polling slot
+  hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
+  hipGraph_t cg_graph[2] = {nullptr, nullptr};
+  // profiling: events around the bond and SpMV kernels
+  int profiling = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;   // (kind, index of start event)
+};
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess) {                                                           \
+      ctx->err = std::string("HIP error: ") + hipGetErrorString(_e) + " at " #expr;   \
+      return BDEM_E_HIP;                                                              \
+    }                                                                                 \
+  } while (0)
+
+static int fail(bdem_ctx *ctx, int code, const std::string &m) {
+  if (ctx) ctx->err = m;
+  else g_create_error = m;
+  return code;
+}
+
+extern "C" void bdem_default_options(bdem_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->gravity[2] = -9.81;
+  o->ground_normal[2] = 1.0;
+  o->k_contact = 0.0;
+  o->newton_tol = 0.0;
+  o->newton_rtol = 1e-8;
+  o->armijo_c = 1e-4;
+  o->cg_rtol_max = 0.5;
+  o->max_newton = 50;
+  o->max_cg = 2000;
+  o->max_ls = 30;
+  o->precision = BDEM_PREC_FP64;
+  o->break_each_step = 1;
+  o->cg_chunk = 16;
+  o->use_graph = 0;
+}
+
+extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
+                                       const bdem_options *opt) {
+  if (!p || !b || p->n <= 0 || b->nb < 0 || (b->nb > 0 && !b->ij)) return 0;
+  std::vector<int> pcnt;
+  std::vector<int64_t> bcnt;
+  std::string err;
+  if (!scene_sizes(p, b, pcnt, bcnt, err)) return 0;
+  bdem_options o;
+  if (opt) o = *opt;
+  else bdem_default_options(&o);
+  Sizes S = compute_sizes(pcnt, bcnt, p->n, b->nb, o.precision == BDEM_PREC_MIXED);
+  DevPtrs d{};
+  Layout L;
+  make_layout(S, d, L);
+  return L.total + ALIGN;
+}
+
+static void destroy_resources(bdem_ctx *ctx) {
+  for (int k = 0; k < 2; ++k) {
+    if (ctx->cg_exec[k]) (void)hipGraphExecDestroy(ctx->cg_exec[k]);
+    if (ctx->cg_graph[k]) (void)hipGraphDestroy(ctx->cg_graph[k]);
+    if (ctx->ev_slot[k]) (void)hipEventDestroy(ctx->ev_slot[k]);
+  }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+  if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+  if (ctx->own_mem && ctx->mem) (void)hipFree(ctx->mem);
+}
+
+extern "C" void bdem_destroy(bdem_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  destroy_resources(ctx);
+  delete ctx;
+}
+
+extern "C" const char *bdem_last_error(const bdem_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" int bdem_sizes(const bdem_ctx *ctx, int32_t *n, int64_t *nb, int32_t *ns) {
+  if (!ctx) return BDEM_E_INVALID;
+  if (n) *n = ctx->S.n;
+  if (nb) *nb = ctx->S.nb;
+  if (ns) *ns = ctx->S.n_scenes;
+  return BDEM_OK;
+}
+
+extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const bdem_material *mats,
+                           int32_t n_mats, const bdem_options *opt, void *hip_stream,
+                           void *workspace_dev, size_t workspace_bytes, bdem_ctx **out) {
+  if (!out) return fail(nullptr, BDEM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!p || !b || !mats || n_mats <= 0) return fail(nullptr, BDEM_E_INVALID, "NULL argument");
+  const int n = p->n;
+  if (n <= 0 || !p->pos || !p->quat || !p->radius || !p->material)
+    return fail(nullptr, BDEM_E_INVALID, "particles: n <= 0 or a required array is NULL");
+  if (b->nb < 0 || (b->nb > 0 && !b->ij)) return fail(nullptr, BDEM_E_INVALID, "bonds: bad nb / ij");
+  if (b->nb > (int64_t)1 << 30) return fail(nullptr, BDEM_E_INVALID, "too many bonds");
+  bdem_options o;
+  if (opt) o = *opt;
+  else bdem_default_options(&o);
+  if (o.precision != BDEM_PREC_FP64 && o.precision != BDEM_PREC_MIXED)
+    return fail(nullptr, BDEM_E_INVALID, "unknown precision");
+  if (o.mu_s != 0.0 || o.mu_r != 0.0)
+    return fail(nullptr, BDEM_E_INVALID, "friction is not implemented (mu_s = mu_r = 0 required)");
+  if (o.max_newton < 0 || o.max_cg <= 0 || o.max_ls < 0 || o.cg_chunk <= 0)
+    return fail(nullptr, BDEM_E_INVALID, "bad iteration limits");
+  // ---- validation ----
+  for (int i = 0; i < n; ++i) {
+    const double *q = p->quat + 4 * i;
+    const double qn = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (!std::isfinite(qn) || std::fabs(qn - 1.0) > 1e-6) return fail(nullptr, BDEM_E_INVALID, "non-unit quaternion");
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(p->pos[3 * i + k])) return fail(nullptr, BDEM_E_NONFINITE, "non-finite position");
+    if (!(p->radius[i] > 0.0)) return fail(nullptr, BDEM_E_INVALID, "radius must be > 0");
+    if (p->material[i] < 0 || p->material[i] >= n_mats) return fail(nullptr, BDEM_E_INVALID, "bad material index");
+    if (p->flags && p->flags[i] > 2) return fail(nullptr, BDEM_E_INVALID, "bad particle flag");
+  }
+  for (int k = 0; k < n_mats; ++k) {
+    const bdem_material &m = mats[k];
+    if (!(m.young > 0.0) || !(m.density > 0.0) || !(m.poisson > -1.0) || m.poisson >= 0.5)
+      return fail(nullptr, BDEM_E_INVALID, "bad material constants");
+    if (m.shear_mode != 0 && m.shear_mode != 1) return fail(nullptr, BDEM_E_INVALID, "bad shear_mode");
+    for (int c = 0; c < 4; ++c)
+      if (!(m.stiff_scale[c] >= 0.0)) return fail(nullptr, BDEM_E_INVALID, "bad stiff_scale");
+  }
+  std::vector<int> pcnt;
+  std::vector<int64_t> bcnt;
+  std::string err;
+  if (!scene_sizes(p, b, pcnt, bcnt, err)) return fail(nullptr, BDEM_E_INVALID, err);
+  {
+    std::vector<uint64_t> keys(b->nb);
+    for (int64_t k = 0; k < b->nb; ++k) {
+      uint32_t i = b->ij[2 * k], j = b->ij[2 * k + 1];
+      if (i == j) return fail(nullptr, BDEM_E_INVALID, "bond with i == j");
+      if (b->material && (b->material[k] < 0 || b->material[k] >= n_mats))
+        return fail(nullptr, BDEM_E_INVALID, "bad bond material");
+      keys[k] = ((uint64_t)std::min(i, j) << 32) | std::max(i, j);
+    }
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
+      return fail(nullptr, BDEM_E_INVALID, "duplicate bond");
+  }
+  bdem_ctx *ctx = new bdem_ctx();
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->opt = o;
+  ctx->S = compute_sizes(pcnt, bcnt, n, b->nb, o.precision == BDEM_PREC_MIXED);
+  Sizes &S = ctx->S;
+  const int NS = S.n_scenes;
+  // ---- internal order: scenes padded to TILE particles / bonds ----
+  ctx->scene_pbeg.assign(NS + 1, 0);
+  ctx->scene_bbeg.assign(NS + 1, 0);
+  for (int s = 0; s < NS; ++s) {
+    ctx->scene_pbeg[s + 1] = ctx->scene_pbeg[s] + (pcnt[s] + TILE - 1) / TILE * TILE;
+    ctx->scene_bbeg[s + 1] = ctx->scene_bbeg[s] + (int)((bcnt[s] + TILE - 1) / TILE * TILE);
+  }
+  ctx->p_int.resize(n);
+  {
+    std::vector<int> fill(NS, 0);
+    for (int i = 0; i < n; ++i) {
+      const int s = p->scene ? p->scene[i] : 0;
+      ctx->p_int[i] = ctx->scene_pbeg[s] + fill[s]++;
+    }
+  }
+  const int NP = S.n_pad, NB = S.nb_pad;
+  std::vector<double4> h_pn(NP, make_double4(0, 0, 0, 0)), h_qn(NP, make_double4(0, 0, 0, 1)),
+      h_vn(NP, make_double4(0, 0, 0, 0)), h_wn(NP, make_double4(0, 0, 0, 0)),
+      h_pc(NP, make_double4(0, 0, 1, 0));
+  std::vector<uint8_t> h_flags(NP, 255);
+  std::vector<int> h_psid(NP, 0);
+  for (int s = 0; s < NS; ++s)
+    for (int r = ctx->scene_pbeg[s]; r < ctx->scene_pbeg[s + 1]; ++r) h_psid[r] = s;
+  double Emax = 0.0, rmax = 0.0;
+  for (int k = 0; k < n_mats; ++k) Emax = std::max(Emax, mats[k].young);
+  for (int i = 0; i < n; ++i) {
+    const int r = ctx->p_int[i];
+    h_pn[r] = make_double4(p->pos[3 * i], p->pos[3 * i + 1], p->pos[3 * i + 2], 0.0);
+    h_qn[r] = make_double4(p->quat[4 * i], p->quat[4 * i + 1], p->quat[4 * i + 2], p->quat[4 * i + 3]);
+    if (p->vel) h_vn[r] = make_double4(p->vel[3 * i], p->vel[3 * i + 1], p->vel[3 * i + 2], 0.0);
+    if (p->qvel) h_wn[r] = make_double4(p->qvel[4 * i], p->qvel[4 * i + 1], p->qvel[4 * i + 2], p->qvel[4 * i + 3]);
+    const double rad = p->radius[i], rho = mats[p->material[i]].density;
+    // solid sphere; extended mass M_s = diag(m I3, (8/5) m r^2 I4)  (Section 3.1)
+    const double m = rho * 4.0 / 3.0 * M_PI * rad * rad * rad;
+    h_pc[r] = make_double4(m, 8.0 / 5.0 * m * rad * rad, rad, 0.0);
+    h_flags[r] = p->flags ? p->flags[i] : 0;
+    rmax = std::max(rmax, rad);
+  }
+  // ---- bonds: per scene, sorted by (min row, max row) ----
+  std::vector<int64_t> order(b->nb);
+  std::iota(order.begin(), order.end(), 0);
+  auto key = [&](int64_t k) {
+    const int ri = ctx->p_int[b->ij[2 * k]], rj = ctx->p_int[b->ij[2 * k + 1]];
+    return ((uint64_t)std::min(ri, rj) << 32) | (uint32_t)std::max(ri, rj);
+  };
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t c) { return key(a) < key(c); });
+  ctx->b_int.assign(b->nb, 0);
+  std::vector<int2> h_bij(std::max(NB, 1), make_int2(0, 0));
+  std::vector<double4> h_ra(std::max(NB, 1), make_double4(1, 0, 0, 1)), h_rb(std::max(NB, 1), make_double4(0, 0, 0, 0)),
+      h_rc(std::max(NB, 1), make_double4(1, 0, 0, 0));
+  std::vector<double2> h_str(std::max(NB, 1), make_double2(0, 0));
+  std::vector<uint8_t> h_alive(std::max(NB, 1), 0);
+  std::vector<int> h_bsid(std::max(NB, 1), 0);
+  for (int s = 0; s < NS; ++s)
+    for (int k = ctx->scene_bbeg[s]; k < ctx->scene_bbeg[s + 1]; ++k) h_bsid[k] = s;
+  {
+    std::vector<int> fill(NS, 0);
+    for (int64_t k : order) {
+      const int i = b->ij[2 * k], j = b->ij[2 * k + 1];
+      const int s = p->scene ? p->scene[i] : 0;
+      const int bi = ctx->scene_bbeg[s] + fill[s]++;
+      ctx->b_int[k] = bi;
+      const int ri = ctx->p_int[i], rj = ctx->p_int[j];
+      h_bij[bi] = make_int2(ri, rj);
+      const double u[3] = {p->pos[3 * j] - p->pos[3 * i], p->pos[3 * j + 1] - p->pos[3 * i + 1],
+                           p->pos[3 * j + 2] - p->pos[3 * i + 2]};
+      const double l0 = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      if (!(l0 > 0.0) || !std::isfinite(l0)) {
+        destroy_resources(ctx);
+        delete ctx;
+        return fail(nullptr, BDEM_E_INVALID, "bonded particles coincide");
+      }
+      const bdem_material &m = mats[b->material ? b->material[k] : p->material[i]];
+      const double E = m.young, G = E / (2.0 * (1.0 + m.poisson));
+      const double r0 = 0.5 * (p->radius[i] + p->radius[j]);
+      const double Sa = M_PI * r0 * r0, I = M_PI * r0 * r0 * r0 * r0 / 4.0, J = 2.0 * I;
+      const double L2 = m.shear_mode == BDEM_SHEAR_LITERAL ? 1.0 : l0 * l0;
+      h_ra[bi] = make_double4(u[0] / l0, u[1] / l0, u[2] / l0, l0);
+      h_rb[bi] = make_double4(E * Sa / l0 * m.stiff_scale[0], G * Sa / l0 * m.stiff_scale[1] * L2,
+                              G * J / l0 * m.stiff_scale[2], E * I / l0 * m.stiff_scale[3]);
+      h_rc[bi] = make_double4(Sa, r0 / I, r0 / J, m.tension_only ? 1.0 : 0.0);
+      h_str[bi] = make_double2(m.sigma_c, m.tau_c);
+      h_alive[bi] = 1;
+    }
+  }
+  // ---- block-CSR pattern: row r lists its bonds sorted by neighbour ----
+  std::vector<int> rp(NP + 1, 0);
+  for (int bi = 0; bi < NB; ++bi) {
+    if (!h_alive[bi]) continue;   // padding (all real bonds start alive)
+    rp[h_bij[bi].x + 1]++;
+    rp[h_bij[bi].y + 1]++;
+  }
+  for (int r = 0; r < NP; ++r) rp[r + 1] += rp[r];
+  std::vector<std::vector<std::pair<int, int>>> adj(NP);   // (neighbour, bond*2 + end)
+  for (int bi = 0; bi < NB; ++bi) {
+    if (!h_alive[bi]) continue;
+    adj[h_bij[bi].x].push_back({h_bij[bi].y, 2 * bi});
+    adj[h_bij[bi].y].push_back({h_bij[bi].x, 2 * bi + 1});
+  }
+  std::vector<int> h_col(std::max(S.n_slots, 1), 0);
+  ctx->bslot_h.assign(std::max(NB, 1), make_int2(-1, -1));
+  for (int r = 0; r < NP; ++r) {
+    std::sort(adj[r].begin(), adj[r].end());
+    for (size_t k = 0; k < adj[r].size(); ++k) {
+      const int slot = rp[r] + (int)k;
+      h_col[slot] = adj[r][k].first;
+      const int bi = adj[r][k].second >> 1, end = adj[r][k].second & 1;
+      if (end == 0) ctx->bslot_h[bi].x = slot;
+      else ctx->bslot_h[bi].y = slot;
+    }
+  }
+  adj.clear();
+  adj.shrink_to_fit();
+  // ---- device memory ----
+  Layout L;
+  make_layout(S, ctx->d, L);
+  const size_t need = L.total + ALIGN;
+  if (workspace_dev) {
+    if (workspace_bytes < need) {
+      destroy_resources(ctx);
+      delete ctx;
+      return fail(nullptr, BDEM_E_NOMEM, "workspace too small");
+    }
+    ctx->mem = workspace_dev;
+  } else {
+    if (hipMalloc(&ctx->mem, need) != hipSuccess) {
+      destroy_resources(ctx);
+      delete ctx;
+      return fail(nullptr, BDEM_E_NOMEM, "hipMalloc failed");
+    }
+    ctx->own_mem = true;
+  }
+  char *base = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(ctx->mem) + ALIGN - 1) / ALIGN * ALIGN);
+  L.bind(base);
+  DevPtrs &d = ctx->d;
+  d.n_pad = NP;
+  d.nb_pad = NB;
+  d.n_slots = S.n_slots;
+  // ---- params ----
+  Params &P = ctx->P;
+  P.gx = o.gravity[0]; P.gy = o.gravity[1]; P.gz = o.gravity[2];
+  {
+    const double gn = std::sqrt(o.ground_normal[0] * o.ground_normal[0] + o.ground_normal[1] * o.ground_normal[1] +
+                                o.ground_normal[2] * o.ground_normal[2]);
+    if (o.k_contact != 0.0 && !(gn > 0.0)) {
+      destroy_resources(ctx);
+      delete ctx;
+      return fail(nullptr, BDEM_E_INVALID, "ground normal is zero");
+    }
+    P.gnx = gn > 0 ? o.ground_normal[0] / gn : 0.0;
+    P.gny = gn > 0 ? o.ground_normal[1] / gn : 0.0;
+    P.gnz = gn > 0 ? o.ground_normal[2] / gn : 0.0;
+  }
+  P.gh = o.ground_offset;
+  P.kc = o.k_contact < 0.0 ? Emax * rmax : o.k_contact;   // Section 5.4: of the order of E r_max
+  P.newton_tol = o.newton_tol;
+  P.newton_rtol = o.newton_rtol;
+  P.armijo_c = o.armijo_c;
+  P.cg_rtol_max = o.cg_rtol_max;
+  P.max_newton = o.max_newton;
+  P.max_cg = o.max_cg;
+  P.max_ls = o.max_ls;
+  P.n_scenes = NS;
+  // ---- upload ----
+  hipStream_t st = ctx->stream;
+  auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
+  std::vector<SceneCtl> ctl0(NS);
+  std::memset(ctl0.data(), 0, sizeof(SceneCtl) * NS);
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chk(up(d.pn, h_pn.data(), NP * sizeof(double4)));
+  chk(up(d.qn, h_qn.data(), NP * sizeof(double4)));
+  chk(up(d.vn, h_vn.data(), NP * sizeof(double4)));
+  chk(up(d.wn, h_wn.data(), NP * sizeof(double4)));
+  chk(up(d.pconst, h_pc.data(), NP * sizeof(double4)));
+  chk(up(d.flags, h_flags.data(), NP));
+  chk(up(d.psid, h_psid.data(), NP * sizeof(int)));
+  chk(up(d.row_ptr, rp.data(), (NP + 1) * sizeof(int)));
+  chk(up(d.col, h_col.data(), h_col.size() * sizeof(int)));
+  chk(up(d.bij, h_bij.data(), h_bij.size() * sizeof(int2)));
+  chk(up(d.brest_a, h_ra.data(), h_ra.size() * sizeof(double4)));
+  chk(up(d.brest_b, h_rb.data(), h_rb.size() * sizeof(double4)));
+  chk(up(d.brest_c, h_rc.data(), h_rc.size() * sizeof(double4)));
+  chk(up(d.bstrength, h_str.data(), h_str.size() * sizeof(double2)));
+  chk(up(d.alive, h_alive.data(), h_alive.size()));
+  chk(up(d.bslot, ctx->bslot_h.data(), ctx->bslot_h.size() * sizeof(int2)));
+  chk(up(d.bsid, h_bsid.data(), h_bsid.size() * sizeof(int)));
+  chk(up(d.ctl, ctl0.data(), NS * sizeof(SceneCtl)));
+  chk(up(d.scene_pbeg, ctx->scene_pbeg.data(), (NS + 1) * sizeof(int)));
+  chk(up(d.scene_bbeg, ctx->scene_bbeg.data(), (NS + 1) * sizeof(int)));
+  // iterate / trial / prediction start as the state; solver buffers zero
+  chk(hipMemcpyAsync(d.px, d.pn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
+  chk(hipMemcpyAsync(d.qx, d.qn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
+  chk(hipMemcpyAsync(d.ph, d.pn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
+  chk(hipMemcpyAsync(d.qh, d.qn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
+  chk(hipMemcpyAsync(d.pt, d.pn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
+  chk(hipMemcpyAsync(d.qt, d.qn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
+  for (double *v : {d.z, d.cx, d.cr, d.cs, d.cp, d.cAp}) chk(hipMemsetAsync(v, 0, (size_t)NP * 6 * sizeof(double), st));
+  const size_t T = S.mixed ? 4 : 8;
+  chk(hipMemsetAsync(d.hoff, 0, (size_t)std::max(S.n_slots, 1) * 36 * T, st));
+  chk(hipMemsetAsync(d.hhalf, 0, (size_t)std::max(S.n_slots, 1) * 21 * T, st));
+  chk(hipMemsetAsync(d.ghalf, 0, (size_t)std::max(S.n_slots, 1) * 6 * sizeof(double), st));
+  chk(hipMemsetAsync(d.hdiag, 0, (size_t)NP * 21 * T, st));
+  chk(hipMemsetAsync(d.dinv, 0, (size_t)NP * 21 * T, st));
+  chk(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
+  chk(hipHostMalloc((void **)&ctx->h_counters, 8 * sizeof(int), hipHostMallocDefault));
+  chk(hipHostMalloc((void **)&ctx->h_ctl, NS * sizeof(SceneCtl), hipHostMallocDefault));
+  for (int k = 0; k < 2; ++k) chk(hipEventCreateWithFlags(&ctx->ev_slot[k], hipEventDisableTiming));
+  chk(hipStreamSynchronize(st));
+  if (e != hipSuccess) {
+    const std::string m = std::string("HIP error during create: ") + hipGetErrorString(e);
+    destroy_resources(ctx);
+    delete ctx;
+    return fail(nullptr, BDEM_E_HIP, m);
+  }
+  *out = ctx;
+  return BDEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// helpers for the step driver
+// ---------------------------------------------------------------------------
+
+static int read_counters(bdem_ctx *ctx, int slot) {
+  HIP_TRY(hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return BDEM_OK;
+}
+
+static void prof_mark(bdem_ctx *ctx, int kind, bool start) {
+  if (!ctx->profiling) return;
+  if (ctx->ev_used + 1 >= ctx->ev_pool.size()) {
+    const size_t add = 1024;
+    for (size_t k = 0; k < add; ++k) {
+      hipEvent_t ev;
+      (void)hipEventCreate(&ev);
+      ctx->ev_pool.push_back(ev);
+    }
+  }
+  if (start) ctx->ev_marks.push_back({kind, ctx->ev_used});
+  (void)hipEventRecord(ctx->ev_pool[ctx->ev_used++], ctx->stream);
+}
+
+static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
+  for (auto &m : ctx->ev_marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev_pool[m.second], ctx->ev_pool[m.second + 1]) == hipSuccess) {
+      ms_kind[m.first] += ms;
+      cnt_kind[m.first] += 1;
+    }
+  }
+  ctx->ev_marks.clear();
+  ctx->ev_used = 0;
+}
+
+static int build_cg_graphs(bdem_ctx *ctx, int chunk) {
+  const bool mixed = ctx->S.mixed;
+  for (int slot = 0; slot < 2; ++slot) {
+    HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < chunk; ++k) {
+      launch_spmv(ctx->d, mixed, ctx->stream);
+      launch_cg_rest(ctx->d, ctx->P, mixed, ctx->stream);
+    }
+    launch_count_active(ctx->d, ctx->S.n_scenes, ctx->stream);
+    (void)hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int), hipMemcpyDeviceToHost,
+                         ctx->stream);
+    HIP_TRY(hipStreamEndCapture(ctx->stream, &ctx->cg_graph[slot]));
+    HIP_TRY(hipGraphInstantiate(&ctx->cg_exec[slot], ctx->cg_graph[slot], nullptr, nullptr, 0));
+  }
+  return BDEM_OK;
+}
+
+// PCG for every scene whose cg_active flag is set.  Iterations are issued in
+// chunks; after each chunk the active-scene count is copied to pinned host
+// memory.  Pipelined polling: the host reads the count of chunk c-1 while
+// chunk c is in flight, so the device never waits on the host.
+static int run_pcg(bdem_ctx *ctx) {
+  const bool mixed = ctx->S.mixed;
+  hipStream_t st = ctx->stream;
+  launch_cg_init(ctx->d, mixed, st);
+  launch_cg_start(ctx->d, ctx->S.n_scenes, st);
+  launch_count_active(ctx->d, ctx->S.n_scenes, st);
+  int rc = read_counters(ctx, 0);
+  if (rc) return rc;
+  if (ctx->h_counters[1] == 0) return BDEM_OK;
+  const int chunk = std::max(1, ctx->opt.cg_chunk);
+  const bool graph = ctx->opt.use_graph && st != nullptr && !ctx->profiling;
+  if (graph && !ctx->cg_exec[0]) {
+    rc = build_cg_graphs(ctx, chunk);
+    if (rc) return rc;
+  }
+  const int max_chunks = ctx->opt.max_cg / chunk + 3;
+  int pending = -1;
+  for (int c = 0; c < max_chunks; ++c) {
+    const int slot = c & 1;
+    if (graph) {
+      HIP_TRY(hipGraphLaunch(ctx->cg_exec[slot], st));
+    } else {
+      for (int k = 0; k < chunk; ++k) {
+        prof_mark(ctx, 1, true);
+        launch_spmv(ctx->d, mixed, st);
+        prof_mark(ctx, 1, false);
+        launch_cg_rest(ctx->d, ctx->P, mixed, st);
+      }
+      launch_count_active(ctx->d, ctx->S.n_scenes, st);
+      HIP_TRY(hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int),
+                             hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipEventRecord(ctx->ev_slot[slot], st));
+    if (pending >= 0) {
+      HIP_TRY(hipEventSynchronize(ctx->ev_slot[pending]));
+      if (ctx->h_counters[4 * pending + 1] == 0) break;
+    }
+    pending = slot;
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return BDEM_OK;
+}
+
+static int run_line_search(bdem_ctx *ctx) {
+  hipStream_t st = ctx->stream;
+  for (int it = 0; it <= ctx->opt.max_ls + 2; ++it) {
+    launch_ls_trial(ctx->d, ctx->P, st);
+    launch_bond_energy(ctx->d, true, st);
+    launch_ls_decide(ctx->d, ctx->P, st);
+    launch_ls_accept(ctx->d, st);
+    launch_count_active(ctx->d, ctx->S.n_scenes, st);
+    int rc = read_counters(ctx, 0);
+    if (rc) return rc;
+    if (ctx->h_counters[2] == 0) return BDEM_OK;
+  }
+  return BDEM_OK;
+}
+
+static double elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+// one implicit step of every scene (Algorithm 3), dt per scene
+static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, bool per_scene) {
+  const int NS = ctx->S.n_scenes;
+  for (int s = 0; s < NS; ++s)
+    if (!(dts[s] > 0.0) || !std::isfinite(dts[s])) return fail(ctx, BDEM_E_INVALID, "dt must be > 0");
+  hipStream_t st = ctx->stream;
+  DevPtrs &d = ctx->d;
+  const bool mixed = ctx->S.mixed;
+  hipEvent_t ph[6];
+  for (auto &e : ph) HIP_TRY(hipEventCreate(&e));
+  struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int k = 0; k < 6; ++k) (void)hipEventDestroy(e[k]); } } guard{ph};
+  double t_eval = 0, t_cg = 0, t_ls = 0;
+  HIP_TRY(hipEventRecord(ph[0], st));
+  // reset the control blocks
+  for (int s = 0; s < NS; ++s) {
+    SceneCtl &c = ctx->h_ctl[s];
+    std::memset(&c, 0, sizeof(c));
+    c.dt = dts[s];
+    c.inv_dt2 = 1.0 / (dts[s] * dts[s]);
+    c.newton_active = 1;
+  }
+  HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
+  launch_predict(d, true, st);
+  for (int k = 0; k <= ctx->opt.max_newton + 1; ++k) {
+    HIP_TRY(hipEventRecord(ph[1], st));
+    prof_mark(ctx, 0, true);
+    launch_bond_eval(d, mixed, true, true, st);
+    prof_mark(ctx, 0, false);
+    launch_particle_eval(d, ctx->P, mixed, true, false, st);
+    launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, st);
+    launch_count_active(d, NS, st);
+    int rc = read_counters(ctx, 0);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ph[2], st));
+    t_eval += elapsed(ph[1], ph[2]);
+    if (ctx->h_counters[3] > 0) return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
+    if (ctx->h_counters[0] == 0) break;
+    rc = run_pcg(ctx);
+    if (rc) return rc;
+    launch_cg_slope(d, NS, st);
+    HIP_TRY(hipEventRecord(ph[3], st));
+    rc = run_line_search(ctx);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ph[4], st));
+    HIP_TRY(hipEventSynchronize(ph[4]));
+    t_cg += elapsed(ph[2], ph[3]);
+    t_ls += elapsed(ph[3], ph[4]);
+  }
+  // outcome per scene
+  HIP_TRY(hipMemcpyAsync(ctx->h_ctl, d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int s = 0; s < NS; ++s)
+    if (ctx->h_ctl[s].status == ST_NONFINITE) return fail(ctx, BDEM_E_NONFINITE, "non-finite objective or gradient");
+  HIP_TRY(hipEventRecord(ph[1], st));
+  launch_finish_step(d, st);
+  int64_t broken = 0;
+  if (ctx->opt.break_each_step && ctx->S.nb_pad > 0) {
+    launch_bond_fracture(d, st);
+    const int nt = ctx->S.nb_pad / TILE;
+    std::vector<int> cnt(nt);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), d.part_cnt, nt * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int v : cnt) broken += v;
+    if (per_scene && stats) {
+      for (int s = 0; s < NS; ++s) {
+        int64_t bs = 0;
+        for (int t = ctx->scene_bbeg[s] / TILE; t < ctx->scene_bbeg[s + 1] / TILE; ++t) bs += cnt[t];
+        stats[s].bonds_broken = bs;
+      }
+    }
+  }
+  HIP_TRY(hipEventRecord(ph[5], st));
+  HIP_TRY(hipEventSynchronize(ph[5]));
+  double kind_ms[2] = {0, 0};
+  int kind_cnt[2] = {0, 0};
+  prof_collect(ctx, kind_ms, kind_cnt);
+  int ret = BDEM_OK;
+  for (int s = 0; s < NS; ++s) {
+    const SceneCtl &c = ctx->h_ctl[s];
+    if (c.status == ST_NOT_CONVERGED) ret = std::max(ret, (int)BDEM_W_NOT_CONVERGED);
+    if (c.status == ST_LS_FAILED) ret = std::max(ret, (int)BDEM_W_LS_FAILED);
+  }
+  if (stats) {
+    auto fill = [&](bdem_step_stats &o, const SceneCtl &c) {
+      o.newton_iters = c.newton_it;
+      o.cg_iters = c.cg_total;
+      o.ls_backtracks = c.ls_total;
+      o.status = c.status;
+      o.grad0 = c.gnorm0;
+      o.grad_final = c.gnorm;
+      o.phi = c.phi;
+      o.t_ms[0] = 0;
+      o.t_ms[1] = t_eval;
+      o.t_ms[2] = t_cg;
+      o.t_ms[3] = t_ls;
+      o.t_ms[4] = elapsed(ph[1], ph[5]);
+      o.t_ms[5] = elapsed(ph[0], ph[5]);
+      o.t_ms[6] = kind_ms[0];
+      o.t_ms[7] = kind_ms[1];
+    };
+    if (per_scene) {
+      for (int s = 0; s < NS; ++s) fill(stats[s], ctx->h_ctl[s]);
+    } else {
+      bdem_step_stats &o = *stats;
+      std::memset(&o, 0, sizeof(o));
+      fill(o, ctx->h_ctl[0]);
+      o.newton_iters = o.cg_iters = o.ls_backtracks = 0;
+      o.grad0 = o.grad_final = o.phi = 0;
+      for (int s = 0; s < NS; ++s) {
+        const SceneCtl &c = ctx->h_ctl[s];
+        o.newton_iters += c.newton_it;
+        o.cg_iters += c.cg_total;
+        o.ls_backtracks += c.ls_total;
+        o.grad0 = std::max(o.grad0, c.gnorm0);
+        o.grad_final = std::max(o.grad_final, c.gnorm);
+        o.phi += c.phi;
+        o.status = std::max(o.status, c.status);
+      }
+      o.bonds_broken = broken;
+    }
+  }
+  ctx->prof_cnt[0] = kind_cnt[0];
+  ctx->prof_cnt[1] = kind_cnt[1];
+  return ret;
+}
+
+extern "C" int bdem_step(bdem_ctx *ctx, double dt, bdem_step_stats *stats) {
+  if (!ctx) return BDEM_E_INVALID;
+  std::vector<double> dts(ctx->S.n_scenes, dt);
+  return step_impl(ctx, dts.data(), stats, false);
+}
+
+extern "C" int bdem_step_batched(bdem_ctx *ctx, const double *dt_per_scene, bdem_step_stats *stats) {
+  if (!ctx || !dt_per_scene) return BDEM_E_INVALID;
+  return step_impl(ctx, dt_per_scene, stats, true);
+}
+
+// ---------------------------------------------------------------------------
+// state I/O
+// ---------------------------------------------------------------------------
+
+static int download4(bdem_ctx *ctx, const double4 *src, double *dst, int comps) {
+  std::vector<double4> h(ctx->S.n_pad);
+  HIP_TRY(hipMemcpyAsync(h.data(), src, h.size() * sizeof(double4), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < ctx->S.n; ++i) {
+    const double4 v = h[ctx->p_int[i]];
+    const double a[4] = {v.x, v.y, v.z, v.w};
+    for (int c = 0; c < comps; ++c) dst[comps * i + c] = a[c];
+  }
+  return BDEM_OK;
+}
+
+static int upload4(bdem_ctx *ctx, double4 *dst, const double *src, int comps) {
+  std::vector<double4> h(ctx->S.n_pad);
+  HIP_TRY(hipMemcpyAsync(h.data(), dst, h.size() * sizeof(double4), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < ctx->S.n; ++i) {
+    double a[4] = {0, 0, 0, 0};
+    for (int c = 0; c < comps; ++c) a[c] = src[comps * i + c];
+    h[ctx->p_int[i]] = make_double4(a[0], a[1], a[2], a[3]);
+  }
+  HIP_TRY(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(double4), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return BDEM_OK;
+}
+
+static bool unit_quats(const double *q, int n) {
+  for (int i = 0; i < n; ++i) {
+    const double s = std::sqrt(q[4 * i] * q[4 * i] + q[4 * i + 1] * q[4 * i + 1] + q[4 * i + 2] * q[4 * i + 2] +
+                               q[4 * i + 3] * q[4 * i + 3]);
+    if (!std::isfinite(s) || std::fabs(s - 1.0) > 1e-6) return false;
+  }
+  return true;
+}
+static bool finite(const double *a, size_t n) {
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(a[k])) return false;
+  return true;
+}
+
+extern "C" int bdem_get_state(const bdem_ctx *cctx, double *pos, double *quat, double *vel,
+                              double *qvel, uint8_t *alive) {
+  bdem_ctx *ctx = const_cast<bdem_ctx *>(cctx);
+  if (!ctx) return BDEM_E_INVALID;
+  int rc;
+  if (pos && (rc = download4(ctx, ctx->d.pn, pos, 3))) return rc;
+  if (quat && (rc = download4(ctx, ctx->d.qn, quat, 4))) return rc;
+  if (vel && (rc = download4(ctx, ctx->d.vn, vel, 3))) return rc;
+  if (qvel && (rc = download4(ctx, ctx->d.wn, qvel, 4))) return rc;
+  if (alive && ctx->S.nb > 0) {
+    std::vector<uint8_t> h(ctx->S.nb_pad);
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->d.alive, h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < ctx->S.nb; ++k) alive[k] = h[ctx->b_int[k]];
+  }
+  return BDEM_OK;
+}
+
+extern "C" int bdem_set_state(bdem_ctx *ctx, const double *pos, const double *quat, const double *vel,
+                              const double *qvel, const uint8_t *alive) {
+  if (!ctx) return BDEM_E_INVALID;
+  const int n = ctx->S.n;
+  if (quat && !unit_quats(quat, n)) return fail(ctx, BDEM_E_INVALID, "non-unit quaternion");
+  if ((pos && !finite(pos, 3 * (size_t)n)) || (vel && !finite(vel, 3 * (size_t)n)) ||
+      (qvel && !finite(qvel, 4 * (size_t)n)))
+    return fail(ctx, BDEM_E_NONFINITE, "non-finite state");
+  int rc;
+  if (pos && (rc = upload4(ctx, ctx->d.pn, pos, 3))) return rc;
+  if (quat && (rc = upload4(ctx, ctx->d.qn, quat, 4))) return rc;
+  if (vel && (rc = upload4(ctx, ctx->d.vn, vel, 3))) return rc;
+  if (qvel && (rc = upload4(ctx, ctx->d.wn, qvel, 4))) return rc;
+  if (alive && ctx->S.nb > 0) {
+    std::vector<uint8_t> h(ctx->S.nb_pad);
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx->d.alive, h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int64_t k = 0; k < ctx->S.nb; ++k) h[ctx->b_int[k]] = alive[k] ? 1 : 0;
+    HIP_TRY(hipMemcpyAsync(ctx->d.alive, h.data(), h.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  return BDEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// objective / gradient / Hessian at a given state
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static void expand_blocks(const std::vector<T> &hd, const std::vector<T> &ho, bdem_ctx *ctx,
+                          double *hdiag36, double *hoff36) {
+  auto up = [](int r, int c) { return r <= c ? r * 6 - (r * (r - 1)) / 2 + (c - r) : c * 6 - (c * (c - 1)) / 2 + (r - c); };
+  if (hdiag36)
+    for (int i = 0; i < ctx->S.n; ++i) {
+      const T *src = hd.data() + (size_t)ctx->p_int[i] * 21;
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) hdiag36[36 * (size_t)i + r * 6 + c] = double(src[up(r, c)]);
+    }
+  if (hoff36)
+    for (int64_t k = 0; k < ctx->S.nb; ++k) {
+      const int slot = ctx->bslot_h[ctx->b_int[k]].x;
+      const T *src = ho.data() + (size_t)slot * 36;
+      for (int e = 0; e < 36; ++e) hoff36[36 * (size_t)k + e] = double(src[e]);
+    }
+}
+
+extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, const double *pos_eval,
+                                     const double *quat_eval, double *energy, double *grad6,
+                                     double *hdiag36, double *hoff36) {
+  if (!ctx) return BDEM_E_INVALID;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, BDEM_E_INVALID, "dt must be > 0");
+  const int n = ctx->S.n, NS = ctx->S.n_scenes, NP = ctx->S.n_pad;
+  if (quat_eval && !unit_quats(quat_eval, n)) return fail(ctx, BDEM_E_INVALID, "non-unit quaternion");
+  if (pos_eval && !finite(pos_eval, 3 * (size_t)n)) return fail(ctx, BDEM_E_NONFINITE, "non-finite state");
+  hipStream_t st = ctx->stream;
+  DevPtrs &d = ctx->d;
+  const bool mixed = ctx->S.mixed, hess = (what & BDEM_EGH_H) != 0, psd = (what & BDEM_EGH_PSD) != 0;
+  const bool pot = (what & BDEM_EGH_POTENTIAL_ONLY) != 0;
+  for (int s = 0; s < NS; ++s) {
+    SceneCtl &c = ctx->h_ctl[s];
+    std::memset(&c, 0, sizeof(c));
+    c.dt = dt;
+    c.inv_dt2 = 1.0 / (dt * dt);
+    c.newton_active = 1;
+  }
+  HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
+  launch_predict(d, false, st);
+  launch_copy_state_to_iterate(d, st);
+  int rc;
+  if (pos_eval && (rc = upload4(ctx, d.px, pos_eval, 3))) return rc;
+  if (quat_eval && (rc = upload4(ctx, d.qx, quat_eval, 4))) return rc;
+  launch_bond_eval(d, mixed, psd, hess, st);
+  launch_particle_eval(d, ctx->P, mixed, hess, pot, st);
+  launch_newton_check(d, ctx->P, 1, st);
+  launch_count_active(d, NS, st);
+  if ((rc = read_counters(ctx, 0))) return rc;
+  if (ctx->h_counters[3] > 0) return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
+  HIP_TRY(hipMemcpyAsync(ctx->h_ctl, d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost, st));
+  std::vector<double> z;
+  if (grad6) {
+    z.resize((size_t)NP * 6);
+    HIP_TRY(hipMemcpyAsync(z.data(), d.z, z.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  if (hess && (hdiag36 || hoff36)) {
+    const size_t ns = std::max(ctx->S.n_slots, 1);
+    if (mixed) {
+      std::vector<float> hd((size_t)NP * 21), ho(ns * 36);
+      HIP_TRY(hipMemcpyAsync(hd.data(), d.hdiag, hd.size() * 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(ho.data(), d.hoff, ho.size() * 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      expand_blocks(hd, ho, ctx, hdiag36, hoff36);
+    } else {
+      std::vector<double> hd((size_t)NP * 21), ho(ns * 36);
+      HIP_TRY(hipMemcpyAsync(hd.data(), d.hdiag, hd.size() * 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(ho.data(), d.hoff, ho.size() * 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      expand_blocks(hd, ho, ctx, hdiag36, hoff36);
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (grad6)
+    for (int i = 0; i < n; ++i)
+      for (int c = 0; c < 6; ++c) grad6[6 * (size_t)i + c] = z[(size_t)ctx->p_int[i] * 6 + c];
+  if (energy) {
+    double e = 0.0;
+    for (int s = 0; s < NS; ++s) e += ctx->h_ctl[s].phi;
+    *energy = e;
+  }
+  for (int s = 0; s < NS; ++s)
+    if (ctx->h_ctl[s].status == ST_NONFINITE) return fail(ctx, BDEM_E_NONFINITE, "non-finite objective");
+  return BDEM_OK;
+}
+
+extern "C" int bdem_break_bonds(bdem_ctx *ctx, int64_t *n_broken, uint8_t *alive_out) {
+  if (!ctx) return BDEM_E_INVALID;
+  hipStream_t st = ctx->stream;
+  int64_t broken = 0;
+  if (ctx->S.nb_pad > 0) {
+    launch_bond_fracture(ctx->d, st);
+    const int nt = ctx->S.nb_pad / TILE;
+    std::vector<int> cnt(nt);
+    HIP_TRY(hipMemcpyAsync(cnt.data(), ctx->d.part_cnt, nt * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int v : cnt) broken += v;
+  }
+  if (n_broken) *n_broken = broken;
+  if (alive_out) return bdem_get_state(ctx, nullptr, nullptr, nullptr, nullptr, alive_out);
+  return BDEM_OK;
+}
+
+extern "C" int bdem_set_profiling(bdem_ctx *ctx, int32_t enable) {
+  if (!ctx) return BDEM_E_INVALID;
+  ctx->profiling = enable ? 1 : 0;
+  return BDEM_OK;
+}
+
+extern "C" int bdem_profile_counts(const bdem_ctx *ctx, int32_t *bond_launches, int32_t *spmv_launches) {
+  if (!ctx) return BDEM_E_INVALID;
+  if (bond_launches) *bond_launches = ctx->prof_cnt[0];
+  if (spmv_launches) *spmv_launches = ctx->prof_cnt[1];
+  return BDEM_OK;
+}

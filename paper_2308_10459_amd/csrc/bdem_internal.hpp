@@ -1,0 +1,115 @@
+// Internal layout of a bdem_ctx on the device, shared by the host driver and
+// the kernel launchers.  Not part of the public ABI.
+//
+// Layout in HBM (internal order; scenes are padded to multiples of TILE
+// particles and TILE bonds so every kernel block belongs to one scene):
+//   particles : double4 per particle for p_n, q_n, v_n, qdot_n, p_hat, q_hat,
+//               iterate p, q and trial p, q;  double4 (m, c, r, 0) constants;
+//               uint8 flags; int scene id.
+//   bonds     : int2 (i, j);  double4 (d0, l0);  double4 (k_n, k_t L^2,
+//               GJ/l0, EI/l0);  double4 (S, r0/I, r0/J, tension_only);
+//               double2 (sigma_c, tau_c); uint8 alive; int2 slot (row i, row j).
+//   Hessian   : diagonal blocks, 21 packed values per particle (T);
+//               off-diagonal blocks in full block-CSR, 36 values per slot (T),
+//               two slots per bond; per-slot halves of the diagonal block
+//               (21 T) and of the reduced gradient (6 double) written by the
+//               bond kernel and summed in a fixed order by the particle kernel.
+//   solver    : 6 doubles per particle for z, CG x, r, s (= M^-1 r), p, Ap;
+//               block-Jacobi inverse, 21 packed values per particle (T).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bdem {
+
+constexpr int TILE = 256;       // particles / bonds per scene-aligned tile
+constexpr int SPMV_ROWS = 64;   // block rows per SpMV workgroup (384 lanes)
+
+// per-scene control block, device resident; every decision of the Newton /
+// PCG / line-search loops is taken on the device from these values
+struct SceneCtl {
+  double dt, inv_dt2;
+  double gnorm, gnorm0, phi, phi_trial, slope, alpha_ls;
+  double rz, rz_new, rr, pAp, alpha, beta, cg_tol;
+  double last_move, xmax;
+  int newton_active, cg_active, ls_active, ls_accept;
+  int newton_it, cg_it, ls_it, status;
+  int cg_total, ls_total, nonfinite, pad_;
+};
+
+enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LS_FAILED = 2, ST_NONFINITE = 3 };
+
+struct Params {
+  // environment
+  double gx, gy, gz;
+  double gnx, gny, gnz, gh, kc;
+  double newton_tol, newton_rtol, armijo_c, cg_rtol_max;
+  int max_newton, max_cg, max_ls;
+  int n_scenes;
+};
+
+struct DevPtrs {
+  int n_pad, nb_pad, n_slots;
+  // particles
+  double4 *pn, *qn, *vn, *wn;        // state x_n and rates
+  double4 *ph, *qh;                  // prediction
+  double4 *px, *qx;                  // Newton iterate
+  double4 *pt, *qt;                  // line-search trial
+  double4 *pconst;                   // (m, c, r, 0)
+  uint8_t *flags;                    // FREE / FIXED / KINEMATIC ; 255 = padding
+  int *psid;                         // scene id per particle
+  int *row_ptr;                      // n_pad + 1, off-diagonal slots per row
+  int *col;                          // n_slots
+  // bonds
+  int2 *bij;
+  double4 *brest_a, *brest_b, *brest_c;
+  double2 *bstrength;
+  uint8_t *alive;
+  int2 *bslot;
+  int *bsid;
+  // Hessian / gradient (T = float or double, typed at the launch)
+  void *hdiag;   // n_pad * 21
+  void *hoff;    // n_slots * 36
+  void *hhalf;   // n_slots * 21
+  void *h9;      // nb_pad * 45: per-bond packed reduced 9x9 before projection
+  double *ghalf; // n_slots * 6
+  void *dinv;    // n_pad * 21
+  double *z;     // 6 n_pad
+  // CG
+  double *cx, *cr, *cs, *cp, *cAp;
+  // reductions
+  double2 *part_a, *part_b, *part_c;  // per-block compensated partials
+  double *part_max;                   // per-block maxima (2 per block)
+  int *part_cnt;                      // per-block integer counts
+  SceneCtl *ctl;                      // n_scenes
+  int *scene_pbeg;                    // n_scenes + 1 (particle index, multiple of TILE)
+  int *scene_bbeg;                    // n_scenes + 1 (bond index, multiple of TILE)
+  int *counters;                      // [0] newton active, [1] cg active, [2] ls active, [3] status OR
+  int *degenerate;                    // bonds with |q_i + q_j| below the threshold
+};
+
+// ----- launchers (kernels in the .hip files) -----
+// bond kernels
+void launch_bond_eval(const DevPtrs &d, bool mixed, bool psd, bool hess, hipStream_t s);
+void launch_bond_energy(const DevPtrs &d, bool trial, hipStream_t s);
+void launch_bond_fracture(const DevPtrs &d, hipStream_t s);
+// particle kernels
+void launch_predict(const DevPtrs &d, bool write_iterate, hipStream_t s);
+void launch_copy_state_to_iterate(const DevPtrs &d, hipStream_t s);
+void launch_particle_eval(const DevPtrs &d, const Params &P, bool mixed, bool hess,
+                          bool potential_only, hipStream_t s);
+void launch_ls_trial(const DevPtrs &d, const Params &P, hipStream_t s);
+void launch_ls_accept(const DevPtrs &d, hipStream_t s);
+void launch_finish_step(const DevPtrs &d, hipStream_t s);
+// per-scene decisions
+void launch_newton_check(const DevPtrs &d, const Params &P, int first, hipStream_t s);
+void launch_count_active(const DevPtrs &d, int n_scenes, hipStream_t s);
+void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
+// PCG
+void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
+void launch_cg_start(const DevPtrs &d, int n_scenes, hipStream_t s);
+void launch_spmv(const DevPtrs &d, bool mixed, hipStream_t s);
+void launch_cg_rest(const DevPtrs &d, const Params &P, bool mixed, hipStream_t s);
+void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s);
+
+}  // namespace bdem

@@ -1,0 +1,451 @@
+// Bond-parallel kernels: per-bond energy / reduced Riemannian gradient /
+// reduced Riemannian Hessian (Sections 3.2, 4.1, 4.2), the SPD projection of
+// Section 5.2, the line-search energy pass and the fracture test of
+// Section 3.3.
+//
+// One thread per bond.  Bonds are tiled TILE per workgroup and every tile
+// belongs to a single scene.  The bond writes its off-diagonal 6x6 blocks
+// into the two block-CSR slots it owns (row i and row j) and its shares of
+// the two diagonal blocks and of the reduced gradient into per-slot halves,
+// which the particle kernel sums in a fixed order: no atomics, bitwise
+// deterministic.
+//
+// Reduced coordinates per bond: the energy depends on p_i, p_j only through
+// u = p_j - p_i, so its 12x12 reduced Hessian equals T^T H9 T with T the
+// orthonormal-row map (p_i, y_i, p_j, y_j) -> ((p_j - p_i)/sqrt2, y_i, y_j).
+// The eigen-clamp of the 12x12 therefore equals T^T clamp(H9) T exactly and
+// is computed on the 9x9 H9.
+#include "bdem_internal.hpp"
+#include "bdem_math.hpp"
+
+namespace bdem {
+
+struct BondGeom {
+  // FP64 quantities shared by energy, gradient and Hessian
+  double n[3], d[3], d0[3], w[4], Aw[4];
+  double l, l0, e, h, phi, y, F, F1, F2;
+  double gphi_u[3], gphi_w[4];
+  double tp[3], m[3];   // t' = vec(conj(q_j) q_i), m = K' t'
+  double kn, kts, ktw, kb;
+};
+
+__device__ __forceinline__ void bond_geometry(const double4 Pi, const double4 Qi,
+                                              const double4 Pj, const double4 Qj,
+                                              const double4 ra, const double4 rb, BondGeom &g) {
+  g.d0[0] = ra.x; g.d0[1] = ra.y; g.d0[2] = ra.z; g.l0 = ra.w;
+  g.kn = rb.x; g.kts = rb.y; g.ktw = rb.z; g.kb = rb.w;
+  const double u[3] = {Pj.x - Pi.x, Pj.y - Pi.y, Pj.z - Pi.z};
+  g.l = sqrt(dot3(u, u));
+  const double il = 1.0 / g.l;
+  g.n[0] = u[0] * il; g.n[1] = u[1] * il; g.n[2] = u[2] * il;
+  g.e = g.l - g.l0;
+  // shear: phi(u, w) = n . d(w), d(w) = R(w/|w|) d0, as the Rayleigh quotient
+  // w^T A_n w / w^T w with A_n = [[-(n.d0) I + d0 n^T + n d0^T, d0 x n], [(d0 x n)^T, n.d0]]
+  g.w[0] = Qi.x + Qj.x; g.w[1] = Qi.y + Qj.y; g.w[2] = Qi.z + Qj.z; g.w[3] = Qi.w + Qj.w;
+  const double *v = g.w;
+  const double sw = g.w[3];
+  g.h = 1.0 / dot4(g.w, g.w);
+  const double nd0 = dot3(g.n, g.d0), vn = dot3(v, g.n), vd = dot3(v, g.d0);
+  double d0xn[3];
+  cross3(g.d0, g.n, d0xn);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.Aw[k] = -nd0 * v[k] + g.d0[k] * vn + g.n[k] * vd + sw * d0xn[k];
+  g.Aw[3] = dot3(d0xn, v) + nd0 * sw;
+  g.phi = g.h * dot4(g.w, g.Aw);
+  double vxd0[3];
+  cross3(v, g.d0, vxd0);
+  const double vv = dot3(v, v);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.d[k] = g.h * ((sw * sw - vv) * g.d0[k] + 2.0 * vd * v[k] + 2.0 * sw * vxd0[k]);
+  const double dx = g.n[0] - g.d[0], dy = g.n[1] - g.d[1], dz = g.n[2] - g.d[2];
+  g.y = dx * dx + dy * dy + dz * dz;
+  theta2_fn(g.y, g.F, g.F1, g.F2);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g.gphi_w[k] = 2.0 * g.h * (g.Aw[k] - g.phi * g.w[k]);
+  const double nd = dot3(g.n, g.d);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.gphi_u[k] = (g.d[k] - nd * g.n[k]) * il;
+  // bend / twist: t' = vec(conj(q_j) q_i); K' = EI/l0 I + (GJ - EI)/l0 d0 d0^T
+  const double qjc[4] = {-Qj.x, -Qj.y, -Qj.z, Qj.w}, qi[4] = {Qi.x, Qi.y, Qi.z, Qi.w};
+  double r[4];
+  qmul(qjc, qi, r);
+  g.tp[0] = r[0]; g.tp[1] = r[1]; g.tp[2] = r[2];
+  const double td = dot3(g.tp, g.d0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g.m[k] = g.kb * g.tp[k] + (g.ktw - g.kb) * td * g.d0[k];
+}
+
+__device__ __forceinline__ double bond_energy_of(const BondGeom &g) {
+  return 0.5 * g.kn * g.e * g.e + 0.5 * g.kts * g.F + 0.5 * dot3(g.tp, g.m);
+}
+
+template <typename T, bool HESS>
+__global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int b = lb * TILE + threadIdx.x;
+  const int scene = d.bsid[lb * TILE];
+  if (!d.ctl[scene].newton_active) return;   // uniform over the block
+  const int2 ij = d.bij[b];
+  const int2 sl = d.bslot[b];
+  const bool real = sl.x >= 0;
+  const bool alive = real && d.alive[b];
+  KSum esum = {0.0, 0.0};
+  if (alive) {
+    const int i = ij.x, j = ij.y;
+    BondGeom g;
+    const double4 Qi = d.qx[i], Qj = d.qx[j];
+    bond_geometry(d.px[i], Qi, d.px[j], Qj, d.brest_a[b], d.brest_b[b], g);
+    if (!(dot4(g.w, g.w) >= 1e-12)) atomicAdd(d.degenerate, 1);
+    kadd(esum, bond_energy_of(g));
+    // ---------------- reduced gradient (FP64) ----------------
+    const double qi[4] = {Qi.x, Qi.y, Qi.z, Qi.w}, qj[4] = {Qj.x, Qj.y, Qj.z, Qj.w};
+    double gu[3], gw[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gu[k] = g.kn * g.e * g.n[k] - g.kts * g.F1 * g.gphi_u[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gw[k] = -g.kts * g.F1 * g.gphi_w[k];
+    // bend: grad_{q_i} = G_l(q_j)^T m = q_j (m, 0); grad_{q_j} = -G_l(q_i)^T m = -q_i (m, 0)
+    const double m4[4] = {g.m[0], g.m[1], g.m[2], 0.0};
+    double bqi[4], bqj[4];
+    qmul(qj, m4, bqi);
+    qmul(qi, m4, bqj);
+    double gqi[4], gqj[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { gqi[k] = gw[k] + bqi[k]; gqj[k] = gw[k] - bqj[k]; }
+    // reduce: z_r = G_l(q) grad_q = vec(conj(q) grad_q)
+    const double qic[4] = {-qi[0], -qi[1], -qi[2], qi[3]}, qjc[4] = {-qj[0], -qj[1], -qj[2], qj[3]};
+    double ri[4], rj[4];
+    qmul(qic, gqi, ri);
+    qmul(qjc, gqj, rj);
+    const double lam_i = dot4(qi, gqi), lam_j = dot4(qj, gqj);
+    double *gi = d.ghalf + (size_t)sl.x * 6, *gj = d.ghalf + (size_t)sl.y * 6;
+    gi[0] = -gu[0]; gi[1] = -gu[1]; gi[2] = -gu[2]; gi[3] = ri[0]; gi[4] = ri[1]; gi[5] = ri[2];
+    gj[0] = gu[0];  gj[1] = gu[1];  gj[2] = gu[2];  gj[3] = rj[0]; gj[4] = rj[1]; gj[5] = rj[2];
+    if (HESS) {
+      // ---------------- reduced Hessian (precision T) ----------------
+      const T kts = T(g.kts), F1 = T(g.F1), F2 = T(g.F2), h = T(g.h), phi = T(g.phi);
+      const T il = T(1.0 / g.l);
+      T n[3], dd[3], d0[3], gpu[3], gpw[4], w[4], Aw[4];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) { n[k] = T(g.n[k]); dd[k] = T(g.d[k]); d0[k] = T(g.d0[k]); gpu[k] = T(g.gphi_u[k]); }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { gpw[k] = T(g.gphi_w[k]); w[k] = T(g.w[k]); Aw[k] = T(g.Aw[k]); }
+      const T nd = dot3(n, dd);
+      // stretch: k_n [n n^T + (1 - l0/l)(I - n n^T)]
+      const T kn = T(g.kn), lat = T(1.0 - g.l0 / g.l);
+      T Huu[9];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T nn = n[r] * n[c];
+          const T hphi = -(dd[r] * n[c] + n[r] * dd[c] + nd * ((r == c ? T(1) : T(0)) - T(3) * nn)) * il * il;
+          Huu[r * 3 + c] = kn * (nn + lat * ((r == c ? T(1) : T(0)) - nn)) +
+                           T(2) * kts * F2 * gpu[r] * gpu[c] - kts * F1 * hphi;
+        }
+      // shear, mixed block: d(phi)/du dw = (P_n / l) J_d, J_d row k = 2h (A_{e_k} w - d_k w)
+      const T v[3] = {w[0], w[1], w[2]}, sw = w[3];
+      const T vd = dot3(v, d0);
+      T vxd0[3];
+      cross3(v, d0, vxd0);
+      T Jd[12];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        // A_{e_k} w = (-d0_k v + d0 v_k + e_k (d0.v) + s (d0 x e_k), (v x d0)_k + d0_k s)
+        T ek[3] = {T(0), T(0), T(0)};
+        ek[k] = T(1);
+        T d0xe[3];
+        cross3(d0, ek, d0xe);
+        T a4[4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a4[c] = -d0[k] * v[c] + d0[c] * v[k] + ek[c] * vd + sw * d0xe[c];
+        a4[3] = vxd0[k] + d0[k] * sw;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Jd[k * 4 + c] = T(2) * h * (a4[c] - dd[k] * w[c]);
+      }
+      T Huw[12];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          T pj = T(0);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) pj += ((r == k ? T(1) : T(0)) - n[r] * n[k]) * Jd[k * 4 + c];
+          Huw[r * 4 + c] = T(2) * kts * F2 * gpu[r] * gpw[c] - kts * F1 * pj * il;
+        }
+      // shear, w block: 2h (A_n - phi I) - 2h (w gphi^T + gphi w^T)
+      T An[16];
+      {
+        const T nd0 = dot3(n, d0);
+        T d0xn[3];
+        cross3(d0, n, d0xn);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) An[r * 4 + c] = (r == c ? -nd0 : T(0)) + d0[r] * n[c] + n[r] * d0[c];
+          An[r * 4 + 3] = d0xn[r];
+          An[12 + r] = d0xn[r];
+        }
+        An[15] = nd0;
+      }
+      T Hww[16];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const T hp = T(2) * h * (An[r * 4 + c] - (r == c ? phi : T(0))) -
+                       T(2) * h * (w[r] * gpw[c] + gpw[r] * w[c]);
+          Hww[r * 4 + c] = T(2) * kts * F2 * gpw[r] * gpw[c] - kts * F1 * hp;
+        }
+      (void)Aw;
+      // bend / twist 4x4 blocks: G_j^T K' G_j, G_i^T K' G_i, -G_j^T K' G_i + B(m)
+      T Gi[12], Gj[12];
+      {
+        const T tqi[4] = {T(qi[0]), T(qi[1]), T(qi[2]), T(qi[3])};
+        const T tqj[4] = {T(qj[0]), T(qj[1]), T(qj[2]), T(qj[3])};
+        gleft(tqi, Gi);
+        gleft(tqj, Gj);
+      }
+      const T kb = T(g.kb), ktw = T(g.ktw), m[3] = {T(g.m[0]), T(g.m[1]), T(g.m[2])};
+      T KGi[12], KGj[12];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const T di = d0[0] * Gi[c] + d0[1] * Gi[4 + c] + d0[2] * Gi[8 + c];
+        const T dj = d0[0] * Gj[c] + d0[1] * Gj[4 + c] + d0[2] * Gj[8 + c];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          KGi[r * 4 + c] = kb * Gi[r * 4 + c] + (ktw - kb) * d0[r] * di;
+          KGj[r * 4 + c] = kb * Gj[r * 4 + c] + (ktw - kb) * d0[r] * dj;
+        }
+      }
+      T Mii[16], Mjj[16], Mij[16];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          T aii = T(0), ajj = T(0), aij = T(0);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            aii += Gj[k * 4 + r] * KGj[k * 4 + c];
+            ajj += Gi[k * 4 + r] * KGi[k * 4 + c];
+            aij -= Gj[k * 4 + r] * KGi[k * 4 + c];
+          }
+          Mii[r * 4 + c] = Hww[r * 4 + c] + aii;
+          Mjj[r * 4 + c] = Hww[r * 4 + c] + ajj;
+          Mij[r * 4 + c] = Hww[r * 4 + c] + aij;
+        }
+      // B(m) = [[-m^x, m], [-m^T, 0]]  (rows q_i, columns q_j)
+      Mij[0 * 4 + 1] += m[2];  Mij[0 * 4 + 2] -= m[1];
+      Mij[1 * 4 + 0] -= m[2];  Mij[1 * 4 + 2] += m[0];
+      Mij[2 * 4 + 0] += m[1];  Mij[2 * 4 + 1] -= m[0];
+      Mij[0 * 4 + 3] += m[0];  Mij[1 * 4 + 3] += m[1];  Mij[2 * 4 + 3] += m[2];
+      Mij[3 * 4 + 0] -= m[0];  Mij[3 * 4 + 1] -= m[1];  Mij[3 * 4 + 2] -= m[2];
+      // assemble the scaled 9x9 (u/sqrt2, y_i, y_j), packed upper triangle
+      T Rii[9], Rjj[9], Rij[9];
+      gmgt(Gi, Mii, Gi, Rii);
+      gmgt(Gj, Mjj, Gj, Rjj);
+      gmgt(Gi, Mij, Gj, Rij);
+      const T li = T(lam_i), lj = T(lam_j);
+      T Uri[9], Urj[9];   // H_uw G^T
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T ai = T(0), aj = T(0);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) { ai += Huw[r * 4 + k] * Gi[c * 4 + k]; aj += Huw[r * 4 + k] * Gj[c * 4 + k]; }
+          Uri[r * 3 + c] = ai;
+          Urj[r * 3 + c] = aj;
+        }
+      const T s2 = T(1.4142135623730950488);
+      T *A = reinterpret_cast<T *>(d.h9) + (size_t)b * 45;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (c >= r) {
+            A[up9(r, c)] = T(2) * Huu[r * 3 + c];
+            A[up9(3 + r, 3 + c)] = Rii[r * 3 + c] - (r == c ? li : T(0));
+            A[up9(6 + r, 6 + c)] = Rjj[r * 3 + c] - (r == c ? lj : T(0));
+          }
+          A[up9(r, 3 + c)] = s2 * Uri[r * 3 + c];
+          A[up9(r, 6 + c)] = s2 * Urj[r * 3 + c];
+          A[up9(3 + r, 6 + c)] = Rij[r * 3 + c];
+        }
+    }
+  } else if (real) {
+    // broken bond: its slots contribute nothing
+    double *gi = d.ghalf + (size_t)sl.x * 6, *gj = d.ghalf + (size_t)sl.y * 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) { gi[k] = 0.0; gj[k] = 0.0; }
+  }
+  const KSum tot = block_ksum(esum);
+  if (threadIdx.x == 0) d.part_a[lb] = make_double2(tot.s, tot.c);
+}
+
+// Eigen-clamp of the per-bond 9x9 (Section 5.2, per bond) and scatter into
+// the bond's two off-diagonal slots and two diagonal halves.  Reads the packed
+// 9x9 written by k_bond_eval; holds only the Jacobi state in registers.
+template <typename T, bool PSD>
+__global__ __launch_bounds__(TILE) void k_bond_project(DevPtrs d) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int b = lb * TILE + threadIdx.x;
+  const int scene = d.bsid[lb * TILE];
+  if (!d.ctl[scene].newton_active) return;
+  const int2 sl = d.bslot[b];
+  if (sl.x < 0) return;
+  T *hoff = reinterpret_cast<T *>(d.hoff);
+  T *hhalf = reinterpret_cast<T *>(d.hhalf);
+  T *oi = hoff + (size_t)sl.x * 36, *oj = hoff + (size_t)sl.y * 36;
+  T *hi = hhalf + (size_t)sl.x * 21, *hj = hhalf + (size_t)sl.y * 21;
+  if (!d.alive[b]) {
+#pragma unroll
+    for (int k = 0; k < 36; ++k) { oi[k] = T(0); oj[k] = T(0); }
+#pragma unroll
+    for (int k = 0; k < 21; ++k) { hi[k] = T(0); hj[k] = T(0); }
+    return;
+  }
+  T A[45];
+  const T *src = reinterpret_cast<const T *>(d.h9) + (size_t)b * 45;
+#pragma unroll
+  for (int k = 0; k < 45; ++k) A[k] = src[k];
+  if (PSD) psd_clamp9<T>(A);
+  // unscale: P_uu = A_uu / 2, P_ur = A_ur / sqrt2, P_rr = A_rr
+  const T is2 = T(0.70710678118654752440), hf = T(0.5);
+  const int2 ij = d.bij[b];
+  const bool couple = d.flags[ij.x] == 0 && d.flags[ij.y] == 0;
+  const T cpl = couple ? T(1) : T(0);
+  // block (i, j): rows (p_i, y_i), cols (p_j, y_j) = [[-P_uu, -P_u,rj], [P_ri,u, P_ri,rj]];
+  // block (j, i) is its transpose
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T uu = -hf * A[up9(r, c)] * cpl;
+      const T uj = -is2 * A[up9(r, 6 + c)] * cpl;
+      const T iu = is2 * A[up9(c, 3 + r)] * cpl;
+      const T ij_ = A[up9(3 + r, 6 + c)] * cpl;
+      oi[r * 6 + c] = uu;
+      oi[r * 6 + 3 + c] = uj;
+      oi[(3 + r) * 6 + c] = iu;
+      oi[(3 + r) * 6 + 3 + c] = ij_;
+      oj[c * 6 + r] = uu;
+      oj[(3 + c) * 6 + r] = uj;
+      oj[c * 6 + 3 + r] = iu;
+      oj[(3 + c) * 6 + 3 + r] = ij_;
+    }
+  // diagonal halves: i: [[P_uu, -P_u,ri], [., P_ri,ri]],  j: [[P_uu, P_u,rj], [., P_rj,rj]]
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = r; c < 6; ++c) {
+      T vi, vj;
+      if (r < 3 && c < 3) { vi = hf * A[up9(r, c)]; vj = vi; }
+      else if (r < 3) { vi = -is2 * A[up9(r, c)]; vj = is2 * A[up9(r, c + 3)]; }
+      else { vi = A[up9(r, c)]; vj = A[up9(r + 3, c + 3)]; }
+      hi[up6(r, c)] = vi;
+      hj[up6(r, c)] = vj;
+    }
+}
+
+// Energy of every alive bond at the iterate (trial = false) or the line-search
+// trial state (trial = true), FP64; one compensated partial per tile.
+__global__ __launch_bounds__(TILE) void k_bond_energy(DevPtrs d, int trial) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int b = lb * TILE + threadIdx.x;
+  const int scene = d.bsid[lb * TILE];
+  const SceneCtl &c = d.ctl[scene];
+  if (trial ? !c.ls_active : !c.newton_active) return;
+  const double4 *P = trial ? d.pt : d.px;
+  const double4 *Q = trial ? d.qt : d.qx;
+  KSum esum = {0.0, 0.0};
+  const int2 sl = d.bslot[b];
+  if (sl.x >= 0 && d.alive[b]) {
+    const int2 ij = d.bij[b];
+    BondGeom g;
+    bond_geometry(P[ij.x], Q[ij.x], P[ij.y], Q[ij.y], d.brest_a[b], d.brest_b[b], g);
+    kadd(esum, bond_energy_of(g));
+  }
+  const KSum tot = block_ksum(esum);
+  if (threadIdx.x == 0) d.part_b[lb] = make_double2(tot.s, tot.c);
+}
+
+// Section 3.3 with implicit forces, at the state x_n (after the step):
+//   sigma = |F_n| / S + |M_b| r0 / I,  tau = |F_s| / S + |M_t| r0 / J,
+//   |F_n| = k_n |l - l0|,  |F_s| = k_t L^2 theta / l  (|d theta / d p| = 1/l),
+//   M = K t: |M_t| = GJ/l0 |d0 . t'|,  |M_b| = EI/l0 |t' - (d0 . t') d0|.
+// All bonds are tested at the same state; breaks are permanent.
+__global__ __launch_bounds__(TILE) void k_bond_fracture(DevPtrs d) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int b = lb * TILE + threadIdx.x;
+  int broke = 0;
+  const int2 sl = d.bslot[b];
+  if (sl.x >= 0 && d.alive[b]) {
+    const double2 st = d.bstrength[b];
+    if (st.x > 0.0 || st.y > 0.0) {
+      const int2 ij = d.bij[b];
+      BondGeom g;
+      bond_geometry(d.pn[ij.x], d.qn[ij.x], d.pn[ij.y], d.qn[ij.y], d.brest_a[b], d.brest_b[b], g);
+      const double4 rc = d.brest_c[b];   // (S, r0/I, r0/J, tension_only)
+      double e = g.e;
+      if (rc.w != 0.0 && e < 0.0) e = 0.0;
+      const double Fn = g.kn * fabs(e);
+      const double theta = 2.0 * asin(fmin(1.0, 0.5 * sqrt(g.y)));
+      const double Fs = g.kts * theta / g.l;
+      const double td = dot3(g.tp, g.d0);
+      const double b0 = g.tp[0] - td * g.d0[0], b1 = g.tp[1] - td * g.d0[1], b2 = g.tp[2] - td * g.d0[2];
+      const double Mt = g.ktw * fabs(td);
+      const double Mb = g.kb * sqrt(b0 * b0 + b1 * b1 + b2 * b2);
+      const double sigma = Fn / rc.x + Mb * rc.y;
+      const double tau = Fs / rc.x + Mt * rc.z;
+      if ((st.x > 0.0 && sigma > st.x) || (st.y > 0.0 && tau > st.y)) {
+        d.alive[b] = 0;
+        broke = 1;
+      }
+    }
+  }
+  // deterministic per-tile count
+  __shared__ int cnt[TILE / 64];
+  unsigned long long bal = __ballot(broke);
+  if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int k = 0; k < TILE / 64; ++k) s += cnt[k];
+    d.part_cnt[lb] = s;
+  }
+}
+
+void launch_bond_eval(const DevPtrs &d, bool mixed, bool psd, bool hess, hipStream_t s) {
+  const int nblk = d.nb_pad / TILE;
+  if (nblk == 0) return;
+  if (mixed) {
+    if (hess) k_bond_eval<float, true><<<nblk, TILE, 0, s>>>(d);
+    else k_bond_eval<float, false><<<nblk, TILE, 0, s>>>(d);
+  } else {
+    if (hess) k_bond_eval<double, true><<<nblk, TILE, 0, s>>>(d);
+    else k_bond_eval<double, false><<<nblk, TILE, 0, s>>>(d);
+  }
+  if (!hess) return;
+  if (mixed) {
+    if (psd) k_bond_project<float, true><<<nblk, TILE, 0, s>>>(d);
+    else k_bond_project<float, false><<<nblk, TILE, 0, s>>>(d);
+  } else {
+    if (psd) k_bond_project<double, true><<<nblk, TILE, 0, s>>>(d);
+    else k_bond_project<double, false><<<nblk, TILE, 0, s>>>(d);
+  }
+}
+
+void launch_bond_energy(const DevPtrs &d, bool trial, hipStream_t s) {
+  const int nblk = d.nb_pad / TILE;
+  if (nblk == 0) return;
+  k_bond_energy<<<nblk, TILE, 0, s>>>(d, trial ? 1 : 0);
+}
+
+void launch_bond_fracture(const DevPtrs &d, hipStream_t s) {
+  const int nblk = d.nb_pad / TILE;
+  if (nblk == 0) return;
+  k_bond_fracture<<<nblk, TILE, 0, s>>>(d);
+}
+
+}  // namespace bdem

@@ -1,0 +1,302 @@
+// Particle-parallel kernels of one implicit step (Algorithm 3):
+//   prediction and initial guess, per-particle terms of the incremental
+//   potential (inertia with the constant extended mass matrix M_s of
+//   Section 3.1, gravity, ground repulsion of Section 5.4), fixed-order
+//   assembly of the bond halves into the diagonal block and the reduced
+//   gradient, the block-Jacobi inverse, the exp-map retraction of Section 4.1
+//   with the trial energy, and the velocity update.
+// One thread per particle, TILE particles per workgroup, one scene per tile.
+#include "bdem_internal.hpp"
+#include "bdem_math.hpp"
+
+namespace bdem {
+
+// initial guess x0 = x_n + v_n dt, q normalised; kinematic particles move
+// with their own velocity, fixed particles stay (their q is held).
+__global__ __launch_bounds__(TILE) void k_predict(DevPtrs d, int write_iterate) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  const uint8_t f = d.flags[r];
+  if (f == 255) return;
+  const double dt = d.ctl[d.psid[r]].dt;
+  const double4 p = d.pn[r], q = d.qn[r], v = d.vn[r], w = d.wn[r];
+  double4 ph = p, qh = q;
+  if (f != 1) { ph.x += dt * v.x; ph.y += dt * v.y; ph.z += dt * v.z; }
+  if (f == 0) { qh.x += dt * w.x; qh.y += dt * w.y; qh.z += dt * w.z; qh.w += dt * w.w; }
+  d.ph[r] = ph;
+  d.qh[r] = qh;
+  if (!write_iterate) return;
+  d.px[r] = ph;
+  const double inv = 1.0 / sqrt(qh.x * qh.x + qh.y * qh.y + qh.z * qh.z + qh.w * qh.w);
+  d.qx[r] = (f == 0) ? make_double4(qh.x * inv, qh.y * inv, qh.z * inv, qh.w * inv) : q;
+}
+
+__global__ __launch_bounds__(TILE) void k_copy_state(DevPtrs d) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  d.px[r] = d.pn[r];
+  d.qx[r] = d.qn[r];
+}
+
+// energy and Euclidean derivatives of the particle's own terms
+struct PTerms {
+  double E;
+  double gp[3], gr[3];
+  double kgap;   // k_c if the ground penalty is active
+};
+
+__device__ __forceinline__ void particle_terms(const Params &P, double idt2, double4 pc,
+                                               double4 p, double4 q, double4 ph, double4 qh,
+                                               PTerms &t) {
+  const double m = pc.x, c = pc.y, rad = pc.z;
+  const double ep[3] = {p.x - ph.x, p.y - ph.y, p.z - ph.z};
+  const double eq[4] = {q.x - qh.x, q.y - qh.y, q.z - qh.z, q.w - qh.w};
+  t.E = 0.5 * m * idt2 * (ep[0] * ep[0] + ep[1] * ep[1] + ep[2] * ep[2]) +
+        0.5 * c * idt2 * (eq[0] * eq[0] + eq[1] * eq[1] + eq[2] * eq[2] + eq[3] * eq[3]) -
+        m * (P.gx * p.x + P.gy * p.y + P.gz * p.z);
+  t.gp[0] = m * idt2 * ep[0] - m * P.gx;
+  t.gp[1] = m * idt2 * ep[1] - m * P.gy;
+  t.gp[2] = m * idt2 * ep[2] - m * P.gz;
+  t.kgap = 0.0;
+  if (P.kc != 0.0) {
+    const double gap = P.gnx * p.x + P.gny * p.y + P.gnz * p.z - P.gh - rad;
+    if (gap < 0.0) {
+      t.E += 0.5 * P.kc * gap * gap;
+      t.gp[0] += P.kc * gap * P.gnx;
+      t.gp[1] += P.kc * gap * P.gny;
+      t.gp[2] += P.kc * gap * P.gnz;
+      t.kgap = P.kc;
+    }
+  }
+  // reduced rotational gradient G_l(q) c/dt^2 (q - q_hat) = vec(conj(q) (c/dt^2)(q - q_hat))
+  const double qc[4] = {-q.x, -q.y, -q.z, q.w};
+  const double g4[4] = {c * idt2 * eq[0], c * idt2 * eq[1], c * idt2 * eq[2], c * idt2 * eq[3]};
+  double rr[4];
+  qmul(qc, g4, rr);
+  t.gr[0] = rr[0]; t.gr[1] = rr[1]; t.gr[2] = rr[2];
+}
+
+// symmetric 6x6 (packed upper, double) -> inverse via Cholesky; false if not PD
+__device__ __forceinline__ bool spd_inverse6(const double (&A)[21], double (&Ainv)[21]) {
+  double L[6][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double dj = A[up6(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k];
+    if (!(dj > 0.0)) return false;
+    dj = sqrt(dj);
+    L[j][j] = dj;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double v = A[up6(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / dj;
+    }
+  }
+  // X = L^-1 (lower)
+  double X[6][6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i < c) { X[i][c] = 0.0; continue; }
+      double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k)
+        if (k >= c) v -= L[i][k] * X[k][c];
+      X[i][c] = v / L[i][i];
+    }
+  // A^-1 = X^T X
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = r; c < 6; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v += X[k][r] * X[k][c];
+      Ainv[up6(r, c)] = v;
+    }
+  return true;
+}
+
+template <typename T, bool HESS>
+__global__ __launch_bounds__(TILE) void k_particle_eval(DevPtrs d, Params P, int potential_only) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  const int scene = d.psid[blockIdx.x * TILE];
+  const SceneCtl &ctl = d.ctl[scene];
+  if (!ctl.newton_active) return;
+  const uint8_t f = d.flags[r];
+  KSum e = {0.0, 0.0}, g2 = {0.0, 0.0};
+  double z[6] = {0, 0, 0, 0, 0, 0};
+  double D[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) D[k] = 0.0;
+  if (f != 255) {
+    const int beg = d.row_ptr[r], end = d.row_ptr[r + 1];
+    const T *hh = reinterpret_cast<const T *>(d.hhalf);
+    for (int k = beg; k < end; ++k) {
+      const double *gh = d.ghalf + (size_t)k * 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) z[c] += gh[c];
+      if (HESS) {
+#pragma unroll
+        for (int c = 0; c < 21; ++c) D[c] += double(hh[(size_t)k * 21 + c]);
+      }
+    }
+    const double idt2 = potential_only ? 0.0 : ctl.inv_dt2;
+    const double4 q = d.qx[r], qh = d.qh[r];
+    PTerms t;
+    particle_terms(P, idt2, d.pconst[r], d.px[r], q, d.ph[r], qh, t);
+    kadd(e, t.E);
+    z[0] += t.gp[0]; z[1] += t.gp[1]; z[2] += t.gp[2];
+    z[3] += t.gr[0]; z[4] += t.gr[1]; z[5] += t.gr[2];
+    if (HESS) {
+      const double m = d.pconst[r].x, c = d.pconst[r].y;
+      const double n[3] = {P.gnx, P.gny, P.gnz};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) D[up6(a, b)] += (a == b ? m * idt2 : 0.0) + t.kgap * n[a] * n[b];
+      const double rot = c * idt2 * (q.x * qh.x + q.y * qh.y + q.z * qh.z + q.w * qh.w);
+      const double rotc = rot > 0.0 ? rot : 0.0;   // PSD clamp of the particle's own block
+      D[up6(3, 3)] += rotc; D[up6(4, 4)] += rotc; D[up6(5, 5)] += rotc;
+    }
+    if (f != 0) {   // fixed / kinematic: not an unknown
+#pragma unroll
+      for (int c = 0; c < 6; ++c) z[c] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 21; ++k) D[k] = 0.0;
+      D[up6(0, 0)] = D[up6(1, 1)] = D[up6(2, 2)] = D[up6(3, 3)] = D[up6(4, 4)] = D[up6(5, 5)] = 1.0;
+    }
+  } else {
+    D[up6(0, 0)] = D[up6(1, 1)] = D[up6(2, 2)] = D[up6(3, 3)] = D[up6(4, 4)] = D[up6(5, 5)] = 1.0;
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    d.z[(size_t)r * 6 + c] = z[c];
+    kadd(g2, z[c] * z[c]);
+  }
+  if (HESS) {
+    T *hd = reinterpret_cast<T *>(d.hdiag) + (size_t)r * 21;
+    T *di = reinterpret_cast<T *>(d.dinv) + (size_t)r * 21;
+    double Di[21];
+    if (!spd_inverse6(D, Di)) {
+#pragma unroll
+      for (int k = 0; k < 21; ++k) Di[k] = 0.0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const double v = D[up6(a, a)];
+        Di[up6(a, a)] = v > 0.0 ? 1.0 / v : 1.0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 21; ++k) { hd[k] = T(D[k]); di[k] = T(Di[k]); }
+  }
+  const KSum te = block_ksum(e);
+  const KSum tg = block_ksum(g2);
+  if (threadIdx.x == 0) {
+    d.part_b[blockIdx.x] = make_double2(te.s, te.c);
+    d.part_c[blockIdx.x] = make_double2(tg.s, tg.c);
+  }
+}
+
+// trial state of the line search: p + a dp, q (x) exp(a y) renormalised in
+// FP64 (Section 4.1, manifold-update-1/2; dq = G_l(q)^T y = q (y, 0) so the
+// geodesic step is a right multiplication by (sin|a y| y/|y|, cos|a y|)),
+// plus the particle part of the trial energy and the step size maxima.
+__global__ __launch_bounds__(TILE) void k_ls_trial(DevPtrs d, Params P) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  const int scene = d.psid[blockIdx.x * TILE];
+  const SceneCtl &ctl = d.ctl[scene];
+  if (!ctl.ls_active) return;
+  const uint8_t f = d.flags[r];
+  KSum e = {0.0, 0.0};
+  double mv = 0.0, xm = 0.0;
+  if (f != 255) {
+    const double a = ctl.alpha_ls;
+    const double4 p = d.px[r], q = d.qx[r];
+    const double *x = d.cx + (size_t)r * 6;
+    double4 pt = p, qt = q;
+    if (f == 0) {
+      pt = make_double4(p.x + a * x[0], p.y + a * x[1], p.z + a * x[2], 0.0);
+      const double y[3] = {a * x[3], a * x[4], a * x[5]};
+      const double th = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+      double sc, cc;
+      if (th < 1e-8) { sc = 1.0 - th * th / 6.0; cc = 1.0 - 0.5 * th * th; }
+      else { sc = sin(th) / th; cc = cos(th); }
+      const double e4[4] = {sc * y[0], sc * y[1], sc * y[2], cc};
+      const double q4[4] = {q.x, q.y, q.z, q.w};
+      double o[4];
+      qmul(q4, e4, o);
+      const double inv = 1.0 / sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2] + o[3] * o[3]);
+      qt = make_double4(o[0] * inv, o[1] * inv, o[2] * inv, o[3] * inv);
+    }
+    d.pt[r] = pt;
+    d.qt[r] = qt;
+    PTerms t;
+    particle_terms(P, ctl.inv_dt2, d.pconst[r], pt, qt, d.ph[r], d.qh[r], t);
+    kadd(e, t.E);
+    mv = fmax(fmax(fabs(pt.x - p.x), fabs(pt.y - p.y)), fabs(pt.z - p.z));
+    mv = fmax(mv, fmax(fmax(fabs(qt.x - q.x), fabs(qt.y - q.y)), fmax(fabs(qt.z - q.z), fabs(qt.w - q.w))));
+    xm = fmax(fmax(fabs(pt.x), fabs(pt.y)), fabs(pt.z));
+  }
+  const KSum te = block_ksum(e);
+  mv = block_max(mv);
+  xm = block_max(xm);
+  if (threadIdx.x == 0) {
+    d.part_b[blockIdx.x] = make_double2(te.s, te.c);
+    d.part_max[2 * blockIdx.x] = mv;
+    d.part_max[2 * blockIdx.x + 1] = xm;
+  }
+}
+
+__global__ __launch_bounds__(TILE) void k_ls_accept(DevPtrs d) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  const int scene = d.psid[blockIdx.x * TILE];
+  if (!d.ctl[scene].ls_accept) return;
+  d.px[r] = d.pt[r];
+  d.qx[r] = d.qt[r];
+}
+
+// v_{n+1} = (x_{n+1} - x_n) / dt, then x_n <- x_{n+1} (Algorithm 3).
+// Friction hook of Algorithm 3: off.
+__global__ __launch_bounds__(TILE) void k_finish(DevPtrs d) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  if (d.flags[r] == 255) return;
+  const double idt = 1.0 / d.ctl[d.psid[r]].dt;
+  const double4 p = d.px[r], q = d.qx[r], p0 = d.pn[r], q0 = d.qn[r];
+  d.vn[r] = make_double4((p.x - p0.x) * idt, (p.y - p0.y) * idt, (p.z - p0.z) * idt, 0.0);
+  d.wn[r] = make_double4((q.x - q0.x) * idt, (q.y - q0.y) * idt, (q.z - q0.z) * idt,
+                         (q.w - q0.w) * idt);
+  d.pn[r] = p;
+  d.qn[r] = q;
+}
+
+void launch_predict(const DevPtrs &d, bool write_iterate, hipStream_t s) {
+  k_predict<<<d.n_pad / TILE, TILE, 0, s>>>(d, write_iterate ? 1 : 0);
+}
+void launch_copy_state_to_iterate(const DevPtrs &d, hipStream_t s) {
+  k_copy_state<<<d.n_pad / TILE, TILE, 0, s>>>(d);
+}
+void launch_particle_eval(const DevPtrs &d, const Params &P, bool mixed, bool hess,
+                          bool potential_only, hipStream_t s) {
+  const int nb = d.n_pad / TILE, po = potential_only ? 1 : 0;
+  if (mixed) {
+    if (hess) k_particle_eval<float, true><<<nb, TILE, 0, s>>>(d, P, po);
+    else k_particle_eval<float, false><<<nb, TILE, 0, s>>>(d, P, po);
+  } else {
+    if (hess) k_particle_eval<double, true><<<nb, TILE, 0, s>>>(d, P, po);
+    else k_particle_eval<double, false><<<nb, TILE, 0, s>>>(d, P, po);
+  }
+}
+void launch_ls_trial(const DevPtrs &d, const Params &P, hipStream_t s) {
+  k_ls_trial<<<d.n_pad / TILE, TILE, 0, s>>>(d, P);
+}
+void launch_ls_accept(const DevPtrs &d, hipStream_t s) {
+  k_ls_accept<<<d.n_pad / TILE, TILE, 0, s>>>(d);
+}
+void launch_finish_step(const DevPtrs &d, hipStream_t s) {
+  k_finish<<<d.n_pad / TILE, TILE, 0, s>>>(d);
+}
+
+}  // namespace bdem
