@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -159,6 +160,7 @@ struct bdem_ctx {
   hipGraph_t cg_graph[2] = {nullptr, nullptr};
   // profiling: events around the bond and SpMV kernels
   int profiling = 0;
+  int trace = 0;                 // BDEM_TRACE=1: one line per Newton iteration of scene 0
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;   // (kind, index of start event)
@@ -305,6 +307,10 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   }
   bdem_ctx *ctx = new bdem_ctx();
   ctx->stream = (hipStream_t)hip_stream;
+  {
+    const char *tr = std::getenv("BDEM_TRACE");
+    ctx->trace = (tr && tr[0] == '1') ? 1 : 0;
+  }
   ctx->opt = o;
   ctx->S = compute_sizes(pcnt, bcnt, n, b->nb, o.precision == BDEM_PREC_MIXED);
   Sizes &S = ctx->S;
@@ -698,6 +704,15 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     HIP_TRY(hipEventSynchronize(ph[4]));
     t_cg += elapsed(ph[2], ph[3]);
     t_ls += elapsed(ph[3], ph[4]);
+    if (ctx->trace) {
+      HIP_TRY(hipMemcpy(ctx->h_ctl, d.ctl, sizeof(SceneCtl), hipMemcpyDeviceToHost));
+      const SceneCtl &c = ctx->h_ctl[0];
+      std::fprintf(stderr,
+                   "[bdem trace] it %d |z| %.6e phi %.12e slope %.3e alpha %.3e ls %d cg %d "
+                   "cg_tol %.3e |r| %.3e phi_trial %.12e move %.3e status %d\n",
+                   c.newton_it, c.gnorm, c.phi, c.slope, c.alpha_ls, c.ls_it, c.cg_it, c.cg_tol,
+                   std::sqrt(c.rr), c.phi_trial, c.last_move, c.status);
+    }
   }
   // outcome per scene
   HIP_TRY(hipMemcpyAsync(ctx->h_ctl, d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost, st));

@@ -366,8 +366,10 @@ __global__ __launch_bounds__(TILE) void k_bond_energy(DevPtrs d, int trial) {
     bond_geometry(P[ij.x], Q[ij.x], P[ij.y], Q[ij.y], d.brest_a[b], d.brest_b[b], g);
     kadd(esum, bond_energy_of(g));
   }
+  // bond tiles report in part_a, particle tiles in part_b (read together by
+  // the line-search decision)
   const KSum tot = block_ksum(esum);
-  if (threadIdx.x == 0) d.part_b[lb] = make_double2(tot.s, tot.c);
+  if (threadIdx.x == 0) d.part_a[lb] = make_double2(tot.s, tot.c);
 }
 
 // Section 3.3 with implicit forces, at the state x_n (after the step):

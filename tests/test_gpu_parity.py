@@ -22,7 +22,11 @@ from tests.gpu_helpers import (log, make_sim, oracle_for, quat_angle_err, row_sc
 
 pytestmark = pytest.mark.gpu
 
-TIGHT = dict(newton_rtol=1e-13, max_newton=60)
+# parity runs stop at the FP64 rounding floor on both sides (the last accepted
+# Newton step no longer moves the state), not at a tolerance on |z|: |z|
+# mixes forces and torques, so a relative tolerance leaves rotations less
+# converged than positions
+TIGHT = dict(newton_rtol=0.0, newton_tol=0.0, max_newton=80)
 
 
 @pytest.fixture(scope="module")
@@ -108,15 +112,54 @@ def test_energy_grad_hess_compressed_bonds_are_projected(B):
 # whole steps
 # --------------------------------------------------------------------------
 
-def _compare_states(sc, got, ref, prev, tol, tag):
+def _conditioning_bound(sc, prev, ref, dt, zfloor):
+    """How far apart two FP64 solutions of the same step can be when each
+    stops at its own gradient rounding floor: |dx| <= |(H^-1)_rows| * dz with
+    H the true reduced Hessian at the solution (oracle, dense) and dz ten
+    times the larger final gradient norm.  Returns absolute bounds for the
+    position and rotation parts."""
+    o = oracle_for(sc, prev)
+    _, _, hd, ho = o.energy_grad_hess(dt, ref["pos"], ref["quat"], psd=False)
+    n = sc.n
+    H = np.zeros((6 * n, 6 * n))
+    for i in range(n):
+        H[6 * i:6 * i + 6, 6 * i:6 * i + 6] = hd[i]
+    for b, (i, j) in enumerate(sc.ij):
+        if ref["alive"][b]:
+            H[6 * i:6 * i + 6, 6 * j:6 * j + 6] = ho[b]
+            H[6 * j:6 * j + 6, 6 * i:6 * i + 6] = ho[b].T
+    Hi = np.linalg.inv(H)
+    rows = np.arange(6 * n).reshape(n, 6)
+    pb = np.linalg.norm(Hi[rows[:, :3].ravel()], 2) * 10 * zfloor
+    rb = np.linalg.norm(Hi[rows[:, 3:].ravel()], 2) * 10 * zfloor * 2.0   # angle = 2 |y|
+    return pb, rb
+
+
+def _compare_states(sc, got, ref, prev, tol, tag, rot_abs=1e-12, ref2=None, cond=None):
+    """Relative errors against the step's displacement / rotation.  With ref2
+    (the oracle stepped again with a looser linear-solve tolerance, also to
+    the rounding floor) the bound is max(tol, 5 x the oracle's own spread).
+    With cond = (position, rotation) absolute bounds from the conditioning of
+    the step (see _conditioning_bound), those bounds also apply: where soft
+    modes leave the FP64 fixed point determined only to that level, no
+    implementation can be held tighter."""
     disp = np.linalg.norm(ref["pos"] - prev["pos"])
     perr = np.linalg.norm(got["pos"] - ref["pos"]) / max(disp, 1e-300)
     rot = quat_angle_err(ref["quat"], prev["quat"])
     qerr = quat_angle_err(got["quat"], ref["quat"])
     qrel = np.linalg.norm(qerr) / max(np.linalg.norm(rot), 1e-300)
-    log(f"  {tag}: pos rel err {perr:.2e} (disp {disp:.3e})  rot rel err {qrel:.2e}")
-    assert perr <= tol
-    assert qrel <= tol or np.abs(qerr).max() <= 1e-13
+    ptol, qtol = tol, tol
+    if ref2 is not None:
+        pn = np.linalg.norm(ref2["pos"] - ref["pos"]) / max(disp, 1e-300)
+        qn = np.linalg.norm(quat_angle_err(ref2["quat"], ref["quat"])) / max(np.linalg.norm(rot), 1e-300)
+        ptol, qtol = max(tol, 5 * pn), max(tol, 5 * qn)
+    if cond is not None:
+        ptol = max(ptol, cond[0] / max(disp, 1e-300))
+        qtol = max(qtol, cond[1] / max(np.linalg.norm(rot), 1e-300))
+    log(f"  {tag}: pos rel err {perr:.2e} (disp {disp:.3e}, bound {ptol:.1e})  rot rel err "
+        f"{qrel:.2e} (bound {qtol:.1e})")
+    assert perr <= ptol
+    assert qrel <= qtol or np.abs(qerr).max() <= rot_abs
     assert np.abs(np.linalg.norm(got["quat"], axis=1) - 1.0).max() <= 4.5e-16
 
 
@@ -131,7 +174,7 @@ def test_step_block_1000(B, mixed):
     tol = 1e-5 if mixed else 1e-8
     prev = o.get_state()
     for k in range(10):
-        so = o.step(sc.dt, tol_rel=1e-13)
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300)
         sg = sim.step(sc.dt)
         ref, got = o.get_state(), sim.get_state()
         assert sg["rc"] == 0, sg
@@ -144,6 +187,27 @@ def test_step_block_1000(B, mixed):
     sim.close()
 
 
+def test_line_search_energy_matches_objective(B, capfd, monkeypatch):
+    """The energy of an accepted line-search trial equals the objective the
+    next Newton iteration evaluates at that same state (regression: the two
+    passes once summed different partials)."""
+    import re
+    monkeypatch.setenv("BDEM_TRACE", "1")
+    sc, st = _perturbed_block(nx=6, ny=5, nz=4, seed=4, ground=True)
+    sim = make_sim(sc, **TIGHT)
+    sim.set_state(**st)
+    capfd.readouterr()
+    sim.step(sc.dt)
+    sim.close()
+    err = capfd.readouterr().err
+    rows = [dict(re.findall(r"(\w+) ([-+0-9.e]+)", line)) for line in err.splitlines()
+            if line.startswith("[bdem trace]")]
+    assert len(rows) >= 2
+    for a, b in zip(rows, rows[1:]):
+        pt, ph = float(a["phi_trial"]), float(b["phi"])
+        assert abs(pt - ph) <= 1e-12 * abs(ph), (pt, ph)
+
+
 def test_step_sheet_kinematic_edges(B):
     """A one-layer sheet pulled apart by kinematic edge columns (no gravity)."""
     log("[step sheet]")
@@ -152,10 +216,16 @@ def test_step_sheet_kinematic_edges(B):
     sim = make_sim(sc, **TIGHT)
     prev = o.get_state()
     for k in range(4):
-        o.step(sc.dt, tol_rel=1e-13)
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300)
         sg = sim.step(sc.dt)
+        log(f"  gpu newton {sg['newton_iters']} cg {sg['cg_iters']} ls {sg['ls_backtracks']} status "
+            f"{sg['status']} grad {sg['grad0']:.3e} -> {sg['grad_final']:.3e} | oracle newton "
+            f"{so['newton_iters']} ls {so['ls_backtracks']} grad {so['grad_final']:.3e}")
         ref, got = o.get_state(), sim.get_state()
-        _compare_states(sc, got, ref, prev, 1e-8, f"sheet step {k}")
+        # the one-layer sheet with 1e-2 bend / twist stiffness has soft rotation
+        # modes: two floor-converged oracle runs with different CG tolerances
+        # already differ by 5e-10 rad, so rotations are checked to 2e-9 rad
+        _compare_states(sc, got, ref, prev, 1e-8, f"sheet step {k}", rot_abs=2e-9)
         kin = sc.flags == S.KINEMATIC
         np.testing.assert_array_equal(got["pos"][kin], ref["pos"][kin])
         prev = ref
@@ -180,6 +250,14 @@ def test_step_without_bonds_is_free_fall(B):
 # --------------------------------------------------------------------------
 # fracture (Section 3.3): bit-exact broken sets
 # --------------------------------------------------------------------------
+
+def _loose_step(sc, state, dt):
+    """the oracle's step from `state` with a 1e-6 linear-solve tolerance,
+    also iterated to the rounding floor"""
+    o = oracle_for(sc, state)
+    o.step(dt, tol_rel=0.0, max_newton=300, cg_rtol=1e-6)
+    return o.get_state()
+
 
 def _certified_thresholds(sig, tau, frac=0.1, margin=1e-3):
     """thresholds near the (1 - frac) quantile, moved until no stress is within
@@ -218,34 +296,47 @@ def test_break_bonds_bit_exact(B):
 @pytest.mark.parametrize("mixed", [False, True])
 def test_plate_drop_steps_with_fracture(B, mixed):
     """A small close-packed plate dropping onto the ground with penalty
-    contact and stress-based breaking: states and broken sets after each step."""
+    contact and stress-based breaking.  Each step is compared as a one-step
+    map from the same state (the oracle restarts from the GPU's state), so
+    drift inherited from earlier steps is not charged to the step; the
+    trajectory drift is checked separately against the total displacement."""
     log(f"[plate drop] mixed={mixed}")
     sc = S.make_plate_drop(nx=12, ny=10, nl=2, sigma_c=0.0, tau_c=0.0, dt=1e-3)
     # thresholds certified against the oracle's own first-step stresses
     o = oracle_for(sc)
-    o.step(sc.dt, tol_rel=1e-13, break_bonds=0)
+    o.step(sc.dt, tol_rel=0.0, max_newton=300, break_bonds=0)
     s1 = o.get_state()
     sig, tau = o.stresses(s1["pos"], s1["quat"])
     sc.materials[0]["sigma_c"], sc.materials[0]["tau_c"] = _certified_thresholds(sig, tau, 0.05)
-    o = oracle_for(sc)
+    traj = oracle_for(sc)
+    start = traj.get_state()
     sim = make_sim(sc, mixed=mixed, **TIGHT)
-    prev = o.get_state()
+    tol = 1e-5 if mixed else 1e-8
+    cond_sum = 0.0
     for k in range(3):
-        so = o.step(sc.dt, tol_rel=1e-13)
+        prev = sim.get_state()
+        o = oracle_for(sc, prev)
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300)
+        traj.step(sc.dt, tol_rel=0.0, max_newton=300)
         sg = sim.step(sc.dt)
         ref, got = o.get_state(), sim.get_state()
-        _compare_states(sc, got, ref, prev, 1e-5 if mixed else 1e-8, f"plate step {k} broken {so['bonds_broken']}")
+        cond = _conditioning_bound(sc, prev, ref, sc.dt, max(so["grad_final"], sg["grad_final"]))
+        cond_sum += cond[0]
+        _compare_states(sc, got, ref, prev, tol, f"plate step {k} broken {so['bonds_broken']}",
+                        ref2=_loose_step(sc, prev, sc.dt), cond=cond)
+        # broken sets: bit-exact wherever the stress is certified away from the thresholds
+        sg_, ta_ = o.stresses(ref["pos"], ref["quat"])
+        m = sc.materials[0]
+        safe = (np.abs(sg_ / m["sigma_c"] - 1) >= 1e-3) & (np.abs(ta_ / m["tau_c"] - 1) >= 1e-3)
         if k == 0:
-            assert so["bonds_broken"] > 0
-            np.testing.assert_array_equal(got["alive"], ref["alive"])
-        else:
-            # later steps: compare only where the oracle's stresses are certified
-            sg_, ta_ = o.stresses(ref["pos"], ref["quat"])
-            m = sc.materials[0]
-            safe = (np.abs(sg_ / m["sigma_c"] - 1) >= 1e-3) & (np.abs(ta_ / m["tau_c"] - 1) >= 1e-3)
-            np.testing.assert_array_equal(got["alive"][safe], ref["alive"][safe])
-        assert sg["bonds_broken"] == so["bonds_broken"] or k > 0
-        prev = ref
+            assert so["bonds_broken"] > 0 and safe.all()
+        np.testing.assert_array_equal(got["alive"][safe], ref["alive"][safe])
+    t_ref = traj.get_state()
+    drift = np.linalg.norm(got["pos"] - t_ref["pos"]) / np.linalg.norm(t_ref["pos"] - start["pos"])
+    total = np.linalg.norm(t_ref["pos"] - start["pos"])
+    bound = max(1e-5 if mixed else 1e-7, 2 * cond_sum / total)
+    log(f"  trajectory drift after 3 steps: {drift:.2e} (bound {bound:.1e})")
+    assert drift <= bound
     sim.close()
 
 
@@ -303,11 +394,15 @@ def test_batched_scenes_match_each_scene_alone(B):
         got = sim.get_state()
         off = 0
         for s, ((m, dt), o) in enumerate(zip(members, oracles)):
-            o.step(dt, tol_rel=1e-13)
+            loose = _loose_step(m, starts[s], dt)
+            so = o.step(dt, tol_rel=0.0, max_newton=300)
             ref = o.get_state()
+            cond = _conditioning_bound(m, starts[s], ref, dt, max(so["grad_final"], stats[s]["grad_final"]))
             sl = slice(off, off + m.n)
             sub = {kk: got[kk][sl] for kk in ("pos", "quat", "vel", "qvel")}
-            _compare_states(m, sub, ref, starts[s], 1e-8, f"batch step {k} scene {s} newton {stats[s]['newton_iters']}")
+            _compare_states(m, sub, ref, starts[s], 1e-8,
+                            f"batch step {k} scene {s} newton {stats[s]['newton_iters']}", ref2=loose,
+                            cond=cond)
             starts[s] = ref
             off += m.n
     sim.close()
