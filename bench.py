@@ -45,11 +45,16 @@ def bond_algorithmic_bytes(n, nb_alive, elt):
 
 
 def run_path(scene, mixed, steps, warmup, profile):
+    """Warm up, then time `steps` implicit steps with the library defaults.
+    With profile, HIP events on the library's stream bracket every bond
+    evaluation and every SpMV launch of the timed steps; PCG issues one
+    iteration ahead of its convergence poll and the timings of the one
+    iteration issued after convergence (whose kernels return at once) are
+    dropped, so the SpMV average covers working launches only."""
     import torch
     from paper_2308_10459_amd import bdem as B
     prec = B.BDEM_PREC_MIXED if mixed else B.BDEM_PREC_FP64
-    sim = B.Simulator(scene, precision=prec, use_graph=0 if profile else 1)
-    stream = sim.stream
+    sim = B.Simulator(scene, precision=prec, use_graph=0, cg_chunk=1)
     for k in range(warmup):
         st = sim.step(scene.dt)
         log(f"  warmup {k}: newton {st['newton_iters']} cg {st['cg_iters']} broken {st['bonds_broken']}")
@@ -120,11 +125,14 @@ def cpu_baseline(target_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="ceramic_plate")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--mixed-only", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -137,27 +145,44 @@ def main():
     log("mixed path:")
     mixed = run_path(scene, True, args.steps, args.warmup, profile=True)
     fsteps = args.steps if args.fp64_steps is None else args.fp64_steps
-    log("fp64 path:")
-    fp64 = run_path(scene, False, fsteps, args.warmup, profile=True)
+    if args.mixed_only:
+        fsteps = 0
+    fp64 = None
+    if fsteps:
+        log("fp64 path:")
+        fp64 = run_path(scene, False, fsteps, args.warmup, profile=True)
+    if args.copy_probe:
+        import torch
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 1 GiB device-to-device copies")
 
-    def rates(r, elt):
-        nwt = r["newton"] / r["wall_s"]
+    def rates(r, elt, steps):
+        if steps == 0:
+            return None
+        nwt = r["newton"] / r["wall_s"] if r["wall_s"] > 0 and r["newton"] else 0.0
         be = r["alive_bonds"] * r["bond_launch"] / (r["bond_ms"] * 1e-3) if r["bond_ms"] > 0 else 0.0
         spmv_avg_ms = r["spmv_ms"] / max(r["spmv_launch"], 1)
         bytes_spmv = spmv_algorithmic_bytes(scene.n, r["alive_bonds"], elt)
         bond_avg_ms = r["bond_ms"] / max(r["bond_launch"], 1)
         bytes_bond = bond_algorithmic_bytes(scene.n, r["alive_bonds"], elt)
         return dict(newton_iters_per_s=nwt, bond_hessian_evals_per_s=be,
-                    ms_per_step=1e3 * r["wall_s"] / max(1, r["steps"]) if "steps" in r else None,
+                    bond_hessian_evals_per_wall_s=r["alive_bonds"] * r["newton"] / r["wall_s"],
+                    ms_per_step=1e3 * r["wall_s"] / steps,
                     cg_iters_per_newton=r["cg"] / max(r["newton"], 1),
                     ls_backtracks_per_newton=r["ls"] / max(r["newton"], 1),
-                    spmv_avg_ms=spmv_avg_ms, spmv_gbs=bytes_spmv / (spmv_avg_ms * 1e-3) / 1e9,
-                    spmv_bytes=bytes_spmv, bond_avg_ms=bond_avg_ms,
+                    spmv_launches=r["spmv_launch"], spmv_avg_ms=spmv_avg_ms,
+                    spmv_gbs=bytes_spmv / (spmv_avg_ms * 1e-3) / 1e9 if spmv_avg_ms > 0 else 0.0,
+                    spmv_bytes=bytes_spmv, bond_launches=r["bond_launch"], bond_avg_ms=bond_avg_ms,
                     bond_gbs=bytes_bond / (bond_avg_ms * 1e-3) / 1e9 if bond_avg_ms > 0 else 0.0,
-                    newton_iters=r["newton"], cg_iters=r["cg"], bonds_broken=r["broken"])
+                    bond_bytes=bytes_bond,
+                    newton_iters=r["newton"], cg_iters=r["cg"], bonds_broken=r["broken"],
+                    alive_bonds=r["alive_bonds"])
 
-    mixed["steps"], fp64["steps"] = args.steps, fsteps
-    rm, rf = rates(mixed, 4), rates(fp64, 8)
+    rm, rf = rates(mixed, 4, args.steps), rates(fp64, 8, fsteps)
     out = {
         "metric": METRIC,
         "value": rm["newton_iters_per_s"],
@@ -177,7 +202,8 @@ def main():
         "bond_hessian_evals_per_s": rm["bond_hessian_evals_per_s"],
         "mixed": rm,
         "fp64": rf,
-        "mixed_over_fp64_newton_iters_per_s": rm["newton_iters_per_s"] / max(rf["newton_iters_per_s"], 1e-30),
+        "mixed_over_fp64_newton_iters_per_s": (rm["newton_iters_per_s"] / rf["newton_iters_per_s"]
+                                               if rf and rf["newton_iters_per_s"] > 0 else None),
         "roofline": {"bound": "hbm", "kernel": "k_spmv<float>", "achieved": rm["spmv_gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rm["spmv_gbs"] / HBM_PEAK_GBS,
                      "traffic": None,

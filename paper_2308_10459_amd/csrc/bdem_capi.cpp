@@ -59,7 +59,7 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.flags), np);
   L.add(reinterpret_cast<void **>(&d.psid), np * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.row_ptr), (np + 1) * sizeof(int));
-  L.add(reinterpret_cast<void **>(&d.col), ns * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.slot), ns * sizeof(int2));
   L.add(reinterpret_cast<void **>(&d.bij), std::max<size_t>(nbp, 1) * sizeof(int2));
   for (double4 **p : {&d.brest_a, &d.brest_b, &d.brest_c})
     L.add(reinterpret_cast<void **>(p), std::max<size_t>(nbp, 1) * sizeof(double4));
@@ -73,7 +73,7 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(&d.h9, std::max<size_t>(nbp, 1) * 45 * T);
   L.add(reinterpret_cast<void **>(&d.ghalf), ns * 6 * sizeof(double));
   L.add(&d.dinv, np * 21 * T);
-  for (double **p : {&d.z, &d.cx, &d.cr, &d.cs, &d.cp, &d.cAp})
+  for (double **p : {&d.z, &d.cx, &d.cr, &d.cs, &d.cp, &d.cAp, &d.cq})
     L.add(reinterpret_cast<void **>(p), np * 6 * sizeof(double));
   for (double2 **p : {&d.part_a, &d.part_b, &d.part_c})
     L.add(reinterpret_cast<void **>(p), npart * sizeof(double2));
@@ -322,12 +322,38 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     ctx->scene_pbeg[s + 1] = ctx->scene_pbeg[s] + (pcnt[s] + TILE - 1) / TILE * TILE;
     ctx->scene_bbeg[s + 1] = ctx->scene_bbeg[s] + (int)((bcnt[s] + TILE - 1) / TILE * TILE);
   }
+  // internal particle order: within each scene, along a Morton (Z-order)
+  // curve of the initial positions, so bonded particles sit in nearby rows
+  // (locality of the bond gathers, the assembly and the symmetric SpMV)
   ctx->p_int.resize(n);
   {
-    std::vector<int> fill(NS, 0);
-    for (int i = 0; i < n; ++i) {
-      const int s = p->scene ? p->scene[i] : 0;
-      ctx->p_int[i] = ctx->scene_pbeg[s] + fill[s]++;
+    std::vector<uint64_t> code(n);
+    int i0 = 0;
+    while (i0 < n) {
+      const int s = p->scene ? p->scene[i0] : 0;
+      int i1 = i0;
+      while (i1 < n && (p->scene ? p->scene[i1] : 0) == s) ++i1;
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int i = i0; i < i1; ++i)
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], p->pos[3 * i + k]);
+          hi[k] = std::max(hi[k], p->pos[3 * i + k]);
+        }
+      const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+      for (int i = i0; i < i1; ++i) {
+        uint64_t c = 0;
+        uint32_t q[3];
+        for (int k = 0; k < 3; ++k)
+          q[k] = (uint32_t)std::min(2097151.0, std::floor((p->pos[3 * i + k] - lo[k]) / ext * 2097151.0));
+        for (int bit = 20; bit >= 0; --bit)
+          for (int k = 0; k < 3; ++k) c = (c << 1) | ((q[k] >> bit) & 1u);
+        code[i] = c;
+      }
+      std::vector<int> idx(i1 - i0);
+      std::iota(idx.begin(), idx.end(), i0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return code[a] < code[c]; });
+      for (int k = 0; k < (int)idx.size(); ++k) ctx->p_int[idx[k]] = ctx->scene_pbeg[s] + k;
+      i0 = i1;
     }
   }
   const int NP = S.n_pad, NB = S.nb_pad;
@@ -414,14 +440,14 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     adj[h_bij[bi].x].push_back({h_bij[bi].y, 2 * bi});
     adj[h_bij[bi].y].push_back({h_bij[bi].x, 2 * bi + 1});
   }
-  std::vector<int> h_col(std::max(S.n_slots, 1), 0);
+  std::vector<int2> h_slot(std::max(S.n_slots, 1), make_int2(0, 0));
   ctx->bslot_h.assign(std::max(NB, 1), make_int2(-1, -1));
   for (int r = 0; r < NP; ++r) {
     std::sort(adj[r].begin(), adj[r].end());
     for (size_t k = 0; k < adj[r].size(); ++k) {
       const int slot = rp[r] + (int)k;
-      h_col[slot] = adj[r][k].first;
       const int bi = adj[r][k].second >> 1, end = adj[r][k].second & 1;
+      h_slot[slot] = make_int2(adj[r][k].first, 2 * bi + end);
       if (end == 0) ctx->bslot_h[bi].x = slot;
       else ctx->bslot_h[bi].y = slot;
     }
@@ -493,7 +519,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(up(d.flags, h_flags.data(), NP));
   chk(up(d.psid, h_psid.data(), NP * sizeof(int)));
   chk(up(d.row_ptr, rp.data(), (NP + 1) * sizeof(int)));
-  chk(up(d.col, h_col.data(), h_col.size() * sizeof(int)));
+  chk(up(d.slot, h_slot.data(), h_slot.size() * sizeof(int2)));
   chk(up(d.bij, h_bij.data(), h_bij.size() * sizeof(int2)));
   chk(up(d.brest_a, h_ra.data(), h_ra.size() * sizeof(double4)));
   chk(up(d.brest_b, h_rb.data(), h_rb.size() * sizeof(double4)));
@@ -512,7 +538,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(hipMemcpyAsync(d.qh, d.qn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
   chk(hipMemcpyAsync(d.pt, d.pn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
   chk(hipMemcpyAsync(d.qt, d.qn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
-  for (double *v : {d.z, d.cx, d.cr, d.cs, d.cp, d.cAp}) chk(hipMemsetAsync(v, 0, (size_t)NP * 6 * sizeof(double), st));
+  for (double *v : {d.z, d.cx, d.cr, d.cs, d.cp, d.cAp, d.cq}) chk(hipMemsetAsync(v, 0, (size_t)NP * 6 * sizeof(double), st));
   const size_t T = S.mixed ? 4 : 8;
   chk(hipMemsetAsync(d.hoff, 0, (size_t)std::max(S.n_slots, 1) * 36 * T, st));
   chk(hipMemsetAsync(d.hhalf, 0, (size_t)std::max(S.n_slots, 1) * 21 * T, st));
@@ -571,15 +597,21 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
   ctx->ev_used = 0;
 }
 
-static int build_cg_graphs(bdem_ctx *ctx, int chunk) {
+// one PCG iteration: update, SpMV with the three dots, per-scene scalars
+static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   const bool mixed = ctx->S.mixed;
+  launch_cg_update(ctx->d, mixed, ctx->stream);
+  if (profile_spmv) prof_mark(ctx, 1, true);
+  launch_spmv(ctx->d, mixed, ctx->stream);
+  if (profile_spmv) prof_mark(ctx, 1, false);
+  launch_cg_scalars(ctx->d, ctx->P, ctx->stream);
+}
+
+static int build_cg_graphs(bdem_ctx *ctx, int chunk) {
   for (int slot = 0; slot < 2; ++slot) {
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < chunk; ++k) {
-      launch_spmv(ctx->d, mixed, ctx->stream);
-      launch_cg_rest(ctx->d, ctx->P, mixed, ctx->stream);
-    }
-    launch_count_active(ctx->d, ctx->S.n_scenes, ctx->stream);
+    for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, false);
+    if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, ctx->stream);
     (void)hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int), hipMemcpyDeviceToHost,
                          ctx->stream);
     HIP_TRY(hipStreamEndCapture(ctx->stream, &ctx->cg_graph[slot]));
@@ -596,8 +628,11 @@ static int run_pcg(bdem_ctx *ctx) {
   const bool mixed = ctx->S.mixed;
   hipStream_t st = ctx->stream;
   launch_cg_init(ctx->d, mixed, st);
-  launch_cg_start(ctx->d, ctx->S.n_scenes, st);
-  launch_count_active(ctx->d, ctx->S.n_scenes, st);
+  if (ctx->profiling) prof_mark(ctx, 1, true);
+  launch_spmv(ctx->d, mixed, st);
+  if (ctx->profiling) prof_mark(ctx, 1, false);
+  launch_cg_scalars(ctx->d, ctx->P, st);
+  if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, st);
   int rc = read_counters(ctx, 0);
   if (rc) return rc;
   if (ctx->h_counters[1] == 0) return BDEM_OK;
@@ -614,20 +649,23 @@ static int run_pcg(bdem_ctx *ctx) {
     if (graph) {
       HIP_TRY(hipGraphLaunch(ctx->cg_exec[slot], st));
     } else {
-      for (int k = 0; k < chunk; ++k) {
-        prof_mark(ctx, 1, true);
-        launch_spmv(ctx->d, mixed, st);
-        prof_mark(ctx, 1, false);
-        launch_cg_rest(ctx->d, ctx->P, mixed, st);
-      }
-      launch_count_active(ctx->d, ctx->S.n_scenes, st);
+      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling != 0);
+      if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, st);
       HIP_TRY(hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int),
                              hipMemcpyDeviceToHost, st));
     }
     HIP_TRY(hipEventRecord(ctx->ev_slot[slot], st));
     if (pending >= 0) {
       HIP_TRY(hipEventSynchronize(ctx->ev_slot[pending]));
-      if (ctx->h_counters[4 * pending + 1] == 0) break;
+      if (ctx->h_counters[4 * pending + 1] == 0) {
+        // the chunk just issued ran after convergence (its kernels returned
+        // at once): its SpMV timings are not SpMV work
+        if (ctx->profiling && !graph) {
+          for (int k = 0; k < chunk && !ctx->ev_marks.empty() && ctx->ev_marks.back().first == 1; ++k)
+            ctx->ev_marks.pop_back();
+        }
+        break;
+      }
     }
     pending = slot;
   }

@@ -23,7 +23,10 @@
 namespace bdem {
 
 constexpr int TILE = 256;       // particles / bonds per scene-aligned tile
-constexpr int SPMV_ROWS = 64;   // block rows per SpMV workgroup (384 lanes)
+constexpr int SPMV_ROWS = 32;     // block rows per SpMV workgroup
+constexpr int SPMV_THREADS = 256; // SpMV workgroup size (>= 6 * SPMV_ROWS)
+constexpr int SPMV_CAP = 512;     // slots staged in LDS per pass of an SpMV workgroup
+constexpr int UPD_ROWS = 64;      // block rows per CG-update workgroup (6 lanes per row)
 
 // per-scene control block, device resident; every decision of the Newton /
 // PCG / line-search loops is taken on the device from these values
@@ -59,7 +62,7 @@ struct DevPtrs {
   uint8_t *flags;                    // FREE / FIXED / KINEMATIC ; 255 = padding
   int *psid;                         // scene id per particle
   int *row_ptr;                      // n_pad + 1, off-diagonal slots per row
-  int *col;                          // n_slots
+  int2 *slot;                        // n_slots: (neighbour row, bond)
   // bonds
   int2 *bij;
   double4 *brest_a, *brest_b, *brest_c;
@@ -69,14 +72,14 @@ struct DevPtrs {
   int *bsid;
   // Hessian / gradient (T = float or double, typed at the launch)
   void *hdiag;   // n_pad * 21
-  void *hoff;    // n_slots * 36
+  void *hoff;    // n_slots * 36: the block of every slot (both triangles)
   void *hhalf;   // n_slots * 21
   void *h9;      // nb_pad * 45: per-bond packed reduced 9x9 before projection
   double *ghalf; // n_slots * 6
   void *dinv;    // n_pad * 21
   double *z;     // 6 n_pad
   // CG
-  double *cx, *cr, *cs, *cp, *cAp;
+  double *cx, *cr, *cs, *cp, *cAp, *cq;
   // reductions
   double2 *part_a, *part_b, *part_c;  // per-block compensated partials
   double *part_max;                   // per-block maxima (2 per block)
@@ -107,9 +110,9 @@ void launch_count_active(const DevPtrs &d, int n_scenes, hipStream_t s);
 void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
 // PCG
 void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
-void launch_cg_start(const DevPtrs &d, int n_scenes, hipStream_t s);
 void launch_spmv(const DevPtrs &d, bool mixed, hipStream_t s);
-void launch_cg_rest(const DevPtrs &d, const Params &P, bool mixed, hipStream_t s);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s);
+void launch_cg_update(const DevPtrs &d, bool mixed, hipStream_t s);
 void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s);
 
 }  // namespace bdem

@@ -112,151 +112,213 @@ __device__ __forceinline__ void store6(double *p, const double (&v)[6]) {
   q[2] = make_double2(v[4], v[5]);
 }
 
-// r = -z, x = 0, s = M^-1 r, p = s ; partials r.s, r.r
+// Preconditioned CG in the Chronopoulos-Gear arrangement: the same Krylov
+// iterates as textbook PCG with one reduction phase per iteration.  With
+// u = M^-1 r, w = H u:
+//   gamma = (r, u), delta = (w, u);  beta = gamma / gamma_prev;
+//   alpha = gamma / (delta - beta gamma / alpha_prev);
+//   p = u + beta p;  q = w + beta q;  x += alpha p;  r -= alpha q;  u = M^-1 r.
+// One iteration = k_cg_update, k_spmv (w = H u plus the three dots r.u, w.u,
+// r.r) and k_cg_scalars (per scene).  Buffers: cx = x, cr = r, cs = u,
+// cAp = w, cp = p, cq = q.
+
+// r = -z, x = 0, u = M^-1 r, p = q = 0
 template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs d) {
   const int r = blockIdx.x * TILE + threadIdx.x;
   const int scene = d.psid[blockIdx.x * TILE];
   if (!d.ctl[scene].cg_active) return;
-  double z[6], rv[6], sv[6];
+  double z[6], rv[6], uv[6];
   load6(d.z + (size_t)r * 6, z);
 #pragma unroll
   for (int k = 0; k < 6; ++k) rv[k] = -z[k];
-  sym6_apply(reinterpret_cast<const T *>(d.dinv) + (size_t)r * 21, rv, sv);
+  sym6_apply(reinterpret_cast<const T *>(d.dinv) + (size_t)r * 21, rv, uv);
   const double zero[6] = {0, 0, 0, 0, 0, 0};
   store6(d.cx + (size_t)r * 6, zero);
   store6(d.cr + (size_t)r * 6, rv);
-  store6(d.cs + (size_t)r * 6, sv);
-  store6(d.cp + (size_t)r * 6, sv);
-  KSum rs = {0.0, 0.0}, rr = {0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < 6; ++k) { kadd(rs, rv[k] * sv[k]); kadd(rr, rv[k] * rv[k]); }
-  const KSum a = block_ksum(rs), b = block_ksum(rr);
-  if (threadIdx.x == 0) {
-    d.part_a[blockIdx.x] = make_double2(a.s, a.c);
-    d.part_b[blockIdx.x] = make_double2(b.s, b.c);
-  }
+  store6(d.cs + (size_t)r * 6, uv);
+  store6(d.cp + (size_t)r * 6, zero);
+  store6(d.cq + (size_t)r * 6, zero);
 }
 
-__global__ void k_cg_start(DevPtrs d) {
-  const int s = blockIdx.x;
-  SceneCtl &c = d.ctl[s];
-  if (!c.cg_active) return;
-  const int pb = d.scene_pbeg[s] / TILE, pe = d.scene_pbeg[s + 1] / TILE;
-  const KSum rs = range_ksum(d.part_a, pb, pe);
-  const KSum rr = range_ksum(d.part_b, pb, pe);
-  if (threadIdx.x != 0) return;
-  c.rz = rs.s + rs.c;
-  c.rr = rr.s + rr.c;
-  if (!(sqrt(c.rr) > c.cg_tol) || !(c.rz > 0.0)) c.cg_active = 0;
+// one row of a 6x6 block (6 contiguous values of type T) widened to FP64
+__device__ __forceinline__ void load_row6(const float *h, double (&v)[6]) {
+  const float2 *q = reinterpret_cast<const float2 *>(h);   // 8-byte aligned
+  const float2 a = q[0], b = q[1], c = q[2];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
 }
+__device__ __forceinline__ void load_row6(const double *h, double (&v)[6]) { load6(h, v); }
 
-// Ap = H p: lane (row, component); 64 block rows per workgroup; partial p.Ap
-template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) void k_spmv(DevPtrs d) {
+// w = H u plus the partial dots (r, u), (w, u), (r, r) of the workgroup.
+// Workgroup = SPMV_ROWS consecutive block rows of one scene; their slots are
+// one contiguous range of the block-CSR arrays.  Phase 1 is slot-parallel:
+// thread (slot, c) forms component c of H_slot u_j, all loads of a trip issued
+// before any use, so the matrix streams through in address order; the products
+// go to LDS in passes of SPMV_CAP slots.  Phase 2: thread (row, c) adds the
+// diagonal block times u_row and its row's slot products in slot order, so the
+// sum order is fixed and results are reproducible.
+template <typename T> __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(DevPtrs d) {
+  constexpr int U = 2;   // trips per thread in flight
+  __shared__ double prod[SPMV_CAP * 6 + 1];   // last entry absorbs clamped lanes
   const int lb = xcd_block(blockIdx.x, gridDim.x);
-  const int row0 = lb * SPMV_ROWS;
-  const int scene = d.psid[row0];
+  const int r0 = lb * SPMV_ROWS;
+  const int scene = d.psid[r0];
   if (!d.ctl[scene].cg_active) return;
   const int t = threadIdx.x;
-  const int row = row0 + t / 6, c = t - (t / 6) * 6;
-  const T *D = reinterpret_cast<const T *>(d.hdiag) + (size_t)row * 21;
-  const double *p = d.cp;
-  double pr[6];
-  load6(p + (size_t)row * 6, pr);
-  double acc = 0.0;
+  const int s0 = d.row_ptr[r0], s1 = d.row_ptr[r0 + SPMV_ROWS];
+  const int rl = t / 6, c_out = t - (t / 6) * 6;
+  const bool rowthr = t < 6 * SPMV_ROWS;
+  const int row = r0 + (rowthr ? rl : 0);
+  const T *Hoff = reinterpret_cast<const T *>(d.hoff);
+  const double *u = d.cs;
+  double acc = 0.0, uc = 0.0, rc = 0.0;
+  int rbeg = 0, rend = 0;
+  if (rowthr) {
+    rbeg = d.row_ptr[row];
+    rend = d.row_ptr[row + 1];
+    const T *D = reinterpret_cast<const T *>(d.hdiag) + (size_t)row * 21;
+    double ur[6];
+    load6(u + (size_t)row * 6, ur);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) acc += double(D[up6(c, k)]) * pr[k];
-  const int beg = d.row_ptr[row], end = d.row_ptr[row + 1];
-  const T *H = reinterpret_cast<const T *>(d.hoff);
-  for (int k = beg; k < end; ++k) {
-    const int j = d.col[k];
-    double pj[6];
-    load6(p + (size_t)j * 6, pj);
-    const T *h = H + (size_t)k * 36 + c * 6;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) acc += double(h[e]) * pj[e];
+    for (int k = 0; k < 6; ++k) acc += double(D[up6(c_out, k)]) * ur[k];
+    uc = u[(size_t)row * 6 + c_out];
+    rc = d.cr[(size_t)row * 6 + c_out];
   }
-  d.cAp[(size_t)row * 6 + c] = acc;
-  KSum pap = {0.0, 0.0};
-  kadd(pap, p[(size_t)row * 6 + c] * acc);
-  const KSum tot = block_ksum(pap);
-  if (t == 0) d.part_c[lb] = make_double2(tot.s, tot.c);
+  for (int cb = s0; cb < s1; cb += SPMV_CAP) {
+    const int ce = min(cb + SPMV_CAP, s1);
+    const int nsc = (ce - cb) * 6;
+    for (int base = 0; base < nsc; base += SPMV_THREADS * U) {
+      int sl[U], cc[U], jj[U];
+      double hv[U][6], uj[U][6];
+#pragma unroll
+      for (int m = 0; m < U; ++m) {   // lanes past the end repeat the last product
+        const int id = min(base + m * SPMV_THREADS + t, nsc - 1);
+        sl[m] = id / 6;
+        cc[m] = id - sl[m] * 6;
+      }
+#pragma unroll
+      for (int m = 0; m < U; ++m) {
+        jj[m] = d.slot[cb + sl[m]].x;
+        load_row6(Hoff + (size_t)(cb + sl[m]) * 36 + cc[m] * 6, hv[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < U; ++m) load6(u + (size_t)jj[m] * 6, uj[m]);
+#pragma unroll
+      for (int m = 0; m < U; ++m) {
+        double a = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) a += hv[m][e] * uj[m][e];
+        prod[(base + m * SPMV_THREADS + t < nsc) ? sl[m] * 6 + cc[m] : SPMV_CAP * 6] = a;
+      }
+    }
+    __syncthreads();
+    if (rowthr) {
+      const int lo = max(rbeg, cb), hi = min(rend, ce);
+      for (int k = lo; k < hi; ++k) acc += prod[(k - cb) * 6 + c_out];
+    }
+    __syncthreads();
+  }
+  if (rowthr) d.cAp[(size_t)row * 6 + c_out] = acc;
+  KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
+  if (rowthr) {
+    kadd(ru, rc * uc);
+    kadd(wu, acc * uc);
+    kadd(rr, rc * rc);
+  }
+  const KSum a = block_ksum(ru), bsum = block_ksum(wu), cs = block_ksum(rr);
+  if (t == 0) {
+    d.part_a[lb] = make_double2(a.s, a.c);
+    d.part_b[lb] = make_double2(bsum.s, bsum.c);
+    d.part_c[lb] = make_double2(cs.s, cs.c);
+  }
 }
 
-__global__ void k_cg_alpha(DevPtrs d) {
+// per-scene scalars of one iteration and the stop test |r| <= eps_r |z|
+__global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
   const int s = blockIdx.x;
   SceneCtl &c = d.ctl[s];
-  if (!c.cg_active) return;
-  const int b0 = d.scene_pbeg[s] / SPMV_ROWS, b1 = d.scene_pbeg[s + 1] / SPMV_ROWS;
-  const KSum pap = range_ksum(d.part_c, b0, b1);
-  if (threadIdx.x != 0) return;
-  c.pAp = pap.s + pap.c;
-  if (!(c.pAp > 0.0) || !isfinite(c.pAp)) {   // breakdown: keep the current x
-    c.cg_active = 0;
-    c.alpha = 0.0;
+  if (!c.cg_active) {
+    if (gridDim.x == 1 && threadIdx.x == 0) d.counters[1] = 0;
     return;
   }
-  c.alpha = c.rz / c.pAp;
-}
-
-// x += alpha p ; r -= alpha Ap ; s = M^-1 r ; partials r.s, r.r
-template <typename T> __global__ __launch_bounds__(TILE) void k_cg_update(DevPtrs d) {
-  const int r = blockIdx.x * TILE + threadIdx.x;
-  const int scene = d.psid[blockIdx.x * TILE];
-  const SceneCtl &c = d.ctl[scene];
-  if (!c.cg_active) return;
-  const double a = c.alpha;
-  double x[6], rv[6], p[6], ap[6], sv[6];
-  load6(d.cx + (size_t)r * 6, x);
-  load6(d.cr + (size_t)r * 6, rv);
-  load6(d.cp + (size_t)r * 6, p);
-  load6(d.cAp + (size_t)r * 6, ap);
+  const int b0 = d.scene_pbeg[s] / SPMV_ROWS, b1 = d.scene_pbeg[s + 1] / SPMV_ROWS;
+  KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
+  constexpr int U = 4;   // partials per thread in flight
+  for (int k0 = b0; k0 < b1; k0 += U * (int)blockDim.x) {
+    double2 pa[U], pb[U], pc[U];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) { x[k] += a * p[k]; rv[k] -= a * ap[k]; }
-  sym6_apply(reinterpret_cast<const T *>(d.dinv) + (size_t)r * 21, rv, sv);
-  store6(d.cx + (size_t)r * 6, x);
-  store6(d.cr + (size_t)r * 6, rv);
-  store6(d.cs + (size_t)r * 6, sv);
-  KSum rs = {0.0, 0.0}, rr = {0.0, 0.0};
+    for (int m = 0; m < U; ++m) {
+      const int k = min(k0 + m * (int)blockDim.x + (int)threadIdx.x, b1 - 1);
+      pa[m] = d.part_a[k];
+      pb[m] = d.part_b[k];
+      pc[m] = d.part_c[k];
+    }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) { kadd(rs, rv[k] * sv[k]); kadd(rr, rv[k] * rv[k]); }
-  const KSum ta = block_ksum(rs), tb = block_ksum(rr);
-  if (threadIdx.x == 0) {
-    d.part_a[blockIdx.x] = make_double2(ta.s, ta.c);
-    d.part_b[blockIdx.x] = make_double2(tb.s, tb.c);
+    for (int m = 0; m < U; ++m) {
+      if (k0 + m * (int)blockDim.x + (int)threadIdx.x >= b1) continue;
+      ru = kmerge(ru, KSum{pa[m].x, pa[m].y});
+      wu = kmerge(wu, KSum{pb[m].x, pb[m].y});
+      rr = kmerge(rr, KSum{pc[m].x, pc[m].y});
+    }
   }
-}
-
-// beta = r.s_new / r.s ; stop at |r| <= eps_r |z| or max_cg
-__global__ void k_cg_beta(DevPtrs d, Params P) {
-  const int s = blockIdx.x;
-  SceneCtl &c = d.ctl[s];
-  if (!c.cg_active) return;
-  const int pb = d.scene_pbeg[s] / TILE, pe = d.scene_pbeg[s + 1] / TILE;
-  const KSum rs = range_ksum(d.part_a, pb, pe);
-  const KSum rr = range_ksum(d.part_b, pb, pe);
+  ru = block_ksum(ru);
+  wu = block_ksum(wu);
+  rr = block_ksum(rr);
   if (threadIdx.x != 0) return;
-  const double rz_new = rs.s + rs.c;
+  const double gamma = ru.s + ru.c, delta = wu.s + wu.c;
   c.rr = rr.s + rr.c;
-  c.beta = rz_new / c.rz;
-  c.rz = rz_new;
-  c.cg_it += 1;
-  c.cg_total += 1;
-  if (!(sqrt(c.rr) > c.cg_tol) || c.cg_it >= P.max_cg || !(rz_new > 0.0)) c.cg_active = 0;
+  bool stop = !(sqrt(c.rr) > c.cg_tol) || c.cg_it >= P.max_cg || !(gamma > 0.0);
+  double alpha = 0.0, beta = 0.0;
+  if (!stop) {
+    if (c.cg_it == 0) {
+      beta = 0.0;
+      alpha = gamma / delta;
+      if (!(delta > 0.0)) stop = true;
+    } else {
+      beta = gamma / c.rz;
+      const double den = delta - beta * gamma / c.alpha;
+      alpha = gamma / den;
+      if (!(den > 0.0)) stop = true;
+    }
+  }
+  if (stop || !isfinite(alpha) || !isfinite(beta)) {   // x holds the solution of this solve
+    c.cg_active = 0;
+  } else {
+    c.rz = gamma;
+    c.alpha = alpha;
+    c.beta = beta;
+    c.cg_it += 1;
+    c.cg_total += 1;
+  }
+  if (gridDim.x == 1) d.counters[1] = c.cg_active;
 }
 
-// p = s + beta p
-__global__ __launch_bounds__(TILE) void k_cg_pupdate(DevPtrs d) {
-  const int r = blockIdx.x * TILE + threadIdx.x;
-  const int scene = d.psid[blockIdx.x * TILE];
+// p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r.
+// Thread (row, component): every vector is read and written with unit
+// stride; the new residual of the row is shared through LDS for M^-1 r.
+template <typename T> __global__ __launch_bounds__(6 * UPD_ROWS) void k_cg_update(DevPtrs d) {
+  __shared__ double rs[6 * UPD_ROWS];
+  const int r0 = blockIdx.x * UPD_ROWS;
+  const int scene = d.psid[r0];
   const SceneCtl &c = d.ctl[scene];
   if (!c.cg_active) return;
-  const double b = c.beta;
-  double p[6], sv[6];
-  load6(d.cp + (size_t)r * 6, p);
-  load6(d.cs + (size_t)r * 6, sv);
+  const double a = c.alpha, b = c.beta;
+  const int t = threadIdx.x;
+  const size_t o = (size_t)r0 * 6 + t;
+  const double x = d.cx[o], rv = d.cr[o], u = d.cs[o], w = d.cAp[o], p = d.cp[o], q = d.cq[o];
+  const double pn = u + b * p, qn = w + b * q;
+  const double xn = x + a * pn, rn = rv - a * qn;
+  rs[t] = rn;
+  d.cp[o] = pn;
+  d.cq[o] = qn;
+  d.cx[o] = xn;
+  d.cr[o] = rn;
+  __syncthreads();
+  const int rl = t / 6, cc = t - rl * 6;
+  const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)(r0 + rl) * 21;
+  double un = 0.0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) p[k] = sv[k] + b * p[k];
-  store6(d.cp + (size_t)r * 6, p);
+  for (int k = 0; k < 6; ++k) un += double(Di[up6(cc, k)]) * rs[rl * 6 + k];
+  d.cs[o] = un;
 }
 
 // ---------------------------------------------------------------------------
@@ -343,21 +405,20 @@ void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s) {
   if (mixed) k_cg_init<float><<<nb, TILE, 0, s>>>(d);
   else k_cg_init<double><<<nb, TILE, 0, s>>>(d);
 }
-void launch_cg_start(const DevPtrs &d, int n_scenes, hipStream_t s) {
-  k_cg_start<<<n_scenes, 256, 0, s>>>(d);
-}
 void launch_spmv(const DevPtrs &d, bool mixed, hipStream_t s) {
+  static_assert(TILE % SPMV_ROWS == 0 && 6 * SPMV_ROWS <= SPMV_THREADS, "SpMV tiling");
   const int nsp = d.n_pad / SPMV_ROWS;
-  if (mixed) k_spmv<float><<<nsp, 6 * SPMV_ROWS, 0, s>>>(d);
-  else k_spmv<double><<<nsp, 6 * SPMV_ROWS, 0, s>>>(d);
+  if (mixed) k_spmv<float><<<nsp, SPMV_THREADS, 0, s>>>(d);
+  else k_spmv<double><<<nsp, SPMV_THREADS, 0, s>>>(d);
 }
-void launch_cg_rest(const DevPtrs &d, const Params &P, bool mixed, hipStream_t s) {
-  const int nb = d.n_pad / TILE;
-  k_cg_alpha<<<P.n_scenes, 256, 0, s>>>(d);
-  if (mixed) k_cg_update<float><<<nb, TILE, 0, s>>>(d);
-  else k_cg_update<double><<<nb, TILE, 0, s>>>(d);
-  k_cg_beta<<<P.n_scenes, 256, 0, s>>>(d, P);
-  k_cg_pupdate<<<nb, TILE, 0, s>>>(d);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s) {
+  k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P);
+}
+void launch_cg_update(const DevPtrs &d, bool mixed, hipStream_t s) {
+  static_assert(TILE % UPD_ROWS == 0, "update tiling");
+  const int nb = d.n_pad / UPD_ROWS;
+  if (mixed) k_cg_update<float><<<nb, 6 * UPD_ROWS, 0, s>>>(d);
+  else k_cg_update<double><<<nb, 6 * UPD_ROWS, 0, s>>>(d);
 }
 void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s) {
   k_slope_part<<<d.n_pad / TILE, TILE, 0, s>>>(d);
