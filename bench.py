@@ -30,6 +30,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "spmv_ceramic_plate_219k.md")
+
+
+def spmv_source_digest():
+    """sha256 of the SpMV kernel's source text (the k_spmv template and the
+    SPMV_* tiling constants): HBM counter figures recorded for one digest are
+    stale once it changes."""
+    import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_2308_10459_amd", "csrc")
+    src = open(os.path.join(csrc, "k_solve.hip")).read()
+    m = re.search(r"template <typename T> __global__ __launch_bounds__\(SPMV_THREADS\) void k_spmv.*?\n}\n",
+                  src, re.S)
+    consts = [ln for ln in open(os.path.join(csrc, "bdem_internal.hpp")) if "SPMV_" in ln]
+    text = (m.group(0) if m else "") + "".join(consts)
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per SpMV launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    import re
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"TRAFFIC kernel=k_spmv<float> digest=(\w+) fetch_bytes=(\d+) write_bytes=(\d+)", txt)
+    if not m or m.group(1) != spmv_source_digest():
+        return None
+    return int(m.group(2)) + int(m.group(3))
+
+
 def spmv_algorithmic_bytes(n, nb_alive, elt):
     """Bytes one SpMV must move at least: every unique block once (one 6x6 per
     bond, the 21 packed values of each diagonal block), the bond's index pair,
@@ -206,7 +238,7 @@ def main():
                                                if rf and rf["newton_iters_per_s"] > 0 else None),
         "roofline": {"bound": "hbm", "kernel": "k_spmv<float>", "achieved": rm["spmv_gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rm["spmv_gbs"] / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": recorded_traffic(),
                      "algorithmic_bytes_per_launch": rm["spmv_bytes"]},
     }
     if not args.no_cpu_baseline:

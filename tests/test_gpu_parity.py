@@ -54,9 +54,12 @@ def _perturbed_block(nx=5, ny=4, nz=3, seed=11, ground=False):
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("psd", [False, True])
 @pytest.mark.parametrize("ground", [False, True])
-def test_energy_grad_hess_block(B, mixed, psd, ground):
-    log(f"[egh block] mixed={mixed} psd={psd} ground={ground}")
-    sc, st = _perturbed_block(ground=ground)
+@pytest.mark.parametrize("dims", [(5, 4, 3), (11, 10, 9)])
+def test_energy_grad_hess_block(B, mixed, psd, ground, dims):
+    # 60 particles (one partial tile); 990 particles = three full 256-particle
+    # tiles and a 222-particle tail, 2,671 bonds (ten full bond tiles and a tail)
+    log(f"[egh block] dims={dims} mixed={mixed} psd={psd} ground={ground}")
+    sc, st = _perturbed_block(*dims, ground=ground)
     o = oracle_for(sc, st)
     dt = 1e-3
     ev_pos, ev_quat, _, _ = S.perturb_state(sc, 5, 1e-4, 0.01)
