@@ -82,7 +82,6 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.ctl), S.n_scenes * sizeof(SceneCtl));
   L.add(reinterpret_cast<void **>(&d.scene_pbeg), (S.n_scenes + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.scene_bbeg), (S.n_scenes + 1) * sizeof(int));
-  L.add(reinterpret_cast<void **>(&d.counters), 4 * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.degenerate), sizeof(int));
 }
 
@@ -546,7 +545,13 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(hipMemsetAsync(d.hdiag, 0, (size_t)NP * 21 * T, st));
   chk(hipMemsetAsync(d.dinv, 0, (size_t)NP * 21 * T, st));
   chk(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
-  chk(hipHostMalloc((void **)&ctx->h_counters, 8 * sizeof(int), hipHostMallocDefault));
+  // counters: written by the decision kernels straight into mapped host
+  // memory, read by the host once an event or the stream has passed them
+  chk(hipHostMalloc((void **)&ctx->h_counters, 8 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+  if (e == hipSuccess) {
+    std::memset(ctx->h_counters, 0, 8 * sizeof(int));
+    chk(hipHostGetDevicePointer((void **)&ctx->d.counters, ctx->h_counters, 0));
+  }
   chk(hipHostMalloc((void **)&ctx->h_ctl, NS * sizeof(SceneCtl), hipHostMallocDefault));
   for (int k = 0; k < 2; ++k) chk(hipEventCreateWithFlags(&ctx->ev_slot[k], hipEventDisableTiming));
   chk(hipStreamSynchronize(st));
@@ -564,9 +569,9 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
 // helpers for the step driver
 // ---------------------------------------------------------------------------
 
-static int read_counters(bdem_ctx *ctx, int slot) {
-  HIP_TRY(hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int),
-                         hipMemcpyDeviceToHost, ctx->stream));
+// the counter slot written by the last decision kernel is valid once the
+// stream has drained
+static int read_counters(bdem_ctx *ctx) {
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return BDEM_OK;
 }
@@ -598,22 +603,20 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
 }
 
 // one PCG iteration: update, SpMV with the three dots, per-scene scalars
-static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
+static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv, int slot) {
   const bool mixed = ctx->S.mixed;
   launch_cg_update(ctx->d, mixed, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, false);
-  launch_cg_scalars(ctx->d, ctx->P, ctx->stream);
+  launch_cg_scalars(ctx->d, ctx->P, slot, ctx->stream);
 }
 
 static int build_cg_graphs(bdem_ctx *ctx, int chunk) {
   for (int slot = 0; slot < 2; ++slot) {
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, false);
-    if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, ctx->stream);
-    (void)hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int), hipMemcpyDeviceToHost,
-                         ctx->stream);
+    for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, false, slot);
+    if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, slot, ctx->stream);
     HIP_TRY(hipStreamEndCapture(ctx->stream, &ctx->cg_graph[slot]));
     HIP_TRY(hipGraphInstantiate(&ctx->cg_exec[slot], ctx->cg_graph[slot], nullptr, nullptr, 0));
   }
@@ -631,9 +634,9 @@ static int run_pcg(bdem_ctx *ctx) {
   if (ctx->profiling) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, st);
   if (ctx->profiling) prof_mark(ctx, 1, false);
-  launch_cg_scalars(ctx->d, ctx->P, st);
-  if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, st);
-  int rc = read_counters(ctx, 0);
+  launch_cg_scalars(ctx->d, ctx->P, 0, st);
+  if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
+  int rc = read_counters(ctx);
   if (rc) return rc;
   if (ctx->h_counters[1] == 0) return BDEM_OK;
   const int chunk = std::max(1, ctx->opt.cg_chunk);
@@ -649,10 +652,8 @@ static int run_pcg(bdem_ctx *ctx) {
     if (graph) {
       HIP_TRY(hipGraphLaunch(ctx->cg_exec[slot], st));
     } else {
-      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling != 0);
-      if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, st);
-      HIP_TRY(hipMemcpyAsync(ctx->h_counters + 4 * slot, ctx->d.counters, 4 * sizeof(int),
-                             hipMemcpyDeviceToHost, st));
+      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling != 0, slot);
+      if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, slot, st);
     }
     HIP_TRY(hipEventRecord(ctx->ev_slot[slot], st));
     if (pending >= 0) {
@@ -680,8 +681,8 @@ static int run_line_search(bdem_ctx *ctx) {
     launch_bond_energy(ctx->d, true, st);
     launch_ls_decide(ctx->d, ctx->P, st);
     launch_ls_accept(ctx->d, st);
-    launch_count_active(ctx->d, ctx->S.n_scenes, st);
-    int rc = read_counters(ctx, 0);
+    launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
+    int rc = read_counters(ctx);
     if (rc) return rc;
     if (ctx->h_counters[2] == 0) return BDEM_OK;
   }
@@ -725,8 +726,8 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     prof_mark(ctx, 0, false);
     launch_particle_eval(d, ctx->P, mixed, true, false, st);
     launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, st);
-    launch_count_active(d, NS, st);
-    int rc = read_counters(ctx, 0);
+    launch_count_active(d, NS, 0, st);
+    int rc = read_counters(ctx);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ph[2], st));
     t_eval += elapsed(ph[1], ph[2]);
@@ -978,8 +979,8 @@ extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, con
   launch_bond_eval(d, mixed, psd, hess, st);
   launch_particle_eval(d, ctx->P, mixed, hess, pot, st);
   launch_newton_check(d, ctx->P, 1, st);
-  launch_count_active(d, NS, st);
-  if ((rc = read_counters(ctx, 0))) return rc;
+  launch_count_active(d, NS, 0, st);
+  if ((rc = read_counters(ctx))) return rc;
   if (ctx->h_counters[3] > 0) return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
   HIP_TRY(hipMemcpyAsync(ctx->h_ctl, d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost, st));
   std::vector<double> z;

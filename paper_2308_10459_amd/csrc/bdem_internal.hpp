@@ -87,7 +87,8 @@ struct DevPtrs {
   SceneCtl *ctl;                      // n_scenes
   int *scene_pbeg;                    // n_scenes + 1 (particle index, multiple of TILE)
   int *scene_bbeg;                    // n_scenes + 1 (bond index, multiple of TILE)
-  int *counters;                      // [0] newton active, [1] cg active, [2] ls active, [3] status OR
+  int *counters;                      // device address of 2 slots x 4 ints in mapped pinned host memory:
+                                      // [0] newton active, [1] cg active, [2] ls active, [3] degenerate bonds
   int *degenerate;                    // bonds with |q_i + q_j| below the threshold
 };
 
@@ -106,12 +107,12 @@ void launch_ls_accept(const DevPtrs &d, hipStream_t s);
 void launch_finish_step(const DevPtrs &d, hipStream_t s);
 // per-scene decisions
 void launch_newton_check(const DevPtrs &d, const Params &P, int first, hipStream_t s);
-void launch_count_active(const DevPtrs &d, int n_scenes, hipStream_t s);
+void launch_count_active(const DevPtrs &d, int n_scenes, int slot, hipStream_t s);
 void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
 // PCG
 void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
 void launch_spmv(const DevPtrs &d, bool mixed, hipStream_t s);
-void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, int slot, hipStream_t s);
 void launch_cg_update(const DevPtrs &d, bool mixed, hipStream_t s);
 void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s);
 

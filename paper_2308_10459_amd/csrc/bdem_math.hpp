@@ -146,6 +146,27 @@ __device__ __forceinline__ KSum block_ksum(KSum v) {
   __syncthreads();
   return r;
 }
+// three block-wide compensated sums in one LDS round (same combination
+// order as three block_ksum calls); every thread gets the results
+__device__ __forceinline__ void block_ksum3(KSum &a, KSum &b, KSum &c) {
+  __shared__ double l3[6][16];
+  a = wave_ksum(a);
+  b = wave_ksum(b);
+  c = wave_ksum(c);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    l3[0][w] = a.s; l3[1][w] = a.c; l3[2][w] = b.s; l3[3][w] = b.c; l3[4][w] = c.s; l3[5][w] = c.c;
+  }
+  __syncthreads();
+  KSum ra = {0.0, 0.0}, rb = {0.0, 0.0}, rc = {0.0, 0.0};
+  for (int k = 0; k < nw; ++k) {
+    ra = kmerge(ra, KSum{l3[0][k], l3[1][k]});
+    rb = kmerge(rb, KSum{l3[2][k], l3[3][k]});
+    rc = kmerge(rc, KSum{l3[4][k], l3[5][k]});
+  }
+  __syncthreads();
+  a = ra; b = rb; c = rc;
+}
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));

@@ -63,7 +63,9 @@ __global__ void k_newton_check(DevPtrs d, Params P, int first) {
   c.cg_it = 0;
 }
 
-__global__ void k_count_active(DevPtrs d, int n_scenes) {
+// active-scene counts into counter slot `slot` (mapped host memory, read by
+// the host after the stream or an event has passed this kernel)
+__global__ void k_count_active(DevPtrs d, int n_scenes, int slot) {
   __shared__ int a[3];
   if (threadIdx.x < 3) a[threadIdx.x] = 0;
   __syncthreads();
@@ -78,8 +80,9 @@ __global__ void k_count_active(DevPtrs d, int n_scenes) {
   atomicAdd(&a[2], nl);
   __syncthreads();
   if (threadIdx.x == 0) {
-    d.counters[0] = a[0]; d.counters[1] = a[1]; d.counters[2] = a[2];
-    d.counters[3] = *d.degenerate;
+    int *c = d.counters + 4 * slot;
+    c[0] = a[0]; c[1] = a[1]; c[2] = a[2];
+    c[3] = *d.degenerate;
   }
 }
 
@@ -224,25 +227,24 @@ template <typename T> __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(Dev
     kadd(wu, acc * uc);
     kadd(rr, rc * rc);
   }
-  const KSum a = block_ksum(ru), bsum = block_ksum(wu), cs = block_ksum(rr);
+  block_ksum3(ru, wu, rr);
   if (t == 0) {
-    d.part_a[lb] = make_double2(a.s, a.c);
-    d.part_b[lb] = make_double2(bsum.s, bsum.c);
-    d.part_c[lb] = make_double2(cs.s, cs.c);
+    d.part_a[lb] = make_double2(ru.s, ru.c);
+    d.part_b[lb] = make_double2(wu.s, wu.c);
+    d.part_c[lb] = make_double2(rr.s, rr.c);
   }
 }
 
-// per-scene scalars of one iteration and the stop test |r| <= eps_r |z|
-__global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
+// per-scene scalars of one iteration and the stop test |r| <= eps_r |z|.
+// The partial loads do not wait for the activity flag: everything the block
+// reads is issued at once, then the three sums share one LDS round.
+__global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P, int slot) {
   const int s = blockIdx.x;
   SceneCtl &c = d.ctl[s];
-  if (!c.cg_active) {
-    if (gridDim.x == 1 && threadIdx.x == 0) d.counters[1] = 0;
-    return;
-  }
   const int b0 = d.scene_pbeg[s] / SPMV_ROWS, b1 = d.scene_pbeg[s + 1] / SPMV_ROWS;
+  const int active = c.cg_active;
   KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
-  constexpr int U = 4;   // partials per thread in flight
+  constexpr int U = 8;   // partials per thread in flight
   for (int k0 = b0; k0 < b1; k0 += U * (int)blockDim.x) {
     double2 pa[U], pb[U], pc[U];
 #pragma unroll
@@ -260,9 +262,11 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
       rr = kmerge(rr, KSum{pc[m].x, pc[m].y});
     }
   }
-  ru = block_ksum(ru);
-  wu = block_ksum(wu);
-  rr = block_ksum(rr);
+  if (!active) {
+    if (gridDim.x == 1 && threadIdx.x == 0) d.counters[4 * slot + 1] = 0;
+    return;
+  }
+  block_ksum3(ru, wu, rr);
   if (threadIdx.x != 0) return;
   const double gamma = ru.s + ru.c, delta = wu.s + wu.c;
   c.rr = rr.s + rr.c;
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
     c.cg_it += 1;
     c.cg_total += 1;
   }
-  if (gridDim.x == 1) d.counters[1] = c.cg_active;
+  if (gridDim.x == 1) d.counters[4 * slot + 1] = c.cg_active;
 }
 
 // p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r.
@@ -397,8 +401,8 @@ __global__ void k_ls_decide(DevPtrs d, Params P) {
 void launch_newton_check(const DevPtrs &d, const Params &P, int first, hipStream_t s) {
   k_newton_check<<<P.n_scenes, 256, 0, s>>>(d, P, first);
 }
-void launch_count_active(const DevPtrs &d, int n_scenes, hipStream_t s) {
-  k_count_active<<<1, 256, 0, s>>>(d, n_scenes);
+void launch_count_active(const DevPtrs &d, int n_scenes, int slot, hipStream_t s) {
+  k_count_active<<<1, 256, 0, s>>>(d, n_scenes, slot);
 }
 void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s) {
   const int nb = d.n_pad / TILE;
@@ -411,8 +415,8 @@ void launch_spmv(const DevPtrs &d, bool mixed, hipStream_t s) {
   if (mixed) k_spmv<float><<<nsp, SPMV_THREADS, 0, s>>>(d);
   else k_spmv<double><<<nsp, SPMV_THREADS, 0, s>>>(d);
 }
-void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s) {
-  k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, int slot, hipStream_t s) {
+  k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P, slot);
 }
 void launch_cg_update(const DevPtrs &d, bool mixed, hipStream_t s) {
   static_assert(TILE % UPD_ROWS == 0, "update tiling");
