@@ -117,6 +117,52 @@ def run_path(scene, mixed, steps, warmup, profile):
     return tot
 
 
+def run_batch(steps, warmup):
+    """The 64-scene batch (992,148 particles, seeded sizes 2K-50K, per-scene
+    dt): aggregate particle-steps per second of the mixed path stepping all
+    scenes in one batched call, of the FP64 path batched, and of the FP64
+    path stepping the scenes one after another (each scene alone)."""
+    import torch
+    from paper_2308_10459_amd import bdem as B
+    from paper_2308_10459_amd import scenes as S
+    sc = S.make_batch()
+    out = {"workload": f"{sc.name}: {sc.n} particles, {sc.nb} bonds, 64 scenes of 2K-50K particles, "
+                       "per-scene dt = 50 x the period estimate", "steps": steps}
+    for label, prec in (("mixed_batched", B.BDEM_PREC_MIXED), ("fp64_batched", B.BDEM_PREC_FP64)):
+        sim = B.Simulator(sc, precision=prec)
+        for _ in range(warmup):
+            sim.step_batched(sc.dt_per_scene)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        newton = 0
+        for _ in range(steps):
+            rc, stats = sim.step_batched(sc.dt_per_scene)
+            newton += sum(st["newton_iters"] for st in stats)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        out[label] = sc.n * steps / wall
+        log(f"  batch {label}: {1e3 * wall / steps:.1f} ms/step, {newton} Newton iterations summed over scenes")
+    wall = 0.0
+    for s in range(len(sc.dt_per_scene)):
+        m = S.subset_scenes(sc, [s])
+        sim = B.Simulator(m, precision=B.BDEM_PREC_FP64)
+        for _ in range(warmup):
+            sim.step_batched(m.dt_per_scene)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step_batched(m.dt_per_scene)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        sim.close()
+    out["fp64_sequential"] = sc.n * steps / wall
+    out["unit"] = "particle-steps/s"
+    out["mixed_batched_over_fp64_sequential"] = out["mixed_batched"] / out["fp64_sequential"]
+    log(f"  batch fp64 one scene at a time: {1e3 * wall / steps:.1f} ms per step of all scenes")
+    return out
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle on a bounded sample of the same workload: a 24x24x16
     sub-plate (9,216 particles) built like the ceramic plate, same material,
@@ -165,6 +211,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--mixed-only", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=3,
+                    help="steps of the 64-scene batch (0: skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -241,6 +289,9 @@ def main():
                      "traffic": recorded_traffic(),
                      "algorithmic_bytes_per_launch": rm["spmv_bytes"]},
     }
+    if args.batch_steps > 0:
+        log("64-scene batch:")
+        out["batch"] = run_batch(args.batch_steps, 1)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle):")
         out["cpu_baseline"] = cpu_baseline()

@@ -103,7 +103,8 @@ typedef struct {
 typedef struct {
   double gravity[3];
   double ground_normal[3], ground_offset; /* plane n.p = h; gap = n.p - h - r */
-  double k_contact;        /* < 0: E_max * r_max (Section 5.4), 0: no ground, > 0: value */
+  double k_contact;        /* < 0: per scene, E_max * r_max over that scene's materials and
+                              particles (Section 5.4); 0: no ground; > 0: this value for all */
   double mu_s, mu_r;       /* friction hook of Algorithm 3; must be 0 (not implemented) */
   double newton_tol;       /* absolute stop |z|_2 <= newton_tol */
   double newton_rtol;      /* relative stop |z|_2 <= newton_rtol |z0|_2 */

@@ -149,6 +149,7 @@ struct bdem_ctx {
   std::vector<int64_t> b_int;    // user bond -> internal bond
   std::vector<int2> bslot_h;     // internal bond -> slots
   std::vector<int> scene_pbeg, scene_bbeg;
+  std::vector<double> scene_kc;  // ground penalty stiffness per scene
   // pinned host mirrors
   int *h_counters = nullptr;     // 2 polling slots x 4
   int prof_cnt[2] = {0, 0};      // profiled launches in the last step (bond, SpMV)
@@ -363,8 +364,9 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   std::vector<int> h_psid(NP, 0);
   for (int s = 0; s < NS; ++s)
     for (int r = ctx->scene_pbeg[s]; r < ctx->scene_pbeg[s + 1]; ++r) h_psid[r] = s;
-  double Emax = 0.0, rmax = 0.0;
-  for (int k = 0; k < n_mats; ++k) Emax = std::max(Emax, mats[k].young);
+  // ground stiffness: the caller's value, or per scene E_max r_max over the
+  // scene's own particle and bond materials (Section 5.4)
+  std::vector<double> s_emax(NS, 0.0), s_rmax(NS, 0.0);
   for (int i = 0; i < n; ++i) {
     const int r = ctx->p_int[i];
     h_pn[r] = make_double4(p->pos[3 * i], p->pos[3 * i + 1], p->pos[3 * i + 2], 0.0);
@@ -376,8 +378,17 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     const double m = rho * 4.0 / 3.0 * M_PI * rad * rad * rad;
     h_pc[r] = make_double4(m, 8.0 / 5.0 * m * rad * rad, rad, 0.0);
     h_flags[r] = p->flags ? p->flags[i] : 0;
-    rmax = std::max(rmax, rad);
+    const int si = p->scene ? p->scene[i] : 0;
+    s_rmax[si] = std::max(s_rmax[si], rad);
+    s_emax[si] = std::max(s_emax[si], mats[p->material[i]].young);
   }
+  for (int64_t k = 0; k < b->nb; ++k)
+    if (b->material) {
+      const int si = p->scene ? p->scene[b->ij[2 * k]] : 0;
+      s_emax[si] = std::max(s_emax[si], mats[b->material[k]].young);
+    }
+  ctx->scene_kc.assign(NS, 0.0);
+  for (int s = 0; s < NS; ++s) ctx->scene_kc[s] = o.k_contact < 0.0 ? s_emax[s] * s_rmax[s] : o.k_contact;
   // ---- bonds: per scene, sorted by (min row, max row) ----
   std::vector<int64_t> order(b->nb);
   std::iota(order.begin(), order.end(), 0);
@@ -494,7 +505,6 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     P.gnz = gn > 0 ? o.ground_normal[2] / gn : 0.0;
   }
   P.gh = o.ground_offset;
-  P.kc = o.k_contact < 0.0 ? Emax * rmax : o.k_contact;   // Section 5.4: of the order of E r_max
   P.newton_tol = o.newton_tol;
   P.newton_rtol = o.newton_rtol;
   P.armijo_c = o.armijo_c;
@@ -714,6 +724,7 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     std::memset(&c, 0, sizeof(c));
     c.dt = dts[s];
     c.inv_dt2 = 1.0 / (dts[s] * dts[s]);
+    c.kc = ctx->scene_kc[s];
     c.newton_active = 1;
   }
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
@@ -967,6 +978,7 @@ extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, con
     std::memset(&c, 0, sizeof(c));
     c.dt = dt;
     c.inv_dt2 = 1.0 / (dt * dt);
+    c.kc = ctx->scene_kc[s];
     c.newton_active = 1;
   }
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));

@@ -32,6 +32,7 @@ constexpr int UPD_ROWS = 64;      // block rows per CG-update workgroup (6 lanes
 // PCG / line-search loops is taken on the device from these values
 struct SceneCtl {
   double dt, inv_dt2;
+  double kc;   // ground penalty stiffness of the scene (0: no ground)
   double gnorm, gnorm0, phi, phi_trial, slope, alpha_ls;
   double rz, rz_new, rr, pAp, alpha, beta, cg_tol;
   double last_move, xmax;
@@ -45,7 +46,7 @@ enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LS_FAILED = 2, ST_NONFINITE = 3 };
 struct Params {
   // environment
   double gx, gy, gz;
-  double gnx, gny, gnz, gh, kc;
+  double gnx, gny, gnz, gh;
   double newton_tol, newton_rtol, armijo_c, cg_rtol_max;
   int max_newton, max_cg, max_ls;
   int n_scenes;

@@ -43,7 +43,7 @@ struct PTerms {
   double kgap;   // k_c if the ground penalty is active
 };
 
-__device__ __forceinline__ void particle_terms(const Params &P, double idt2, double4 pc,
+__device__ __forceinline__ void particle_terms(const Params &P, double kc, double idt2, double4 pc,
                                                double4 p, double4 q, double4 ph, double4 qh,
                                                PTerms &t) {
   const double m = pc.x, c = pc.y, rad = pc.z;
@@ -56,14 +56,14 @@ __device__ __forceinline__ void particle_terms(const Params &P, double idt2, dou
   t.gp[1] = m * idt2 * ep[1] - m * P.gy;
   t.gp[2] = m * idt2 * ep[2] - m * P.gz;
   t.kgap = 0.0;
-  if (P.kc != 0.0) {
+  if (kc != 0.0) {
     const double gap = P.gnx * p.x + P.gny * p.y + P.gnz * p.z - P.gh - rad;
     if (gap < 0.0) {
-      t.E += 0.5 * P.kc * gap * gap;
-      t.gp[0] += P.kc * gap * P.gnx;
-      t.gp[1] += P.kc * gap * P.gny;
-      t.gp[2] += P.kc * gap * P.gnz;
-      t.kgap = P.kc;
+      t.E += 0.5 * kc * gap * gap;
+      t.gp[0] += kc * gap * P.gnx;
+      t.gp[1] += kc * gap * P.gny;
+      t.gp[2] += kc * gap * P.gnz;
+      t.kgap = kc;
     }
   }
   // reduced rotational gradient G_l(q) c/dt^2 (q - q_hat) = vec(conj(q) (c/dt^2)(q - q_hat))
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(TILE) void k_particle_eval(DevPtrs d, Params P, int
     const double idt2 = potential_only ? 0.0 : ctl.inv_dt2;
     const double4 q = d.qx[r], qh = d.qh[r];
     PTerms t;
-    particle_terms(P, idt2, d.pconst[r], d.px[r], q, d.ph[r], qh, t);
+    particle_terms(P, ctl.kc, idt2, d.pconst[r], d.px[r], q, d.ph[r], qh, t);
     kadd(e, t.E);
     z[0] += t.gp[0]; z[1] += t.gp[1]; z[2] += t.gp[2];
     z[3] += t.gr[0]; z[4] += t.gr[1]; z[5] += t.gr[2];
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(TILE) void k_ls_trial(DevPtrs d, Params P) {
     d.pt[r] = pt;
     d.qt[r] = qt;
     PTerms t;
-    particle_terms(P, ctl.inv_dt2, d.pconst[r], pt, qt, d.ph[r], d.qh[r], t);
+    particle_terms(P, ctl.kc, ctl.inv_dt2, d.pconst[r], pt, qt, d.ph[r], d.qh[r], t);
     kadd(e, t.E);
     mv = fmax(fmax(fabs(pt.x - p.x), fabs(pt.y - p.y)), fabs(pt.z - p.z));
     mv = fmax(mv, fmax(fmax(fabs(qt.x - q.x), fabs(qt.y - q.y)), fmax(fabs(qt.z - q.z), fabs(qt.w - q.w))));

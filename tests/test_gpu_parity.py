@@ -411,6 +411,65 @@ def test_batched_scenes_match_each_scene_alone(B):
     sim.close()
 
 
+def _conditioning_bound_sparse(sc, prev, ref, dt, zfloor):
+    """_conditioning_bound for scenes too large for a dense inverse: the norm
+    of any row block of H^-1 is at most 1 / lambda_min(H), with the smallest
+    eigenvalue of the sparse reduced Hessian found by shift-invert Lanczos."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    o = oracle_for(sc, prev)
+    _, _, hd, ho = o.energy_grad_hess(dt, ref["pos"], ref["quat"], psd=False)
+    n = sc.n
+    rows, cols, vals = [], [], []
+    bi = np.arange(6)
+    for i in range(n):
+        rows.append(np.repeat(6 * i + bi, 6)); cols.append(np.tile(6 * i + bi, 6)); vals.append(hd[i].ravel())
+    for b, (i, j) in enumerate(sc.ij):
+        if ref["alive"][b]:
+            rows.append(np.repeat(6 * i + bi, 6)); cols.append(np.tile(6 * j + bi, 6)); vals.append(ho[b].ravel())
+            rows.append(np.repeat(6 * j + bi, 6)); cols.append(np.tile(6 * i + bi, 6)); vals.append(ho[b].T.ravel())
+    H = sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(6 * n, 6 * n))
+    lam = sla.eigsh(H, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    assert lam > 0.0, lam
+    inv = 1.0 / lam
+    return inv * 10 * zfloor, inv * 10 * zfloor * 2.0
+
+
+def test_full_batch_sampled_scenes(B):
+    """The 64-scene batch at full size (992,148 particles, 4,009,869 bonds,
+    per-scene dt and ground stiffness) stepped once in one batched call on the
+    FP64 path; the smallest box, beam and plate against the oracle run on each
+    scene alone."""
+    sc = S.make_batch()
+    sizes = np.bincount(sc.scene_id)
+    picks = [min((s for s in range(64) if s % 3 == shape), key=lambda k: sizes[k]) for shape in range(3)]
+    log(f"[full batch] n={sc.n} nb={sc.nb} sampled scenes {picks}")
+    sim = make_sim(sc, **TIGHT)
+    start = sim.get_state()
+    rc, stats = sim.step_batched(sc.dt_per_scene)
+    got = sim.get_state()
+    sim.close()
+    log(f"  batched step rc {rc}, newton max {max(st['newton_iters'] for st in stats)}, "
+        f"not converged {[s for s, st in enumerate(stats) if st['status'] != 0]}")
+    for s in picks:
+        m = S.subset_scenes(sc, [s])
+        sel = sc.scene_id == s
+        # the batch's default ground stiffness is per scene: E_max r_max of that scene
+        m.k_contact = m.materials[0]["young"] * m.radius.max()
+        prev = {k: start[k][sel] for k in ("pos", "quat", "vel", "qvel")}
+        prev["alive"] = np.ones(m.nb, dtype=np.uint8)
+        o = oracle_for(m, prev)
+        so = o.step(float(m.dt_per_scene[0]), tol_rel=0.0, max_newton=300)
+        ref = o.get_state()
+        loose = _loose_step(m, prev, float(m.dt_per_scene[0]))
+        cond = _conditioning_bound_sparse(m, prev, ref, float(m.dt_per_scene[0]),
+                                          max(so["grad_final"], stats[s]["grad_final"]))
+        sub = {k: got[k][sel] for k in ("pos", "quat", "vel", "qvel")}
+        assert stats[s]["status"] == 0, stats[s]
+        _compare_states(m, sub, ref, prev, 1e-8, f"scene {s} (n={m.n}) newton {stats[s]['newton_iters']} "
+                        f"cg {stats[s]['cg_iters']}", ref2=loose, cond=cond)
+
+
 # --------------------------------------------------------------------------
 # determinism, checkpoint / restore, graphs
 # --------------------------------------------------------------------------
