@@ -41,7 +41,7 @@ def spmv_source_digest():
     import re
     csrc = os.path.join(ROOT, "paper_2308_10459_amd", "csrc")
     src = open(os.path.join(csrc, "k_solve.hip")).read()
-    m = re.search(r"template <typename T> __global__ __launch_bounds__\(SPMV_THREADS\) void k_spmv.*?\n}\n",
+    m = re.search(r"template <typename T, int NT, int U> __global__ __launch_bounds__\(NT\) void k_spmv.*?\n}\n",
                   src, re.S)
     consts = [ln for ln in open(os.path.join(csrc, "bdem_internal.hpp")) if "SPMV_" in ln]
     text = (m.group(0) if m else "") + "".join(consts)
@@ -86,7 +86,11 @@ def run_path(scene, mixed, steps, warmup, profile):
     import torch
     from paper_2308_10459_amd import bdem as B
     prec = B.BDEM_PREC_MIXED if mixed else B.BDEM_PREC_FP64
-    sim = B.Simulator(scene, precision=prec, use_graph=0, cg_chunk=1)
+    sim = B.Simulator(scene, precision=prec)
+    tuning = sim.autotune([scene.dt])
+    log(f"  autotuned: {tuning}")
+    if profile:   # per-launch events need ungraphed launches; the poll interval stays tuned
+        sim.set_tuning(use_graph=0)
     for k in range(warmup):
         st = sim.step(scene.dt)
         log(f"  warmup {k}: newton {st['newton_iters']} cg {st['cg_iters']} broken {st['bonds_broken']}")
@@ -114,6 +118,7 @@ def run_path(scene, mixed, steps, warmup, profile):
     sim.close()
     tot["wall_s"] = wall
     tot["alive_bonds"] = alive
+    tot["tuning"] = tuning
     return tot
 
 
@@ -260,7 +265,7 @@ def main():
                     bond_gbs=bytes_bond / (bond_avg_ms * 1e-3) / 1e9 if bond_avg_ms > 0 else 0.0,
                     bond_bytes=bytes_bond,
                     newton_iters=r["newton"], cg_iters=r["cg"], bonds_broken=r["broken"],
-                    alive_bonds=r["alive_bonds"])
+                    alive_bonds=r["alive_bonds"], tuning=r["tuning"])
 
     rm, rf = rates(mixed, 4, args.steps), rates(fp64, 8, fsteps)
     out = {

@@ -126,6 +126,18 @@ typedef struct {
   double t_ms[8];
 } bdem_step_stats;
 
+/* Launch shapes of the PCG kernels (none changes a result: every shape
+ * computes the same bits). */
+typedef struct {
+  int32_t spmv_threads;    /* SpMV workgroup size; 32 block rows per workgroup (192, 256, 384) */
+  int32_t spmv_trips;      /* slot products in flight per SpMV thread (1, 2, 4) */
+  int32_t update_rows;     /* block rows per CG-update workgroup (32, 64, 128) */
+  int32_t cg_chunk;        /* PCG iterations issued per host poll */
+  int32_t use_graph;       /* 1: those iterations replay a captured HIP graph */
+  int32_t pad_;
+  double spmv_us, update_us, pcg_us_per_iter; /* times measured by bdem_autotune (0: not tuned) */
+} bdem_tuning;
+
 /* Defaults: gravity (0,0,-9.81), no ground, newton_tol 0, newton_rtol 1e-8,
  * armijo_c 1e-4, cg_rtol_max 0.5, max_newton 50, max_cg 2000, max_ls 30,
  * FP64, fracture on, cg_chunk 16, no graph. */
@@ -174,6 +186,18 @@ int bdem_get_state(const bdem_ctx *ctx, double *pos, double *quat, double *vel, 
                    uint8_t *alive);
 int bdem_set_state(bdem_ctx *ctx, const double *pos, const double *quat, const double *vel,
                    const double *qvel, const uint8_t *alive);
+
+/* Launch-shape autotuner: assembles the Hessian at the prediction of a step
+ * of length dt_per_scene[s] (the first Newton iteration's matrix), times each
+ * SpMV shape, each CG-update tile and each PCG polling mode (cg_chunk,
+ * use_graph) on it with HIP events, keeps the fastest and reports it in out
+ * (nullable).  The simulation state is not changed, and since every shape
+ * computes the same bits, no later result depends on the choice.  Errors:
+ * INVALID, DEGENERATE, HIP. */
+int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tuning *out);
+/* Current launch shapes / set them explicitly (INVALID if not a listed shape). */
+int bdem_get_tuning(const bdem_ctx *ctx, bdem_tuning *out);
+int bdem_set_tuning(bdem_ctx *ctx, const bdem_tuning *tuning);
 
 /* Sizes of the handle's problem. */
 int bdem_sizes(const bdem_ctx *ctx, int32_t *n, int64_t *nb, int32_t *n_scenes);

@@ -68,6 +68,15 @@ class bdem_step_stats(C.Structure):
         return d
 
 
+class bdem_tuning(C.Structure):
+    _fields_ = [("spmv_threads", C.c_int32), ("spmv_trips", C.c_int32), ("update_rows", C.c_int32),
+                ("cg_chunk", C.c_int32), ("use_graph", C.c_int32), ("pad_", C.c_int32),
+                ("spmv_us", C.c_double), ("update_us", C.c_double), ("pcg_us_per_iter", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
 _ctx_p = C.c_void_p
 _sig = {
     "bdem_default_options": (None, [C.POINTER(bdem_options)]),
@@ -86,6 +95,9 @@ _sig = {
     "bdem_sizes": (C.c_int, [_ctx_p, _i32p, _i64p, _i32p]),
     "bdem_set_profiling": (C.c_int, [_ctx_p, C.c_int32]),
     "bdem_profile_counts": (C.c_int, [_ctx_p, _i32p, _i32p]),
+    "bdem_autotune": (C.c_int, [_ctx_p, _dp, C.POINTER(bdem_tuning)]),
+    "bdem_get_tuning": (C.c_int, [_ctx_p, C.POINTER(bdem_tuning)]),
+    "bdem_set_tuning": (C.c_int, [_ctx_p, C.POINTER(bdem_tuning)]),
     "bdem_destroy": (None, [_ctx_p]),
     "bdem_last_error": (C.c_char_p, [_ctx_p]),
 }
@@ -258,6 +270,27 @@ def bdem_profile_counts(ctx):
     return a.value, b.value
 
 
+def bdem_autotune(ctx, dt_per_scene):
+    dts = np.ascontiguousarray(np.atleast_1d(dt_per_scene), dtype=np.float64)
+    t = bdem_tuning()
+    _check(_lib.bdem_autotune(ctx, dts.ctypes.data_as(_dp), C.byref(t)), ctx)
+    return t.as_dict()
+
+
+def bdem_get_tuning(ctx):
+    t = bdem_tuning()
+    _check(_lib.bdem_get_tuning(ctx, C.byref(t)), ctx)
+    return t.as_dict()
+
+
+def bdem_set_tuning(ctx, **kw):
+    t = bdem_tuning()
+    _check(_lib.bdem_get_tuning(ctx, C.byref(t)), ctx)
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return _check(_lib.bdem_set_tuning(ctx, C.byref(t)), ctx)
+
+
 def bdem_destroy(ctx):
     _lib.bdem_destroy(ctx)
 
@@ -288,6 +321,17 @@ class Simulator:
 
     def break_bonds(self):
         return bdem_break_bonds(self.ctx)
+
+    def autotune(self, dts=None):
+        if dts is None:
+            dts = self.scene.dt_per_scene if self.scene.dt_per_scene is not None else [self.scene.dt]
+        return bdem_autotune(self.ctx, dts)
+
+    def get_tuning(self):
+        return bdem_get_tuning(self.ctx)
+
+    def set_tuning(self, **kw):
+        return bdem_set_tuning(self.ctx, **kw)
 
     def get_state(self):
         return bdem_get_state(self.ctx)

@@ -156,6 +156,8 @@ struct bdem_ctx {
   SceneCtl *h_ctl = nullptr;
   hipEvent_t ev_slot[2] = {nullptr, nullptr};
   // graph of one CG iteration (+ counter copy), one per polling slot
+  int spmv_variant = 0, upd_variant = 0;   // launch shapes (see bdem_autotune)
+  double tune_us[3] = {0.0, 0.0, 0.0};      // measured SpMV, update, PCG-iteration times
   hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
   hipGraph_t cg_graph[2] = {nullptr, nullptr};
   // profiling: events around the bond and SpMV kernels
@@ -615,11 +617,20 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
 // one PCG iteration: update, SpMV with the three dots, per-scene scalars
 static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv, int slot) {
   const bool mixed = ctx->S.mixed;
-  launch_cg_update(ctx->d, mixed, ctx->stream);
+  launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, ctx->stream);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, false);
   launch_cg_scalars(ctx->d, ctx->P, slot, ctx->stream);
+}
+
+static void drop_cg_graphs(bdem_ctx *ctx) {
+  for (int k = 0; k < 2; ++k) {
+    if (ctx->cg_exec[k]) (void)hipGraphExecDestroy(ctx->cg_exec[k]);
+    if (ctx->cg_graph[k]) (void)hipGraphDestroy(ctx->cg_graph[k]);
+    ctx->cg_exec[k] = nullptr;
+    ctx->cg_graph[k] = nullptr;
+  }
 }
 
 static int build_cg_graphs(bdem_ctx *ctx, int chunk) {
@@ -640,9 +651,10 @@ static int build_cg_graphs(bdem_ctx *ctx, int chunk) {
 static int run_pcg(bdem_ctx *ctx) {
   const bool mixed = ctx->S.mixed;
   hipStream_t st = ctx->stream;
+  const size_t mark0 = ctx->ev_marks.size();
   launch_cg_init(ctx->d, mixed, st);
   if (ctx->profiling) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, st);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling) prof_mark(ctx, 1, false);
   launch_cg_scalars(ctx->d, ctx->P, 0, st);
   if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
@@ -668,19 +680,27 @@ static int run_pcg(bdem_ctx *ctx) {
     HIP_TRY(hipEventRecord(ctx->ev_slot[slot], st));
     if (pending >= 0) {
       HIP_TRY(hipEventSynchronize(ctx->ev_slot[pending]));
-      if (ctx->h_counters[4 * pending + 1] == 0) {
-        // the chunk just issued ran after convergence (its kernels returned
-        // at once): its SpMV timings are not SpMV work
-        if (ctx->profiling && !graph) {
-          for (int k = 0; k < chunk && !ctx->ev_marks.empty() && ctx->ev_marks.back().first == 1; ++k)
-            ctx->ev_marks.pop_back();
-        }
-        break;
-      }
+      if (ctx->h_counters[4 * pending + 1] == 0) break;
     }
     pending = slot;
   }
   HIP_TRY(hipStreamSynchronize(st));
+  if (ctx->profiling && !graph) {
+    // SpMV launches issued after every scene had converged returned at once:
+    // keep the timings of the first 1 + max(cg_it) launches of this solve
+    std::vector<SceneCtl> after(ctx->S.n_scenes);
+    HIP_TRY(hipMemcpy(after.data(), ctx->d.ctl, after.size() * sizeof(SceneCtl), hipMemcpyDeviceToHost));
+    int real = 0;
+    for (const auto &c : after) real = std::max(real, c.cg_it);
+    real += 1;
+    std::vector<std::pair<int, size_t>> kept(ctx->ev_marks.begin(), ctx->ev_marks.begin() + mark0);
+    int seen = 0;
+    for (size_t k = mark0; k < ctx->ev_marks.size(); ++k) {
+      const auto &m = ctx->ev_marks[k];
+      if (m.first != 1 || seen++ < real) kept.push_back(m);
+    }
+    ctx->ev_marks.swap(kept);
+  }
   return BDEM_OK;
 }
 
@@ -1044,6 +1064,150 @@ extern "C" int bdem_break_bonds(bdem_ctx *ctx, int64_t *n_broken, uint8_t *alive
   }
   if (n_broken) *n_broken = broken;
   if (alive_out) return bdem_get_state(ctx, nullptr, nullptr, nullptr, nullptr, alive_out);
+  return BDEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape autotuning
+// ---------------------------------------------------------------------------
+
+static void fill_tuning(const bdem_ctx *ctx, bdem_tuning *t) {
+  spmv_shape(ctx->spmv_variant, &t->spmv_threads, &t->spmv_trips);
+  t->update_rows = update_rows(ctx->upd_variant);
+  t->cg_chunk = ctx->opt.cg_chunk;
+  t->use_graph = ctx->opt.use_graph;
+  t->pad_ = 0;
+  t->spmv_us = ctx->tune_us[0];
+  t->update_us = ctx->tune_us[1];
+  t->pcg_us_per_iter = ctx->tune_us[2];
+}
+
+extern "C" int bdem_get_tuning(const bdem_ctx *ctx, bdem_tuning *out) {
+  if (!ctx || !out) return BDEM_E_INVALID;
+  fill_tuning(ctx, out);
+  return BDEM_OK;
+}
+
+extern "C" int bdem_set_tuning(bdem_ctx *ctx, const bdem_tuning *t) {
+  if (!ctx || !t) return BDEM_E_INVALID;
+  int sv = -1, uv = -1;
+  for (int v = 0; v < spmv_variants(); ++v) {
+    int nt, u;
+    spmv_shape(v, &nt, &u);
+    if (nt == t->spmv_threads && u == t->spmv_trips) sv = v;
+  }
+  for (int v = 0; v < update_variants(); ++v)
+    if (update_rows(v) == t->update_rows) uv = v;
+  if (sv < 0 || uv < 0 || t->cg_chunk < 1 || (t->use_graph != 0 && t->use_graph != 1))
+    return fail(ctx, BDEM_E_INVALID, "no such launch shape");
+  ctx->spmv_variant = sv;
+  ctx->upd_variant = uv;
+  ctx->opt.cg_chunk = t->cg_chunk;
+  ctx->opt.use_graph = t->use_graph;
+  drop_cg_graphs(ctx);
+  return BDEM_OK;
+}
+
+// Times every candidate on this handle's own matrix and keeps the fastest:
+// the Hessian is assembled at the prediction of a step of length dt_per_scene
+// (as the first Newton iteration does), then each SpMV shape, each update
+// tile and each PCG polling mode is timed with HIP events.  Every candidate
+// computes the same bits, so the choice never changes a result.  The
+// simulation state is not modified.
+extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tuning *out) {
+  if (!ctx || !dt_per_scene) return BDEM_E_INVALID;
+  const int NS = ctx->S.n_scenes;
+  for (int s = 0; s < NS; ++s)
+    if (!(dt_per_scene[s] > 0.0) || !std::isfinite(dt_per_scene[s])) return fail(ctx, BDEM_E_INVALID, "dt must be > 0");
+  hipStream_t st = ctx->stream;
+  DevPtrs &d = ctx->d;
+  const bool mixed = ctx->S.mixed;
+  const int prof = ctx->profiling;
+  ctx->profiling = 0;
+  struct Restore { bdem_ctx *c; int p; ~Restore() { c->profiling = p; } } restore{ctx, prof};
+  for (int s = 0; s < NS; ++s) {
+    SceneCtl &c = ctx->h_ctl[s];
+    std::memset(&c, 0, sizeof(c));
+    c.dt = dt_per_scene[s];
+    c.inv_dt2 = 1.0 / (dt_per_scene[s] * dt_per_scene[s]);
+    c.kc = ctx->scene_kc[s];
+    c.newton_active = 1;
+  }
+  HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
+  launch_predict(d, true, st);
+  launch_bond_eval(d, mixed, true, true, st);
+  launch_particle_eval(d, ctx->P, mixed, true, false, st);
+  launch_newton_check(d, ctx->P, 1, st);
+  launch_count_active(d, NS, 0, st);
+  int rc = read_counters(ctx);
+  if (rc) return rc;
+  if (ctx->h_counters[3] > 0) return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
+  if (ctx->h_counters[0] == 0) {   // nothing to solve at this state: keep the current shapes
+    if (out) fill_tuning(ctx, out);
+    return BDEM_OK;
+  }
+  std::vector<SceneCtl> saved(NS), quiet(NS);
+  HIP_TRY(hipMemcpyAsync(saved.data(), d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  quiet = saved;
+  for (auto &c : quiet) { c.alpha = 0.0; c.beta = 0.0; }   // repeated updates leave x, r unchanged
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } eg{e0, e1};
+  auto time_it = [&](auto &&launch, int reps) -> double {
+    launch();
+    launch();
+    (void)hipEventRecord(e0, st);
+    for (int k = 0; k < reps; ++k) launch();
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return 1e3 * ms / reps;
+  };
+  HIP_TRY(hipMemcpyAsync(d.ctl, quiet.data(), NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
+  launch_cg_init(d, mixed, st);
+  double best = 1e300;
+  for (int v = 0; v < spmv_variants(); ++v) {
+    const double us = time_it([&] { launch_spmv(d, mixed, v, st); }, 5);
+    if (us < best) { best = us; ctx->spmv_variant = v; ctx->tune_us[0] = us; }
+  }
+  best = 1e300;
+  for (int v = 0; v < update_variants(); ++v) {
+    const double us = time_it([&] { launch_cg_update(d, mixed, v, st); }, 5);
+    if (us < best) { best = us; ctx->upd_variant = v; ctx->tune_us[1] = us; }
+  }
+  HIP_TRY(hipGetLastError());
+  // PCG polling: each candidate runs the same solve from x = 0
+  const int modes[][2] = {{1, 0}, {4, 0}, {4, 1}, {16, 1}};
+  best = 1e300;
+  const int chunk0 = ctx->opt.cg_chunk, graph0 = ctx->opt.use_graph;
+  int bc = chunk0, bg = graph0;
+  for (const auto &m : modes) {
+    ctx->opt.cg_chunk = m[0];
+    ctx->opt.use_graph = m[1];
+    drop_cg_graphs(ctx);
+    HIP_TRY(hipMemcpyAsync(d.ctl, saved.data(), NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(e0, st));
+    rc = run_pcg(ctx);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    std::vector<SceneCtl> after(NS);
+    HIP_TRY(hipMemcpy(after.data(), d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost));
+    int iters = 1;
+    for (const auto &c : after) iters = std::max(iters, c.cg_it);
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    const double us = 1e3 * ms / iters;
+    if (us < best) { best = us; bc = m[0]; bg = m[1]; ctx->tune_us[2] = us; }
+  }
+  ctx->opt.cg_chunk = bc;
+  ctx->opt.use_graph = bg;
+  drop_cg_graphs(ctx);
+  if (out) fill_tuning(ctx, out);
   return BDEM_OK;
 }
 

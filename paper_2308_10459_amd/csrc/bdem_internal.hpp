@@ -24,9 +24,7 @@ namespace bdem {
 
 constexpr int TILE = 256;       // particles / bonds per scene-aligned tile
 constexpr int SPMV_ROWS = 32;     // block rows per SpMV workgroup
-constexpr int SPMV_THREADS = 256; // SpMV workgroup size (>= 6 * SPMV_ROWS)
 constexpr int SPMV_CAP = 512;     // slots staged in LDS per pass of an SpMV workgroup
-constexpr int UPD_ROWS = 64;      // block rows per CG-update workgroup (6 lanes per row)
 
 // per-scene control block, device resident; every decision of the Newton /
 // PCG / line-search loops is taken on the device from these values
@@ -112,9 +110,13 @@ void launch_count_active(const DevPtrs &d, int n_scenes, int slot, hipStream_t s
 void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
 // PCG
 void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
-void launch_spmv(const DevPtrs &d, bool mixed, hipStream_t s);
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s);
+int spmv_variants();
+void spmv_shape(int variant, int *threads, int *trips);
 void launch_cg_scalars(const DevPtrs &d, const Params &P, int slot, hipStream_t s);
-void launch_cg_update(const DevPtrs &d, bool mixed, hipStream_t s);
+void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s);
+int update_variants();
+int update_rows(int variant);
 void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s);
 
 }  // namespace bdem

@@ -158,9 +158,11 @@ __device__ __forceinline__ void load_row6(const double *h, double (&v)[6]) { loa
 // before any use, so the matrix streams through in address order; the products
 // go to LDS in passes of SPMV_CAP slots.  Phase 2: thread (row, c) adds the
 // diagonal block times u_row and its row's slot products in slot order, so the
-// sum order is fixed and results are reproducible.
-template <typename T> __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(DevPtrs d) {
-  constexpr int U = 2;   // trips per thread in flight
+// sum order is fixed and results are reproducible.  The launch shape (NT
+// threads, U trips in flight) changes neither: threads past 6 * SPMV_ROWS add
+// zeros to the dots after the row threads' waves, so every shape gives the
+// same bits.
+template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d) {
   __shared__ double prod[SPMV_CAP * 6 + 1];   // last entry absorbs clamped lanes
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int r0 = lb * SPMV_ROWS;
@@ -189,12 +191,12 @@ template <typename T> __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(Dev
   for (int cb = s0; cb < s1; cb += SPMV_CAP) {
     const int ce = min(cb + SPMV_CAP, s1);
     const int nsc = (ce - cb) * 6;
-    for (int base = 0; base < nsc; base += SPMV_THREADS * U) {
+    for (int base = 0; base < nsc; base += NT * U) {
       int sl[U], cc[U], jj[U];
       double hv[U][6], uj[U][6];
 #pragma unroll
       for (int m = 0; m < U; ++m) {   // lanes past the end repeat the last product
-        const int id = min(base + m * SPMV_THREADS + t, nsc - 1);
+        const int id = min(base + m * NT + t, nsc - 1);
         sl[m] = id / 6;
         cc[m] = id - sl[m] * 6;
       }
@@ -210,7 +212,7 @@ template <typename T> __global__ __launch_bounds__(SPMV_THREADS) void k_spmv(Dev
         double a = 0.0;
 #pragma unroll
         for (int e = 0; e < 6; ++e) a += hv[m][e] * uj[m][e];
-        prod[(base + m * SPMV_THREADS + t < nsc) ? sl[m] * 6 + cc[m] : SPMV_CAP * 6] = a;
+        prod[(base + m * NT + t < nsc) ? sl[m] * 6 + cc[m] : SPMV_CAP * 6] = a;
       }
     }
     __syncthreads();
@@ -299,9 +301,9 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P, int sl
 // p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r.
 // Thread (row, component): every vector is read and written with unit
 // stride; the new residual of the row is shared through LDS for M^-1 r.
-template <typename T> __global__ __launch_bounds__(6 * UPD_ROWS) void k_cg_update(DevPtrs d) {
-  __shared__ double rs[6 * UPD_ROWS];
-  const int r0 = blockIdx.x * UPD_ROWS;
+template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg_update(DevPtrs d) {
+  __shared__ double rs[6 * ROWS];
+  const int r0 = blockIdx.x * ROWS;
   const int scene = d.psid[r0];
   const SceneCtl &c = d.ctl[scene];
   if (!c.cg_active) return;
@@ -409,20 +411,45 @@ void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s) {
   if (mixed) k_cg_init<float><<<nb, TILE, 0, s>>>(d);
   else k_cg_init<double><<<nb, TILE, 0, s>>>(d);
 }
-void launch_spmv(const DevPtrs &d, bool mixed, hipStream_t s) {
-  static_assert(TILE % SPMV_ROWS == 0 && 6 * SPMV_ROWS <= SPMV_THREADS, "SpMV tiling");
+// launch shapes the autotuner chooses from (bitwise-identical results)
+static const int kSpmvShape[][2] = {{256, 2}, {192, 2}, {256, 1}, {256, 4}, {384, 2}, {192, 4}, {384, 1}};
+static const int kUpdateRows[] = {64, 32, 128};
+int spmv_variants() { return (int)(sizeof(kSpmvShape) / sizeof(kSpmvShape[0])); }
+int update_variants() { return (int)(sizeof(kUpdateRows) / sizeof(kUpdateRows[0])); }
+void spmv_shape(int v, int *threads, int *trips) { *threads = kSpmvShape[v][0]; *trips = kSpmvShape[v][1]; }
+int update_rows(int v) { return kUpdateRows[v]; }
+
+template <typename T> static void spmv_dispatch(const DevPtrs &d, int v, hipStream_t s) {
+  static_assert(TILE % SPMV_ROWS == 0, "SpMV tiling");
   const int nsp = d.n_pad / SPMV_ROWS;
-  if (mixed) k_spmv<float><<<nsp, SPMV_THREADS, 0, s>>>(d);
-  else k_spmv<double><<<nsp, SPMV_THREADS, 0, s>>>(d);
+  switch (v) {
+    case 1: k_spmv<T, 192, 2><<<nsp, 192, 0, s>>>(d); break;
+    case 2: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d); break;
+    case 3: k_spmv<T, 256, 4><<<nsp, 256, 0, s>>>(d); break;
+    case 4: k_spmv<T, 384, 2><<<nsp, 384, 0, s>>>(d); break;
+    case 5: k_spmv<T, 192, 4><<<nsp, 192, 0, s>>>(d); break;
+    case 6: k_spmv<T, 384, 1><<<nsp, 384, 0, s>>>(d); break;
+    default: k_spmv<T, 256, 2><<<nsp, 256, 0, s>>>(d); break;
+  }
+}
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s) {
+  if (mixed) spmv_dispatch<float>(d, variant, s);
+  else spmv_dispatch<double>(d, variant, s);
 }
 void launch_cg_scalars(const DevPtrs &d, const Params &P, int slot, hipStream_t s) {
   k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P, slot);
 }
-void launch_cg_update(const DevPtrs &d, bool mixed, hipStream_t s) {
-  static_assert(TILE % UPD_ROWS == 0, "update tiling");
-  const int nb = d.n_pad / UPD_ROWS;
-  if (mixed) k_cg_update<float><<<nb, 6 * UPD_ROWS, 0, s>>>(d);
-  else k_cg_update<double><<<nb, 6 * UPD_ROWS, 0, s>>>(d);
+template <typename T> static void update_dispatch(const DevPtrs &d, int v, hipStream_t s) {
+  static_assert(TILE % 128 == 0, "update tiling");
+  switch (v) {
+    case 1: k_cg_update<T, 32><<<d.n_pad / 32, 6 * 32, 0, s>>>(d); break;
+    case 2: k_cg_update<T, 128><<<d.n_pad / 128, 6 * 128, 0, s>>>(d); break;
+    default: k_cg_update<T, 64><<<d.n_pad / 64, 6 * 64, 0, s>>>(d); break;
+  }
+}
+void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s) {
+  if (mixed) update_dispatch<float>(d, variant, s);
+  else update_dispatch<double>(d, variant, s);
 }
 void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s) {
   k_slope_part<<<d.n_pad / TILE, TILE, 0, s>>>(d);

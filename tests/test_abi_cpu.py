@@ -44,6 +44,7 @@ def test_struct_sizes_match_header_layout(B):
     assert C.sizeof(B.bdem_options) == 8 * (3 + 3 + 1 + 1 + 2 + 4) + 4 * 7 + 4
     assert C.sizeof(B.bdem_material) == 8 * 9 + 4 * 2
     assert C.sizeof(B.bdem_step_stats) == 4 * 4 + 8 + 8 * 3 + 8 * 8
+    assert C.sizeof(B.bdem_tuning) == 4 * 6 + 8 * 3
 
 
 def test_default_options(B):

@@ -488,6 +488,42 @@ def test_bitwise_determinism_and_graph_replay(B):
             np.testing.assert_array_equal(r[k], runs[0][k])
 
 
+def test_launch_shapes_and_autotune_give_identical_bits(B):
+    """Every SpMV shape, CG-update tile and PCG polling mode produces the same
+    bits as the defaults; the autotuner picks one of them and leaves the state
+    untouched."""
+    sc, st = _perturbed_block(11, 10, 9, seed=21)
+    sim = make_sim(sc, mixed=True, **TIGHT)
+    sim.set_state(**st)
+    sim.step(1e-3)
+    ref = sim.get_state()
+    sim.set_state(**st)
+    t = sim.autotune([1e-3])
+    log(f"[autotune] {t}")
+    assert t["spmv_us"] > 0 and t["update_us"] > 0 and t["pcg_us_per_iter"] > 0
+    assert sim.get_tuning() == t
+    after = sim.get_state()
+    for k in ("pos", "quat", "vel", "qvel"):
+        assert np.array_equal(after[k], st[k]), k
+    sim.step(1e-3)
+    got = sim.get_state()
+    for k in ("pos", "quat", "vel", "qvel"):
+        assert np.array_equal(got[k], ref[k]), k
+    shapes = [(192, 2), (256, 1), (256, 2), (256, 4), (384, 2), (192, 4), (384, 1)]
+    for i, (threads, trips) in enumerate(shapes):
+        rows = (32, 64, 128)[i % 3]
+        chunk, graph = ((1, 0), (4, 1), (16, 1), (3, 0))[i % 4]
+        sim.set_state(**st)
+        sim.set_tuning(spmv_threads=threads, spmv_trips=trips, update_rows=rows, cg_chunk=chunk, use_graph=graph)
+        sim.step(1e-3)
+        got = sim.get_state()
+        for k in ("pos", "quat", "vel", "qvel"):
+            assert np.array_equal(got[k], ref[k]), (threads, trips, rows, chunk, graph, k)
+    with pytest.raises(B.BdemError):
+        sim.set_tuning(spmv_threads=200)
+    sim.close()
+
+
 def test_checkpoint_restore_is_bitwise(B):
     sc = S.make_plate_drop(nx=10, ny=10, nl=2, sigma_c=3e5, tau_c=3e5)
     a = make_sim(sc)
