@@ -615,13 +615,13 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
 }
 
 // one PCG iteration: update, SpMV with the three dots, per-scene scalars
-static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv, int slot) {
+static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   const bool mixed = ctx->S.mixed;
   launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, false);
-  launch_cg_scalars(ctx->d, ctx->P, slot, ctx->stream);
+  launch_cg_scalars(ctx->d, ctx->P, ctx->stream);
 }
 
 static void drop_cg_graphs(bdem_ctx *ctx) {
@@ -636,7 +636,7 @@ static void drop_cg_graphs(bdem_ctx *ctx) {
 static int build_cg_graphs(bdem_ctx *ctx, int chunk) {
   for (int slot = 0; slot < 2; ++slot) {
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, false, slot);
+    for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, false);
     if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, slot, ctx->stream);
     HIP_TRY(hipStreamEndCapture(ctx->stream, &ctx->cg_graph[slot]));
     HIP_TRY(hipGraphInstantiate(&ctx->cg_exec[slot], ctx->cg_graph[slot], nullptr, nullptr, 0));
@@ -652,11 +652,15 @@ static int run_pcg(bdem_ctx *ctx) {
   const bool mixed = ctx->S.mixed;
   hipStream_t st = ctx->stream;
   const size_t mark0 = ctx->ev_marks.size();
+  // poll slots: 1 while PCG runs; with one scene the scalars kernel clears
+  // both when it stops, with several the count kernel rewrites its slot
+  ctx->h_counters[1] = 1;
+  ctx->h_counters[5] = 1;
   launch_cg_init(ctx->d, mixed, st);
   if (ctx->profiling) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling) prof_mark(ctx, 1, false);
-  launch_cg_scalars(ctx->d, ctx->P, 0, st);
+  launch_cg_scalars(ctx->d, ctx->P, st);
   if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
   int rc = read_counters(ctx);
   if (rc) return rc;
@@ -674,7 +678,7 @@ static int run_pcg(bdem_ctx *ctx) {
     if (graph) {
       HIP_TRY(hipGraphLaunch(ctx->cg_exec[slot], st));
     } else {
-      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling != 0, slot);
+      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling != 0);
       if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, slot, st);
     }
     HIP_TRY(hipEventRecord(ctx->ev_slot[slot], st));

@@ -113,7 +113,7 @@ void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
 void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s);
 int spmv_variants();
 void spmv_shape(int variant, int *threads, int *trips);
-void launch_cg_scalars(const DevPtrs &d, const Params &P, int slot, hipStream_t s);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s);
 int update_variants();
 int update_rows(int variant);

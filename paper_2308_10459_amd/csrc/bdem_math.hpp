@@ -215,17 +215,42 @@ template <> struct JacobiTol<double> {
   static constexpr int max_sweeps = 16;
 };
 
+// Rotation angle of one Jacobi step: any (c, s) with c^2 + s^2 = 1 to
+// rounding is an exact orthogonal similarity, so the FP32 path takes the
+// hardware reciprocal and reciprocal square root (1 ulp) instead of the
+// correctly rounded divide and square root; FP64 keeps IEEE operations.
+template <typename T> struct JacobiAngle;
+template <> struct JacobiAngle<float> {
+  __device__ static __forceinline__ void cs(float app, float aqq, float apq, float &t, float &c) {
+    const bool act = apq != 0.0f;
+    const float theta = (aqq - app) * __builtin_amdgcn_rcpf(act ? 2.0f * apq : 1.0f);
+    const float at = fabsf(theta);
+    const float x = fmaf(theta, theta, 1.0f);
+    // 1 / (|theta| + sqrt(theta^2 + 1)); about 1 / (2 |theta|) once theta^2 overflows
+    const float t0 = at < 1e18f ? __builtin_amdgcn_rcpf(at + x * __builtin_amdgcn_rsqf(x))
+                                : 0.5f * __builtin_amdgcn_rcpf(at);
+    t = act ? (theta >= 0.0f ? t0 : -t0) : 0.0f;
+    c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.0f));
+  }
+};
+template <> struct JacobiAngle<double> {
+  __device__ static __forceinline__ void cs(double app, double aqq, double apq, double &t, double &c) {
+    const bool act = apq != 0.0;
+    const double den = act ? 2.0 * apq : 1.0;
+    const double theta = (aqq - app) / den;
+    const double at = fabs(theta);
+    const double t0 = 1.0 / (at + sqrt(theta * theta + 1.0));
+    t = act ? (theta >= 0.0 ? t0 : -t0) : 0.0;
+    c = 1.0 / sqrt(t * t + 1.0);
+  }
+};
+
 template <typename T>
 __device__ __forceinline__ void jacobi_rot(T (&A)[45], T (&V)[81], const int p, const int q) {
   const T apq = A[up9(p, q)];
   const T app = A[up9(p, p)], aqq = A[up9(q, q)];
-  const bool act = apq != T(0);
-  const T den = act ? T(2) * apq : T(1);
-  const T theta = (aqq - app) / den;
-  const T at = fabs(theta);
-  const T t0 = T(1) / (at + sqrt(theta * theta + T(1)));
-  const T t = act ? (theta >= T(0) ? t0 : -t0) : T(0);
-  const T c = T(1) / sqrt(t * t + T(1));
+  T t, c;
+  JacobiAngle<T>::cs(app, aqq, apq, t, c);
   const T s = t * c;
   A[up9(p, p)] = app - t * apq;
   A[up9(q, q)] = aqq + t * apq;

@@ -240,11 +240,14 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
 // per-scene scalars of one iteration and the stop test |r| <= eps_r |z|.
 // The partial loads do not wait for the activity flag: everything the block
 // reads is issued at once, then the three sums share one LDS round.
-__global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P, int slot) {
+__global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
   const int s = blockIdx.x;
   SceneCtl &c = d.ctl[s];
   const int b0 = d.scene_pbeg[s] / SPMV_ROWS, b1 = d.scene_pbeg[s + 1] / SPMV_ROWS;
   const int active = c.cg_active;
+  // the scalars the decision needs, fetched with the partials
+  const double rz_prev = c.rz, alpha_prev = c.alpha, cg_tol = c.cg_tol;
+  const int cg_it = c.cg_it;
   KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
   constexpr int U = 8;   // partials per thread in flight
   for (int k0 = b0; k0 < b1; k0 += U * (int)blockDim.x) {
@@ -264,38 +267,40 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P, int sl
       rr = kmerge(rr, KSum{pc[m].x, pc[m].y});
     }
   }
-  if (!active) {
-    if (gridDim.x == 1 && threadIdx.x == 0) d.counters[4 * slot + 1] = 0;
-    return;
-  }
+  // the host's poll slot holds 1 while the solve runs (set when it starts);
+  // it is written only when this scene stops
+  if (!active) return;
   block_ksum3(ru, wu, rr);
   if (threadIdx.x != 0) return;
   const double gamma = ru.s + ru.c, delta = wu.s + wu.c;
   c.rr = rr.s + rr.c;
-  bool stop = !(sqrt(c.rr) > c.cg_tol) || c.cg_it >= P.max_cg || !(gamma > 0.0);
+  bool stop = !(sqrt(c.rr) > cg_tol) || cg_it >= P.max_cg || !(gamma > 0.0);
   double alpha = 0.0, beta = 0.0;
   if (!stop) {
-    if (c.cg_it == 0) {
+    if (cg_it == 0) {
       beta = 0.0;
       alpha = gamma / delta;
       if (!(delta > 0.0)) stop = true;
     } else {
-      beta = gamma / c.rz;
-      const double den = delta - beta * gamma / c.alpha;
+      beta = gamma / rz_prev;
+      const double den = delta - beta * gamma / alpha_prev;
       alpha = gamma / den;
       if (!(den > 0.0)) stop = true;
     }
   }
   if (stop || !isfinite(alpha) || !isfinite(beta)) {   // x holds the solution of this solve
     c.cg_active = 0;
+    if (gridDim.x == 1) {
+      d.counters[1] = 0;
+      d.counters[5] = 0;
+    }
   } else {
     c.rz = gamma;
     c.alpha = alpha;
     c.beta = beta;
-    c.cg_it += 1;
+    c.cg_it = cg_it + 1;
     c.cg_total += 1;
   }
-  if (gridDim.x == 1) d.counters[4 * slot + 1] = c.cg_active;
 }
 
 // p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r.
@@ -436,8 +441,8 @@ void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s) {
   if (mixed) spmv_dispatch<float>(d, variant, s);
   else spmv_dispatch<double>(d, variant, s);
 }
-void launch_cg_scalars(const DevPtrs &d, const Params &P, int slot, hipStream_t s) {
-  k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P, slot);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s) {
+  k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P);
 }
 template <typename T> static void update_dispatch(const DevPtrs &d, int v, hipStream_t s) {
   static_assert(TILE % 128 == 0, "update tiling");
