@@ -56,7 +56,10 @@ enum {
   BDEM_E_HIP = -2,          /* HIP runtime error */
   BDEM_E_NOMEM = -3,        /* workspace too small / allocation failed */
   BDEM_E_NONFINITE = -4,    /* NaN / Inf in the state or the objective */
-  BDEM_E_DEGENERATE = -5,   /* |q_i + q_j| < 1e-6: shear frame undefined */
+  BDEM_E_DEGENERATE = -5,   /* |q_i + q_j| < 1e-6 for an alive bond at a Newton iterate: the
+                               shear midpoint is undefined.  Line-search trials there count as
+                               infinite energy and are rejected, so only a step's initial guess
+                               can end here. */
   BDEM_E_STATE = -6         /* call not valid in the handle's state */
 };
 

@@ -339,14 +339,20 @@ int orc_bond_energy_parts(const orc_sys *s, int64_t b, const double *pi, const d
   /* shear: angle between the current bond direction n and d = q_c (.) d0,
    * q_c = (q_i + q_j)/|q_i + q_j|;  1/2 k_t (l0 theta)^2 */
   double w[4] = {qi[0] + qj[0], qi[1] + qj[1], qi[2] + qj[2], qi[3] + qj[3]};
-  double wn = sqrt(dot4(w, w));
-  double qc[4] = {w[0] / wn, w[1] / wn, w[2] / wn, w[3] / wn}, d[3];
-  qrotate(qc, s->d0 + 3 * b, d);
-  double nv[3] = {u[0] / l, u[1] / l, u[2] / l};
-  double y = (nv[0] - d[0]) * (nv[0] - d[0]) + (nv[1] - d[1]) * (nv[1] - d[1]) +
-             (nv[2] - d[2]) * (nv[2] - d[2]);
-  double th = 2.0 * asin(0.5 * sqrt(y));
-  parts[1] = 0.5 * s->kt[b] * th * th;
+  if (dot4(w, w) < 1e-12) {
+    /* q_c does not exist (q_j = -q_i): outside the domain of the potential;
+     * a line-search trial here is rejected like any non-finite objective */
+    parts[1] = INFINITY;
+  } else {
+    double wn = sqrt(dot4(w, w));
+    double qc[4] = {w[0] / wn, w[1] / wn, w[2] / wn, w[3] / wn}, d[3];
+    qrotate(qc, s->d0 + 3 * b, d);
+    double nv[3] = {u[0] / l, u[1] / l, u[2] / l};
+    double y = (nv[0] - d[0]) * (nv[0] - d[0]) + (nv[1] - d[1]) * (nv[1] - d[1]) +
+               (nv[2] - d[2]) * (nv[2] - d[2]);
+    double th = 2.0 * asin(0.5 * sqrt(y));
+    parts[1] = 0.5 * s->kt[b] * th * th;
+  }
   /* bend / twist: t = R_0 G_l(q_j) q_i,  1/2 t^T K t */
   double G[12], tp[3], t[3];
   G_left(qj, G);
@@ -1020,6 +1026,24 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
   for (int32_t i = 0; i < n; ++i) {
     double nq = sqrt(dot4(qh + 4 * i, qh + 4 * i));
     for (int r = 0; r < 4; ++r) x_q[4 * i + r] = qh[4 * i + r] / nq;
+  }
+  /* an initial guess outside the domain of the potential (an alive bond with
+   * q_j = -q_i, where the shear midpoint does not exist) is replaced by the
+   * state x_n for the free particles */
+  {
+    int outside = 0;
+    for (int64_t b = 0; b < s->nb && !outside; ++b) {
+      if (!s->alive[b]) continue;
+      const double *qa = x_q + 4 * s->ij[2 * b], *qb = x_q + 4 * s->ij[2 * b + 1];
+      double w[4] = {qa[0] + qb[0], qa[1] + qb[1], qa[2] + qb[2], qa[3] + qb[3]};
+      if (dot4(w, w) < 1e-12) outside = 1;
+    }
+    if (outside)
+      for (int32_t i = 0; i < n; ++i)
+        if (s->flags[i] == 0) {
+          memcpy(x_p + 3 * i, s->pos + 3 * i, sizeof(double) * 3);
+          memcpy(x_q + 4 * i, s->quat + 4 * i, sizeof(double) * 4);
+        }
   }
   int max_cg = o->max_cg > 0 ? o->max_cg : (int)(20 * N6);
   double phi = 0.0, z0 = -1.0, last_move = 0.0, xmax = 0.0;

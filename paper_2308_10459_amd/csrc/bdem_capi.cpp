@@ -743,17 +743,22 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
   double t_eval = 0, t_cg = 0, t_ls = 0;
   HIP_TRY(hipEventRecord(ph[0], st));
   // reset the control blocks
-  for (int s = 0; s < NS; ++s) {
-    SceneCtl &c = ctx->h_ctl[s];
-    std::memset(&c, 0, sizeof(c));
-    c.dt = dts[s];
-    c.inv_dt2 = 1.0 / (dts[s] * dts[s]);
-    c.kc = ctx->scene_kc[s];
-    c.newton_active = 1;
-  }
-  HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
+  auto init_ctl = [&]() -> hipError_t {
+    for (int s = 0; s < NS; ++s) {
+      SceneCtl &c = ctx->h_ctl[s];
+      std::memset(&c, 0, sizeof(c));
+      c.dt = dts[s];
+      c.inv_dt2 = 1.0 / (dts[s] * dts[s]);
+      c.kc = ctx->scene_kc[s];
+      c.newton_active = 1;
+    }
+    hipError_t e = hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(d.degenerate, 0, sizeof(int), st);
+    return e;
+  };
+  HIP_TRY(init_ctl());
   launch_predict(d, true, st);
+  bool restarted = false;
   for (int k = 0; k <= ctx->opt.max_newton + 1; ++k) {
     HIP_TRY(hipEventRecord(ph[1], st));
     prof_mark(ctx, 0, true);
@@ -766,7 +771,18 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ph[2], st));
     t_eval += elapsed(ph[1], ph[2]);
-    if (ctx->h_counters[3] > 0) return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
+    if (ctx->h_counters[3] > 0) {
+      if (k == 0 && !restarted) {
+        // the prediction left the potential's domain: the affected scenes
+        // start from x_n (always inside), evaluated as the first iterate
+        restarted = true;
+        launch_restart_from_state(d, st);
+        HIP_TRY(init_ctl());
+        k = -1;
+        continue;
+      }
+      return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
+    }
     if (ctx->h_counters[0] == 0) break;
     rc = run_pcg(ctx);
     if (rc) return rc;

@@ -36,7 +36,8 @@ struct SceneCtl {
   double last_move, xmax;
   int newton_active, cg_active, ls_active, ls_accept;
   int newton_it, cg_it, ls_it, status;
-  int cg_total, ls_total, nonfinite, pad_;
+  int cg_total, ls_total, nonfinite;
+  int ndegen;   // alive bonds with |q_i + q_j| < 1e-6 at the last evaluated iterate
 };
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LS_FAILED = 2, ST_NONFINITE = 3 };
@@ -99,6 +100,7 @@ void launch_bond_fracture(const DevPtrs &d, hipStream_t s);
 // particle kernels
 void launch_predict(const DevPtrs &d, bool write_iterate, hipStream_t s);
 void launch_copy_state_to_iterate(const DevPtrs &d, hipStream_t s);
+void launch_restart_from_state(const DevPtrs &d, hipStream_t s);
 void launch_particle_eval(const DevPtrs &d, const Params &P, bool mixed, bool hess,
                           bool potential_only, hipStream_t s);
 void launch_ls_trial(const DevPtrs &d, const Params &P, hipStream_t s);

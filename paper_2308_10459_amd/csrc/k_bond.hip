@@ -95,7 +95,12 @@ __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
     BondGeom g;
     const double4 Qi = d.qx[i], Qj = d.qx[j];
     bond_geometry(d.px[i], Qi, d.px[j], Qj, d.brest_a[b], d.brest_b[b], g);
-    if (!(dot4(g.w, g.w) >= 1e-12)) atomicAdd(d.degenerate, 1);
+    // |q_i + q_j| < 1e-6: the shear midpoint is undefined.  A non-finite state
+    // is not counted here; the Newton check reports it as non-finite.
+    if (dot4(g.w, g.w) < 1e-12) {
+      atomicAdd(d.degenerate, 1);
+      atomicAdd(&d.ctl[scene].ndegen, 1);
+    }
     kadd(esum, bond_energy_of(g));
     // ---------------- reduced gradient (FP64) ----------------
     const double qi[4] = {Qi.x, Qi.y, Qi.z, Qi.w}, qj[4] = {Qj.x, Qj.y, Qj.z, Qj.w};
@@ -364,7 +369,9 @@ __global__ __launch_bounds__(TILE) void k_bond_energy(DevPtrs d, int trial) {
     const int2 ij = d.bij[b];
     BondGeom g;
     bond_geometry(P[ij.x], Q[ij.x], P[ij.y], Q[ij.y], d.brest_a[b], d.brest_b[b], g);
-    kadd(esum, bond_energy_of(g));
+    // q_j = -q_i leaves the shear midpoint undefined: outside the potential's
+    // domain, so the objective is infinite and the line search backtracks
+    kadd(esum, dot4(g.w, g.w) < 1e-12 ? INFINITY : bond_energy_of(g));
   }
   // bond tiles report in part_a, particle tiles in part_b (read together by
   // the line-search decision)

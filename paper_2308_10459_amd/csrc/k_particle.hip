@@ -30,6 +30,18 @@ __global__ __launch_bounds__(TILE) void k_predict(DevPtrs d, int write_iterate) 
   d.qx[r] = (f == 0) ? make_double4(qh.x * inv, qh.y * inv, qh.z * inv, qh.w * inv) : q;
 }
 
+// Initial guess outside the potential's domain (an alive bond with
+// q_j = -q_i at the prediction): the free particles of that scene start the
+// Newton iteration from x_n instead; kinematic and fixed particles keep
+// their prescribed positions.
+__global__ __launch_bounds__(TILE) void k_restart_from_state(DevPtrs d) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  if (d.ctl[d.psid[blockIdx.x * TILE]].ndegen == 0) return;   // uniform over the tile
+  if (d.flags[r] != 0) return;
+  d.px[r] = d.pn[r];
+  d.qx[r] = d.qn[r];
+}
+
 __global__ __launch_bounds__(TILE) void k_copy_state(DevPtrs d) {
   const int r = blockIdx.x * TILE + threadIdx.x;
   d.px[r] = d.pn[r];
@@ -275,6 +287,10 @@ __global__ __launch_bounds__(TILE) void k_finish(DevPtrs d) {
 void launch_predict(const DevPtrs &d, bool write_iterate, hipStream_t s) {
   k_predict<<<d.n_pad / TILE, TILE, 0, s>>>(d, write_iterate ? 1 : 0);
 }
+void launch_restart_from_state(const DevPtrs &d, hipStream_t s) {
+  k_restart_from_state<<<d.n_pad / TILE, TILE, 0, s>>>(d);
+}
+
 void launch_copy_state_to_iterate(const DevPtrs &d, hipStream_t s) {
   k_copy_state<<<d.n_pad / TILE, TILE, 0, s>>>(d);
 }

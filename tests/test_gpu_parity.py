@@ -214,7 +214,7 @@ def test_line_search_energy_matches_objective(B, capfd, monkeypatch):
 def test_step_sheet_kinematic_edges(B):
     """A one-layer sheet pulled apart by kinematic edge columns (no gravity)."""
     log("[step sheet]")
-    sc = S.make_textile(nx=14, ny=9, sigma_c=0.0, tau_c=0.0, dt=5e-4)
+    sc = S.make_textile(nx=14, ny=9, sigma_c=0.0, tau_c=0.0, dt=5e-4, notch=0.0)
     o = oracle_for(sc)
     sim = make_sim(sc, **TIGHT)
     prev = o.get_state()
@@ -232,6 +232,48 @@ def test_step_sheet_kinematic_edges(B):
         kin = sc.flags == S.KINEMATIC
         np.testing.assert_array_equal(got["pos"][kin], ref["pos"][kin])
         prev = ref
+    sim.close()
+
+
+def test_prediction_outside_the_domain_restarts_from_the_state(B):
+    """The prediction q_hat = q + dt qdot puts a bonded pair at q_j = -q_i,
+    where the shear midpoint is undefined: the Newton iteration starts from
+    x_n instead (oracle and GPU alike).  With no Newton iteration allowed the
+    step returns that initial guess, so both must return x_n (not the
+    prediction) and agree on the gradient there.  (Beyond that the step is
+    ill-posed: the 4-vector inertia term then pulls j towards the antipode of
+    its neighbour, the same rotation, and cancels i's inertia along the pair's
+    common rotation.)  A state that is itself there cannot be stepped."""
+    sc = S.make_pair(young=1e9)
+    dt = 1e-3
+    q = np.array([0.02, -0.03, 0.05, 1.0]); q /= np.linalg.norm(q)
+    qj = q + np.array([0.01, 0.0, -0.01, 0.0]); qj /= np.linalg.norm(qj)
+    quat = np.stack([q, qj])
+    qvel = np.zeros((2, 4)); qvel[1] = (-q - qj) / dt          # q_hat_j = -q_i
+    vel = np.zeros((2, 3)); vel[1] = [1e-3, 0, 0]
+    st = dict(pos=sc.pos.copy(), quat=quat, vel=vel, qvel=qvel)
+    o = oracle_for(sc, st)
+    so = o.step(dt, max_newton=0)
+    sim = make_sim(sc, max_newton=0)
+    sim.set_state(**st)
+    sg = sim.step(dt)
+    ref, got = o.get_state(), sim.get_state()
+    log(f"[restart] gpu rc {sg['rc']} grad0 {sg['grad0']:.6e} | oracle grad0 {so['grad0']:.6e}")
+    for r in (ref, got):
+        np.testing.assert_array_equal(r["pos"], st["pos"])
+        np.testing.assert_array_equal(r["quat"], st["quat"])
+    assert abs(sg["grad0"] - so["grad0"]) <= 1e-10 * so["grad0"]
+    # the same pair with a regular prediction starts from the prediction
+    qvel2 = np.zeros((2, 4)); qvel2[1] = 1e-2 * (qj - q) / dt
+    st2 = dict(st, qvel=qvel2)
+    sim.set_state(**st2)
+    sim.step(dt)
+    assert not np.array_equal(sim.get_state()["quat"], st["quat"])
+    # a state at q_j = -q_i with zero rates: the prediction is the state itself
+    sim.set_state(quat=np.stack([q, -q]), qvel=np.zeros((2, 4)), vel=np.zeros((2, 3)))
+    with pytest.raises(B.BdemError) as e:
+        sim.step(dt)
+    assert e.value.code == B.BDEM_E_DEGENERATE
     sim.close()
 
 

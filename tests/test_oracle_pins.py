@@ -204,6 +204,24 @@ def test_euclidean_derivatives_central_fd(oracle_mod, axis, shear_mode):
         np.testing.assert_allclose(H, H.T, rtol=0, atol=1e-9 * np.abs(H).max())
 
 
+def test_opposite_quaternions_are_outside_the_domain(oracle_mod):
+    """q_j = -q_i leaves the shear midpoint (q_i + q_j)/|q_i + q_j| undefined:
+    the shear energy is infinite there (a line search backtracks), while the
+    stretch and the bend/twist parts stay finite (the bend/twist vector
+    vec(conj(q_j) q_i) only changes sign)."""
+    sc = S.make_pair()
+    o = oracle_mod.Oracle(sc)
+    q = np.array([0.1, -0.2, 0.3, 0.9]); q /= np.linalg.norm(q)
+    parts = o.bond_energy_parts(0, sc.pos[0], q, sc.pos[1], -q)
+    assert np.isinf(parts[1]) and parts[1] > 0
+    assert np.isfinite(parts[0]) and np.isfinite(parts[2])
+    ref = o.bond_energy_parts(0, sc.pos[0], q, sc.pos[1], q)
+    assert parts[2] == pytest.approx(ref[2], rel=1e-14, abs=1e-300)
+    # just inside the domain the energy is finite
+    qn = -q + 1e-4 * np.array([1.0, 0, 0, 0]); qn /= np.linalg.norm(qn)
+    assert np.isfinite(o.bond_energy_parts(0, sc.pos[0], q, sc.pos[1], qn)[1])
+
+
 def test_theta_series_branch_continuity(oracle_mod):
     """The shear energy is smooth across the series / closed-form switch of
     theta^2(y): gradient FD stays consistent for states with y near 0.1."""
