@@ -212,11 +212,14 @@ def _plate(name, nx, ny, nl, r, seed, young, density, v0, sigma_c, tau_c, dt, st
     return _scene(name, pos, r, ij, mats, vel=vel, k_contact=-1.0, dt=dt, steps=steps)
 
 
-def make_plate_drop(nx=128, ny=128, nl=2, seed=2, sigma_c=2e6, tau_c=2e6, dt=1e-3,
+def make_plate_drop(nx=128, ny=128, nl=2, seed=2, sigma_c=6.5e4, tau_c=2.0e4, dt=1e-3,
                     steps=100):
     """Close-packed plate, 128x128x2 (32768 particles), r = 2.5 mm, 1 % jitter,
     12-nearest-neighbour bond union, E = 1e9, dropping at 5 m/s onto the ground
-    plane with penalty contact, bond breaking by stress thresholds."""
+    plane with penalty contact, bond breaking by stress thresholds.  The
+    thresholds sit near the 95th percentiles of the oracle's bond stresses
+    after the impact step (sigma: 6.2e4, tau: 1.9e4 Pa), so a few percent of
+    the bonds break on impact."""
     return _plate(f"plate_drop_{nx}x{ny}x{nl}", nx, ny, nl, 2.5e-3, seed, 1e9, 1000.0,
                   5.0, sigma_c, tau_c, dt, steps)
 
