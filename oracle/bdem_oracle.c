@@ -1046,7 +1046,8 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
         }
   }
   int max_cg = o->max_cg > 0 ? o->max_cg : (int)(20 * N6);
-  double phi = 0.0, z0 = -1.0, last_move = 0.0, xmax = 0.0;
+  double phi = 0.0, z0 = -1.0, last_move = 0.0, xmax = 0.0, z_prev = 0.0;
+  int unresolved = 0, stall = 0;
   for (int k = 0;; ++k) {
     orc_energy_grad_hess(s, dt, x_p, x_q, 1, &phi, z, hdiag, hoff);
     double zn = sqrt(vdot(z, z, N6));
@@ -1057,6 +1058,13 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
     if (zn <= tol) break;
     /* rounding floor: the last accepted step no longer moved the state */
     if (k > 0 && last_move <= 1e-14 * (1.0 + xmax)) break;
+    /* rounding floor: three accepted steps in a row whose predicted decrease
+     * the objective cannot resolve, without halving the gradient */
+    if (k > 0) {
+      stall = (unresolved && zn > 0.5 * z_prev) ? stall + 1 : 0;
+      if (stall >= 3) break;
+    }
+    z_prev = zn;
     if (k >= o->max_newton) { status = 1; break; }
     /* solve (Hess' f) dx = -grad f in the reduced tangent space */
     for (size_t a = 0; a < N6; ++a) rhs[a] = -z[a];
@@ -1087,6 +1095,7 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
       S.ls_backtracks++;
     }
     if (!accepted) { status = 2; break; }
+    unresolved = -alpha * slope <= 1e-15 * fabs(phi);
     xmax = 0.0;
     for (size_t a = 0; a < 3 * (size_t)n; ++a) {
       double m = fabs(t_p[a] - x_p[a]);

@@ -38,6 +38,8 @@ struct SceneCtl {
   int newton_it, cg_it, ls_it, status;
   int cg_total, ls_total, nonfinite;
   int ndegen;   // alive bonds with |q_i + q_j| < 1e-6 at the last evaluated iterate
+  int unresolved, stall;   // rounding-floor detection (see k_newton_check)
+  double gnorm_prev;
 };
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LS_FAILED = 2, ST_NONFINITE = 3 };

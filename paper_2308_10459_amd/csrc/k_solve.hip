@@ -56,6 +56,13 @@ __global__ void k_newton_check(DevPtrs d, Params P, int first) {
   bool stop = gn <= tol;
   // rounding floor: the last accepted step no longer moved the state
   if (!first && c.last_move <= 1e-14 * (1.0 + c.xmax)) stop = true;
+  // rounding floor: three accepted steps in a row whose predicted decrease
+  // the objective cannot resolve, without halving the gradient
+  if (!first) {
+    c.stall = (c.unresolved && gn > 0.5 * c.gnorm_prev) ? c.stall + 1 : 0;
+    if (c.stall >= 3) stop = true;
+  }
+  c.gnorm_prev = gn;
   if (!stop && c.newton_it >= P.max_newton) { stop = true; c.status = ST_NOT_CONVERGED; }
   if (stop) { c.newton_active = 0; c.cg_active = 0; return; }
   c.cg_tol = fmin(P.cg_rtol_max, sqrt(gn)) * gn;
@@ -386,6 +393,7 @@ __global__ void k_ls_decide(DevPtrs d, Params P) {
   if (isfinite(phit) && phit <= c.phi + P.armijo_c * c.alpha_ls * c.slope) {
     c.ls_accept = 1;
     c.ls_active = 0;
+    c.unresolved = -c.alpha_ls * c.slope <= 1e-15 * fabs(c.phi);
     c.newton_it += 1;
     c.last_move = mv;
     c.xmax = xm;
