@@ -1002,6 +1002,8 @@ void orc_default_options(orc_options *o) {
   o->max_cg = 0; /* 0: 20 * 6n */
   o->max_ls = 30;
   o->break_bonds = 1;
+  o->first_order = 0;
+  o->pad_ = 0;
 }
 
 int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
@@ -1047,9 +1049,13 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
   }
   int max_cg = o->max_cg > 0 ? o->max_cg : (int)(20 * N6);
   double phi = 0.0, z0 = -1.0, last_move = 0.0, xmax = 0.0, z_prev = 0.0;
+  double alpha_prev = 0.5;   /* first-order: the first search starts at alpha = 1 */
   int unresolved = 0, stall = 0;
   for (int k = 0;; ++k) {
-    orc_energy_grad_hess(s, dt, x_p, x_q, 1, &phi, z, hdiag, hoff);
+    if (o->first_order)
+      orc_energy_grad_hess(s, dt, x_p, x_q, 1, &phi, z, NULL, NULL);
+    else
+      orc_energy_grad_hess(s, dt, x_p, x_q, 1, &phi, z, hdiag, hoff);
     double zn = sqrt(vdot(z, z, N6));
     if (k == 0) { z0 = zn; S.grad0 = zn; }
     S.grad_final = zn;
@@ -1066,11 +1072,18 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
     }
     z_prev = zn;
     if (k >= o->max_newton) { status = 1; break; }
-    /* solve (Hess' f) dx = -grad f in the reduced tangent space */
-    for (size_t a = 0; a < N6; ++a) rhs[a] = -z[a];
-    double res;
-    int it = orc_pcg(s, hdiag, hoff, rhs, o->cg_rtol, max_cg, y, &res);
-    S.cg_iters += it >= 0 ? it : -it;
+    if (o->first_order) {
+      /* Algorithm 1: descend along -grad f.  In the reduced coordinates
+       * (dp, y) with dq = G_l(q)^T y the rows of G_l are orthonormal, so
+       * -grad f is y = -z (Section 4.1) */
+      for (size_t a = 0; a < N6; ++a) y[a] = -z[a];
+    } else {
+      /* solve (Hess' f) dx = -grad f in the reduced tangent space */
+      for (size_t a = 0; a < N6; ++a) rhs[a] = -z[a];
+      double res;
+      int it = orc_pcg(s, hdiag, hoff, rhs, o->cg_rtol, max_cg, y, &res);
+      S.cg_iters += it >= 0 ? it : -it;
+    }
     double slope = vdot(z, y, N6);
     if (!(slope < 0.0)) { status = 2; break; }
     /* direction: dp = y_p, dq = G_l(q)^T y_q */
@@ -1079,8 +1092,9 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
       G_left(x_q + 4 * i, G);
       mtm(3, 4, 1, G, y + 6 * i + 3, dq + 4 * i);
     }
-    /* backtracking Armijo line search along the manifold */
-    double alpha = 1.0;
+    /* backtracking Armijo line search along the manifold; the first-order
+     * search starts at twice the last accepted step (at most 1) */
+    double alpha = o->first_order ? fmin(1.0, 2.0 * alpha_prev) : 1.0;
     int accepted = 0;
     double max_move = 0.0;
     for (int ls = 0; ls <= o->max_ls; ++ls) {
@@ -1095,6 +1109,7 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
       S.ls_backtracks++;
     }
     if (!accepted) { status = 2; break; }
+    alpha_prev = alpha;
     unresolved = -alpha * slope <= 1e-15 * fabs(phi);
     xmax = 0.0;
     for (size_t a = 0; a < 3 * (size_t)n; ++a) {

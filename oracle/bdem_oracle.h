@@ -102,6 +102,8 @@ typedef struct {
   double cg_rtol;            /* linear solve relative tolerance */
   double armijo_c;
   int32_t max_newton, max_cg, max_ls, break_bonds;
+  int32_t first_order;       /* 1: Algorithm 1 (Riemannian gradient descent) instead of Algorithm 2 */
+  int32_t pad_;
 } orc_options;
 
 typedef struct {
@@ -111,7 +113,8 @@ typedef struct {
 } orc_stats;
 
 void orc_default_options(orc_options *o);
-/* one implicit time step (Algorithm 3 with Algorithm 2 inside) */
+/* one implicit time step (Algorithm 3 with Algorithm 2 inside, or with
+ * Algorithm 1 when first_order is set) */
 int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st);
 /* stress test of every alive bond at the current state; breaks are permanent */
 int orc_break_bonds(orc_sys *s, int64_t *n_broken);

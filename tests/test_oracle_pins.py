@@ -632,3 +632,83 @@ def test_step_matches_independent_minimiser(oracle_mod):
     assert st["rc"] == 0
     np.testing.assert_allclose(pos, got["pos"], rtol=0, atol=1e-5 * disp)
     np.testing.assert_allclose(quat, got["quat"], rtol=0, atol=1e-5)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1: first-order manifold optimisation as the step's solver
+# --------------------------------------------------------------------------
+
+def _soft_block(seed=2):
+    sc = S.make_block(nx=3, ny=3, nz=3, young=1e5, rot_angle=0.05, seed=seed)
+    pos, quat, vel, qvel = S.perturb_state(sc, seed, 1e-3, 0.05, vel_scale=0.05, qvel_scale=0.5)
+    return sc, dict(pos=pos, quat=quat, vel=vel, qvel=qvel)
+
+
+def test_first_order_iteration_is_a_retracted_gradient_step(oracle_mod):
+    """One iteration of Algorithm 1 moves p by -alpha grad_p f and q along the
+    great circle of Section 4.1 in the direction -(I - q q^T) grad_q F, with
+    alpha = 2^-k the first halving from 1 that satisfies the Armijo test."""
+    sc, st = _soft_block()
+    dt = sc.dt
+    o = oracle_mod.Oracle(sc)
+    o.set_state(**st)
+    ref = oracle_mod.Oracle(sc)       # never stepped: energies at this step's prediction
+    ref.set_state(**st)
+    # the first iterate is the normalised prediction
+    ph, qh = o.predict(dt)
+    x0q = qh / np.linalg.norm(qh, axis=1, keepdims=True)
+    free = sc.flags == 0
+    x0p = np.where(free[:, None], ph, st["pos"])
+    x0q = np.where(free[:, None], x0q, st["quat"])
+    phi0, z, _, _ = o.energy_grad_hess(dt, x0p, x0q, hess=False)
+    o.step(dt, first_order=1, max_newton=1, break_bonds=0)
+    got = o.get_state()
+    slope = -np.sum(z * z)
+    found = None
+    for k in range(31):
+        a = 2.0 ** -k
+        tp = x0p - a * z[:, :3]
+        tq = np.empty_like(x0q)
+        for i in range(sc.n):
+            _, _, G = oracle_mod.quat_matrices(x0q[i])
+            d = -G.T @ z[i, 3:]                     # -(I - q q^T) grad_q F
+            t = np.linalg.norm(a * d)
+            tq[i] = x0q[i] * np.cos(t) + (a * d / t) * np.sin(t) if t > 0 else x0q[i]
+            tq[i] /= np.linalg.norm(tq[i])
+        if np.abs(tp - got["pos"]).max() <= 1e-13 and np.abs(tq - got["quat"]).max() <= 1e-13:
+            found = (k, a, tp, tq)
+            break
+    assert found is not None
+    k, a, tp, tq = found
+    assert ref.energy(dt, tp, tq) <= phi0 + 1e-4 * a * slope
+    if k > 0:   # the step before it failed the test
+        tp2 = x0p - 2 * a * z[:, :3]
+        tq2 = np.array([oracle_mod.quat_exp_step(x0q[i], -(oracle_mod.quat_matrices(x0q[i])[2].T @ z[i, 3:]),
+                                                 2 * a) for i in range(sc.n)])
+        assert not ref.energy(dt, tp2, tq2) <= phi0 + 1e-4 * 2 * a * slope
+
+
+def test_first_order_reaches_the_second_order_fixed_point(oracle_mod):
+    """Algorithm 1 and Algorithm 2 minimise the same incremental potential:
+    run to a tight gradient tolerance they stop at the same state (within
+    |grad f| / lambda_min, the first-order stop criterion's own accuracy).
+    A chain of r = 0.5 m spheres keeps the rotational and translational
+    scales comparable, so steepest descent converges in hundreds of steps."""
+    sc = S.make_chain(n=5, spacing=1.0, r=0.5, young=1e7, gravity=(0.0, 0.0, -9.81))
+    sc.flags[0] = S.FIXED
+    pos, quat, vel, qvel = S.perturb_state(sc, 3, 0.02, 0.1, vel_scale=0.3, qvel_scale=0.5)
+    st = dict(pos=pos, quat=quat, vel=vel, qvel=qvel)
+    dt = 1e-2
+    a = oracle_mod.Oracle(sc); a.set_state(**st)
+    sa = a.step(dt, tol_rel=1e-13, break_bonds=0)
+    b = oracle_mod.Oracle(sc); b.set_state(**st)
+    sb = b.step(dt, first_order=1, tol_rel=1e-10, max_newton=200000, break_bonds=0)
+    assert sa["rc"] == 0 and sb["rc"] == 0 and sb["cg_iters"] == 0
+    assert sb["newton_iters"] > 10 * sa["newton_iters"]
+    ra, rb = a.get_state(), b.get_state()
+    # inertia bounds the reduced Hessian from below by min(m, c) / dt^2
+    m = 1000.0 * 4.0 / 3.0 * np.pi * 0.5 ** 3
+    lam = min(m, 1.6 * m * 0.25) / dt ** 2
+    bound = 10 * sb["grad_final"] / lam
+    assert np.abs(rb["pos"] - ra["pos"]).max() <= bound
+    assert np.abs(rb["quat"] - ra["quat"]).max() <= bound
