@@ -118,6 +118,10 @@ typedef struct {
   int32_t break_each_step; /* apply the fracture test at the end of every step */
   int32_t cg_chunk;        /* PCG iterations between host convergence checks */
   int32_t use_graph;       /* replay the PCG chunk as a captured HIP graph */
+  int32_t solver;          /* BDEM_SOLVER_NEWTON: Algorithm 2 (default); BDEM_SOLVER_FIRST_ORDER:
+                              Algorithm 1, steepest descent along -grad f with the same retraction
+                              and line search (its search starts at twice the last accepted step,
+                              at most 1); max_newton then caps its iterations */
 } bdem_options;
 
 typedef struct {
@@ -140,6 +144,8 @@ typedef struct {
   int32_t pad_;
   double spmv_us, update_us, pcg_us_per_iter; /* times measured by bdem_autotune (0: not tuned) */
 } bdem_tuning;
+
+enum { BDEM_SOLVER_NEWTON = 0, BDEM_SOLVER_FIRST_ORDER = 1 };
 
 /* Defaults: gravity (0,0,-9.81), no ground, newton_tol 0, newton_rtol 1e-8,
  * armijo_c 1e-4, cg_rtol_max 0.5, max_newton 50, max_cg 2000, max_ls 30,

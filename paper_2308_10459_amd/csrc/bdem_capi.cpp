@@ -200,6 +200,7 @@ extern "C" void bdem_default_options(bdem_options *o) {
   o->break_each_step = 1;
   o->cg_chunk = 16;
   o->use_graph = 0;
+  o->solver = BDEM_SOLVER_NEWTON;
 }
 
 extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
@@ -269,6 +270,8 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     return fail(nullptr, BDEM_E_INVALID, "unknown precision");
   if (o.mu_s != 0.0 || o.mu_r != 0.0)
     return fail(nullptr, BDEM_E_INVALID, "friction is not implemented (mu_s = mu_r = 0 required)");
+  if (o.solver != BDEM_SOLVER_NEWTON && o.solver != BDEM_SOLVER_FIRST_ORDER)
+    return fail(nullptr, BDEM_E_INVALID, "solver must be BDEM_SOLVER_NEWTON or BDEM_SOLVER_FIRST_ORDER");
   if (o.max_newton < 0 || o.max_cg <= 0 || o.max_ls < 0 || o.cg_chunk <= 0)
     return fail(nullptr, BDEM_E_INVALID, "bad iteration limits");
   // ---- validation ----
@@ -515,6 +518,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   P.max_cg = o.max_cg;
   P.max_ls = o.max_ls;
   P.n_scenes = NS;
+  P.first_order = o.solver == BDEM_SOLVER_FIRST_ORDER ? 1 : 0;
   // ---- upload ----
   hipStream_t st = ctx->stream;
   auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
@@ -761,10 +765,11 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
   bool restarted = false;
   for (int k = 0; k <= ctx->opt.max_newton + 1; ++k) {
     HIP_TRY(hipEventRecord(ph[1], st));
+    const bool hess = !ctx->P.first_order;   // Algorithm 1 needs the gradient only
     prof_mark(ctx, 0, true);
-    launch_bond_eval(d, mixed, true, true, st);
+    launch_bond_eval(d, mixed, true, hess, st);
     prof_mark(ctx, 0, false);
-    launch_particle_eval(d, ctx->P, mixed, true, false, st);
+    launch_particle_eval(d, ctx->P, mixed, hess, false, st);
     launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, st);
     launch_count_active(d, NS, 0, st);
     int rc = read_counters(ctx);
@@ -784,9 +789,13 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
       return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
     }
     if (ctx->h_counters[0] == 0) break;
-    rc = run_pcg(ctx);
-    if (rc) return rc;
-    launch_cg_slope(d, NS, st);
+    if (ctx->P.first_order) {
+      launch_steepest(d, st);
+    } else {
+      rc = run_pcg(ctx);
+      if (rc) return rc;
+    }
+    launch_cg_slope(d, ctx->P, st);
     HIP_TRY(hipEventRecord(ph[3], st));
     rc = run_line_search(ctx);
     if (rc) return rc;

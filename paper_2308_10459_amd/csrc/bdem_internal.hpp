@@ -40,6 +40,7 @@ struct SceneCtl {
   int ndegen;   // alive bonds with |q_i + q_j| < 1e-6 at the last evaluated iterate
   int unresolved, stall;   // rounding-floor detection (see k_newton_check)
   double gnorm_prev;
+  double alpha_prev;       // last accepted line-search step
 };
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LS_FAILED = 2, ST_NONFINITE = 3 };
@@ -51,6 +52,7 @@ struct Params {
   double newton_tol, newton_rtol, armijo_c, cg_rtol_max;
   int max_newton, max_cg, max_ls;
   int n_scenes;
+  int first_order;   // Algorithm 1 instead of Algorithm 2
 };
 
 struct DevPtrs {
@@ -121,6 +123,7 @@ void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s);
 int update_variants();
 int update_rows(int variant);
-void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s);
+void launch_cg_slope(const DevPtrs &d, const Params &P, hipStream_t s);
+void launch_steepest(const DevPtrs &d, hipStream_t s);
 
 }  // namespace bdem

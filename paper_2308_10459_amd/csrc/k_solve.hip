@@ -356,7 +356,19 @@ __global__ __launch_bounds__(TILE) void k_slope_part(DevPtrs d) {
   if (threadIdx.x == 0) d.part_a[blockIdx.x] = make_double2(t.s, t.c);
 }
 
-__global__ void k_slope(DevPtrs d) {
+// Algorithm 1 direction: -grad f.  In the reduced coordinates (dp, y) with
+// dq = G_l(q)^T y the rows of G_l are orthonormal, so -grad f is x = -z.
+__global__ __launch_bounds__(TILE) void k_steepest(DevPtrs d) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  if (!d.ctl[d.psid[blockIdx.x * TILE]].newton_active) return;
+  double z[6];
+  load6(d.z + (size_t)r * 6, z);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) z[k] = -z[k];
+  store6(d.cx + (size_t)r * 6, z);
+}
+
+__global__ void k_slope(DevPtrs d, Params P) {
   const int s = blockIdx.x;
   SceneCtl &c = d.ctl[s];
   if (!c.newton_active) return;
@@ -364,7 +376,8 @@ __global__ void k_slope(DevPtrs d) {
   const KSum a = range_ksum(d.part_a, pb, pe);
   if (threadIdx.x != 0) return;
   c.slope = a.s + a.c;
-  c.alpha_ls = 1.0;
+  // first-order search: from twice the last accepted step (1 on the first)
+  c.alpha_ls = P.first_order ? fmin(1.0, 2.0 * (c.newton_it == 0 ? 0.5 : c.alpha_prev)) : 1.0;
   c.ls_it = 0;
   c.ls_accept = 0;
   if (!(c.slope < 0.0)) {   // not a descent direction: nothing more to gain
@@ -394,6 +407,7 @@ __global__ void k_ls_decide(DevPtrs d, Params P) {
     c.ls_accept = 1;
     c.ls_active = 0;
     c.unresolved = -c.alpha_ls * c.slope <= 1e-15 * fabs(c.phi);
+    c.alpha_prev = c.alpha_ls;
     c.newton_it += 1;
     c.last_move = mv;
     c.xmax = xm;
@@ -464,9 +478,12 @@ void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s) 
   if (mixed) update_dispatch<float>(d, variant, s);
   else update_dispatch<double>(d, variant, s);
 }
-void launch_cg_slope(const DevPtrs &d, int n_scenes, hipStream_t s) {
+void launch_cg_slope(const DevPtrs &d, const Params &P, hipStream_t s) {
   k_slope_part<<<d.n_pad / TILE, TILE, 0, s>>>(d);
-  k_slope<<<n_scenes, 256, 0, s>>>(d);
+  k_slope<<<P.n_scenes, 256, 0, s>>>(d, P);
+}
+void launch_steepest(const DevPtrs &d, hipStream_t s) {
+  k_steepest<<<d.n_pad / TILE, TILE, 0, s>>>(d);
 }
 void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s) {
   k_ls_decide<<<P.n_scenes, 256, 0, s>>>(d, P);

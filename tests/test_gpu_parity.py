@@ -277,6 +277,54 @@ def test_prediction_outside_the_domain_restarts_from_the_state(B):
     sim.close()
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("iters", [1, 5])
+def test_first_order_iterations_match_oracle(B, mixed, iters):
+    """Algorithm 1 (steepest descent along -grad f, exp-map retraction, Armijo
+    search warm-started at twice the last step): the first iterations of a
+    step on both sides take the same steps (the gradient is FP64 on both
+    paths, so the mixed path has no Hessian to differ in)."""
+    sc, st = _perturbed_block(ground=True)
+    o = oracle_for(sc, st)
+    so = o.step(sc.dt, first_order=1, max_newton=iters, break_bonds=0)
+    sim = make_sim(sc, mixed=mixed, solver=B.BDEM_SOLVER_FIRST_ORDER, max_newton=iters,
+                   break_each_step=0)
+    sim.set_state(**st)
+    sg = sim.step(sc.dt)
+    log(f"[first order x{iters}] gpu ls {sg['ls_backtracks']} cg {sg['cg_iters']} | oracle ls {so['ls_backtracks']}")
+    assert sg["cg_iters"] == 0 and sg["newton_iters"] == iters and sg["ls_backtracks"] == so["ls_backtracks"]
+    got, ref = sim.get_state(), o.get_state()
+    disp = np.abs(ref["pos"] - st["pos"]).max()
+    assert np.abs(got["pos"] - ref["pos"]).max() <= 1e-12 * disp
+    assert np.abs(got["quat"] - ref["quat"]).max() <= 1e-13
+    sim.close()
+
+
+def test_first_order_step_reaches_the_newton_fixed_point(B):
+    """A first-order step run to a tight gradient tolerance stops at the
+    second-order fixed point (oracle), within |grad f| / lambda_min."""
+    sc = S.make_chain(n=5, spacing=1.0, r=0.5, young=1e7, gravity=(0.0, 0.0, -9.81))
+    sc.flags[0] = S.FIXED
+    pos, quat, vel, qvel = S.perturb_state(sc, 3, 0.02, 0.1, vel_scale=0.3, qvel_scale=0.5)
+    st = dict(pos=pos, quat=quat, vel=vel, qvel=qvel)
+    dt = 1e-2
+    o = oracle_for(sc, st)
+    o.step(dt, tol_rel=1e-13, break_bonds=0)
+    ref = o.get_state()
+    sim = make_sim(sc, solver=B.BDEM_SOLVER_FIRST_ORDER, newton_rtol=1e-10, max_newton=200000)
+    sim.set_state(**st)
+    sg = sim.step(dt)
+    got = sim.get_state()
+    m = 1000.0 * 4.0 / 3.0 * np.pi * 0.5 ** 3
+    bound = 10 * sg["grad_final"] / (min(m, 0.4 * m) / dt ** 2)
+    log(f"[first order converged] iterations {sg['newton_iters']} grad {sg['grad0']:.3e} -> "
+        f"{sg['grad_final']:.3e}; pos err {np.abs(got['pos'] - ref['pos']).max():.2e} (bound {bound:.1e})")
+    assert sg["rc"] == 0 and sg["newton_iters"] > 50
+    assert np.abs(got["pos"] - ref["pos"]).max() <= bound
+    assert np.abs(got["quat"] - ref["quat"]).max() <= bound
+    sim.close()
+
+
 def test_step_without_bonds_is_free_fall(B):
     sc = S.make_pair(gravity=(0.0, 0.0, -9.81))
     sc.ij = np.zeros((0, 2), dtype=np.int32)
