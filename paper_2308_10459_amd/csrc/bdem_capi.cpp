@@ -59,7 +59,7 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.flags), np);
   L.add(reinterpret_cast<void **>(&d.psid), np * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.row_ptr), (np + 1) * sizeof(int));
-  L.add(reinterpret_cast<void **>(&d.slot), ns * sizeof(int2));
+  L.add(reinterpret_cast<void **>(&d.col), ns * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.bij), std::max<size_t>(nbp, 1) * sizeof(int2));
   for (double4 **p : {&d.brest_a, &d.brest_b, &d.brest_c})
     L.add(reinterpret_cast<void **>(p), std::max<size_t>(nbp, 1) * sizeof(double4));
@@ -455,14 +455,14 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     adj[h_bij[bi].x].push_back({h_bij[bi].y, 2 * bi});
     adj[h_bij[bi].y].push_back({h_bij[bi].x, 2 * bi + 1});
   }
-  std::vector<int2> h_slot(std::max(S.n_slots, 1), make_int2(0, 0));
+  std::vector<int> h_col(std::max(S.n_slots, 1), 0);
   ctx->bslot_h.assign(std::max(NB, 1), make_int2(-1, -1));
   for (int r = 0; r < NP; ++r) {
     std::sort(adj[r].begin(), adj[r].end());
     for (size_t k = 0; k < adj[r].size(); ++k) {
       const int slot = rp[r] + (int)k;
       const int bi = adj[r][k].second >> 1, end = adj[r][k].second & 1;
-      h_slot[slot] = make_int2(adj[r][k].first, 2 * bi + end);
+      h_col[slot] = adj[r][k].first;
       if (end == 0) ctx->bslot_h[bi].x = slot;
       else ctx->bslot_h[bi].y = slot;
     }
@@ -534,7 +534,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(up(d.flags, h_flags.data(), NP));
   chk(up(d.psid, h_psid.data(), NP * sizeof(int)));
   chk(up(d.row_ptr, rp.data(), (NP + 1) * sizeof(int)));
-  chk(up(d.slot, h_slot.data(), h_slot.size() * sizeof(int2)));
+  chk(up(d.col, h_col.data(), h_col.size() * sizeof(int)));
   chk(up(d.bij, h_bij.data(), h_bij.size() * sizeof(int2)));
   chk(up(d.brest_a, h_ra.data(), h_ra.size() * sizeof(double4)));
   chk(up(d.brest_b, h_rb.data(), h_rb.size() * sizeof(double4)));

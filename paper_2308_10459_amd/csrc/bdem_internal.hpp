@@ -8,7 +8,7 @@
 //               uint8 flags; int scene id.
 //   bonds     : int2 (i, j);  double4 (d0, l0);  double4 (k_n, k_t L^2,
 //               GJ/l0, EI/l0);  double4 (S, r0/I, r0/J, tension_only);
-//               double2 (sigma_c, tau_c); uint8 alive; int2 slot (row i, row j).
+//               double2 (sigma_c, tau_c); uint8 alive; int2 slot of the bond in rows i and j.
 //   Hessian   : diagonal blocks, 21 packed values per particle (T);
 //               off-diagonal blocks in full block-CSR, 36 values per slot (T),
 //               two slots per bond; per-slot halves of the diagonal block
@@ -66,7 +66,7 @@ struct DevPtrs {
   uint8_t *flags;                    // FREE / FIXED / KINEMATIC ; 255 = padding
   int *psid;                         // scene id per particle
   int *row_ptr;                      // n_pad + 1, off-diagonal slots per row
-  int2 *slot;                        // n_slots: (neighbour row, bond)
+  int *col;                          // n_slots: neighbour row of each off-diagonal slot
   // bonds
   int2 *bij;
   double4 *brest_a, *brest_b, *brest_c;

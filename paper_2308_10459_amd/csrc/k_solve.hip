@@ -209,7 +209,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
       }
 #pragma unroll
       for (int m = 0; m < U; ++m) {
-        jj[m] = d.slot[cb + sl[m]].x;
+        jj[m] = d.col[cb + sl[m]];
         load_row6(Hoff + (size_t)(cb + sl[m]) * 36 + cc[m] * 6, hv[m]);
       }
 #pragma unroll
