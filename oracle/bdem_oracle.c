@@ -655,10 +655,20 @@ static void reduce_to_manifold(int nblk, const double *const *q, const double *g
   free(P); free(Gf); free(Hm); free(T); free(gp);
 }
 
-int orc_bond_reduced(const orc_sys *s, int64_t b, const double *pi, const double *qi,
-                     const double *pj, const double *qj, int psd, double *g12, double *h12) {
+/* Reduced gradient and Hessian of one bond for the unknowns (p_i, q_i, p_j, q_j):
+ * V_b is evaluated at the endpoint states (epi, eqi, epj, eqj); its Euclidean
+ * gradient and Hessian with respect to the unknowns are those at the
+ * evaluation point times wg and wh (1 and 1 when it is the unknown itself,
+ * 1/2 and 1/4 when it is the midpoint (x + x_n)/2 of Section 3.1); the
+ * reduction of Sections 4.1-4.2 uses the unknowns' own quaternions. */
+static int bond_reduced_at(const orc_sys *s, int64_t b, const double *qi, const double *qj,
+                           const double *epi, const double *eqi, const double *epj,
+                           const double *eqj, double wg, double wh, int psd, double *g12,
+                           double *h12) {
   double g14[14], H14[196], Hr[144];
-  if (orc_bond_eval(s, b, pi, qi, pj, qj, NULL, g14, H14)) return -1;
+  if (orc_bond_eval(s, b, epi, eqi, epj, eqj, NULL, g14, H14)) return -1;
+  for (int a = 0; a < 14; ++a) g14[a] *= wg;
+  for (int a = 0; a < 196; ++a) H14[a] *= wh;
   const double *qs[2] = {qi, qj};
   reduce_to_manifold(2, qs, g14, H14, g12, Hr);
   if (h12) {
@@ -666,6 +676,11 @@ int orc_bond_reduced(const orc_sys *s, int64_t b, const double *pi, const double
     else memcpy(h12, Hr, sizeof Hr);
   }
   return 0;
+}
+
+int orc_bond_reduced(const orc_sys *s, int64_t b, const double *pi, const double *qi,
+                     const double *pj, const double *qj, int psd, double *g12, double *h12) {
+  return bond_reduced_at(s, b, qi, qj, pi, qi, pj, qj, 1.0, 1.0, psd, g12, h12);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -683,15 +698,19 @@ int orc_predict(const orc_sys *s, double dt, double *ph, double *qh) {
   return 0;
 }
 
-/* energy, Euclidean gradient (7) and Hessian (7x7) of particle i's own terms */
+/* Energy, Euclidean gradient (7) and Hessian (7x7) of particle i's own terms:
+ * the inertia 1/(2 dt^2) (x - x_t)^T M_s (x - x_t) about the target (ph, qh),
+ * plus gravity and ground evaluated at the position pv, whose gradient and
+ * Hessian enter with the weights wg and wh (see bond_reduced_at). */
 static double particle_terms(const orc_sys *s, int32_t i, double dt, const double *p,
                              const double *q, const double *ph, const double *qh,
-                             int potential_only, double *g7, double *H7) {
+                             const double *pv, double wg, double wh, int potential_only,
+                             double *g7, double *H7) {
   double m = s->mass[i], c = s->cq[i], idt2 = potential_only ? 0.0 : 1.0 / (dt * dt);
   double E = 0.0;
   if (g7) memset(g7, 0, 7 * sizeof(double));
   if (H7) memset(H7, 0, 49 * sizeof(double));
-  /* inertia: 1/(2 dt^2) (x - x_hat)^T M_s (x - x_hat) */
+  /* inertia: 1/(2 dt^2) (x - x_t)^T M_s (x - x_t) */
   for (int r = 0; r < 3; ++r) {
     double e = p[r] - ph[r];
     E += 0.5 * m * idt2 * e * e;
@@ -705,17 +724,17 @@ static double particle_terms(const orc_sys *s, int32_t i, double dt, const doubl
     if (H7) H7[(3 + r) * 7 + 3 + r] += c * idt2;
   }
   /* gravity: -m g . p */
-  E -= m * dot3(s->gravity, p);
-  if (g7) for (int r = 0; r < 3; ++r) g7[r] -= m * s->gravity[r];
+  E -= m * dot3(s->gravity, pv);
+  if (g7) for (int r = 0; r < 3; ++r) g7[r] -= wg * m * s->gravity[r];
   /* ground: 1/2 k_c min(0, gap)^2 with gap = n . p - h - r */
   if (s->kc != 0.0) {
-    double gap = dot3(s->gn, p) - s->gh - s->radius[i];
+    double gap = dot3(s->gn, pv) - s->gh - s->radius[i];
     if (gap < 0.0) {
       E += 0.5 * s->kc * gap * gap;
-      if (g7) for (int r = 0; r < 3; ++r) g7[r] += s->kc * gap * s->gn[r];
+      if (g7) for (int r = 0; r < 3; ++r) g7[r] += wg * s->kc * gap * s->gn[r];
       if (H7)
         for (int r = 0; r < 3; ++r)
-          for (int cc = 0; cc < 3; ++cc) H7[r * 7 + cc] += s->kc * s->gn[r] * s->gn[cc];
+          for (int cc = 0; cc < 3; ++cc) H7[r * 7 + cc] += wh * s->kc * s->gn[r] * s->gn[cc];
     }
   }
   return E;
@@ -732,14 +751,88 @@ static void kadd(ksum *k, double x) {
   k->s = t;
 }
 
-int orc_energy(const orc_sys *s, double dt, const double *pos, const double *quat,
-               int potential_only, double *phi) {
-  double *ph = (double *)malloc(sizeof(double) * 3 * s->n), *qh = (double *)malloc(sizeof(double) * 4 * s->n);
+/* ------------------------------------------------------------------------ */
+/* the objective of one step (Section 3.1)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* midpoint = 0: Phi(x) = 1/(2 dt^2)|x - x_hat|^2_{M_s} + V(x), the form the
+ * experiments use; midpoint = 1: Phi(x) = 1/(2 dt^2)|x - z_hat|^2_{M_s} +
+ * V((x + x_n)/2), the variational midpoint form.  tp / tq: the inertia target. */
+typedef struct {
+  int midpoint;
+  const double *tp, *tq;
+} objective;
+
+int orc_midpoint_target(const orc_sys *s, double dt, double *zp, double *zq) {
+  int32_t n = s->n;
+  double *ph = (double *)malloc(sizeof(double) * 3 * n), *qh = (double *)malloc(sizeof(double) * 4 * n);
+  double *mp = (double *)malloc(sizeof(double) * 3 * n), *mq = (double *)malloc(sizeof(double) * 4 * n);
+  double *gv = (double *)calloc(7 * (size_t)n, sizeof(double));
   orc_predict(s, dt, ph, qh);
+  /* x_hat = 2 x_i - x_{i-1}, so x_{i-1} = 2 x_i - x_hat; midpoint (x_{i-1} + x_i) / 2 */
+  for (int32_t i = 0; i < n; ++i) {
+    for (int r = 0; r < 3; ++r) {
+      double prev = 2.0 * s->pos[3 * i + r] - ph[3 * i + r];
+      mp[3 * i + r] = 0.5 * (prev + s->pos[3 * i + r]);
+    }
+    for (int r = 0; r < 4; ++r) {
+      double prev = 2.0 * s->quat[4 * i + r] - qh[4 * i + r];
+      mq[4 * i + r] = 0.5 * (prev + s->quat[4 * i + r]);
+    }
+  }
+  /* Euclidean gradient of V at that midpoint: particle terms, then bonds in order */
+  for (int32_t i = 0; i < n; ++i) {
+    double g7[7];
+    particle_terms(s, i, dt, mp + 3 * i, mq + 4 * i, mp + 3 * i, mq + 4 * i, mp + 3 * i, 1.0,
+                   1.0, 1, g7, NULL);
+    for (int r = 0; r < 7; ++r) gv[7 * i + r] += g7[r];
+  }
+  int64_t nb = s->nb;
+  double *gb = (double *)malloc(sizeof(double) * 14 * (nb > 0 ? nb : 1));
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < nb; ++b) {
+    if (!s->alive[b]) continue;
+    int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
+    orc_bond_eval(s, b, mp + 3 * i, mq + 4 * i, mp + 3 * j, mq + 4 * j, NULL, gb + 14 * b, NULL);
+  }
+  for (int64_t b = 0; b < nb; ++b) {
+    if (!s->alive[b]) continue;
+    int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
+    for (int r = 0; r < 7; ++r) { gv[7 * i + r] += gb[14 * b + r]; gv[7 * j + r] += gb[14 * b + 7 + r]; }
+  }
+  /* z_hat = x_hat - 1/2 M_s^{-1} dt^2 grad V; particles that are not unknowns keep x_hat */
+  for (int32_t i = 0; i < n; ++i) {
+    int free_ = is_solved(s, i);
+    double fm = free_ ? 0.5 * dt * dt / s->mass[i] : 0.0, fc = free_ ? 0.5 * dt * dt / s->cq[i] : 0.0;
+    for (int r = 0; r < 3; ++r) zp[3 * i + r] = ph[3 * i + r] - fm * gv[7 * i + r];
+    for (int r = 0; r < 4; ++r) zq[4 * i + r] = qh[4 * i + r] - fc * gv[7 * i + 3 + r];
+  }
+  free(ph); free(qh); free(mp); free(mq); free(gv); free(gb);
+  return 0;
+}
+
+/* evaluation point of V for the state (pos, quat): itself, or (x + x_n)/2 */
+static void eval_point(const orc_sys *s, const objective *ob, const double *pos,
+                       const double *quat, double *ep, double *eq) {
+  int32_t n = s->n;
+  if (ob->midpoint) {
+    for (size_t a = 0; a < 3 * (size_t)n; ++a) ep[a] = 0.5 * (pos[a] + s->pos[a]);
+    for (size_t a = 0; a < 4 * (size_t)n; ++a) eq[a] = 0.5 * (quat[a] + s->quat[a]);
+  } else {
+    memcpy(ep, pos, sizeof(double) * 3 * n);
+    memcpy(eq, quat, sizeof(double) * 4 * n);
+  }
+}
+
+static int objective_energy(const orc_sys *s, double dt, const objective *ob, const double *pos,
+                            const double *quat, int potential_only, double *phi) {
+  int32_t n = s->n;
+  double *ep = (double *)malloc(sizeof(double) * 3 * n), *eq = (double *)malloc(sizeof(double) * 4 * n);
+  eval_point(s, ob, pos, quat, ep, eq);
   ksum acc = {0, 0};
-  for (int32_t i = 0; i < s->n; ++i)
-    kadd(&acc, particle_terms(s, i, dt, pos + 3 * i, quat + 4 * i, ph + 3 * i, qh + 4 * i,
-                              potential_only, NULL, NULL));
+  for (int32_t i = 0; i < n; ++i)
+    kadd(&acc, particle_terms(s, i, dt, pos + 3 * i, quat + 4 * i, ob->tp + 3 * i, ob->tq + 4 * i,
+                              ep + 3 * i, 1.0, 1.0, potential_only, NULL, NULL));
   double *eb = (double *)malloc(sizeof(double) * (s->nb > 0 ? s->nb : 1));
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < s->nb; ++b) {
@@ -747,28 +840,31 @@ int orc_energy(const orc_sys *s, double dt, const double *pos, const double *qua
     eb[b] = 0.0;
     if (!s->alive[b]) continue;
     int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
-    orc_bond_energy_parts(s, b, pos + 3 * i, quat + 4 * i, pos + 3 * j, quat + 4 * j, parts);
+    orc_bond_energy_parts(s, b, ep + 3 * i, eq + 4 * i, ep + 3 * j, eq + 4 * j, parts);
     eb[b] = parts[0] + parts[1] + parts[2];
   }
   for (int64_t b = 0; b < s->nb; ++b) kadd(&acc, eb[b]);
   *phi = acc.s + acc.c;
-  free(eb); free(ph); free(qh);
+  free(eb); free(ep); free(eq);
   return 0;
 }
 
-int orc_energy_grad_hess(const orc_sys *s, double dt, const double *pos, const double *quat,
-                         int psd, double *phi, double *z, double *hdiag, double *hoff) {
+static int objective_grad_hess(const orc_sys *s, double dt, const objective *ob,
+                               const double *pos, const double *quat, int psd, double *phi,
+                               double *z, double *hdiag, double *hoff) {
   int32_t n = s->n;
-  double *ph = (double *)malloc(sizeof(double) * 3 * n), *qh = (double *)malloc(sizeof(double) * 4 * n);
-  orc_predict(s, dt, ph, qh);
-  if (phi) orc_energy(s, dt, pos, quat, 0, phi);
+  const double wg = ob->midpoint ? 0.5 : 1.0, wh = ob->midpoint ? 0.25 : 1.0;
+  double *ep = (double *)malloc(sizeof(double) * 3 * n), *eq = (double *)malloc(sizeof(double) * 4 * n);
+  eval_point(s, ob, pos, quat, ep, eq);
+  if (phi) objective_energy(s, dt, ob, pos, quat, 0, phi);
   if (z) memset(z, 0, sizeof(double) * 6 * n);
   if (hdiag) memset(hdiag, 0, sizeof(double) * 36 * n);
   if (hoff && s->nb > 0) memset(hoff, 0, sizeof(double) * 36 * s->nb);
   /* particle terms */
   for (int32_t i = 0; i < n; ++i) {
     double g7[7], H7[49], g6[6], H6[36], P6[36];
-    particle_terms(s, i, dt, pos + 3 * i, quat + 4 * i, ph + 3 * i, qh + 4 * i, 0, g7, H7);
+    particle_terms(s, i, dt, pos + 3 * i, quat + 4 * i, ob->tp + 3 * i, ob->tq + 4 * i,
+                   ep + 3 * i, wg, wh, 0, g7, H7);
     const double *qs[1] = {quat + 4 * i};
     reduce_to_manifold(1, qs, g7, H7, g6, H6);
     if (psd) orc_psd_project(6, H6, P6);
@@ -784,8 +880,8 @@ int orc_energy_grad_hess(const orc_sys *s, double dt, const double *pos, const d
   for (int64_t b = 0; b < nb; ++b) {
     if (!s->alive[b]) continue;
     int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
-    orc_bond_reduced(s, b, pos + 3 * i, quat + 4 * i, pos + 3 * j, quat + 4 * j, psd,
-                     gb + 12 * b, hb + 144 * b);
+    bond_reduced_at(s, b, quat + 4 * i, quat + 4 * j, ep + 3 * i, eq + 4 * i, ep + 3 * j,
+                    eq + 4 * j, wg, wh, psd, gb + 12 * b, hb + 144 * b);
   }
   for (int64_t b = 0; b < nb; ++b) {
     if (!s->alive[b]) continue;
@@ -814,8 +910,45 @@ int orc_energy_grad_hess(const orc_sys *s, double dt, const double *pos, const d
       int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
       if (!is_solved(s, i) || !is_solved(s, j)) memset(hoff + 36 * b, 0, 36 * sizeof(double));
     }
-  free(gb); free(hb); free(ph); free(qh);
+  free(gb); free(hb); free(ep); free(eq);
   return 0;
+}
+
+/* inertia target of the step: x_hat, or z_hat for the midpoint form */
+static void step_target(const orc_sys *s, double dt, int midpoint, double *tp, double *tq) {
+  if (midpoint) orc_midpoint_target(s, dt, tp, tq);
+  else orc_predict(s, dt, tp, tq);
+}
+
+int orc_objective(const orc_sys *s, double dt, int midpoint, const double *pos,
+                  const double *quat, int potential_only, double *phi) {
+  double *tp = (double *)malloc(sizeof(double) * 3 * s->n), *tq = (double *)malloc(sizeof(double) * 4 * s->n);
+  step_target(s, dt, midpoint, tp, tq);
+  objective ob = {midpoint != 0, tp, tq};
+  int rc = objective_energy(s, dt, &ob, pos, quat, potential_only, phi);
+  free(tp); free(tq);
+  return rc;
+}
+
+int orc_objective_grad_hess(const orc_sys *s, double dt, int midpoint, const double *pos,
+                            const double *quat, int psd, double *phi, double *z, double *hdiag,
+                            double *hoff) {
+  double *tp = (double *)malloc(sizeof(double) * 3 * s->n), *tq = (double *)malloc(sizeof(double) * 4 * s->n);
+  step_target(s, dt, midpoint, tp, tq);
+  objective ob = {midpoint != 0, tp, tq};
+  int rc = objective_grad_hess(s, dt, &ob, pos, quat, psd, phi, z, hdiag, hoff);
+  free(tp); free(tq);
+  return rc;
+}
+
+int orc_energy(const orc_sys *s, double dt, const double *pos, const double *quat,
+               int potential_only, double *phi) {
+  return orc_objective(s, dt, 0, pos, quat, potential_only, phi);
+}
+
+int orc_energy_grad_hess(const orc_sys *s, double dt, const double *pos, const double *quat,
+                         int psd, double *phi, double *z, double *hdiag, double *hoff) {
+  return orc_objective_grad_hess(s, dt, 0, pos, quat, psd, phi, z, hdiag, hoff);
 }
 
 void orc_hess_apply(const orc_sys *s, const double *hdiag, const double *hoff,
@@ -1003,7 +1136,7 @@ void orc_default_options(orc_options *o) {
   o->max_ls = 30;
   o->break_bonds = 1;
   o->first_order = 0;
-  o->pad_ = 0;
+  o->midpoint = 0;
 }
 
 int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
@@ -1029,15 +1162,22 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
     double nq = sqrt(dot4(qh + 4 * i, qh + 4 * i));
     for (int r = 0; r < 4; ++r) x_q[4 * i + r] = qh[4 * i + r] / nq;
   }
+  /* inertia target: x_hat, or z_hat of the midpoint form (Section 3.1) */
+  if (o->midpoint) orc_midpoint_target(s, dt, ph, qh);
+  const objective ob = {o->midpoint != 0, ph, qh};
   /* an initial guess outside the domain of the potential (an alive bond with
-   * q_j = -q_i, where the shear midpoint does not exist) is replaced by the
-   * state x_n for the free particles */
+   * q_j = -q_i at the point V is evaluated, where the shear midpoint does not
+   * exist) is replaced by the state x_n for the free particles */
   {
     int outside = 0;
     for (int64_t b = 0; b < s->nb && !outside; ++b) {
       if (!s->alive[b]) continue;
-      const double *qa = x_q + 4 * s->ij[2 * b], *qb = x_q + 4 * s->ij[2 * b + 1];
-      double w[4] = {qa[0] + qb[0], qa[1] + qb[1], qa[2] + qb[2], qa[3] + qb[3]};
+      int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
+      const double *qa = x_q + 4 * i, *qb = x_q + 4 * j;
+      double w[4];
+      for (int r = 0; r < 4; ++r)
+        w[r] = o->midpoint ? 0.5 * (qa[r] + s->quat[4 * i + r]) + 0.5 * (qb[r] + s->quat[4 * j + r])
+                           : qa[r] + qb[r];
       if (dot4(w, w) < 1e-12) outside = 1;
     }
     if (outside)
@@ -1053,9 +1193,9 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
   int unresolved = 0, stall = 0;
   for (int k = 0;; ++k) {
     if (o->first_order)
-      orc_energy_grad_hess(s, dt, x_p, x_q, 1, &phi, z, NULL, NULL);
+      objective_grad_hess(s, dt, &ob, x_p, x_q, 1, &phi, z, NULL, NULL);
     else
-      orc_energy_grad_hess(s, dt, x_p, x_q, 1, &phi, z, hdiag, hoff);
+      objective_grad_hess(s, dt, &ob, x_p, x_q, 1, &phi, z, hdiag, hoff);
     double zn = sqrt(vdot(z, z, N6));
     if (k == 0) { z0 = zn; S.grad0 = zn; }
     S.grad_final = zn;
@@ -1103,7 +1243,7 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
         orc_quat_exp_step(x_q + 4 * i, dq + 4 * i, alpha, t_q + 4 * i);
       }
       double phit;
-      orc_energy(s, dt, t_p, t_q, 0, &phit);
+      objective_energy(s, dt, &ob, t_p, t_q, 0, &phit);
       if (phit <= phi + o->armijo_c * alpha * slope) { accepted = 1; break; }
       alpha *= 0.5;
       S.ls_backtracks++;

@@ -70,6 +70,23 @@ int orc_predict(const orc_sys *s, double dt, double *p_hat, double *q_hat);
 int orc_energy(const orc_sys *s, double dt, const double *pos, const double *quat,
                int potential_only, double *phi);
 
+/* z_hat = x_hat - 1/2 M_s^{-1} dt^2 grad V((x_{i-1} + x_i)/2) of the
+ * variational midpoint form (Section 3.1, Appendix C), with x_i the current
+ * state, x_hat its prediction and x_{i-1} = 2 x_i - x_hat; grad V is the
+ * Euclidean gradient over (p, q).  Particles that are not unknowns keep
+ * z_hat = x_hat.  zp (3n), zq (4n). */
+int orc_midpoint_target(const orc_sys *s, double dt, double *zp, double *zq);
+
+/* The objective of a step: midpoint = 0 is orc_energy / orc_energy_grad_hess;
+ * midpoint = 1: Phi(x) = 1/(2 dt^2)|x - z_hat|^2_{M_s} + V((x + x_i)/2), whose
+ * Euclidean gradient and Hessian carry V's at the midpoint times 1/2 and 1/4,
+ * reduced at the quaternions of x. */
+int orc_objective(const orc_sys *s, double dt, int midpoint, const double *pos,
+                  const double *quat, int potential_only, double *phi);
+int orc_objective_grad_hess(const orc_sys *s, double dt, int midpoint, const double *pos,
+                            const double *quat, int psd, double *phi, double *z, double *hdiag,
+                            double *hoff);
+
 /* Phi, reduced gradient z (6n) and reduced Hessian: diagonal blocks hdiag
  * (36n, row-major 6x6) and one off-diagonal block per bond hoff (36nb, the
  * (i,j) block, rows of i, columns of j).  Any output may be NULL.  Broken
@@ -103,7 +120,7 @@ typedef struct {
   double armijo_c;
   int32_t max_newton, max_cg, max_ls, break_bonds;
   int32_t first_order;       /* 1: Algorithm 1 (Riemannian gradient descent) instead of Algorithm 2 */
-  int32_t pad_;
+  int32_t midpoint;          /* 1: the variational midpoint objective of Section 3.1 */
 } orc_options;
 
 typedef struct {

@@ -26,7 +26,7 @@ class Options(C.Structure):
     _fields_ = [("tol_abs", C.c_double), ("tol_rel", C.c_double), ("cg_rtol", C.c_double),
                 ("armijo_c", C.c_double), ("max_newton", C.c_int32), ("max_cg", C.c_int32),
                 ("max_ls", C.c_int32), ("break_bonds", C.c_int32), ("first_order", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("midpoint", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -66,6 +66,10 @@ def lib():
         L.orc_energy.argtypes = [C.c_void_p, C.c_double, _dp, _dp, C.c_int, _dp]
         L.orc_energy_grad_hess.argtypes = [C.c_void_p, C.c_double, _dp, _dp, C.c_int, _dp,
                                            _dp, _dp, _dp]
+        L.orc_midpoint_target.argtypes = [C.c_void_p, C.c_double, _dp, _dp]
+        L.orc_objective.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, C.c_int, _dp]
+        L.orc_objective_grad_hess.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, C.c_int,
+                                              _dp, _dp, _dp, _dp]
         L.orc_hess_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_pcg.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp]
         L.orc_psd_project.argtypes = [C.c_int, _dp, _dp]
@@ -186,17 +190,23 @@ class Oracle:
         lib().orc_predict(self.h, dt, _p(ph), _p(qh))
         return ph, qh
 
-    def energy(self, dt, pos=None, quat=None, potential_only=False):
+    def midpoint_target(self, dt):
+        zp, zq = np.empty((self.n, 3)), np.empty((self.n, 4))
+        lib().orc_midpoint_target(self.h, dt, _p(zp), _p(zq))
+        return zp, zq
+
+    def energy(self, dt, pos=None, quat=None, potential_only=False, midpoint=False):
         st = None
         if pos is None or quat is None:
             st = self.get_state()
         pos = _f64(st["pos"] if pos is None else pos)
         quat = _f64(st["quat"] if quat is None else quat)
         phi = C.c_double()
-        lib().orc_energy(self.h, dt, _p(pos), _p(quat), int(potential_only), C.byref(phi))
+        lib().orc_objective(self.h, dt, int(midpoint), _p(pos), _p(quat), int(potential_only),
+                            C.byref(phi))
         return phi.value
 
-    def energy_grad_hess(self, dt, pos=None, quat=None, psd=True, hess=True):
+    def energy_grad_hess(self, dt, pos=None, quat=None, psd=True, hess=True, midpoint=False):
         if pos is None or quat is None:
             st = self.get_state()
             pos = st["pos"] if pos is None else pos
@@ -205,8 +215,8 @@ class Oracle:
         phi, z = C.c_double(), np.empty((self.n, 6))
         hd = np.empty((self.n, 6, 6)) if hess else None
         ho = np.empty((max(self.nb, 1), 6, 6)) if hess else None
-        lib().orc_energy_grad_hess(self.h, dt, _p(pos), _p(quat), int(psd), C.byref(phi),
-                                   _p(z), _p(hd), _p(ho))
+        lib().orc_objective_grad_hess(self.h, dt, int(midpoint), _p(pos), _p(quat), int(psd),
+                                      C.byref(phi), _p(z), _p(hd), _p(ho))
         return phi.value, z, hd, (None if ho is None else ho[:self.nb])
 
     def hess_apply(self, hdiag, hoff, x):

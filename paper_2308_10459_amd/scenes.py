@@ -388,6 +388,16 @@ def make_chain(n=3, spacing=0.02, r=0.01, young=1e7, gravity=(0.0, 0.0, 0.0), **
                   k_contact=0.0)
 
 
+def make_triangle(side=0.02, r=0.01, young=1e7, gravity=(0.0, 0.0, 0.0), **matkw):
+    """Three particles bonded pairwise, an equilateral triangle in the xy plane
+    centred on the origin, at rest."""
+    pos = np.array([[0.0, 0.0, 0.0], [side, 0.0, 0.0], [0.5 * side, 0.5 * math.sqrt(3.0) * side, 0.0]])
+    pos -= pos.mean(axis=0)
+    ij = np.array([[0, 1], [1, 2], [0, 2]], dtype=np.int32)
+    return _scene("triangle", pos, r, ij, [material(young, **matkw)], gravity=gravity,
+                  k_contact=0.0)
+
+
 def perturb_state(sc: Scene, seed, pos_scale, rot_angle, vel_scale=0.0, qvel_scale=0.0):
     """Seeded random displacement / rotation / velocity of a scene's free particles.
     Returns (pos, quat, vel, qvel); quaternions stay unit."""

@@ -712,3 +712,223 @@ def test_first_order_reaches_the_second_order_fixed_point(oracle_mod):
     bound = 10 * sb["grad_final"] / lam
     assert np.abs(rb["pos"] - ra["pos"]).max() <= bound
     assert np.abs(rb["quat"] - ra["quat"]).max() <= bound
+
+
+# --------------------------------------------------------------------------
+# Section 3.1 / Appendix C: the variational midpoint form (PIN-M1..M5)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dt", [1e-3, 1e-4])
+@pytest.mark.parametrize("one_fixed", [False, True])
+def test_midpoint_axial_oscillation_closed_form(oracle_mod, dt, one_fixed):
+    """A stretch oscillator under the midpoint recurrence
+    (u_{n+1} - 2u_n + u_{n-1}) / dt^2 = -w^2 (u_{n+1} + 2u_n + u_{n-1}) / 4
+    keeps its amplitude exactly and turns by theta = 2 atan(w dt / 2) per step;
+    from rest at u_0 (so u_{-1} = u_0), u_n = u_0 cos((n + 1/2) theta) / cos(theta / 2)."""
+    O = oracle_mod
+    E, r, l0, rho = 1e7, 0.01, 0.02, 1000.0
+    kn = E * math.pi * r * r / l0
+    m = rho * 4 / 3 * math.pi * r ** 3
+    w = math.sqrt((1.0 if one_fixed else 2.0) * kn / m)
+    th = 2 * math.atan(w * dt / 2)
+    sc = S.make_pair(axis=(1, 0, 0), length=l0, r=r, young=E)
+    if one_fixed:
+        sc.flags[0] = S.FIXED
+    o = O.Oracle(sc)
+    d0 = 1e-6
+    pos = sc.pos.copy()
+    pos[1, 0] += d0
+    o.set_state(pos=pos)
+    got = []
+    for _ in range(40):
+        st = o.step(dt, midpoint=1, tol_rel=1e-13)
+        assert st["rc"] == 0
+        p = o.get_state()["pos"]
+        got.append(p[1, 0] - p[0, 0] - l0)
+        assert np.abs(p[:, 1:]).max() < 1e-18
+    ref = d0 * np.cos((np.arange(40) + 1.5) * th) / math.cos(th / 2)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-9 * d0)
+
+
+def test_midpoint_torsion_matches_the_scalar_recurrence(oracle_mod):
+    """A twist oscillator (one sphere fixed, the other turning about the bond
+    axis) stays on the circle q = (sin f, 0, 0, cos f): V = 1/2 K (q_x)^2 with
+    K = GJ/l0, inertia c = 8/5 m r^2.  Written in that plane the midpoint step
+    is a scalar equation for f_{n+1}: the tangential part at q_{n+1} of
+    c (q_{n+1} - z_hat) / dt^2 + 1/2 dV((q_{n+1} + q_n)/2) vanishes, with
+    z_hat = 2 q_n - q_{n-1} - dt^2/(2c) dV((q_{n-1} + q_n)/2).  Solved here
+    by bracketing, independent of the oracle's 3D machinery."""
+    from scipy.optimize import brentq
+    O = oracle_mod
+    E, nu, r, l0, rho = 1e7, 0.3, 0.01, 0.02, 1000.0
+    K = E / (2 * (1 + nu)) * math.pi * r ** 4 / 2 / l0
+    m = rho * 4 / 3 * math.pi * r ** 3
+    c = 8 / 5 * m * r * r
+    dt = 1e-4
+    sc = S.make_pair(axis=(1, 0, 0), length=l0, r=r, young=E)
+    sc.flags[0] = S.FIXED
+    o = O.Oracle(sc)
+    f0 = 0.3
+    quat = sc.quat.copy()
+    quat[1] = [math.sin(f0), 0, 0, math.cos(f0)]
+    o.set_state(quat=quat)
+
+    def Q(f):
+        return np.array([math.sin(f), math.cos(f)])
+
+    def dV(q):
+        return np.array([K * q[0], 0.0])
+
+    def next_angle(fp, fc):
+        zh = 2 * Q(fc) - Q(fp) - 0.5 * dt * dt / c * dV(0.5 * (Q(fp) + Q(fc)))
+
+        def F(f):
+            t = np.array([math.cos(f), -math.sin(f)])
+            return t @ (c / dt ** 2 * (Q(f) - zh) + 0.5 * dV(0.5 * (Q(f) + Q(fc))))
+        return brentq(F, fc - 0.5, fc + 0.5, xtol=1e-15, rtol=1e-15)
+
+    fp = fc = f0
+    worst, seen = 0.0, []
+    for _ in range(80):
+        assert o.step(dt, midpoint=1, tol_rel=1e-13)["rc"] == 0
+        q = o.get_state()["quat"][1]
+        assert np.abs(q[1:3]).max() < 1e-15
+        fp, fc = fc, next_angle(fp, fc)
+        worst = max(worst, abs(math.atan2(q[0], q[3]) - fc))
+        seen.append(fc)
+    assert worst <= 1e-8
+    assert min(seen) < -0.25 and max(seen) > 0.25      # at least one full swing
+
+
+def _spinning_triangle():
+    """Stretch-only spring triangle spinning about z with some vibration:
+    V depends on positions only and is invariant under rotations."""
+    sc = S.make_triangle(stiff_scale=(1.0, 0.0, 0.0, 0.0))
+    om = np.array([0.3, -0.2, 400.0])
+    sc.vel = np.cross(om, sc.pos) + np.array([[0.5, 0, 0], [0, 0, 0], [0, 1.0, -0.5]])
+    return sc
+
+
+def _triangle_grad(sc, x):
+    kn = 1e7 * math.pi * 0.01 ** 2 / 0.02
+    g = np.zeros_like(x)
+    for i, j in sc.ij:
+        u = x[j] - x[i]
+        ln = np.linalg.norm(u)
+        f = kn * (ln - 0.02) * u / ln
+        g[j] += f
+        g[i] -= f
+    return g
+
+
+def test_midpoint_conserves_discrete_momenta(oracle_mod):
+    """For a rotation-invariant V(positions) the midpoint recurrence conserves
+    sum m (x_{n+1} - x_n) and J_n = sum m x_n x x_{n+1} - dt^2/4 sum
+    (x_{n+1} - x_n) x grad V((x_n + x_{n+1})/2) exactly (a telescoping identity
+    of the recurrence: sum x x grad V(x) = 0).  Implicit Euler loses J."""
+    O = oracle_mod
+    sc = _spinning_triangle()
+    m = 1000 * 4 / 3 * math.pi * 0.01 ** 3
+    dt = 2e-4
+    drift = {}
+    for mid in (1, 0):
+        o = O.Oracle(sc)
+        xs = [o.get_state()["pos"].copy()]
+        for _ in range(60):
+            assert o.step(dt, midpoint=mid, tol_rel=1e-14)["rc"] == 0
+            xs.append(o.get_state()["pos"].copy())
+        assert np.abs(o.get_state()["quat"] - sc.quat).max() == 0.0
+        J, P = [], []
+        for a, b in zip(xs[:-1], xs[1:]):
+            J.append((m * np.cross(a, b)).sum(0) - dt * dt / 4 * np.cross(b - a, _triangle_grad(sc, 0.5 * (a + b))).sum(0))
+            P.append(m * (b - a).sum(0))
+        J, P = np.array(J), np.array(P)
+        drift[mid] = np.abs(J - J[0]).max() / np.abs(J[0]).max()
+        assert np.abs(P - P[0]).max() <= 1e-12 * np.abs(P[0]).max()
+    assert drift[1] <= 1e-7
+    assert drift[0] >= 1e-4
+
+
+def test_midpoint_is_second_order_and_euler_first(oracle_mod):
+    """Positions at T = 2 ms of the spinning triangle against a dt = T/2048
+    run of the same scheme: halving dt three times shrinks the midpoint error
+    by ~2^6 and the implicit-Euler error by ~2^3."""
+    O = oracle_mod
+    T = 2e-3
+
+    def run(dt, mid):
+        o = O.Oracle(_spinning_triangle())
+        for _ in range(int(round(T / dt))):
+            o.step(dt, midpoint=mid, tol_rel=1e-14)
+        return o.get_state()["pos"]
+
+    ratio = {}
+    for mid in (1, 0):
+        ref = run(T / 2048, mid)
+        e16, e128 = (np.abs(run(T / k, mid) - ref).max() for k in (16, 128))
+        ratio[mid] = e16 / e128
+    assert ratio[1] >= 30.0          # order >= 1.6
+    assert ratio[0] <= 8.5           # order <= 1.03
+
+
+def test_midpoint_free_fall_exact(oracle_mod):
+    """No bonds: grad V = -m g everywhere, z_hat = x_hat + dt^2 g / 2 and the
+    midpoint step is the exact discrete free fall, as the implicit-Euler one."""
+    O = oracle_mod
+    sc = S.make_pair(gravity=(0.0, 0.0, -9.81))
+    sc.ij = np.zeros((0, 2), dtype=np.int32)
+    sc.vel = np.array([[0.3, -0.2, 1.0], [0.0, 0.0, 0.0]])
+    o = O.Oracle(sc)
+    dt = 1e-3
+    for nstep in range(1, 21):
+        o.step(dt, midpoint=1)
+    st = o.get_state()
+    g = np.array([0, 0, -9.81])
+    ref = sc.pos + nstep * dt * sc.vel + 0.5 * nstep * (nstep + 1) * dt * dt * g
+    np.testing.assert_allclose(st["pos"], ref, rtol=1e-14, atol=1e-15)
+
+
+def test_midpoint_objective_derivatives_along_geodesics(oracle_mod):
+    """d/ds and d^2/ds^2 of the midpoint objective along p + s dp,
+    Exp_q(s G_l(q)^T y) for every free particle equal z.y and y^T H y of its
+    reduced, unprojected gradient and Hessian: the 1/2 and 1/4 weights of V at
+    (x + x_n)/2 and the reduction at the quaternions of x."""
+    O = oracle_mod
+    sc = S.make_block(nx=3, ny=2, nz=2, rot_angle=0.05)
+    sc.flags[:] = S.FREE
+    sc.k_contact = 1e6
+    sc.ground_offset = 0.01 + 1e-4
+    pos, quat, vel, qvel = S.perturb_state(sc, 21, 2e-4, 0.05, vel_scale=0.2, qvel_scale=5.0)
+    o = O.Oracle(sc)
+    o.set_state(pos=pos, quat=quat, vel=vel, qvel=qvel)
+    dt = 1e-3
+    ev_pos, ev_quat, _, _ = S.perturb_state(sc, 22, 2e-4, 0.05)
+    phi, z, hd, ho = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=False, midpoint=True)
+    n = sc.n
+    H = np.zeros((6 * n, 6 * n))
+    for i in range(n):
+        H[6 * i:6 * i + 6, 6 * i:6 * i + 6] = hd[i]
+    for b, (i, j) in enumerate(sc.ij):
+        H[6 * i:6 * i + 6, 6 * j:6 * j + 6] = ho[b]
+        H[6 * j:6 * j + 6, 6 * i:6 * i + 6] = ho[b].T
+    assert abs(phi - o.energy(dt, ev_pos, ev_quat, midpoint=True)) <= 1e-15 * abs(phi)
+    for _ in range(3):
+        y = RNG.normal(size=(n, 6))
+        y[:, :3] *= 1e-2
+        G = [O.quat_matrices(ev_quat[i])[2] for i in range(n)]
+
+        def f(s):
+            q = np.array([O.quat_exp_step(ev_quat[i], G[i].T @ y[i, 3:], s) for i in range(n)])
+            return o.energy(dt, ev_pos + s * y[:, :3], q, midpoint=True)
+
+        d1 = lambda h: (f(h) - f(-h)) / (2 * h)
+        d2 = lambda h: (f(h) - 2 * f(0) + f(-h)) / h ** 2
+        h = 1e-3
+        r1 = (4 * d1(h / 2) - d1(h)) / 3
+        r2 = (4 * d2(h / 2) - d2(h)) / 3
+        yv = y.ravel()
+        assert abs(r1 - z.ravel() @ yv) <= 1e-7 * abs(z.ravel() @ yv) + 1e-9
+        assert abs(r2 - yv @ H @ yv) <= 1e-6 * abs(yv @ H @ yv)
+    # the midpoint objective differs from the implicit-Euler one at this state
+    phi_e, z_e, _, _ = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=False)
+    assert np.abs(z_e - z).max() > 1e-3 * np.abs(z).max()
