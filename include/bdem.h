@@ -122,6 +122,14 @@ typedef struct {
                               Algorithm 1, steepest descent along -grad f with the same retraction
                               and line search (its search starts at twice the last accepted step,
                               at most 1); max_newton then caps its iterations */
+  int32_t integrator;      /* BDEM_INTEGRATOR_EULER (default): Phi(x) = |x - x_hat|^2_{M_s}/(2 dt^2)
+                              + V(x), the first-order form Section 3.1 uses in its experiments;
+                              BDEM_INTEGRATOR_MIDPOINT: the variational midpoint form of Section 3.1
+                              and Appendix C, Phi(x) = |x - z_hat|^2_{M_s}/(2 dt^2) + V((x + x_n)/2)
+                              with z_hat = x_hat - dt^2/2 M_s^{-1} grad V((x_{n-1} + x_n)/2),
+                              x_{n-1} = x_n - dt v_n: second order in the positions; the
+                              unit-norm constraint holds at the new state */
+  int32_t pad_;            /* reserved */
 } bdem_options;
 
 typedef struct {
@@ -146,10 +154,11 @@ typedef struct {
 } bdem_tuning;
 
 enum { BDEM_SOLVER_NEWTON = 0, BDEM_SOLVER_FIRST_ORDER = 1 };
+enum { BDEM_INTEGRATOR_EULER = 0, BDEM_INTEGRATOR_MIDPOINT = 1 };
 
 /* Defaults: gravity (0,0,-9.81), no ground, newton_tol 0, newton_rtol 1e-8,
  * armijo_c 1e-4, cg_rtol_max 0.5, max_newton 50, max_cg 2000, max_ls 30,
- * FP64, fracture on, cg_chunk 16, no graph. */
+ * FP64, fracture on, cg_chunk 16, no graph, Newton solver, implicit-Euler form. */
 void bdem_default_options(bdem_options *opt);
 
 /* Device bytes bdem_create needs for this problem (0 on invalid input). */
@@ -173,8 +182,9 @@ int bdem_step(bdem_ctx *ctx, double dt, bdem_step_stats *stats);
 int bdem_step_batched(bdem_ctx *ctx, const double *dt_per_scene,
                       bdem_step_stats *stats_per_scene);
 
-/* Objective at an evaluation state without solving (Section 3.1 Phi with the
- * prediction x_hat = x_n + dt v_n of the current state; Sections 4.1-4.2
+/* Objective at an evaluation state without solving (Section 3.1 Phi of the
+ * configured integrator, with the prediction x_hat = x_n + dt v_n of the
+ * current state, and z_hat in the midpoint form; Sections 4.1-4.2
  * reduced Riemannian gradient and Hessian; Section 5.2 projection when
  * BDEM_EGH_PSD).  pos_eval / quat_eval NULL: the current state.  Outputs
  * (host, nullable): energy (1), grad6 (6n), hdiag36 (36n: the 6x6 diagonal

@@ -26,6 +26,7 @@ BDEM_E_DEGENERATE, BDEM_E_STATE = -5, -6
 BDEM_FREE, BDEM_FIXED, BDEM_KINEMATIC = 0, 1, 2
 BDEM_PREC_FP64, BDEM_PREC_MIXED = 0, 1
 BDEM_SOLVER_NEWTON, BDEM_SOLVER_FIRST_ORDER = 0, 1
+BDEM_INTEGRATOR_EULER, BDEM_INTEGRATOR_MIDPOINT = 0, 1
 BDEM_EGH_E, BDEM_EGH_G, BDEM_EGH_H, BDEM_EGH_PSD, BDEM_EGH_POTENTIAL_ONLY = 1, 2, 4, 8, 16
 
 _dp = C.POINTER(C.c_double)
@@ -56,7 +57,7 @@ class bdem_options(C.Structure):
                 ("armijo_c", C.c_double), ("cg_rtol_max", C.c_double), ("max_newton", C.c_int32),
                 ("max_cg", C.c_int32), ("max_ls", C.c_int32), ("precision", C.c_int32),
                 ("break_each_step", C.c_int32), ("cg_chunk", C.c_int32), ("use_graph", C.c_int32),
-                ("solver", C.c_int32)]
+                ("solver", C.c_int32), ("integrator", C.c_int32), ("pad_", C.c_int32)]
 
 
 class bdem_step_stats(C.Structure):

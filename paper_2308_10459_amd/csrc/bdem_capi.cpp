@@ -201,6 +201,8 @@ extern "C" void bdem_default_options(bdem_options *o) {
   o->cg_chunk = 16;
   o->use_graph = 0;
   o->solver = BDEM_SOLVER_NEWTON;
+  o->integrator = BDEM_INTEGRATOR_EULER;
+  o->pad_ = 0;
 }
 
 extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
@@ -272,6 +274,8 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     return fail(nullptr, BDEM_E_INVALID, "friction is not implemented (mu_s = mu_r = 0 required)");
   if (o.solver != BDEM_SOLVER_NEWTON && o.solver != BDEM_SOLVER_FIRST_ORDER)
     return fail(nullptr, BDEM_E_INVALID, "solver must be BDEM_SOLVER_NEWTON or BDEM_SOLVER_FIRST_ORDER");
+  if (o.integrator != BDEM_INTEGRATOR_EULER && o.integrator != BDEM_INTEGRATOR_MIDPOINT)
+    return fail(nullptr, BDEM_E_INVALID, "integrator must be BDEM_INTEGRATOR_EULER or BDEM_INTEGRATOR_MIDPOINT");
   if (o.max_newton < 0 || o.max_cg <= 0 || o.max_ls < 0 || o.cg_chunk <= 0)
     return fail(nullptr, BDEM_E_INVALID, "bad iteration limits");
   // ---- validation ----
@@ -519,6 +523,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   P.max_ls = o.max_ls;
   P.n_scenes = NS;
   P.first_order = o.solver == BDEM_SOLVER_FIRST_ORDER ? 1 : 0;
+  P.midpoint = o.integrator == BDEM_INTEGRATOR_MIDPOINT ? 1 : 0;
   // ---- upload ----
   hipStream_t st = ctx->stream;
   auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
@@ -587,6 +592,14 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
 
 // the counter slot written by the last decision kernel is valid once the
 // stream has drained
+// inertia target of a step: the prediction x_hat that k_predict wrote,
+// replaced for the free particles by z_hat in the midpoint form
+static void launch_step_target(const DevPtrs &d, const Params &P, hipStream_t st) {
+  if (!P.midpoint) return;
+  launch_bond_force(d, st);
+  launch_midpoint_target(d, P, st);
+}
+
 static int read_counters(bdem_ctx *ctx) {
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return BDEM_OK;
@@ -716,7 +729,7 @@ static int run_line_search(bdem_ctx *ctx) {
   hipStream_t st = ctx->stream;
   for (int it = 0; it <= ctx->opt.max_ls + 2; ++it) {
     launch_ls_trial(ctx->d, ctx->P, st);
-    launch_bond_energy(ctx->d, true, st);
+    launch_bond_energy(ctx->d, true, ctx->P.midpoint != 0, st);
     launch_ls_decide(ctx->d, ctx->P, st);
     launch_ls_accept(ctx->d, st);
     launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
@@ -762,12 +775,13 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
   };
   HIP_TRY(init_ctl());
   launch_predict(d, true, st);
+  launch_step_target(d, ctx->P, st);
   bool restarted = false;
   for (int k = 0; k <= ctx->opt.max_newton + 1; ++k) {
     HIP_TRY(hipEventRecord(ph[1], st));
     const bool hess = !ctx->P.first_order;   // Algorithm 1 needs the gradient only
     prof_mark(ctx, 0, true);
-    launch_bond_eval(d, mixed, true, hess, st);
+    launch_bond_eval(d, mixed, true, hess, ctx->P.midpoint != 0, st);
     prof_mark(ctx, 0, false);
     launch_particle_eval(d, ctx->P, mixed, hess, false, st);
     launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, st);
@@ -1033,11 +1047,12 @@ extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, con
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
   launch_predict(d, false, st);
+  launch_step_target(d, ctx->P, st);
   launch_copy_state_to_iterate(d, st);
   int rc;
   if (pos_eval && (rc = upload4(ctx, d.px, pos_eval, 3))) return rc;
   if (quat_eval && (rc = upload4(ctx, d.qx, quat_eval, 4))) return rc;
-  launch_bond_eval(d, mixed, psd, hess, st);
+  launch_bond_eval(d, mixed, psd, hess, ctx->P.midpoint != 0, st);
   launch_particle_eval(d, ctx->P, mixed, hess, pot, st);
   launch_newton_check(d, ctx->P, 1, st);
   launch_count_active(d, NS, 0, st);
@@ -1165,7 +1180,8 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
   launch_predict(d, true, st);
-  launch_bond_eval(d, mixed, true, true, st);
+  launch_step_target(d, ctx->P, st);
+  launch_bond_eval(d, mixed, true, true, ctx->P.midpoint != 0, st);
   launch_particle_eval(d, ctx->P, mixed, true, false, st);
   launch_newton_check(d, ctx->P, 1, st);
   launch_count_active(d, NS, 0, st);

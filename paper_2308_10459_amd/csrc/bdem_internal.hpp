@@ -53,6 +53,7 @@ struct Params {
   int max_newton, max_cg, max_ls;
   int n_scenes;
   int first_order;   // Algorithm 1 instead of Algorithm 2
+  int midpoint;      // variational midpoint objective of Section 3.1
 };
 
 struct DevPtrs {
@@ -98,8 +99,10 @@ struct DevPtrs {
 
 // ----- launchers (kernels in the .hip files) -----
 // bond kernels
-void launch_bond_eval(const DevPtrs &d, bool mixed, bool psd, bool hess, hipStream_t s);
-void launch_bond_energy(const DevPtrs &d, bool trial, hipStream_t s);
+void launch_bond_eval(const DevPtrs &d, bool mixed, bool psd, bool hess, bool midpoint,
+                      hipStream_t s);
+void launch_bond_energy(const DevPtrs &d, bool trial, bool midpoint, hipStream_t s);
+void launch_bond_force(const DevPtrs &d, hipStream_t s);
 void launch_bond_fracture(const DevPtrs &d, hipStream_t s);
 // particle kernels
 void launch_predict(const DevPtrs &d, bool write_iterate, hipStream_t s);
@@ -107,6 +110,7 @@ void launch_copy_state_to_iterate(const DevPtrs &d, hipStream_t s);
 void launch_restart_from_state(const DevPtrs &d, hipStream_t s);
 void launch_particle_eval(const DevPtrs &d, const Params &P, bool mixed, bool hess,
                           bool potential_only, hipStream_t s);
+void launch_midpoint_target(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_ls_trial(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_ls_accept(const DevPtrs &d, hipStream_t s);
 void launch_finish_step(const DevPtrs &d, hipStream_t s);

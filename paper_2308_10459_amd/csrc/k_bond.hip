@@ -79,7 +79,16 @@ __device__ __forceinline__ double bond_energy_of(const BondGeom &g) {
   return 0.5 * g.kn * g.e * g.e + 0.5 * g.kts * g.F + 0.5 * dot3(g.tp, g.m);
 }
 
-template <typename T, bool HESS>
+__device__ __forceinline__ double4 mid4(double4 a, double4 b) {
+  return make_double4(0.5 * (a.x + b.x), 0.5 * (a.y + b.y), 0.5 * (a.z + b.z), 0.5 * (a.w + b.w));
+}
+
+// MID = false: V and its derivatives at the unknowns x (the implicit-Euler
+// form of Section 3.1).  MID = true: the variational midpoint form, V at
+// (x + x_n)/2, so the Euclidean gradient and Hessian with respect to x are
+// V's at the midpoint times 1/2 and 1/4; the reduction to the tangent space
+// always uses the unknowns' own quaternions.
+template <typename T, bool HESS, bool MID>
 __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int b = lb * TILE + threadIdx.x;
@@ -94,7 +103,12 @@ __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
     const int i = ij.x, j = ij.y;
     BondGeom g;
     const double4 Qi = d.qx[i], Qj = d.qx[j];
-    bond_geometry(d.px[i], Qi, d.px[j], Qj, d.brest_a[b], d.brest_b[b], g);
+    double4 Pi = d.px[i], Pj = d.px[j], Ei = Qi, Ej = Qj;   // evaluation point of V
+    if (MID) {
+      Pi = mid4(Pi, d.pn[i]); Pj = mid4(Pj, d.pn[j]);
+      Ei = mid4(Qi, d.qn[i]); Ej = mid4(Qj, d.qn[j]);
+    }
+    bond_geometry(Pi, Ei, Pj, Ej, d.brest_a[b], d.brest_b[b], g);
     // |q_i + q_j| < 1e-6: the shear midpoint is undefined.  A non-finite state
     // is not counted here; the Newton check reports it as non-finite.
     if (dot4(g.w, g.w) < 1e-12) {
@@ -103,17 +117,19 @@ __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
     }
     kadd(esum, bond_energy_of(g));
     // ---------------- reduced gradient (FP64) ----------------
+    const double wg = MID ? 0.5 : 1.0;
     const double qi[4] = {Qi.x, Qi.y, Qi.z, Qi.w}, qj[4] = {Qj.x, Qj.y, Qj.z, Qj.w};
+    const double ei[4] = {Ei.x, Ei.y, Ei.z, Ei.w}, ej[4] = {Ej.x, Ej.y, Ej.z, Ej.w};
     double gu[3], gw[4];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gu[k] = g.kn * g.e * g.n[k] - g.kts * g.F1 * g.gphi_u[k];
+    for (int k = 0; k < 3; ++k) gu[k] = wg * (g.kn * g.e * g.n[k] - g.kts * g.F1 * g.gphi_u[k]);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) gw[k] = -g.kts * g.F1 * g.gphi_w[k];
+    for (int k = 0; k < 4; ++k) gw[k] = -wg * g.kts * g.F1 * g.gphi_w[k];
     // bend: grad_{q_i} = G_l(q_j)^T m = q_j (m, 0); grad_{q_j} = -G_l(q_i)^T m = -q_i (m, 0)
-    const double m4[4] = {g.m[0], g.m[1], g.m[2], 0.0};
+    const double m4[4] = {wg * g.m[0], wg * g.m[1], wg * g.m[2], 0.0};
     double bqi[4], bqj[4];
-    qmul(qj, m4, bqi);
-    qmul(qi, m4, bqj);
+    qmul(ej, m4, bqi);
+    qmul(ei, m4, bqj);
     double gqi[4], gqj[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) { gqi[k] = gw[k] + bqi[k]; gqj[k] = gw[k] - bqj[k]; }
@@ -203,7 +219,52 @@ __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
           Hww[r * 4 + c] = T(2) * kts * F2 * gpw[r] * gpw[c] - kts * F1 * hp;
         }
       (void)Aw;
-      // bend / twist 4x4 blocks: G_j^T K' G_j, G_i^T K' G_i, -G_j^T K' G_i + B(m)
+      // bend / twist 4x4 blocks: G_j^T K' G_j, G_i^T K' G_i, -G_j^T K' G_i + B(m),
+      // with G_l of the quaternions V is evaluated at
+      T Mii[16], Mjj[16], Mij[16];
+      {
+        T Bi[12], Bj[12];
+        const T tei[4] = {T(ei[0]), T(ei[1]), T(ei[2]), T(ei[3])};
+        const T tej[4] = {T(ej[0]), T(ej[1]), T(ej[2]), T(ej[3])};
+        gleft(tei, Bi);
+        gleft(tej, Bj);
+        const T kb = T(g.kb), ktw = T(g.ktw);
+        T KGi[12], KGj[12];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const T di = d0[0] * Bi[c] + d0[1] * Bi[4 + c] + d0[2] * Bi[8 + c];
+          const T dj = d0[0] * Bj[c] + d0[1] * Bj[4 + c] + d0[2] * Bj[8 + c];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            KGi[r * 4 + c] = kb * Bi[r * 4 + c] + (ktw - kb) * d0[r] * di;
+            KGj[r * 4 + c] = kb * Bj[r * 4 + c] + (ktw - kb) * d0[r] * dj;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            T aii = T(0), ajj = T(0), aij = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              aii += Bj[k * 4 + r] * KGj[k * 4 + c];
+              ajj += Bi[k * 4 + r] * KGi[k * 4 + c];
+              aij -= Bj[k * 4 + r] * KGi[k * 4 + c];
+            }
+            Mii[r * 4 + c] = Hww[r * 4 + c] + aii;
+            Mjj[r * 4 + c] = Hww[r * 4 + c] + ajj;
+            Mij[r * 4 + c] = Hww[r * 4 + c] + aij;
+          }
+      }
+      const T m[3] = {T(g.m[0]), T(g.m[1]), T(g.m[2])};
+      // B(m) = [[-m^x, m], [-m^T, 0]]  (rows q_i, columns q_j)
+      Mij[0 * 4 + 1] += m[2];  Mij[0 * 4 + 2] -= m[1];
+      Mij[1 * 4 + 0] -= m[2];  Mij[1 * 4 + 2] += m[0];
+      Mij[2 * 4 + 0] += m[1];  Mij[2 * 4 + 1] -= m[0];
+      Mij[0 * 4 + 3] += m[0];  Mij[1 * 4 + 3] += m[1];  Mij[2 * 4 + 3] += m[2];
+      Mij[3 * 4 + 0] -= m[0];  Mij[3 * 4 + 1] -= m[1];  Mij[3 * 4 + 2] -= m[2];
+      // reduction with G_l of the unknowns; assemble the scaled 9x9
+      // (u/sqrt2, y_i, y_j), packed upper triangle
       T Gi[12], Gj[12];
       {
         const T tqi[4] = {T(qi[0]), T(qi[1]), T(qi[2]), T(qi[3])};
@@ -211,41 +272,6 @@ __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
         gleft(tqi, Gi);
         gleft(tqj, Gj);
       }
-      const T kb = T(g.kb), ktw = T(g.ktw), m[3] = {T(g.m[0]), T(g.m[1]), T(g.m[2])};
-      T KGi[12], KGj[12];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const T di = d0[0] * Gi[c] + d0[1] * Gi[4 + c] + d0[2] * Gi[8 + c];
-        const T dj = d0[0] * Gj[c] + d0[1] * Gj[4 + c] + d0[2] * Gj[8 + c];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-          KGi[r * 4 + c] = kb * Gi[r * 4 + c] + (ktw - kb) * d0[r] * di;
-          KGj[r * 4 + c] = kb * Gj[r * 4 + c] + (ktw - kb) * d0[r] * dj;
-        }
-      }
-      T Mii[16], Mjj[16], Mij[16];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          T aii = T(0), ajj = T(0), aij = T(0);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            aii += Gj[k * 4 + r] * KGj[k * 4 + c];
-            ajj += Gi[k * 4 + r] * KGi[k * 4 + c];
-            aij -= Gj[k * 4 + r] * KGi[k * 4 + c];
-          }
-          Mii[r * 4 + c] = Hww[r * 4 + c] + aii;
-          Mjj[r * 4 + c] = Hww[r * 4 + c] + ajj;
-          Mij[r * 4 + c] = Hww[r * 4 + c] + aij;
-        }
-      // B(m) = [[-m^x, m], [-m^T, 0]]  (rows q_i, columns q_j)
-      Mij[0 * 4 + 1] += m[2];  Mij[0 * 4 + 2] -= m[1];
-      Mij[1 * 4 + 0] -= m[2];  Mij[1 * 4 + 2] += m[0];
-      Mij[2 * 4 + 0] += m[1];  Mij[2 * 4 + 1] -= m[0];
-      Mij[0 * 4 + 3] += m[0];  Mij[1 * 4 + 3] += m[1];  Mij[2 * 4 + 3] += m[2];
-      Mij[3 * 4 + 0] -= m[0];  Mij[3 * 4 + 1] -= m[1];  Mij[3 * 4 + 2] -= m[2];
-      // assemble the scaled 9x9 (u/sqrt2, y_i, y_j), packed upper triangle
       T Rii[9], Rjj[9], Rij[9];
       gmgt(Gi, Mii, Gi, Rii);
       gmgt(Gj, Mjj, Gj, Rjj);
@@ -262,20 +288,23 @@ __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
           Uri[r * 3 + c] = ai;
           Urj[r * 3 + c] = aj;
         }
-      const T s2 = T(1.4142135623730950488);
+      // the Euclidean Hessian enters with weight wh (1/4 at the midpoint); the
+      // lambda terms already carry the gradient's weight
+      const T wh = T(MID ? 0.25 : 1.0);
+      const T s2 = T(1.4142135623730950488), s2h = s2 * wh;
       T *A = reinterpret_cast<T *>(d.h9) + (size_t)b * 45;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           if (c >= r) {
-            A[up9(r, c)] = T(2) * Huu[r * 3 + c];
-            A[up9(3 + r, 3 + c)] = Rii[r * 3 + c] - (r == c ? li : T(0));
-            A[up9(6 + r, 6 + c)] = Rjj[r * 3 + c] - (r == c ? lj : T(0));
+            A[up9(r, c)] = T(2) * wh * Huu[r * 3 + c];
+            A[up9(3 + r, 3 + c)] = wh * Rii[r * 3 + c] - (r == c ? li : T(0));
+            A[up9(6 + r, 6 + c)] = wh * Rjj[r * 3 + c] - (r == c ? lj : T(0));
           }
-          A[up9(r, 3 + c)] = s2 * Uri[r * 3 + c];
-          A[up9(r, 6 + c)] = s2 * Urj[r * 3 + c];
-          A[up9(3 + r, 6 + c)] = Rij[r * 3 + c];
+          A[up9(r, 3 + c)] = s2h * Uri[r * 3 + c];
+          A[up9(r, 6 + c)] = s2h * Urj[r * 3 + c];
+          A[up9(3 + r, 6 + c)] = wh * Rij[r * 3 + c];
         }
     }
   } else if (real) {
@@ -354,8 +383,9 @@ __global__ __launch_bounds__(TILE) void k_bond_project(DevPtrs d) {
 }
 
 // Energy of every alive bond at the iterate (trial = false) or the line-search
-// trial state (trial = true), FP64; one compensated partial per tile.
-__global__ __launch_bounds__(TILE) void k_bond_energy(DevPtrs d, int trial) {
+// trial state (trial = true), FP64; one compensated partial per tile.  mid:
+// V at the midpoint (x + x_n)/2 of that state.
+__global__ __launch_bounds__(TILE) void k_bond_energy(DevPtrs d, int trial, int mid) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int b = lb * TILE + threadIdx.x;
   const int scene = d.bsid[lb * TILE];
@@ -368,7 +398,12 @@ __global__ __launch_bounds__(TILE) void k_bond_energy(DevPtrs d, int trial) {
   if (sl.x >= 0 && d.alive[b]) {
     const int2 ij = d.bij[b];
     BondGeom g;
-    bond_geometry(P[ij.x], Q[ij.x], P[ij.y], Q[ij.y], d.brest_a[b], d.brest_b[b], g);
+    double4 Pi = P[ij.x], Qi = Q[ij.x], Pj = P[ij.y], Qj = Q[ij.y];
+    if (mid) {
+      Pi = mid4(Pi, d.pn[ij.x]); Qi = mid4(Qi, d.qn[ij.x]);
+      Pj = mid4(Pj, d.pn[ij.y]); Qj = mid4(Qj, d.qn[ij.y]);
+    }
+    bond_geometry(Pi, Qi, Pj, Qj, d.brest_a[b], d.brest_b[b], g);
     // q_j = -q_i leaves the shear midpoint undefined: outside the potential's
     // domain, so the objective is infinite and the line search backtracks
     kadd(esum, dot4(g.w, g.w) < 1e-12 ? INFINITY : bond_energy_of(g));
@@ -377,6 +412,59 @@ __global__ __launch_bounds__(TILE) void k_bond_energy(DevPtrs d, int trial) {
   // the line-search decision)
   const KSum tot = block_ksum(esum);
   if (threadIdx.x == 0) d.part_a[lb] = make_double2(tot.s, tot.c);
+}
+
+// Euclidean gradient of V_b over (p_i, q_i, p_j, q_j) at the previous
+// midpoint (x_{n-1} + x_n)/2, x_{n-1} = 2 x_n - x_hat, of every bond, for the
+// constant term z_hat of the variational midpoint form (Section 3.1).  The
+// bond writes its two 7-vectors into its slots of row i and row j (8 doubles
+// per slot, in the off-diagonal block buffer, which holds at least 64 bytes
+// per slot and is free until the first Hessian of the step).
+__global__ __launch_bounds__(TILE) void k_bond_force(DevPtrs d) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int b = lb * TILE + threadIdx.x;
+  const int scene = d.bsid[lb * TILE];
+  if (!d.ctl[scene].newton_active) return;
+  const int2 sl = d.bslot[b];
+  if (sl.x < 0) return;
+  double *fi = reinterpret_cast<double *>(d.hoff) + (size_t)sl.x * 8;
+  double *fj = reinterpret_cast<double *>(d.hoff) + (size_t)sl.y * 8;
+  double gi[7] = {0, 0, 0, 0, 0, 0, 0}, gj[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (d.alive[b]) {
+    const int2 ij = d.bij[b];
+    auto prev_mid = [&](int r, double4 &p, double4 &q) {
+      const double4 pn = d.pn[r], qn = d.qn[r], ph = d.ph[r], qh = d.qh[r];
+      // x_{n-1} = 2 x_n - x_hat
+      p = make_double4(0.5 * ((2.0 * pn.x - ph.x) + pn.x), 0.5 * ((2.0 * pn.y - ph.y) + pn.y),
+                       0.5 * ((2.0 * pn.z - ph.z) + pn.z), 0.0);
+      q = make_double4(0.5 * ((2.0 * qn.x - qh.x) + qn.x), 0.5 * ((2.0 * qn.y - qh.y) + qn.y),
+                       0.5 * ((2.0 * qn.z - qh.z) + qn.z), 0.5 * ((2.0 * qn.w - qh.w) + qn.w));
+    };
+    double4 Pi, Qi, Pj, Qj;
+    prev_mid(ij.x, Pi, Qi);
+    prev_mid(ij.y, Pj, Qj);
+    BondGeom g;
+    bond_geometry(Pi, Qi, Pj, Qj, d.brest_a[b], d.brest_b[b], g);
+    const double ei[4] = {Qi.x, Qi.y, Qi.z, Qi.w}, ej[4] = {Qj.x, Qj.y, Qj.z, Qj.w};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double gu = g.kn * g.e * g.n[k] - g.kts * g.F1 * g.gphi_u[k];
+      gi[k] = -gu;
+      gj[k] = gu;
+    }
+    const double m4[4] = {g.m[0], g.m[1], g.m[2], 0.0};
+    double bqi[4], bqj[4];
+    qmul(ej, m4, bqi);
+    qmul(ei, m4, bqj);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double gw = -g.kts * g.F1 * g.gphi_w[k];
+      gi[3 + k] = gw + bqi[k];
+      gj[3 + k] = gw - bqj[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) { fi[k] = gi[k]; fj[k] = gj[k]; }
 }
 
 // Section 3.3 with implicit forces, at the state x_n (after the step):
@@ -425,16 +513,23 @@ __global__ __launch_bounds__(TILE) void k_bond_fracture(DevPtrs d) {
   }
 }
 
-void launch_bond_eval(const DevPtrs &d, bool mixed, bool psd, bool hess, hipStream_t s) {
+template <bool MID>
+static void launch_bond_eval_t(const DevPtrs &d, bool mixed, bool hess, int nblk, hipStream_t s) {
+  if (mixed) {
+    if (hess) k_bond_eval<float, true, MID><<<nblk, TILE, 0, s>>>(d);
+    else k_bond_eval<float, false, MID><<<nblk, TILE, 0, s>>>(d);
+  } else {
+    if (hess) k_bond_eval<double, true, MID><<<nblk, TILE, 0, s>>>(d);
+    else k_bond_eval<double, false, MID><<<nblk, TILE, 0, s>>>(d);
+  }
+}
+
+void launch_bond_eval(const DevPtrs &d, bool mixed, bool psd, bool hess, bool midpoint,
+                      hipStream_t s) {
   const int nblk = d.nb_pad / TILE;
   if (nblk == 0) return;
-  if (mixed) {
-    if (hess) k_bond_eval<float, true><<<nblk, TILE, 0, s>>>(d);
-    else k_bond_eval<float, false><<<nblk, TILE, 0, s>>>(d);
-  } else {
-    if (hess) k_bond_eval<double, true><<<nblk, TILE, 0, s>>>(d);
-    else k_bond_eval<double, false><<<nblk, TILE, 0, s>>>(d);
-  }
+  if (midpoint) launch_bond_eval_t<true>(d, mixed, hess, nblk, s);
+  else launch_bond_eval_t<false>(d, mixed, hess, nblk, s);
   if (!hess) return;
   if (mixed) {
     if (psd) k_bond_project<float, true><<<nblk, TILE, 0, s>>>(d);
@@ -445,10 +540,16 @@ void launch_bond_eval(const DevPtrs &d, bool mixed, bool psd, bool hess, hipStre
   }
 }
 
-void launch_bond_energy(const DevPtrs &d, bool trial, hipStream_t s) {
+void launch_bond_energy(const DevPtrs &d, bool trial, bool midpoint, hipStream_t s) {
   const int nblk = d.nb_pad / TILE;
   if (nblk == 0) return;
-  k_bond_energy<<<nblk, TILE, 0, s>>>(d, trial ? 1 : 0);
+  k_bond_energy<<<nblk, TILE, 0, s>>>(d, trial ? 1 : 0, midpoint ? 1 : 0);
+}
+
+void launch_bond_force(const DevPtrs &d, hipStream_t s) {
+  const int nblk = d.nb_pad / TILE;
+  if (nblk == 0) return;
+  k_bond_force<<<nblk, TILE, 0, s>>>(d);
 }
 
 void launch_bond_fracture(const DevPtrs &d, hipStream_t s) {

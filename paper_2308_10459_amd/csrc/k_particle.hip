@@ -52,30 +52,37 @@ __global__ __launch_bounds__(TILE) void k_copy_state(DevPtrs d) {
 struct PTerms {
   double E;
   double gp[3], gr[3];
-  double kgap;   // k_c if the ground penalty is active
+  double kgap;   // weight * k_c if the ground penalty is active
 };
 
+__device__ __forceinline__ double4 mid4(double4 a, double4 b) {
+  return make_double4(0.5 * (a.x + b.x), 0.5 * (a.y + b.y), 0.5 * (a.z + b.z), 0.5 * (a.w + b.w));
+}
+
+// inertia of (p, q) about the target (ph, qh), plus gravity and ground at the
+// position pv where V is evaluated; their gradient and Hessian with respect
+// to p enter with the weights 1, 1 (pv = p) or 1/2, 1/4 (pv = (p + p_n)/2)
 __device__ __forceinline__ void particle_terms(const Params &P, double kc, double idt2, double4 pc,
                                                double4 p, double4 q, double4 ph, double4 qh,
-                                               PTerms &t) {
+                                               double4 pv, double wg, double wh, PTerms &t) {
   const double m = pc.x, c = pc.y, rad = pc.z;
   const double ep[3] = {p.x - ph.x, p.y - ph.y, p.z - ph.z};
   const double eq[4] = {q.x - qh.x, q.y - qh.y, q.z - qh.z, q.w - qh.w};
   t.E = 0.5 * m * idt2 * (ep[0] * ep[0] + ep[1] * ep[1] + ep[2] * ep[2]) +
         0.5 * c * idt2 * (eq[0] * eq[0] + eq[1] * eq[1] + eq[2] * eq[2] + eq[3] * eq[3]) -
-        m * (P.gx * p.x + P.gy * p.y + P.gz * p.z);
-  t.gp[0] = m * idt2 * ep[0] - m * P.gx;
-  t.gp[1] = m * idt2 * ep[1] - m * P.gy;
-  t.gp[2] = m * idt2 * ep[2] - m * P.gz;
+        m * (P.gx * pv.x + P.gy * pv.y + P.gz * pv.z);
+  t.gp[0] = m * idt2 * ep[0] - wg * m * P.gx;
+  t.gp[1] = m * idt2 * ep[1] - wg * m * P.gy;
+  t.gp[2] = m * idt2 * ep[2] - wg * m * P.gz;
   t.kgap = 0.0;
   if (kc != 0.0) {
-    const double gap = P.gnx * p.x + P.gny * p.y + P.gnz * p.z - P.gh - rad;
+    const double gap = P.gnx * pv.x + P.gny * pv.y + P.gnz * pv.z - P.gh - rad;
     if (gap < 0.0) {
       t.E += 0.5 * kc * gap * gap;
-      t.gp[0] += kc * gap * P.gnx;
-      t.gp[1] += kc * gap * P.gny;
-      t.gp[2] += kc * gap * P.gnz;
-      t.kgap = kc;
+      t.gp[0] += wg * kc * gap * P.gnx;
+      t.gp[1] += wg * kc * gap * P.gny;
+      t.gp[2] += wg * kc * gap * P.gnz;
+      t.kgap = wh * kc;
     }
   }
   // reduced rotational gradient G_l(q) c/dt^2 (q - q_hat) = vec(conj(q) (c/dt^2)(q - q_hat))
@@ -156,9 +163,11 @@ __global__ __launch_bounds__(TILE) void k_particle_eval(DevPtrs d, Params P, int
       }
     }
     const double idt2 = potential_only ? 0.0 : ctl.inv_dt2;
-    const double4 q = d.qx[r], qh = d.qh[r];
+    const double4 p = d.px[r], q = d.qx[r], qh = d.qh[r];
+    const double4 pv = P.midpoint ? mid4(p, d.pn[r]) : p;
     PTerms t;
-    particle_terms(P, ctl.kc, idt2, d.pconst[r], d.px[r], q, d.ph[r], qh, t);
+    particle_terms(P, ctl.kc, idt2, d.pconst[r], p, q, d.ph[r], qh, pv, P.midpoint ? 0.5 : 1.0,
+                   P.midpoint ? 0.25 : 1.0, t);
     kadd(e, t.E);
     z[0] += t.gp[0]; z[1] += t.gp[1]; z[2] += t.gp[2];
     z[3] += t.gr[0]; z[4] += t.gr[1]; z[5] += t.gr[2];
@@ -212,6 +221,41 @@ __global__ __launch_bounds__(TILE) void k_particle_eval(DevPtrs d, Params P, int
   }
 }
 
+// z_hat = x_hat - 1/2 M_s^{-1} dt^2 grad V((x_{n-1} + x_n)/2) of the variational
+// midpoint form (Section 3.1), written over the prediction (ph, qh) of the
+// free particles: the bond gradients that k_bond_force left in the row's
+// slots are summed in slot order, then gravity and ground at the previous
+// midpoint are added.  Fixed and kinematic particles keep x_hat.
+__global__ __launch_bounds__(TILE) void k_midpoint_target(DevPtrs d, Params P) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  const SceneCtl &ctl = d.ctl[d.psid[blockIdx.x * TILE]];
+  if (!ctl.newton_active) return;
+  if (d.flags[r] != 0) return;
+  const double *fh = reinterpret_cast<const double *>(d.hoff);
+  double g[7] = {0, 0, 0, 0, 0, 0, 0};
+  const int beg = d.row_ptr[r], end = d.row_ptr[r + 1];
+  for (int k = beg; k < end; ++k) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) g[c] += fh[(size_t)k * 8 + c];
+  }
+  const double4 pc = d.pconst[r], pn = d.pn[r], ph = d.ph[r], qh = d.qh[r];
+  const double m = pc.x, c = pc.y, rad = pc.z;
+  g[0] -= m * P.gx; g[1] -= m * P.gy; g[2] -= m * P.gz;
+  if (ctl.kc != 0.0) {
+    const double mp[3] = {0.5 * ((2.0 * pn.x - ph.x) + pn.x), 0.5 * ((2.0 * pn.y - ph.y) + pn.y),
+                          0.5 * ((2.0 * pn.z - ph.z) + pn.z)};
+    const double gap = P.gnx * mp[0] + P.gny * mp[1] + P.gnz * mp[2] - P.gh - rad;
+    if (gap < 0.0) {
+      g[0] += ctl.kc * gap * P.gnx;
+      g[1] += ctl.kc * gap * P.gny;
+      g[2] += ctl.kc * gap * P.gnz;
+    }
+  }
+  const double dt2 = ctl.dt * ctl.dt, fm = 0.5 * dt2 / m, fc = 0.5 * dt2 / c;
+  d.ph[r] = make_double4(ph.x - fm * g[0], ph.y - fm * g[1], ph.z - fm * g[2], ph.w);
+  d.qh[r] = make_double4(qh.x - fc * g[3], qh.y - fc * g[4], qh.z - fc * g[5], qh.w - fc * g[6]);
+}
+
 // trial state of the line search: p + a dp, q (x) exp(a y) renormalised in
 // FP64 (Section 4.1, manifold-update-1/2; dq = G_l(q)^T y = q (y, 0) so the
 // geodesic step is a right multiplication by (sin|a y| y/|y|, cos|a y|)),
@@ -246,7 +290,8 @@ __global__ __launch_bounds__(TILE) void k_ls_trial(DevPtrs d, Params P) {
     d.pt[r] = pt;
     d.qt[r] = qt;
     PTerms t;
-    particle_terms(P, ctl.kc, ctl.inv_dt2, d.pconst[r], pt, qt, d.ph[r], d.qh[r], t);
+    const double4 pv = P.midpoint ? mid4(pt, d.pn[r]) : pt;
+    particle_terms(P, ctl.kc, ctl.inv_dt2, d.pconst[r], pt, qt, d.ph[r], d.qh[r], pv, 1.0, 1.0, t);
     kadd(e, t.E);
     mv = fmax(fmax(fabs(pt.x - p.x), fabs(pt.y - p.y)), fabs(pt.z - p.z));
     mv = fmax(mv, fmax(fmax(fabs(qt.x - q.x), fabs(qt.y - q.y)), fmax(fabs(qt.z - q.z), fabs(qt.w - q.w))));
@@ -304,6 +349,9 @@ void launch_particle_eval(const DevPtrs &d, const Params &P, bool mixed, bool he
     if (hess) k_particle_eval<double, true><<<nb, TILE, 0, s>>>(d, P, po);
     else k_particle_eval<double, false><<<nb, TILE, 0, s>>>(d, P, po);
   }
+}
+void launch_midpoint_target(const DevPtrs &d, const Params &P, hipStream_t s) {
+  k_midpoint_target<<<d.n_pad / TILE, TILE, 0, s>>>(d, P);
 }
 void launch_ls_trial(const DevPtrs &d, const Params &P, hipStream_t s) {
   k_ls_trial<<<d.n_pad / TILE, TILE, 0, s>>>(d, P);

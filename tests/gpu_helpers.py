@@ -46,16 +46,20 @@ def subsystem(scene, sample):
     return sub, parts, bmask
 
 
-def sampled_oracle_egh(scene, state, eval_pos, eval_quat, dt, sample, psd=True, alive=None):
+def sampled_oracle_egh(scene, state, eval_pos, eval_quat, dt, sample, psd=True, alive=None,
+                       midpoint=False):
     """Oracle reduced gradient / diagonal blocks of the sampled particles and the
-    off-diagonal blocks of their bonds, at full-system values."""
+    off-diagonal blocks of their bonds, at full-system values.  The subsystem
+    holds every bond of a sampled particle, so the midpoint form's z_hat of the
+    sampled particles is the full system's too."""
     sub, parts, bmask = subsystem(scene, sample)
     o = Oracle(sub)
     st = {k: state[k][parts] for k in ("pos", "quat", "vel", "qvel")}
     if alive is not None:
         st["alive"] = alive[bmask]
     o.set_state(**st)
-    _, z, hd, ho = o.energy_grad_hess(dt, eval_pos[parts], eval_quat[parts], psd=psd)
+    _, z, hd, ho = o.energy_grad_hess(dt, eval_pos[parts], eval_quat[parts], psd=psd,
+                                      midpoint=midpoint)
     pos_in_sub = np.searchsorted(parts, np.unique(sample))
     return z[pos_in_sub], hd[pos_in_sub], ho, np.nonzero(bmask)[0]
 

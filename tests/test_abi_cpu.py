@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(B):
 
 def test_struct_sizes_match_header_layout(B):
     # doubles first then int32s, natural alignment: the ctypes mirror must not pad differently
-    assert C.sizeof(B.bdem_options) == 8 * (3 + 3 + 1 + 1 + 2 + 4) + 4 * 8
+    assert C.sizeof(B.bdem_options) == 8 * (3 + 3 + 1 + 1 + 2 + 4) + 4 * 10
     assert C.sizeof(B.bdem_material) == 8 * 9 + 4 * 2
     assert C.sizeof(B.bdem_step_stats) == 4 * 4 + 8 + 8 * 3 + 8 * 8
     assert C.sizeof(B.bdem_tuning) == 4 * 6 + 8 * 3
@@ -53,6 +53,7 @@ def test_default_options(B):
     assert o.newton_rtol == 1e-8 and o.cg_rtol_max == 0.5 and o.max_cg == 2000
     assert o.precision == B.BDEM_PREC_FP64 and o.break_each_step == 1
     assert o.solver == B.BDEM_SOLVER_NEWTON
+    assert o.integrator == B.BDEM_INTEGRATOR_EULER
 
 
 def test_workspace_bytes_scales_with_problem(B):
@@ -109,3 +110,4 @@ def test_create_rejects_friction_and_bad_limits(B):
     assert _create_error(B, sc, max_cg=0) == -1
     assert _create_error(B, sc, precision=5) == -1
     assert _create_error(B, sc, solver=2) == -1
+    assert _create_error(B, sc, integrator=2) == -1

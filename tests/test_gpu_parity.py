@@ -736,3 +736,102 @@ def test_ceramic_plate_step_is_a_fixed_point(B, check_step):
     assert np.all(got["alive"][~was] == 0)
     assert np.abs(np.linalg.norm(got["quat"], axis=1) - 1).max() <= 4.5e-16
     sim.close()
+
+
+# --------------------------------------------------------------------------
+# the variational midpoint form of Section 3.1
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("psd", [False, True])
+@pytest.mark.parametrize("dims", [(5, 4, 3), (11, 10, 9)])
+def test_midpoint_energy_grad_hess_block(B, mixed, psd, dims):
+    """Objective, reduced gradient and Hessian of the midpoint form at a state
+    away from x_n (moving particles, ground contact): V and its derivatives
+    at (x + x_n)/2 with weights 1/2 and 1/4, inertia about z_hat."""
+    log(f"[midpoint egh block] dims={dims} mixed={mixed} psd={psd}")
+    sc, st = _perturbed_block(*dims, ground=True)
+    o = oracle_for(sc, st)
+    dt = 1e-3
+    ev_pos, ev_quat, _, _ = S.perturb_state(sc, 5, 1e-4, 0.01)
+    ev_pos[sc.flags != 0], ev_quat[sc.flags != 0] = st["pos"][sc.flags != 0], st["quat"][sc.flags != 0]
+    phi_o, z_o, hd_o, ho_o = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=psd, midpoint=True)
+    sim = make_sim(sc, mixed=mixed, integrator=B.BDEM_INTEGRATOR_MIDPOINT)
+    sim.set_state(**st)
+    what = B.BDEM_EGH_E | B.BDEM_EGH_G | B.BDEM_EGH_H | (B.BDEM_EGH_PSD if psd else 0)
+    phi, z, hd, ho = sim.energy_grad_hess(dt, what, ev_pos, ev_quat)
+    log(f"  phi {phi:.15e} oracle {phi_o:.15e}; grad err {np.abs(z - z_o).max() / np.abs(z_o).max():.2e}")
+    assert abs(phi - phi_o) <= 1e-12 * abs(phi_o)
+    assert np.abs(z - z_o).max() <= 1e-11 * np.abs(z_o).max()
+    scale = row_scale(hd_o, ho_o, sc.ij, sc.n)
+    tol = 1e-4 if mixed else 1e-10
+    ed = np.linalg.norm((hd - hd_o).reshape(sc.n, -1), axis=1) / scale
+    eo = np.linalg.norm((ho - ho_o).reshape(sc.nb, -1), axis=1) / np.minimum(
+        scale[sc.ij[:, 0]], scale[sc.ij[:, 1]])
+    log(f"  max diag err {ed.max():.2e}  max off err {eo.max():.2e}")
+    assert ed.max() <= tol and eo.max() <= tol
+    # the same state under the implicit-Euler form gives another gradient
+    _, z_e, _, _ = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=psd, hess=False)
+    assert np.abs(z_e - z).max() > 1e-3 * np.abs(z).max()
+    pv, _, _, _ = sim.energy_grad_hess(dt, B.BDEM_EGH_E | B.BDEM_EGH_POTENTIAL_ONLY, ev_pos, ev_quat)
+    pv_o = o.energy(dt, ev_pos, ev_quat, potential_only=True, midpoint=True)
+    assert abs(pv - pv_o) <= 1e-12 * max(abs(pv_o), 1e-30) + 1e-18
+    sim.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_midpoint_step_block_1000(B, mixed):
+    """Ten midpoint steps of the 1000-particle block against the oracle's."""
+    log(f"[midpoint step block] mixed={mixed}")
+    sc = S.make_block()
+    o = oracle_for(sc)
+    sim = make_sim(sc, mixed=mixed, integrator=B.BDEM_INTEGRATOR_MIDPOINT, **TIGHT)
+    tol = 1e-5 if mixed else 1e-8
+    prev = o.get_state()
+    for k in range(10):
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300, midpoint=1)
+        sg = sim.step(sc.dt)
+        ref, got = o.get_state(), sim.get_state()
+        assert sg["rc"] == 0 and so["rc"] == 0, (sg, so)
+        _compare_states(sc, got, ref, prev, tol, f"step {k} newton {sg['newton_iters']} cg {sg['cg_iters']}")
+        np.testing.assert_allclose(got["vel"], ref["vel"], rtol=0,
+                                   atol=tol * np.abs(ref["vel"]).max() * 10 + 1e-14)
+        assert abs(sg["phi"] - so["phi"]) <= (1e-6 if mixed else 1e-10) * abs(so["phi"])
+        prev = ref
+    sim.close()
+
+
+def test_midpoint_ceramic_plate_step_is_a_fixed_point(B):
+    """One midpoint step of the 219K-particle plate (mixed precision), checked
+    as the implicit-Euler step is: the oracle's midpoint gradient of the GPU's
+    new state at sampled particles, the objective there, and the broken set
+    on certified bonds."""
+    from oracle.oracle import Oracle
+    sc = S.make_ceramic_plate()
+    log(f"[midpoint ceramic plate] n={sc.n} nb={sc.nb}")
+    sim = make_sim(sc, mixed=True, newton_rtol=1e-10, integrator=B.BDEM_INTEGRATOR_MIDPOINT)
+    st0 = sim.get_state()
+    sg = sim.step(sc.dt)
+    log(f"  newton {sg['newton_iters']} cg {sg['cg_iters']} grad0 {sg['grad0']:.3e} "
+        f"final {sg['grad_final']:.3e} broken {sg['bonds_broken']}")
+    got = sim.get_state()
+    sample = np.random.default_rng(3).choice(sc.n, size=300, replace=False)
+    z_o, _, _, _ = sampled_oracle_egh(sc, st0, got["pos"], got["quat"], sc.dt, sample, psd=True,
+                                      alive=st0["alive"], midpoint=True)
+    log(f"  oracle |z| at sampled particles: {np.abs(z_o).max():.3e}")
+    assert sg["rc"] == 0
+    assert sg["grad_final"] <= 1e-5 * sg["grad0"]
+    assert np.abs(z_o).max() <= sg["grad_final"] * (1 + 1e-6) + 1e-10 * sg["grad0"]
+    o = Oracle(sc)
+    o.set_state(pos=st0["pos"], quat=st0["quat"], vel=st0["vel"], qvel=st0["qvel"], alive=st0["alive"])
+    phi_o = o.energy(sc.dt, got["pos"], got["quat"], midpoint=True)
+    log(f"  objective: GPU {sg['phi']:.12e} oracle {phi_o:.12e}")
+    assert abs(sg["phi"] - phi_o) <= 1e-6 * abs(phi_o)
+    sig, tau = o.stresses(got["pos"], got["quat"])
+    m = sc.materials[0]
+    brk = (sig > m["sigma_c"]) | (tau > m["tau_c"])
+    safe = (np.abs(sig / m["sigma_c"] - 1) >= 1e-3) & (np.abs(tau / m["tau_c"] - 1) >= 1e-3)
+    log(f"  oracle breaks {np.count_nonzero(brk)} ; uncertified {np.count_nonzero(~safe)}")
+    np.testing.assert_array_equal(got["alive"][safe] == 0, brk[safe])
+    assert np.abs(np.linalg.norm(got["quat"], axis=1) - 1).max() <= 4.5e-16
+    sim.close()
