@@ -48,6 +48,14 @@ struct orc_sys {
   double *l0, *d0, *R0, *kn, *kt, *K, *S, *r0, *I, *J, *sigc, *tauc;
   int32_t *tension_only;
   double gravity[3], gn[3], gh, kc;
+  /* element-element repulsion and friction (Section 5.4) */
+  double kself, cmargin, mu_s, mu_r;
+  uint64_t *bkey;                       /* sorted (min(i,j) << 32 | max(i,j)) of every bond */
+  int64_t *bkey_idx;                    /* bond index of each sorted key */
+  int64_t ncp;                          /* contact candidate pairs of the current step */
+  int32_t *cp;                          /* (i, j) with i < j */
+  double *hcp;                          /* (i, j) 6x6 block of each pair at the last Hessian */
+  int hcp_valid;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -182,6 +190,7 @@ void orc_destroy(orc_sys *s) {
                     s->d0, s->R0, s->kn, s->kt, s->K, s->S, s->r0, s->I, s->J, s->sigc, s->tauc};
   for (size_t k = 0; k < sizeof arrs / sizeof arrs[0]; ++k) free(arrs[k]);
   free(s->flags); free(s->ij); free(s->alive); free(s->tension_only);
+  free(s->bkey); free(s->bkey_idx); free(s->cp); free(s->hcp);
   free(s);
 }
 
@@ -275,7 +284,98 @@ orc_sys *orc_create(int32_t n, const double *pos, const double *quat, const doub
   for (int k = 0; k < 3; ++k) s->gn[k] = gnn > 0 ? env[3 + k] / gnn : 0.0;
   s->gh = env[6];
   s->kc = env[7] < 0.0 ? Emax * rmax : env[7];
+  /* element repulsion stiffness k_ec (< 0: E_max r_max, the order Section
+   * 5.4 recommends; 0: off), candidate margin (< 0: r_max), friction */
+  s->kself = env[8] < 0.0 ? Emax * rmax : env[8];
+  s->cmargin = env[9] < 0.0 ? rmax : env[9];
+  s->mu_s = env[10];
+  s->mu_r = env[11];
+  /* bond lookup by endpoint pair */
+  s->bkey = (uint64_t *)malloc(B * sizeof(uint64_t));
+  s->bkey_idx = (int64_t *)malloc(B * sizeof(int64_t));
+  for (int64_t b = 0; b < nb; ++b) {
+    uint64_t i = (uint64_t)ij[2 * b], j = (uint64_t)ij[2 * b + 1];
+    s->bkey[b] = i < j ? (i << 32 | j) : (j << 32 | i);
+    s->bkey_idx[b] = b;
+  }
+  for (int64_t a = 1; a < nb; ++a) {   /* insertion sort: test sizes only */
+    uint64_t k = s->bkey[a];
+    int64_t v = s->bkey_idx[a], c = a - 1;
+    while (c >= 0 && s->bkey[c] > k) { s->bkey[c + 1] = s->bkey[c]; s->bkey_idx[c + 1] = s->bkey_idx[c]; --c; }
+    s->bkey[c + 1] = k;
+    s->bkey_idx[c + 1] = v;
+  }
   return s;
+}
+
+/* bond index joining i and j, or -1 */
+static int64_t find_bond(const orc_sys *s, int32_t i, int32_t j) {
+  uint64_t a = (uint64_t)(i < j ? i : j), b = (uint64_t)(i < j ? j : i), k = a << 32 | b;
+  int64_t lo = 0, hi = s->nb - 1;
+  while (lo <= hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (s->bkey[mid] == k) return s->bkey_idx[mid];
+    if (s->bkey[mid] < k) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+/* Candidate pairs of the element repulsion for one step: every pair i < j
+ * not joined by an alive bond whose centres at the positions p are closer
+ * than r_i + r_j + margin (all pairs are tested). */
+int64_t orc_contact_candidates(orc_sys *s, const double *p) {
+  free(s->cp); free(s->hcp);
+  s->cp = NULL; s->hcp = NULL; s->ncp = 0; s->hcp_valid = 0;
+  if (!(s->kself > 0.0)) return 0;
+  int64_t cap = 0;
+  for (int32_t i = 0; i < s->n; ++i)
+    for (int32_t j = i + 1; j < s->n; ++j) {
+      double u[3] = {p[3 * j] - p[3 * i], p[3 * j + 1] - p[3 * i + 1], p[3 * j + 2] - p[3 * i + 2]};
+      double reach = s->radius[i] + s->radius[j] + s->cmargin;
+      if (!(dot3(u, u) < reach * reach)) continue;
+      int64_t b = find_bond(s, i, j);
+      if (b >= 0 && s->alive[b]) continue;
+      if (s->ncp == cap) {
+        cap = cap ? 2 * cap : 64;
+        s->cp = (int32_t *)realloc(s->cp, 2 * cap * sizeof(int32_t));
+      }
+      s->cp[2 * s->ncp] = i;
+      s->cp[2 * s->ncp + 1] = j;
+      s->ncp++;
+    }
+  s->hcp = (double *)calloc(36 * (size_t)(s->ncp > 0 ? s->ncp : 1), sizeof(double));
+  return s->ncp;
+}
+
+int64_t orc_contacts(const orc_sys *s, int32_t *pairs, int64_t cap) {
+  if (pairs)
+    for (int64_t k = 0; k < s->ncp && k < cap; ++k) { pairs[2 * k] = s->cp[2 * k]; pairs[2 * k + 1] = s->cp[2 * k + 1]; }
+  return s->ncp;
+}
+
+/* Element repulsion of candidate pair k at the positions ep (Section 5.4):
+ * V = 1/2 k_ec min(0, |p_j - p_i| - r_i - r_j)^2.  Returns the energy;
+ * g6 (p_i, p_j) and H36 (6x6 over (p_i, p_j)) are its Euclidean gradient and
+ * Hessian times wg and wh, zero when the spheres do not overlap. */
+static double contact_pair(const orc_sys *s, int64_t k, const double *ep, double wg, double wh,
+                           double *g6, double *H36) {
+  int32_t i = s->cp[2 * k], j = s->cp[2 * k + 1];
+  if (g6) memset(g6, 0, 6 * sizeof(double));
+  if (H36) memset(H36, 0, 36 * sizeof(double));
+  double u[3] = {ep[3 * j] - ep[3 * i], ep[3 * j + 1] - ep[3 * i + 1], ep[3 * j + 2] - ep[3 * i + 2]};
+  double l = sqrt(dot3(u, u)), d = s->radius[i] + s->radius[j];
+  if (!(l < d) || !(l > 0.0)) return 0.0;
+  double e = l - d, n[3] = {u[0] / l, u[1] / l, u[2] / l};
+  if (g6)
+    for (int r = 0; r < 3; ++r) { g6[r] = -wg * s->kself * e * n[r]; g6[3 + r] = wg * s->kself * e * n[r]; }
+  if (H36)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double h = wh * s->kself * (n[r] * n[c] + (1.0 - d / l) * ((r == c) - n[r] * n[c]));
+        H36[r * 6 + c] = h; H36[(3 + r) * 6 + 3 + c] = h;
+        H36[r * 6 + 3 + c] = -h; H36[(3 + r) * 6 + c] = -h;
+      }
+  return 0.5 * s->kself * e * e;
 }
 
 int orc_get_state(const orc_sys *s, double *pos, double *quat, double *vel, double *qvel,
@@ -844,6 +944,7 @@ static int objective_energy(const orc_sys *s, double dt, const objective *ob, co
     eb[b] = parts[0] + parts[1] + parts[2];
   }
   for (int64_t b = 0; b < s->nb; ++b) kadd(&acc, eb[b]);
+  for (int64_t k = 0; k < s->ncp; ++k) kadd(&acc, contact_pair(s, k, ep, 1.0, 1.0, NULL, NULL));
   *phi = acc.s + acc.c;
   free(eb); free(ep); free(eq);
   return 0;
@@ -899,6 +1000,29 @@ static int objective_grad_hess(const orc_sys *s, double dt, const objective *ob,
       for (int r = 0; r < 6; ++r)
         for (int c = 0; c < 6; ++c) hoff[36 * b + r * 6 + c] = H12[r * 12 + 6 + c];
   }
+  /* element repulsion: position blocks only, the pair's 6x6 projected as a whole */
+  for (int64_t k = 0; k < s->ncp; ++k) {
+    int32_t i = s->cp[2 * k], j = s->cp[2 * k + 1];
+    double g6[6], H36[36], P36[36];
+    contact_pair(s, k, ep, wg, wh, g6, H36);
+    if (psd) orc_psd_project(6, H36, P36);
+    else memcpy(P36, H36, sizeof P36);
+    if (z) for (int r = 0; r < 3; ++r) { z[6 * i + r] += g6[r]; z[6 * j + r] += g6[3 + r]; }
+    if (hdiag)
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          hdiag[36 * i + r * 6 + c] += P36[r * 6 + c];
+          hdiag[36 * j + r * 6 + c] += P36[(3 + r) * 6 + 3 + c];
+        }
+    if (hoff) {
+      double *hc = s->hcp + 36 * k;
+      memset(hc, 0, 36 * sizeof(double));
+      if (is_solved(s, i) && is_solved(s, j))
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) hc[r * 6 + c] = P36[r * 6 + 3 + c];
+    }
+  }
+  if (hoff) ((orc_sys *)s)->hcp_valid = 1;
   /* fixed / kinematic particles are not unknowns */
   for (int32_t i = 0; i < n; ++i) {
     if (is_solved(s, i)) continue;
@@ -920,9 +1044,18 @@ static void step_target(const orc_sys *s, double dt, int midpoint, double *tp, d
   else orc_predict(s, dt, tp, tq);
 }
 
-int orc_objective(const orc_sys *s, double dt, int midpoint, const double *pos,
+/* contact candidates of the step that would start from the current state */
+static void step_candidates(orc_sys *s, double dt) {
+  double *ph = (double *)malloc(sizeof(double) * 3 * s->n), *qh = (double *)malloc(sizeof(double) * 4 * s->n);
+  orc_predict(s, dt, ph, qh);
+  orc_contact_candidates(s, ph);
+  free(ph); free(qh);
+}
+
+int orc_objective(orc_sys *s, double dt, int midpoint, const double *pos,
                   const double *quat, int potential_only, double *phi) {
   double *tp = (double *)malloc(sizeof(double) * 3 * s->n), *tq = (double *)malloc(sizeof(double) * 4 * s->n);
+  step_candidates(s, dt);
   step_target(s, dt, midpoint, tp, tq);
   objective ob = {midpoint != 0, tp, tq};
   int rc = objective_energy(s, dt, &ob, pos, quat, potential_only, phi);
@@ -930,10 +1063,11 @@ int orc_objective(const orc_sys *s, double dt, int midpoint, const double *pos,
   return rc;
 }
 
-int orc_objective_grad_hess(const orc_sys *s, double dt, int midpoint, const double *pos,
+int orc_objective_grad_hess(orc_sys *s, double dt, int midpoint, const double *pos,
                             const double *quat, int psd, double *phi, double *z, double *hdiag,
                             double *hoff) {
   double *tp = (double *)malloc(sizeof(double) * 3 * s->n), *tq = (double *)malloc(sizeof(double) * 4 * s->n);
+  step_candidates(s, dt);
   step_target(s, dt, midpoint, tp, tq);
   objective ob = {midpoint != 0, tp, tq};
   int rc = objective_grad_hess(s, dt, &ob, pos, quat, psd, phi, z, hdiag, hoff);
@@ -941,12 +1075,12 @@ int orc_objective_grad_hess(const orc_sys *s, double dt, int midpoint, const dou
   return rc;
 }
 
-int orc_energy(const orc_sys *s, double dt, const double *pos, const double *quat,
+int orc_energy(orc_sys *s, double dt, const double *pos, const double *quat,
                int potential_only, double *phi) {
   return orc_objective(s, dt, 0, pos, quat, potential_only, phi);
 }
 
-int orc_energy_grad_hess(const orc_sys *s, double dt, const double *pos, const double *quat,
+int orc_energy_grad_hess(orc_sys *s, double dt, const double *pos, const double *quat,
                          int psd, double *phi, double *z, double *hdiag, double *hoff) {
   return orc_objective_grad_hess(s, dt, 0, pos, quat, psd, phi, z, hdiag, hoff);
 }
@@ -954,6 +1088,17 @@ int orc_energy_grad_hess(const orc_sys *s, double dt, const double *pos, const d
 void orc_hess_apply(const orc_sys *s, const double *hdiag, const double *hoff,
                     const double *x, double *y) {
   for (int32_t i = 0; i < s->n; ++i) mm(6, 6, 1, hdiag + 36 * i, x + 6 * i, y + 6 * i);
+  /* element-repulsion couplings of the last Hessian evaluation */
+  if (s->hcp_valid)
+    for (int64_t k = 0; k < s->ncp; ++k) {
+      int32_t i = s->cp[2 * k], j = s->cp[2 * k + 1];
+      const double *Hc = s->hcp + 36 * k;
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+          y[6 * i + r] += Hc[r * 6 + c] * x[6 * j + c];
+          y[6 * j + c] += Hc[r * 6 + c] * x[6 * i + r];
+        }
+    }
   for (int64_t b = 0; b < s->nb; ++b) {
     if (!s->alive[b]) continue;
     int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
@@ -1126,6 +1271,97 @@ int orc_break_bonds(orc_sys *s, int64_t *n_broken) {
 /* Algorithm 3: one implicit step, manifold Newton (Algorithm 2) inside      */
 /* ------------------------------------------------------------------------ */
 
+/* Friction of Section 5.4, applied to the velocities after the step, from
+ * the contacts at x_{n+1}: the ground (gap < 0, F_n = k_c |gap|, the ground at
+ * rest) and every candidate pair that overlaps (F_n = k_ec |l - r_i - r_j|).
+ * Per contact, with the relative velocity v_ij = v_n + v_t about the contact
+ * normal and the relative angular velocity w_ij (world frame,
+ * w = 2 vec(qdot conj(q))):
+ *   dv_i = -min(1, mu_s |F_n| dt / (m_i |v_t|)) v_t,
+ *   dw_i = -min(1, mu_r |F_n| r_i dt / (I_i |w_ij|)) w_ij,   I_i = 2/5 m_i r_i^2.
+ * The sums over a particle's contacts are projected on the direction of its
+ * own velocity (angular velocity) and clipped so they at most stop it.  All
+ * particles use the velocities before friction; fixed and kinematic
+ * particles keep theirs. */
+static void ang_vel(const double *q, const double *qd, double *w) {
+  double qc[4] = {-q[0], -q[1], -q[2], q[3]}, t[4];
+  orc_quat_mul(qd, qc, t);
+  w[0] = 2.0 * t[0]; w[1] = 2.0 * t[1]; w[2] = 2.0 * t[2];
+}
+
+static void friction_contact(double mu_s, double mu_r, double Fn, double dt, double m, double Iw,
+                             double r, const double *n, const double *vrel, const double *wrel,
+                             double *dv, double *dw) {
+  double vn = dot3(vrel, n), vt[3] = {vrel[0] - vn * n[0], vrel[1] - vn * n[1], vrel[2] - vn * n[2]};
+  double vtn = sqrt(dot3(vt, vt));
+  if (mu_s > 0.0 && vtn > 0.0) {
+    double f = fmin(1.0, mu_s * Fn * dt / (m * vtn));
+    for (int k = 0; k < 3; ++k) dv[k] -= f * vt[k];
+  }
+  double wn = sqrt(dot3(wrel, wrel));
+  if (mu_r > 0.0 && wn > 0.0) {
+    double f = fmin(1.0, mu_r * Fn * r * dt / (Iw * wn));
+    for (int k = 0; k < 3; ++k) dw[k] -= f * wrel[k];
+  }
+}
+
+static void clip_along(const double *v, const double *d, double *out) {
+  double vn = sqrt(dot3(v, v));
+  out[0] = out[1] = out[2] = 0.0;
+  if (!(vn > 0.0)) return;
+  double s = dot3(d, v) / vn;
+  s = fmax(-vn, fmin(0.0, s));
+  for (int k = 0; k < 3; ++k) out[k] = s * v[k] / vn;
+}
+
+void orc_friction(orc_sys *s, double dt) {
+  int32_t n = s->n;
+  double *dv = (double *)calloc(3 * (size_t)n, sizeof(double)), *dw = (double *)calloc(3 * (size_t)n, sizeof(double));
+  double *w = (double *)malloc(sizeof(double) * 3 * n);
+  for (int32_t i = 0; i < n; ++i) ang_vel(s->quat + 4 * i, s->qvel + 4 * i, w + 3 * i);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!is_solved(s, i) || s->kc == 0.0) continue;
+    double gap = dot3(s->gn, s->pos + 3 * i) - s->gh - s->radius[i];
+    if (!(gap < 0.0)) continue;
+    double m = s->mass[i], Iw = 0.4 * m * s->radius[i] * s->radius[i];
+    friction_contact(s->mu_s, s->mu_r, s->kc * fabs(gap), dt, m, Iw, s->radius[i], s->gn,
+                     s->vel + 3 * i, w + 3 * i, dv + 3 * i, dw + 3 * i);
+  }
+  for (int64_t k = 0; k < s->ncp; ++k) {
+    int32_t a = s->cp[2 * k], b = s->cp[2 * k + 1];
+    const double *pa = s->pos + 3 * a, *pb = s->pos + 3 * b;
+    double u[3] = {pa[0] - pb[0], pa[1] - pb[1], pa[2] - pb[2]};
+    double l = sqrt(dot3(u, u)), d = s->radius[a] + s->radius[b];
+    if (!(l < d) || !(l > 0.0)) continue;
+    double Fn = s->kself * fabs(l - d), nab[3] = {u[0] / l, u[1] / l, u[2] / l};
+    for (int side = 0; side < 2; ++side) {
+      int32_t i = side ? b : a, j = side ? a : b;
+      if (!is_solved(s, i)) continue;
+      double nrm[3] = {side ? -nab[0] : nab[0], side ? -nab[1] : nab[1], side ? -nab[2] : nab[2]};
+      double vrel[3], wrel[3];
+      for (int c = 0; c < 3; ++c) {
+        vrel[c] = s->vel[3 * i + c] - s->vel[3 * j + c];
+        wrel[c] = w[3 * i + c] - w[3 * j + c];
+      }
+      double m = s->mass[i], Iw = 0.4 * m * s->radius[i] * s->radius[i];
+      friction_contact(s->mu_s, s->mu_r, Fn, dt, m, Iw, s->radius[i], nrm, vrel, wrel,
+                       dv + 3 * i, dw + 3 * i);
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    if (!is_solved(s, i)) continue;
+    double cv[3], cw[3];
+    clip_along(s->vel + 3 * i, dv + 3 * i, cv);
+    clip_along(w + 3 * i, dw + 3 * i, cw);
+    for (int c = 0; c < 3; ++c) s->vel[3 * i + c] += cv[c];
+    /* qdot += 1/2 (dw, 0) q */
+    double dq4[4] = {cw[0], cw[1], cw[2], 0.0}, t[4];
+    orc_quat_mul(dq4, s->quat + 4 * i, t);
+    for (int c = 0; c < 4; ++c) s->qvel[4 * i + c] += 0.5 * t[c];
+  }
+  free(dv); free(dw); free(w);
+}
+
 void orc_default_options(orc_options *o) {
   o->tol_abs = 0.0;
   o->tol_rel = 1e-12;
@@ -1162,6 +1398,8 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
     double nq = sqrt(dot4(qh + 4 * i, qh + 4 * i));
     for (int r = 0; r < 4; ++r) x_q[4 * i + r] = qh[4 * i + r] / nq;
   }
+  /* element-repulsion candidates of this step, at the predicted positions */
+  orc_contact_candidates(s, ph);
   /* inertia target: x_hat, or z_hat of the midpoint form (Section 3.1) */
   if (o->midpoint) orc_midpoint_target(s, dt, ph, qh);
   const objective ob = {o->midpoint != 0, ph, qh};
@@ -1278,6 +1516,8 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
       s->quat[4 * i + r] = x_q[4 * i + r];
     }
   }
+  /* friction: explicit velocity change (Section 5.4, Algorithm 3) */
+  if (s->mu_s > 0.0 || s->mu_r > 0.0) orc_friction(s, dt);
   /* update bond state with x_{n+1} */
   if (o->break_bonds) orc_break_bonds(s, &S.bonds_broken);
   S.status = status;

@@ -26,9 +26,10 @@ typedef struct orc_sys orc_sys;
 /* material row: young, poisson, density, sigma_c, tau_c, s_stretch, s_shear,
  * s_twist, s_bend, shear_mode (0: length scaled, 1: literal), tension_only */
 #define ORC_MAT_STRIDE 11
-/* env: gravity[3], ground_normal[3], ground_offset, k_contact
- * (k_contact < 0: E_max * r_max, 0: no ground) */
-#define ORC_ENV_LEN 8
+/* env: gravity[3], ground_normal[3], ground_offset, k_contact,
+ * k_self, contact_margin, mu_s, mu_r
+ * (k_contact, k_self < 0: E_max * r_max, 0: off; contact_margin < 0: r_max) */
+#define ORC_ENV_LEN 12
 
 orc_sys *orc_create(int32_t n, const double *pos, const double *quat, const double *vel,
                     const double *qvel, const double *radius, const int32_t *pmat,
@@ -67,7 +68,7 @@ int orc_predict(const orc_sys *s, double dt, double *p_hat, double *q_hat);
 
 /* Phi at (pos, quat) with the prediction of the current state and dt.
  * potential_only != 0: V only (bonds + gravity + ground, no inertia). */
-int orc_energy(const orc_sys *s, double dt, const double *pos, const double *quat,
+int orc_energy(orc_sys *s, double dt, const double *pos, const double *quat,
                int potential_only, double *phi);
 
 /* z_hat = x_hat - 1/2 M_s^{-1} dt^2 grad V((x_{i-1} + x_i)/2) of the
@@ -81,9 +82,9 @@ int orc_midpoint_target(const orc_sys *s, double dt, double *zp, double *zq);
  * midpoint = 1: Phi(x) = 1/(2 dt^2)|x - z_hat|^2_{M_s} + V((x + x_i)/2), whose
  * Euclidean gradient and Hessian carry V's at the midpoint times 1/2 and 1/4,
  * reduced at the quaternions of x. */
-int orc_objective(const orc_sys *s, double dt, int midpoint, const double *pos,
+int orc_objective(orc_sys *s, double dt, int midpoint, const double *pos,
                   const double *quat, int potential_only, double *phi);
-int orc_objective_grad_hess(const orc_sys *s, double dt, int midpoint, const double *pos,
+int orc_objective_grad_hess(orc_sys *s, double dt, int midpoint, const double *pos,
                             const double *quat, int psd, double *phi, double *z, double *hdiag,
                             double *hoff);
 
@@ -92,8 +93,20 @@ int orc_objective_grad_hess(const orc_sys *s, double dt, int midpoint, const dou
  * (i,j) block, rows of i, columns of j).  Any output may be NULL.  Broken
  * bonds contribute nothing.  Fixed / kinematic particles: z = 0, diagonal
  * block = identity, off-diagonal blocks touching them = 0. */
-int orc_energy_grad_hess(const orc_sys *s, double dt, const double *pos, const double *quat,
+int orc_energy_grad_hess(orc_sys *s, double dt, const double *pos, const double *quat,
                          int psd, double *phi, double *z, double *hdiag, double *hoff);
+
+/* Element repulsion (Section 5.4): the candidate pairs of a step are every
+ * pair i < j not joined by an alive bond whose centres at the positions p
+ * are closer than r_i + r_j + margin; the step takes them at its predicted
+ * positions, and orc_energy / orc_objective* rebuild them from the prediction
+ * of the current state.  Returns their number.  orc_contacts copies up to
+ * cap pairs (2 x int32 each) and returns the number.  The couplings of the
+ * last Hessian evaluation enter orc_hess_apply and orc_pcg. */
+int64_t orc_contact_candidates(orc_sys *s, const double *p);
+int64_t orc_contacts(const orc_sys *s, int32_t *pairs, int64_t cap);
+/* friction of Section 5.4 applied to the current velocities */
+void orc_friction(orc_sys *s, double dt);
 
 /* y = H x with the blocks of orc_energy_grad_hess */
 void orc_hess_apply(const orc_sys *s, const double *hdiag, const double *hoff,

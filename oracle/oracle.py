@@ -19,7 +19,7 @@ _u8p = C.POINTER(C.c_uint8)
 _i64p = C.POINTER(C.c_int64)
 
 MAT_STRIDE = 11
-ENV_LEN = 8
+ENV_LEN = 12
 
 
 class Options(C.Structure):
@@ -70,6 +70,11 @@ def lib():
         L.orc_objective.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, C.c_int, _dp]
         L.orc_objective_grad_hess.argtypes = [C.c_void_p, C.c_double, C.c_int, _dp, _dp, C.c_int,
                                               _dp, _dp, _dp, _dp]
+        L.orc_contact_candidates.restype = C.c_int64
+        L.orc_contact_candidates.argtypes = [C.c_void_p, _dp]
+        L.orc_contacts.restype = C.c_int64
+        L.orc_contacts.argtypes = [C.c_void_p, _i32p, C.c_int64]
+        L.orc_friction.argtypes = [C.c_void_p, C.c_double]
         L.orc_hess_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_pcg.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp]
         L.orc_psd_project.argtypes = [C.c_int, _dp, _dp]
@@ -102,7 +107,8 @@ def material_table(materials):
 
 def env_vector(scene):
     return np.array([*scene.gravity, *scene.ground_normal, scene.ground_offset,
-                     scene.k_contact], dtype=np.float64)
+                     scene.k_contact, scene.k_self, scene.contact_margin, scene.mu_s,
+                     scene.mu_r], dtype=np.float64)
 
 
 def default_options(**kw):
@@ -189,6 +195,19 @@ class Oracle:
         ph, qh = np.empty((self.n, 3)), np.empty((self.n, 4))
         lib().orc_predict(self.h, dt, _p(ph), _p(qh))
         return ph, qh
+
+    def contact_candidates(self, pos):
+        """Candidate pairs of the element repulsion at positions pos (n x 3)."""
+        return lib().orc_contact_candidates(self.h, _p(_f64(pos)))
+
+    def contacts(self):
+        k = lib().orc_contacts(self.h, None, 0)
+        out = np.zeros((k, 2), dtype=np.int32)
+        lib().orc_contacts(self.h, _p(out, _i32p), k)
+        return out
+
+    def friction(self, dt):
+        lib().orc_friction(self.h, dt)
 
     def midpoint_target(self, dt):
         zp, zq = np.empty((self.n, 3)), np.empty((self.n, 4))

@@ -54,6 +54,10 @@ class Scene:
     ground_normal: tuple = (0.0, 0.0, 1.0)
     ground_offset: float = 0.0
     k_contact: float = 0.0   # <0: E_max * r_max ; 0: no ground ; >0: value
+    k_self: float = 0.0      # element repulsion: <0: E_max * r_max ; 0: off ; >0: value
+    contact_margin: float = -1.0   # candidate reach beyond r_i + r_j (<0: r_max)
+    mu_s: float = 0.0        # sliding friction coefficient
+    mu_r: float = 0.0        # rolling friction coefficient
     dt: float = 1e-3
     steps: int = 1
     scene_id: Optional[np.ndarray] = None   # (n,) int32, non-decreasing (batches)

@@ -932,3 +932,194 @@ def test_midpoint_objective_derivatives_along_geodesics(oracle_mod):
     # the midpoint objective differs from the implicit-Euler one at this state
     phi_e, z_e, _, _ = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=False)
     assert np.abs(z_e - z).max() > 1e-3 * np.abs(z).max()
+
+
+# --------------------------------------------------------------------------
+# Section 5.4: element repulsion and friction (PIN-C1..C6)
+# --------------------------------------------------------------------------
+
+def _loose_spheres(pos, r=0.01, **kw):
+    """Spheres without bonds, at the given centres."""
+    sc = S.make_pair(**kw)
+    sc.pos = np.asarray(pos, dtype=np.float64)
+    n = len(sc.pos)
+    sc.quat = np.tile([0.0, 0.0, 0.0, 1.0], (n, 1))
+    sc.vel, sc.qvel = np.zeros((n, 3)), np.zeros((n, 4))
+    sc.radius = np.full(n, r)
+    sc.pmat = np.zeros(n, dtype=np.int32)
+    sc.flags = np.zeros(n, dtype=np.uint8)
+    sc.ij = np.zeros((0, 2), dtype=np.int32)
+    return sc
+
+
+def test_contact_candidates_follow_the_rule(oracle_mod):
+    """Candidates: every pair closer than r_i + r_j + margin that no alive bond
+    joins; a broken bond's pair becomes a candidate."""
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    sc = S.make_block(nx=4, ny=4, nz=3)
+    sc.pos = sc.pos + rng.uniform(-4e-3, 4e-3, size=sc.pos.shape)
+    sc.k_self, sc.contact_margin = 1e5, 3e-3
+    o = O.Oracle(sc)
+    alive = np.ones(sc.nb, dtype=np.uint8)
+    alive[::3] = 0
+    o.set_state(alive=alive)
+    o.contact_candidates(sc.pos)
+    got = {tuple(p) for p in o.contacts()}
+    bonded = {tuple(sorted(p)) for p, a in zip(sc.ij.tolist(), alive) if a}
+    ref = set()
+    for i in range(sc.n):
+        for j in range(i + 1, sc.n):
+            if np.linalg.norm(sc.pos[j] - sc.pos[i]) < 0.02 + 3e-3 and (i, j) not in bonded:
+                ref.add((i, j))
+    assert got == ref and len(ref) > 20
+    assert any(tuple(sorted(p)) in got for p, a in zip(sc.ij.tolist(), alive) if not a)
+
+
+def test_contact_pair_energy_and_derivatives(oracle_mod):
+    """Two overlapping spheres: V = 1/2 k (l - 2r)^2; the objective's gradient
+    and (unprojected) Hessian against central differences; projected, the
+    pair block is k n n^T (its transverse eigenvalue k (1 - d/l) < 0 is
+    clamped)."""
+    O = oracle_mod
+    k, r = 2e5, 0.01
+    n = _unit([0.3, -0.5, 0.8])
+    sc = _loose_spheres([np.zeros(3), 0.0185 * n], r=r, gravity=(0.0, 0.0, 0.0))
+    sc.k_self = k
+    o = O.Oracle(sc)
+    dt = 1.0
+    V = o.energy(dt, potential_only=True)
+    assert abs(V - 0.5 * k * (0.0185 - 0.02) ** 2) <= 1e-15 * V
+    x0 = sc.pos.copy()
+    _, z, hd, _ = o.energy_grad_hess(dt, x0, sc.quat, psd=False)
+    _, _, hdp, _ = o.energy_grad_hess(dt, x0, sc.quat, psd=True)
+
+    def Vf(x):
+        return o.energy(dt, x, sc.quat, potential_only=True)
+
+    h = 1e-6
+    g = np.zeros((2, 3))
+    for a in range(2):
+        for c in range(3):
+            e = np.zeros((2, 3)); e[a, c] = h
+            g[a, c] = (Vf(x0 + e) - Vf(x0 - e)) / (2 * h)
+    np.testing.assert_allclose(z[:, :3], g, rtol=1e-6, atol=1e-9 * np.abs(g).max())
+    # diagonal position block of particle 0: d^2 V / dp_0^2
+    H = np.zeros((3, 3))
+    for c in range(3):
+        e = np.zeros((2, 3)); e[0, c] = h
+        gp = o.energy_grad_hess(dt, x0 + e, sc.quat, psd=False)[1][0, :3]
+        gm = o.energy_grad_hess(dt, x0 - e, sc.quat, psd=False)[1][0, :3]
+        H[:, c] = (gp - gm) / (2 * h)
+    # inertia with dt = 1 adds m I
+    m = 1000 * 4 / 3 * math.pi * r ** 3
+    np.testing.assert_allclose(hd[0][:3, :3] - m * np.eye(3), H, rtol=1e-6, atol=1e-6 * k)
+    np.testing.assert_allclose(hdp[0][:3, :3] - m * np.eye(3), k * np.outer(n, n), rtol=1e-12,
+                               atol=1e-9 * k)
+
+
+def test_sphere_rests_on_a_sphere(oracle_mod):
+    """A free sphere on a fixed one under gravity settles where the repulsion
+    carries its weight: overlap m g / k_ec."""
+    O = oracle_mod
+    r, k = 0.01, 1e4
+    sc = _loose_spheres([[0, 0, 0], [0, 0, 0.02]], r=r, gravity=(0.0, 0.0, -9.81))
+    sc.flags[0] = S.FIXED
+    sc.k_self = k
+    o = O.Oracle(sc)
+    for _ in range(300):
+        assert o.step(5e-3)["rc"] == 0
+    m = 1000 * 4 / 3 * math.pi * r ** 3
+    gap = o.get_state()["pos"][1, 2] - 0.02
+    np.testing.assert_allclose(gap, -m * 9.81 / k, rtol=1e-9)
+    assert len(o.contacts()) == 1
+
+
+def test_head_on_collision_conserves_momentum(oracle_mod):
+    """Two free spheres meeting head on: the repulsion is internal, so total
+    momentum is kept exactly through the collision; they separate again."""
+    O = oracle_mod
+    r = 0.01
+    sc = _loose_spheres([[0, 0, 0], [0.021, 0.0, 0.0]], r=r, gravity=(0.0, 0.0, 0.0))
+    sc.vel = np.array([[0.5, 0.0, 0.0], [-0.2, 0.0, 0.0]])
+    sc.k_self = 1e4
+    o = O.Oracle(sc)
+    P0 = sc.vel.sum(axis=0)
+    touched = False
+    for _ in range(80):
+        assert o.step(1e-3)["rc"] == 0
+        st = o.get_state()
+        np.testing.assert_allclose(st["vel"].sum(axis=0), P0, rtol=0, atol=1e-12)
+        touched |= np.linalg.norm(st["pos"][1] - st["pos"][0]) < 0.02
+    assert touched
+    v = o.get_state()["vel"]
+    assert v[0, 0] < v[1, 0]       # separating
+    assert np.abs(o.get_state()["pos"][:, 1:]).max() == 0.0
+
+
+def test_sliding_and_rolling_friction_on_the_ground(oracle_mod):
+    """A sphere resting on the ground (gap -m g / k_c, so F_n = m g) sliding at
+    v0 and spinning at w0: each step removes mu_s g dt of speed and
+    mu_r F_n r dt / I = 2.5 mu_r g dt / r of spin, until each stops at
+    exactly zero."""
+    O = oracle_mod
+    r, kc, g, dt = 0.01, 1e5, 9.81, 1e-3
+    m = 1000 * 4 / 3 * math.pi * r ** 3
+    sc = _loose_spheres([[0, 0, r - m * g / kc]], r=r, gravity=(0.0, 0.0, -g))
+    sc.k_contact = kc
+    sc.mu_s, sc.mu_r = 0.3, 0.005
+    v0, w0 = 0.05, 0.5
+    sc.vel = np.array([[v0, 0.0, 0.0]])
+    sc.qvel = np.array([[0.0, 0.0, 0.5 * w0, 0.0]])   # qdot = 1/2 (w, 0) q, q = 1
+    o = O.Oracle(sc)
+    for k in range(1, 46):
+        assert o.step(dt, tol_rel=1e-14)["rc"] == 0
+        st = o.get_state()
+        vx = st["vel"][0, 0]
+        q, qd = st["quat"][0], st["qvel"][0]
+        w = 2 * O.quat_mul(qd, np.array([-q[0], -q[1], -q[2], q[3]]))[:3]
+        np.testing.assert_allclose(vx, max(0.0, v0 - k * 0.3 * g * dt), rtol=0, atol=1e-9)
+        # the exp-map step of a free spin loses O((w dt)^2) of it per step
+        np.testing.assert_allclose(w[2], max(0.0, w0 - k * 2.5 * 0.005 * g * dt / r), rtol=0,
+                                   atol=2e-6 * w0)
+        assert abs(st["pos"][0, 2] - sc.pos[0, 2]) <= 1e-12
+    assert vx == 0.0 and w[2] == 0.0
+
+
+def test_contact_objective_derivatives_along_geodesics(oracle_mod):
+    """A loose cluster of overlapping unbonded spheres plus a bonded pair:
+    d/ds, d^2/ds^2 of Phi along p + s dp, Exp_q(s G^T y) match z.y and
+    y^T H y of the assembled unprojected Hessian (bond, particle and
+    repulsion blocks, the latter through orc_hess_apply)."""
+    O = oracle_mod
+    rng = np.random.default_rng(8)
+    sc = S.make_block(nx=3, ny=2, nz=2, rot_angle=0.05)
+    sc.flags[:] = S.FREE
+    sc.pos = sc.pos * 0.93 + rng.uniform(-1e-3, 1e-3, size=sc.pos.shape)
+    sc.ij = sc.ij[::2].copy()
+    sc.k_self = 3e4
+    o = O.Oracle(sc)
+    dt = 1e-2
+    st = o.get_state()
+    phi, z, hd, ho = o.energy_grad_hess(dt, st["pos"], st["quat"], psd=False)
+    assert len(o.contacts()) > 3
+    n = sc.n
+    for _ in range(3):
+        y = rng.normal(size=(n, 6))
+        y[:, :3] *= 1e-2
+        G = [O.quat_matrices(st["quat"][i])[2] for i in range(n)]
+
+        def f(s):
+            q = np.array([O.quat_exp_step(st["quat"][i], G[i].T @ y[i, 3:], s) for i in range(n)])
+            return o.energy(dt, st["pos"] + s * y[:, :3], q)
+
+        d1 = lambda h: (f(h) - f(-h)) / (2 * h)
+        d2 = lambda h: (f(h) - 2 * f(0) + f(-h)) / h ** 2
+        h = 1e-3
+        r1 = (4 * d1(h / 2) - d1(h)) / 3
+        r2 = (4 * d2(h / 2) - d2(h)) / 3
+        # energy() rebuilt the candidates from the same state: re-evaluate the Hessian
+        _, _, hd, ho = o.energy_grad_hess(dt, st["pos"], st["quat"], psd=False)
+        Hy = o.hess_apply(hd, ho, y)
+        assert abs(r1 - z.ravel() @ y.ravel()) <= 1e-7 * abs(z.ravel() @ y.ravel()) + 1e-12
+        assert abs(r2 - y.ravel() @ Hy.ravel()) <= 1e-6 * abs(y.ravel() @ Hy.ravel())
