@@ -60,7 +60,8 @@ enum {
                                shear midpoint is undefined.  Line-search trials there count as
                                infinite energy and are rejected, so only a step's initial guess
                                can end here. */
-  BDEM_E_STATE = -6         /* call not valid in the handle's state */
+  BDEM_E_STATE = -6,        /* call not valid in the handle's state */
+  BDEM_E_CAPACITY = -7      /* a particle has more than 32 element-repulsion candidates */
 };
 
 enum { BDEM_FREE = 0, BDEM_FIXED = 1, BDEM_KINEMATIC = 2 };  /* per-particle flags */
@@ -108,7 +109,19 @@ typedef struct {
   double ground_normal[3], ground_offset; /* plane n.p = h; gap = n.p - h - r */
   double k_contact;        /* < 0: per scene, E_max * r_max over that scene's materials and
                               particles (Section 5.4); 0: no ground; > 0: this value for all */
-  double mu_s, mu_r;       /* friction hook of Algorithm 3; must be 0 (not implemented) */
+  double mu_s, mu_r;       /* friction of Section 5.4 (>= 0; 0: off), applied to the velocities
+                              after each step, before the fracture test: per contact (ground,
+                              overlapping candidate pair) dv_i = -min(1, mu_s F_n dt/(m_i |v_t|)) v_t
+                              and dw_i = -min(1, mu_r F_n r_i dt/(I_i |w_ij|)) w_ij, I_i = 2/5 m r^2;
+                              the sums are projected on the particle's own (angular) velocity and
+                              clipped so they at most stop it */
+  double k_self;           /* element repulsion of Section 5.4, 1/2 k_ec min(0, l - r_i - r_j)^2 over
+                              the candidate pairs of each step: < 0: per scene E_max * r_max;
+                              0: off (default); > 0: this value */
+  double contact_margin;   /* candidates of a step: pairs of one scene not joined by an alive bond
+                              whose centres at the predicted positions are closer than
+                              r_i + r_j + contact_margin (< 0: the scene's r_max; default -1); at
+                              most 32 per particle (BDEM_E_CAPACITY otherwise) */
   double newton_tol;       /* absolute stop |z|_2 <= newton_tol */
   double newton_rtol;      /* relative stop |z|_2 <= newton_rtol |z0|_2 */
   double armijo_c;         /* sufficient-decrease constant */
@@ -199,6 +212,12 @@ int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, const double *
  * with sigma > sigma_c or tau > tau_c break permanently.  n_broken (nullable)
  * = newly broken; alive_out (nb, nullable) = the alive mask after the test. */
 int bdem_break_bonds(bdem_ctx *ctx, int64_t *n_broken, uint8_t *alive_out);
+
+/* Element-repulsion candidate pairs (Section 5.4) of the last step or
+ * evaluation, in user particle indices, i < j, sorted: up to cap pairs are
+ * written to pairs (2 x int32 each); count (nullable) receives their number.
+ * No pairs when k_self = 0.  Errors: INVALID, HIP. */
+int bdem_contact_pairs(const bdem_ctx *ctx, int64_t cap, int32_t *pairs, int64_t *count);
 
 /* Checkpoint / restore of the mutable state (host arrays, nullable). */
 int bdem_get_state(const bdem_ctx *ctx, double *pos, double *quat, double *vel, double *qvel,

@@ -22,7 +22,7 @@ _lib = C.CDLL(LIB_PATH)
 
 BDEM_OK, BDEM_W_NOT_CONVERGED, BDEM_W_LS_FAILED = 0, 1, 2
 BDEM_E_INVALID, BDEM_E_HIP, BDEM_E_NOMEM, BDEM_E_NONFINITE = -1, -2, -3, -4
-BDEM_E_DEGENERATE, BDEM_E_STATE = -5, -6
+BDEM_E_DEGENERATE, BDEM_E_STATE, BDEM_E_CAPACITY = -5, -6, -7
 BDEM_FREE, BDEM_FIXED, BDEM_KINEMATIC = 0, 1, 2
 BDEM_PREC_FP64, BDEM_PREC_MIXED = 0, 1
 BDEM_SOLVER_NEWTON, BDEM_SOLVER_FIRST_ORDER = 0, 1
@@ -53,7 +53,8 @@ class bdem_material(C.Structure):
 class bdem_options(C.Structure):
     _fields_ = [("gravity", C.c_double * 3), ("ground_normal", C.c_double * 3),
                 ("ground_offset", C.c_double), ("k_contact", C.c_double), ("mu_s", C.c_double),
-                ("mu_r", C.c_double), ("newton_tol", C.c_double), ("newton_rtol", C.c_double),
+                ("mu_r", C.c_double), ("k_self", C.c_double), ("contact_margin", C.c_double),
+                ("newton_tol", C.c_double), ("newton_rtol", C.c_double),
                 ("armijo_c", C.c_double), ("cg_rtol_max", C.c_double), ("max_newton", C.c_int32),
                 ("max_cg", C.c_int32), ("max_ls", C.c_int32), ("precision", C.c_int32),
                 ("break_each_step", C.c_int32), ("cg_chunk", C.c_int32), ("use_graph", C.c_int32),
@@ -93,6 +94,7 @@ _sig = {
     "bdem_energy_grad_hess": (C.c_int, [_ctx_p, C.c_double, C.c_int32, _dp, _dp, _dp, _dp,
                                         _dp, _dp]),
     "bdem_break_bonds": (C.c_int, [_ctx_p, _i64p, _u8p]),
+    "bdem_contact_pairs": (C.c_int, [_ctx_p, C.c_int64, _i32p, _i64p]),
     "bdem_get_state": (C.c_int, [_ctx_p, _dp, _dp, _dp, _dp, _u8p]),
     "bdem_set_state": (C.c_int, [_ctx_p, _dp, _dp, _dp, _dp, _u8p]),
     "bdem_sizes": (C.c_int, [_ctx_p, _i32p, _i64p, _i32p]),
@@ -182,7 +184,9 @@ class _Inputs:
 
 def scene_options(scene, **overrides):
     o = bdem_default_options(gravity=scene.gravity, ground_normal=scene.ground_normal,
-                             ground_offset=scene.ground_offset, k_contact=scene.k_contact)
+                             ground_offset=scene.ground_offset, k_contact=scene.k_contact,
+                             k_self=scene.k_self, contact_margin=scene.contact_margin,
+                             mu_s=scene.mu_s, mu_r=scene.mu_r)
     for k, v in overrides.items():
         setattr(o, k, v)
     return o
@@ -233,6 +237,16 @@ def bdem_energy_grad_hess(ctx, dt, what, pos=None, quat=None):
     _check(_lib.bdem_energy_grad_hess(ctx, float(dt), int(what), _p(pos), _p(quat), C.byref(e),
                                       _p(g), _p(hd), _p(ho)), ctx)
     return e.value, g, hd, (None if ho is None else ho[:nb])
+
+
+def bdem_contact_pairs(ctx):
+    """Element-repulsion candidate pairs of the last step (user indices, i < j)."""
+    k = C.c_int64()
+    _check(_lib.bdem_contact_pairs(ctx, 0, None, C.byref(k)), ctx)
+    out = np.zeros((k.value, 2), dtype=np.int32)
+    if k.value:
+        _check(_lib.bdem_contact_pairs(ctx, k.value, _p(out, _i32p), C.byref(k)), ctx)
+    return out
 
 
 def bdem_break_bonds(ctx):
@@ -324,6 +338,9 @@ class Simulator:
 
     def break_bonds(self):
         return bdem_break_bonds(self.ctx)
+
+    def contact_pairs(self):
+        return bdem_contact_pairs(self.ctx)
 
     def autotune(self, dts=None):
         if dts is None:

@@ -32,6 +32,8 @@ struct Sizes {
   int64_t nb = 0;
   int nb_pad = 0, n_slots = 0;
   bool mixed = false;
+  bool contact = false;   // element repulsion on: candidate lists and hash grid
+  int n_bucket = 0;
 };
 
 // ordered list of device buffers carved out of one allocation
@@ -83,6 +85,14 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.scene_pbeg), (S.n_scenes + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.scene_bbeg), (S.n_scenes + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.degenerate), sizeof(int));
+  const size_t npc = S.contact ? np : 1, nsc = S.contact ? ns : 1;
+  L.add(reinterpret_cast<void **>(&d.slot_bond), nsc * sizeof(int));
+  for (int **p : {&d.cand, &d.cact}) L.add(reinterpret_cast<void **>(p), npc * CMAXC * sizeof(int));
+  for (int **p : {&d.ncand, &d.nact, &d.gitem}) L.add(reinterpret_cast<void **>(p), npc * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.gcnt), std::max(S.n_bucket, 1) * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.gbeg), (std::max(S.n_bucket, 1) + 1) * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.cand_over), sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.part_d), std::max<size_t>(ntile_p, 1) * sizeof(double2));
 }
 
 // scene sizes from the particle and bond arrays (no validation beyond what
@@ -133,6 +143,17 @@ Sizes compute_sizes(const std::vector<int> &pcnt, const std::vector<int64_t> &bc
   return S;
 }
 
+// element repulsion on (bdem_options.k_self != 0): hash-grid size, a power
+// of two of at least twice the padded particle count
+void enable_contact(Sizes &S, const bdem_options &o) {
+  S.contact = o.k_self != 0.0;
+  S.n_bucket = 0;
+  if (!S.contact) return;
+  int nb = 1024;
+  while (nb < 2 * S.n_pad) nb <<= 1;
+  S.n_bucket = nb;
+}
+
 }  // namespace
 
 struct bdem_ctx {
@@ -150,6 +171,7 @@ struct bdem_ctx {
   std::vector<int2> bslot_h;     // internal bond -> slots
   std::vector<int> scene_pbeg, scene_bbeg;
   std::vector<double> scene_kc;  // ground penalty stiffness per scene
+  std::vector<double> scene_kself, scene_cmargin, scene_ccell;   // element repulsion per scene
   // pinned host mirrors
   int *h_counters = nullptr;     // 2 polling slots x 4
   int prof_cnt[2] = {0, 0};      // profiled launches in the last step (bond, SpMV)
@@ -203,6 +225,8 @@ extern "C" void bdem_default_options(bdem_options *o) {
   o->solver = BDEM_SOLVER_NEWTON;
   o->integrator = BDEM_INTEGRATOR_EULER;
   o->pad_ = 0;
+  o->k_self = 0.0;
+  o->contact_margin = -1.0;
 }
 
 extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
@@ -216,6 +240,7 @@ extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds
   if (opt) o = *opt;
   else bdem_default_options(&o);
   Sizes S = compute_sizes(pcnt, bcnt, p->n, b->nb, o.precision == BDEM_PREC_MIXED);
+  enable_contact(S, o);
   DevPtrs d{};
   Layout L;
   make_layout(S, d, L);
@@ -270,8 +295,10 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   else bdem_default_options(&o);
   if (o.precision != BDEM_PREC_FP64 && o.precision != BDEM_PREC_MIXED)
     return fail(nullptr, BDEM_E_INVALID, "unknown precision");
-  if (o.mu_s != 0.0 || o.mu_r != 0.0)
-    return fail(nullptr, BDEM_E_INVALID, "friction is not implemented (mu_s = mu_r = 0 required)");
+  if (!(o.mu_s >= 0.0) || !(o.mu_r >= 0.0) || !std::isfinite(o.mu_s) || !std::isfinite(o.mu_r))
+    return fail(nullptr, BDEM_E_INVALID, "friction coefficients must be finite and >= 0");
+  if (!std::isfinite(o.k_self) || !std::isfinite(o.contact_margin))
+    return fail(nullptr, BDEM_E_INVALID, "k_self and contact_margin must be finite");
   if (o.solver != BDEM_SOLVER_NEWTON && o.solver != BDEM_SOLVER_FIRST_ORDER)
     return fail(nullptr, BDEM_E_INVALID, "solver must be BDEM_SOLVER_NEWTON or BDEM_SOLVER_FIRST_ORDER");
   if (o.integrator != BDEM_INTEGRATOR_EULER && o.integrator != BDEM_INTEGRATOR_MIDPOINT)
@@ -322,6 +349,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   }
   ctx->opt = o;
   ctx->S = compute_sizes(pcnt, bcnt, n, b->nb, o.precision == BDEM_PREC_MIXED);
+  enable_contact(ctx->S, o);
   Sizes &S = ctx->S;
   const int NS = S.n_scenes;
   // ---- internal order: scenes padded to TILE particles / bonds ----
@@ -398,6 +426,16 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     }
   ctx->scene_kc.assign(NS, 0.0);
   for (int s = 0; s < NS; ++s) ctx->scene_kc[s] = o.k_contact < 0.0 ? s_emax[s] * s_rmax[s] : o.k_contact;
+  // element repulsion: k_ec (default E_max r_max of the scene, the order
+  // Section 5.4 recommends), candidate margin (default r_max), grid cell
+  ctx->scene_kself.assign(NS, 0.0);
+  ctx->scene_cmargin.assign(NS, 0.0);
+  ctx->scene_ccell.assign(NS, 1.0);
+  for (int s = 0; s < NS; ++s) {
+    ctx->scene_kself[s] = o.k_self < 0.0 ? s_emax[s] * s_rmax[s] : o.k_self;
+    ctx->scene_cmargin[s] = o.contact_margin < 0.0 ? s_rmax[s] : o.contact_margin;
+    ctx->scene_ccell[s] = 2.0 * s_rmax[s] + ctx->scene_cmargin[s];
+  }
   // ---- bonds: per scene, sorted by (min row, max row) ----
   std::vector<int64_t> order(b->nb);
   std::iota(order.begin(), order.end(), 0);
@@ -459,7 +497,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     adj[h_bij[bi].x].push_back({h_bij[bi].y, 2 * bi});
     adj[h_bij[bi].y].push_back({h_bij[bi].x, 2 * bi + 1});
   }
-  std::vector<int> h_col(std::max(S.n_slots, 1), 0);
+  std::vector<int> h_col(std::max(S.n_slots, 1), 0), h_sb(std::max(S.n_slots, 1), 0);
   ctx->bslot_h.assign(std::max(NB, 1), make_int2(-1, -1));
   for (int r = 0; r < NP; ++r) {
     std::sort(adj[r].begin(), adj[r].end());
@@ -467,6 +505,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
       const int slot = rp[r] + (int)k;
       const int bi = adj[r][k].second >> 1, end = adj[r][k].second & 1;
       h_col[slot] = adj[r][k].first;
+      h_sb[slot] = bi;
       if (end == 0) ctx->bslot_h[bi].x = slot;
       else ctx->bslot_h[bi].y = slot;
     }
@@ -498,6 +537,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   d.n_pad = NP;
   d.nb_pad = NB;
   d.n_slots = S.n_slots;
+  d.n_bucket = S.n_bucket;
   // ---- params ----
   Params &P = ctx->P;
   P.gx = o.gravity[0]; P.gy = o.gravity[1]; P.gz = o.gravity[2];
@@ -524,6 +564,9 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   P.n_scenes = NS;
   P.first_order = o.solver == BDEM_SOLVER_FIRST_ORDER ? 1 : 0;
   P.midpoint = o.integrator == BDEM_INTEGRATOR_MIDPOINT ? 1 : 0;
+  P.contact = S.contact ? 1 : 0;
+  P.mu_s = o.mu_s;
+  P.mu_r = o.mu_r;
   // ---- upload ----
   hipStream_t st = ctx->stream;
   auto up = [&](void *dst, const void *src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
@@ -551,6 +594,11 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(up(d.ctl, ctl0.data(), NS * sizeof(SceneCtl)));
   chk(up(d.scene_pbeg, ctx->scene_pbeg.data(), (NS + 1) * sizeof(int)));
   chk(up(d.scene_bbeg, ctx->scene_bbeg.data(), (NS + 1) * sizeof(int)));
+  if (S.contact) {
+    chk(up(d.slot_bond, h_sb.data(), h_sb.size() * sizeof(int)));
+    chk(hipMemsetAsync(d.ncand, 0, NP * sizeof(int), st));
+    chk(hipMemsetAsync(d.nact, 0, NP * sizeof(int), st));
+  }
   // iterate / trial / prediction start as the state; solver buffers zero
   chk(hipMemcpyAsync(d.px, d.pn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
   chk(hipMemcpyAsync(d.qx, d.qn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
@@ -600,6 +648,22 @@ static void launch_step_target(const DevPtrs &d, const Params &P, hipStream_t st
   launch_midpoint_target(d, P, st);
 }
 
+// element-repulsion candidates of a step, at the predicted positions (before
+// the midpoint form replaces the prediction by z_hat); fails when a particle
+// has more candidates than the per-particle capacity
+static int contact_candidates(bdem_ctx *ctx) {
+  if (!ctx->P.contact) return BDEM_OK;
+  hipStream_t st = ctx->stream;
+  launch_contact_broad_phase(ctx->d, st);
+  int over = 0;
+  HIP_TRY(hipMemcpyAsync(&over, ctx->d.cand_over, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (over > 0)
+    return fail(ctx, BDEM_E_CAPACITY, std::to_string(over) +
+                " particles have more than 32 element-repulsion candidates (reduce contact_margin)");
+  return BDEM_OK;
+}
+
 static int read_counters(bdem_ctx *ctx) {
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return BDEM_OK;
@@ -638,6 +702,7 @@ static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   if (profile_spmv) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, false);
+  if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, ctx->stream);
   launch_cg_scalars(ctx->d, ctx->P, ctx->stream);
 }
 
@@ -677,6 +742,7 @@ static int run_pcg(bdem_ctx *ctx) {
   if (ctx->profiling) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling) prof_mark(ctx, 1, false);
+  if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, st);
   launch_cg_scalars(ctx->d, ctx->P, st);
   if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
   int rc = read_counters(ctx);
@@ -730,6 +796,7 @@ static int run_line_search(bdem_ctx *ctx) {
   for (int it = 0; it <= ctx->opt.max_ls + 2; ++it) {
     launch_ls_trial(ctx->d, ctx->P, st);
     launch_bond_energy(ctx->d, true, ctx->P.midpoint != 0, st);
+    if (ctx->P.contact) launch_contact_trial_energy(ctx->d, ctx->P, st);
     launch_ls_decide(ctx->d, ctx->P, st);
     launch_ls_accept(ctx->d, st);
     launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
@@ -767,6 +834,9 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
       c.dt = dts[s];
       c.inv_dt2 = 1.0 / (dts[s] * dts[s]);
       c.kc = ctx->scene_kc[s];
+      c.kself = ctx->scene_kself[s];
+      c.cmargin = ctx->scene_cmargin[s];
+      c.ccell = ctx->scene_ccell[s];
       c.newton_active = 1;
     }
     hipError_t e = hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st);
@@ -775,6 +845,10 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
   };
   HIP_TRY(init_ctl());
   launch_predict(d, true, st);
+  {
+    const int rc = contact_candidates(ctx);
+    if (rc) return rc;
+  }
   launch_step_target(d, ctx->P, st);
   bool restarted = false;
   for (int k = 0; k <= ctx->opt.max_newton + 1; ++k) {
@@ -822,9 +896,9 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
       const SceneCtl &c = ctx->h_ctl[0];
       std::fprintf(stderr,
                    "[bdem trace] it %d |z| %.6e phi %.12e slope %.3e alpha %.3e ls %d cg %d "
-                   "cg_tol %.3e |r| %.3e phi_trial %.12e move %.3e status %d\n",
+                   "cg_tol %.3e |r| %.3e phi_trial %.12e move %.3e status %d (r,u) %.3e (w,u) %.3e\n",
                    c.newton_it, c.gnorm, c.phi, c.slope, c.alpha_ls, c.ls_it, c.cg_it, c.cg_tol,
-                   std::sqrt(c.rr), c.phi_trial, c.last_move, c.status);
+                   std::sqrt(c.rr), c.phi_trial, c.last_move, c.status, c.rz_new, c.pAp);
     }
   }
   // outcome per scene
@@ -834,6 +908,7 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     if (ctx->h_ctl[s].status == ST_NONFINITE) return fail(ctx, BDEM_E_NONFINITE, "non-finite objective or gradient");
   HIP_TRY(hipEventRecord(ph[1], st));
   launch_finish_step(d, st);
+  if (ctx->P.mu_s > 0.0 || ctx->P.mu_r > 0.0) launch_friction(d, ctx->P, st);
   int64_t broken = 0;
   if (ctx->opt.break_each_step && ctx->S.nb_pad > 0) {
     launch_bond_fracture(d, st);
@@ -1042,14 +1117,18 @@ extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, con
     c.dt = dt;
     c.inv_dt2 = 1.0 / (dt * dt);
     c.kc = ctx->scene_kc[s];
+    c.kself = ctx->scene_kself[s];
+    c.cmargin = ctx->scene_cmargin[s];
+    c.ccell = ctx->scene_ccell[s];
     c.newton_active = 1;
   }
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
   launch_predict(d, false, st);
+  int rc;
+  if ((rc = contact_candidates(ctx))) return rc;
   launch_step_target(d, ctx->P, st);
   launch_copy_state_to_iterate(d, st);
-  int rc;
   if (pos_eval && (rc = upload4(ctx, d.px, pos_eval, 3))) return rc;
   if (quat_eval && (rc = upload4(ctx, d.qx, quat_eval, 4))) return rc;
   launch_bond_eval(d, mixed, psd, hess, ctx->P.midpoint != 0, st);
@@ -1108,6 +1187,32 @@ extern "C" int bdem_break_bonds(bdem_ctx *ctx, int64_t *n_broken, uint8_t *alive
   }
   if (n_broken) *n_broken = broken;
   if (alive_out) return bdem_get_state(ctx, nullptr, nullptr, nullptr, nullptr, alive_out);
+  return BDEM_OK;
+}
+
+extern "C" int bdem_contact_pairs(const bdem_ctx *ctx, int64_t cap, int32_t *pairs, int64_t *count) {
+  if (!ctx || cap < 0 || (cap > 0 && !pairs)) return BDEM_E_INVALID;
+  std::vector<std::pair<int, int>> out;
+  if (ctx->S.contact) {
+    const int NP = ctx->S.n_pad;
+    std::vector<int> nc(NP), cand((size_t)NP * CMAXC);
+    if (hipMemcpy(nc.data(), ctx->d.ncand, NP * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(cand.data(), ctx->d.cand, cand.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return BDEM_E_HIP;
+    std::vector<int> user(NP, -1);
+    for (int i = 0; i < ctx->S.n; ++i) user[ctx->p_int[i]] = i;
+    for (int r = 0; r < NP; ++r)
+      for (int k = 0; k < nc[r]; ++k) {
+        const int a = user[r], b = user[cand[(size_t)r * CMAXC + k]];
+        if (a >= 0 && b >= 0 && a < b) out.push_back({a, b});
+      }
+    std::sort(out.begin(), out.end());
+  }
+  if (count) *count = (int64_t)out.size();
+  for (int64_t k = 0; k < cap && k < (int64_t)out.size(); ++k) {
+    pairs[2 * k] = out[k].first;
+    pairs[2 * k + 1] = out[k].second;
+  }
   return BDEM_OK;
 }
 
@@ -1175,11 +1280,18 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
     c.dt = dt_per_scene[s];
     c.inv_dt2 = 1.0 / (dt_per_scene[s] * dt_per_scene[s]);
     c.kc = ctx->scene_kc[s];
+    c.kself = ctx->scene_kself[s];
+    c.cmargin = ctx->scene_cmargin[s];
+    c.ccell = ctx->scene_ccell[s];
     c.newton_active = 1;
   }
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
   launch_predict(d, true, st);
+  {
+    const int rc = contact_candidates(ctx);
+    if (rc) return rc;
+  }
   launch_step_target(d, ctx->P, st);
   launch_bond_eval(d, mixed, true, true, ctx->P.midpoint != 0, st);
   launch_particle_eval(d, ctx->P, mixed, true, false, st);

@@ -25,6 +25,7 @@ namespace bdem {
 constexpr int TILE = 256;       // particles / bonds per scene-aligned tile
 constexpr int SPMV_ROWS = 32;     // block rows per SpMV workgroup
 constexpr int SPMV_CAP = 512;     // slots staged in LDS per pass of an SpMV workgroup
+constexpr int CMAXC = 32;         // element-repulsion candidates per particle
 
 // per-scene control block, device resident; every decision of the Newton /
 // PCG / line-search loops is taken on the device from these values
@@ -41,6 +42,9 @@ struct SceneCtl {
   int unresolved, stall;   // rounding-floor detection (see k_newton_check)
   double gnorm_prev;
   double alpha_prev;       // last accepted line-search step
+  double kself;            // element-repulsion stiffness of the scene (0: off)
+  double cmargin;          // candidate reach beyond r_i + r_j
+  double ccell;            // broad-phase cell size (>= 2 r_max + margin)
 };
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_LS_FAILED = 2, ST_NONFINITE = 3 };
@@ -54,6 +58,8 @@ struct Params {
   int n_scenes;
   int first_order;   // Algorithm 1 instead of Algorithm 2
   int midpoint;      // variational midpoint objective of Section 3.1
+  int contact;       // element repulsion enabled in some scene
+  double mu_s, mu_r; // friction coefficients (Section 5.4)
 };
 
 struct DevPtrs {
@@ -95,6 +101,14 @@ struct DevPtrs {
   int *counters;                      // device address of 2 slots x 4 ints in mapped pinned host memory:
                                       // [0] newton active, [1] cg active, [2] ls active, [3] degenerate bonds
   int *degenerate;                    // bonds with |q_i + q_j| below the threshold
+  // element repulsion (Section 5.4); allocated only when enabled
+  int *slot_bond;                     // n_slots: bond of each off-diagonal slot
+  int *cand, *ncand;                  // CMAXC candidates per particle (sorted), their count
+  int *cact, *nact;                   // overlapping candidates at the last evaluation
+  int *gcnt, *gbeg, *gitem;           // broad-phase hash grid: counts, starts, items
+  int n_bucket;                       // power of two
+  int *cand_over;                     // particles with more than CMAXC candidates
+  double2 *part_d;                    // per-tile partial of the repulsion's w.u in PCG
 };
 
 // ----- launchers (kernels in the .hip files) -----
@@ -113,6 +127,11 @@ void launch_particle_eval(const DevPtrs &d, const Params &P, bool mixed, bool he
 void launch_midpoint_target(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_ls_trial(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_ls_accept(const DevPtrs &d, hipStream_t s);
+// element repulsion and friction
+void launch_contact_broad_phase(const DevPtrs &d, hipStream_t s);
+void launch_contact_spmv(const DevPtrs &d, const Params &P, hipStream_t s);
+void launch_contact_trial_energy(const DevPtrs &d, const Params &P, hipStream_t s);
+void launch_friction(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_finish_step(const DevPtrs &d, hipStream_t s);
 // per-scene decisions
 void launch_newton_check(const DevPtrs &d, const Params &P, int first, hipStream_t s);

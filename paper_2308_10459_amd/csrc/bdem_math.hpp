@@ -222,7 +222,10 @@ template <> struct JacobiTol<double> {
 template <typename T> struct JacobiAngle;
 template <> struct JacobiAngle<float> {
   __device__ static __forceinline__ void cs(float app, float aqq, float apq, float &t, float &c) {
-    const bool act = apq != 0.0f;
+    // rotate only where the hardware reciprocal of 2 apq is finite: for a
+    // denormal apq it overflows, and with aqq == app (symmetric, unstrained
+    // bonds) theta would be 0 * inf; such an off-diagonal is left in place
+    const bool act = fabsf(apq) >= 1e-30f;
     const float theta = (aqq - app) * __builtin_amdgcn_rcpf(act ? 2.0f * apq : 1.0f);
     const float at = fabsf(theta);
     const float x = fmaf(theta, theta, 1.0f);

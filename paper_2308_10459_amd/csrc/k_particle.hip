@@ -6,7 +6,7 @@
 //   gradient, the block-Jacobi inverse, the exp-map retraction of Section 4.1
 //   with the trial energy, and the velocity update.
 // One thread per particle, TILE particles per workgroup, one scene per tile.
-#include "bdem_internal.hpp"
+#include "bdem_contact.hpp"
 #include "bdem_math.hpp"
 
 namespace bdem {
@@ -171,6 +171,32 @@ __global__ __launch_bounds__(TILE) void k_particle_eval(DevPtrs d, Params P, int
     kadd(e, t.E);
     z[0] += t.gp[0]; z[1] += t.gp[1]; z[2] += t.gp[2];
     z[3] += t.gr[0]; z[4] += t.gr[1]; z[5] += t.gr[2];
+    if (ctl.kself > 0.0) {
+      // element repulsion (Section 5.4): half of each overlapping candidate
+      // pair's energy, this row's gradient and projected diagonal share
+      // (k n n^T), and the overlapping free partners for the Hessian product
+      const int nc = d.ncand[r];
+      const double rr = d.pconst[r].z, kc = ctl.kself;
+      const double wg = P.midpoint ? 0.5 : 1.0, wh = P.midpoint ? 0.25 : 1.0;
+      int na = 0;
+      for (int m = 0; m < nc; ++m) {
+        const int j = d.cand[(size_t)r * CMAXC + m];
+        double n[3], g;
+        if (!contact_overlap(pv, contact_point(d, d.px, j, P.midpoint), rr, d.pconst[j].z, n, g)) continue;
+        kadd(e, 0.25 * kc * g * g);
+        z[0] -= wg * kc * g * n[0]; z[1] -= wg * kc * g * n[1]; z[2] -= wg * kc * g * n[2];
+        if (HESS) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = a; b < 3; ++b) D[up6(a, b)] += wh * kc * n[a] * n[b];
+        }
+        if (f == 0 && d.flags[j] == 0) d.cact[(size_t)r * CMAXC + na++] = j;
+      }
+      d.nact[r] = na;
+    } else if (P.contact) {
+      d.nact[r] = 0;
+    }
     if (HESS) {
       const double m = d.pconst[r].x, c = d.pconst[r].y;
       const double n[3] = {P.gnx, P.gny, P.gnz};
@@ -191,6 +217,7 @@ __global__ __launch_bounds__(TILE) void k_particle_eval(DevPtrs d, Params P, int
     }
   } else {
     D[up6(0, 0)] = D[up6(1, 1)] = D[up6(2, 2)] = D[up6(3, 3)] = D[up6(4, 4)] = D[up6(5, 5)] = 1.0;
+    if (P.contact) d.nact[r] = 0;
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {

@@ -274,6 +274,11 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
       rr = kmerge(rr, KSum{pc[m].x, pc[m].y});
     }
   }
+  // the element repulsion's share of (w, u), added after the bond SpMV
+  if (P.contact) {
+    const int t0 = d.scene_pbeg[s] / TILE, t1 = d.scene_pbeg[s + 1] / TILE;
+    for (int k = t0 + (int)threadIdx.x; k < t1; k += blockDim.x) wu = kmerge(wu, KSum{d.part_d[k].x, d.part_d[k].y});
+  }
   // the host's poll slot holds 1 while the solve runs (set when it starts);
   // it is written only when this scene stops
   if (!active) return;
@@ -281,6 +286,8 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
   if (threadIdx.x != 0) return;
   const double gamma = ru.s + ru.c, delta = wu.s + wu.c;
   c.rr = rr.s + rr.c;
+  c.rz_new = gamma;   // kept for the trace
+  c.pAp = delta;
   bool stop = !(sqrt(c.rr) > cg_tol) || cg_it >= P.max_cg || !(gamma > 0.0);
   double alpha = 0.0, beta = 0.0;
   if (!stop) {

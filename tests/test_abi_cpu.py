@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(B):
 
 def test_struct_sizes_match_header_layout(B):
     # doubles first then int32s, natural alignment: the ctypes mirror must not pad differently
-    assert C.sizeof(B.bdem_options) == 8 * (3 + 3 + 1 + 1 + 2 + 4) + 4 * 10
+    assert C.sizeof(B.bdem_options) == 8 * (3 + 3 + 1 + 1 + 2 + 2 + 4) + 4 * 10
     assert C.sizeof(B.bdem_material) == 8 * 9 + 4 * 2
     assert C.sizeof(B.bdem_step_stats) == 4 * 4 + 8 + 8 * 3 + 8 * 8
     assert C.sizeof(B.bdem_tuning) == 4 * 6 + 8 * 3
@@ -106,7 +106,8 @@ def test_create_rejects_invalid_inputs(B, mutate, code):
 
 def test_create_rejects_friction_and_bad_limits(B):
     sc = S.make_chain(n=3)
-    assert _create_error(B, sc, mu_s=0.1) == -1
+    assert _create_error(B, sc, mu_s=-0.1) == -1
+    assert _create_error(B, sc, k_self=float("nan")) == -1
     assert _create_error(B, sc, max_cg=0) == -1
     assert _create_error(B, sc, precision=5) == -1
     assert _create_error(B, sc, solver=2) == -1

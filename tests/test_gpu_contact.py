@@ -1,0 +1,286 @@
+"""Element repulsion and friction (Section 5.4) on the GPU against the oracle.
+
+Tolerances as in test_gpu_parity: FP64 energy 1e-12, gradient 1e-11 of its
+max, blocks 1e-10 of the row scale; mixed 1e-6 / 1e-11 / 1e-4; positions
+after a step 1e-8 (FP64) or 1e-5 (mixed) of the displacement, widened only
+by the conditioning bound where both sides stop at their rounding floors.
+Candidate sets are compared exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2308_10459_amd import scenes as S
+from tests.gpu_helpers import log, make_sim, oracle_for, row_scale
+from tests.test_gpu_parity import TIGHT, _compare_states, _conditioning_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_10459_amd import bdem
+    return bdem
+
+
+def _loose_cluster(nx, ny, nz, seed=8, k_self=3e4):
+    """Block with every other bond removed, squeezed to 93% so unbonded
+    neighbours overlap; bottom layer fixed."""
+    rng = np.random.default_rng(seed)
+    sc = S.make_block(nx=nx, ny=ny, nz=nz, rot_angle=0.02)
+    sc.pos = sc.pos * 0.93 + rng.uniform(-5e-4, 5e-4, size=sc.pos.shape)
+    sc.ij = sc.ij[::2].copy()
+    sc.k_self = k_self
+    sc.vel = rng.uniform(-0.05, 0.05, size=(sc.n, 3)) * (sc.flags == 0)[:, None]
+    return sc
+
+
+def _pairs_set(a):
+    return {tuple(p) for p in np.asarray(a).tolist()}
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("midpoint", [False, True])
+@pytest.mark.parametrize("dims", [(5, 4, 3), (11, 10, 9)])
+def test_contact_energy_grad_hess(B, mixed, midpoint, dims):
+    log(f"[contact egh] dims={dims} mixed={mixed} midpoint={midpoint}")
+    sc = _loose_cluster(*dims)
+    o = oracle_for(sc)
+    dt = 1e-3
+    st = o.get_state()
+    phi_o, z_o, hd_o, ho_o = o.energy_grad_hess(dt, st["pos"], st["quat"], psd=True, midpoint=midpoint)
+    sim = make_sim(sc, mixed=mixed, integrator=B.BDEM_INTEGRATOR_MIDPOINT if midpoint else 0)
+    what = B.BDEM_EGH_E | B.BDEM_EGH_G | B.BDEM_EGH_H | B.BDEM_EGH_PSD
+    phi, z, hd, ho = sim.energy_grad_hess(dt, what)
+    got_pairs, ref_pairs = _pairs_set(sim.contact_pairs()), _pairs_set(o.contacts())
+    log(f"  candidates {len(ref_pairs)}; phi {phi:.15e} oracle {phi_o:.15e}")
+    assert got_pairs == ref_pairs and len(ref_pairs) > sc.n // 2
+    assert abs(phi - phi_o) <= (1e-6 if mixed else 1e-12) * abs(phi_o)
+    assert np.abs(z - z_o).max() <= 1e-11 * np.abs(z_o).max()
+    scale = row_scale(hd_o, ho_o, sc.ij, sc.n)
+    tol = 1e-4 if mixed else 1e-10
+    ed = np.linalg.norm((hd - hd_o).reshape(sc.n, -1), axis=1) / scale
+    eo = np.linalg.norm((ho - ho_o).reshape(sc.nb, -1), axis=1) / np.minimum(
+        scale[sc.ij[:, 0]], scale[sc.ij[:, 1]])
+    log(f"  max diag err {ed.max():.2e}  max off err {eo.max():.2e}")
+    assert ed.max() <= tol and eo.max() <= tol
+    # the repulsion is in there: without it the gradient differs
+    sc0 = sc.copy()
+    sc0.k_self = 0.0
+    _, z0, _, _ = oracle_for(sc0).energy_grad_hess(dt, st["pos"], st["quat"], psd=True, hess=False,
+                                                  midpoint=midpoint)
+    assert np.abs(z0 - z_o).max() > 1e-3 * np.abs(z_o).max()
+    sim.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("midpoint", [False, True])
+def test_contact_steps_relax_the_squeezed_cluster(B, mixed, midpoint):
+    """Five steps of the squeezed 990-particle cluster (repulsion pushing the
+    unbonded neighbours apart), each compared as a one-step map from the
+    GPU's state."""
+    log(f"[contact steps] mixed={mixed} midpoint={midpoint}")
+    sc = _loose_cluster(11, 10, 9)
+    sim = make_sim(sc, mixed=mixed, integrator=B.BDEM_INTEGRATOR_MIDPOINT if midpoint else 0, **TIGHT)
+    tol = 1e-5 if mixed else 1e-8
+    for k in range(5):
+        prev = sim.get_state()
+        o = oracle_for(sc, prev)
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300, midpoint=int(midpoint))
+        sg = sim.step(sc.dt)
+        ref, got = o.get_state(), sim.get_state()
+        assert sg["rc"] == 0 and so["rc"] == 0, (sg, so)
+        assert _pairs_set(sim.contact_pairs()) == _pairs_set(o.contacts())
+        # bound from the implicit-Euler Hessian (the stiffer one: a tighter bound
+        # for the midpoint form)
+        cond = _conditioning_bound(sc, prev, ref, sc.dt, max(so["grad_final"], sg["grad_final"]))
+        _compare_states(sc, got, ref, prev, tol, f"step {k} newton {sg['newton_iters']} cg {sg['cg_iters']}",
+                        cond=cond)
+        assert abs(sg["phi"] - so["phi"]) <= (1e-6 if mixed else 1e-10) * abs(so["phi"])
+    sim.close()
+
+
+def _two_blocks(speed=2.0):
+    """Two 4x4x4 blocks, bonded inside, none between, flying at each other."""
+    a = S.make_block(nx=4, ny=4, nz=4, rot_angle=0.0)
+    n = a.n
+    sc = a.copy()
+    sc.pos = np.concatenate([a.pos, a.pos + np.array([0.084, 0.003, -0.002])])
+    sc.quat = np.concatenate([a.quat, a.quat])
+    sc.vel = np.concatenate([np.tile([speed, 0.0, 0.0], (n, 1)), np.tile([-speed, 0.0, 0.0], (n, 1))])
+    sc.qvel = np.zeros((2 * n, 4))
+    sc.radius = np.concatenate([a.radius, a.radius])
+    sc.pmat = np.concatenate([a.pmat, a.pmat])
+    sc.flags = np.zeros(2 * n, dtype=np.uint8)
+    sc.ij = np.concatenate([a.ij, a.ij + n]).astype(np.int32)
+    sc.gravity = (0.0, 0.0, 0.0)
+    sc.k_self = -1.0
+    return sc
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_colliding_blocks(B, mixed):
+    log(f"[colliding blocks] mixed={mixed}")
+    sc = _two_blocks()
+    sim = make_sim(sc, mixed=mixed, **TIGHT)
+    tol = 1e-5 if mixed else 1e-8
+    touched = 0
+    for k in range(8):
+        prev = sim.get_state()
+        o = oracle_for(sc, prev)
+        so = o.step(1e-3, tol_rel=0.0, max_newton=300)
+        sg = sim.step(1e-3)
+        ref, got = o.get_state(), sim.get_state()
+        assert sg["rc"] == 0 and so["rc"] == 0, (sg, so)
+        pairs = sim.contact_pairs()
+        assert _pairs_set(pairs) == _pairs_set(o.contacts())
+        d = np.linalg.norm(ref["pos"][pairs[:, 1]] - ref["pos"][pairs[:, 0]], axis=1) if len(pairs) else []
+        touched += int(np.any(np.asarray(d) < 0.02))
+        cond = _conditioning_bound(sc, prev, ref, 1e-3, max(so["grad_final"], sg["grad_final"]))
+        _compare_states(sc, got, ref, prev, tol, f"step {k} pairs {len(pairs)}", cond=cond)
+    assert touched >= 3
+    v = sim.get_state()["vel"]
+    assert v[:64, 0].mean() < 2.0 and v[64:, 0].mean() > -2.0    # slowed by the impact
+    sim.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_friction_on_the_ground(B, mixed):
+    """A 3x3x2 block (no fixed layer) resting on the ground, sliding and
+    spinning, with sliding and rolling friction; velocities after each step
+    against the oracle's from the same state."""
+    log(f"[friction] mixed={mixed}")
+    sc = S.make_block(nx=3, ny=3, nz=2, rot_angle=0.0)
+    sc.flags[:] = S.FREE
+    sc.k_contact = 1e5
+    sc.ground_offset = -0.01 + 2e-4     # the bottom layer (z = 0) overlaps the ground by 0.2 mm
+    sc.mu_s, sc.mu_r = 0.4, 0.02
+    sc.vel = np.tile([0.3, 0.1, 0.0], (sc.n, 1))
+    sc.qvel = np.tile([0.0, 0.0, 0.4, 0.0], (sc.n, 1))
+    sim = make_sim(sc, mixed=mixed, **TIGHT)
+    for k in range(6):
+        prev = sim.get_state()
+        o = oracle_for(sc, prev)
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300)
+        sg = sim.step(sc.dt)
+        ref, got = o.get_state(), sim.get_state()
+        assert sg["rc"] == 0 and so["rc"] == 0
+        cond = _conditioning_bound(sc, prev, ref, sc.dt, max(so["grad_final"], sg["grad_final"]))
+        _compare_states(sc, got, ref, prev, 1e-5 if mixed else 1e-8, f"step {k}", cond=cond)
+        # velocities: the friction change on top of (x_{n+1} - x_n)/dt, so the
+        # states' own difference over dt bounds them too
+        tol = 1e-5 if mixed else 1e-8
+        dp = np.abs(got["pos"] - ref["pos"]).max() / sc.dt
+        dq = np.abs(got["quat"] - ref["quat"]).max() / sc.dt
+        ev = np.abs(got["vel"] - ref["vel"]).max()
+        eq = np.abs(got["qvel"] - ref["qvel"]).max()
+        bv = max(tol * np.abs(ref["vel"]).max(), 3 * dp)
+        bq = max(tol * np.abs(ref["qvel"]).max(), 3 * dq)
+        log(f"  step {k}: vel err {ev:.2e} (bound {bv:.1e}) qvel err {eq:.2e} (bound {bq:.1e})")
+        assert ev <= bv and eq <= bq
+    # friction acted: the block lost speed
+    assert np.abs(sim.get_state()["vel"][:, 0]).mean() < 0.3
+    sim.close()
+
+
+def test_candidate_capacity_is_reported(B):
+    """More than 32 candidates for a particle is an error, not a silent cut."""
+    rng = np.random.default_rng(3)
+    sc = S.make_pair()
+    n = 40
+    sc.pos = rng.uniform(-0.005, 0.005, size=(n, 3))
+    sc.quat = np.tile([0.0, 0.0, 0.0, 1.0], (n, 1))
+    sc.vel, sc.qvel = np.zeros((n, 3)), np.zeros((n, 4))
+    sc.radius = np.full(n, 0.01)
+    sc.pmat = np.zeros(n, dtype=np.int32)
+    sc.flags = np.zeros(n, dtype=np.uint8)
+    sc.ij = np.zeros((0, 2), dtype=np.int32)
+    sc.k_self = 1e3
+    sim = make_sim(sc)
+    with pytest.raises(B.BdemError) as ei:
+        sim.step(1e-3)
+    assert ei.value.code == B.BDEM_E_CAPACITY
+    sim.close()
+
+
+def test_full_size_candidates_match_the_rule(B):
+    """The 219,024-particle ceramic plate with the repulsion on: after its
+    first step the candidate set equals the rule evaluated directly (k-d tree
+    at the predicted positions, minus the bonds alive at the start); the
+    second neighbour shell of the close packing (sqrt 2 x 2r < 3r) is in it."""
+    from scipy.spatial import cKDTree
+    sc = S.make_ceramic_plate()
+    sc.k_self = -1.0
+    log(f"[full-size candidates] n={sc.n} nb={sc.nb}")
+    sim = make_sim(sc, mixed=True, newton_rtol=1e-6)
+    st0 = sim.get_state()
+    sg = sim.step(sc.dt)
+    log(f"  newton {sg['newton_iters']} cg {sg['cg_iters']} rc {sg['rc']}")
+    assert sg["rc"] == 0
+    got = _pairs_set(sim.contact_pairs())
+    ph = st0["pos"] + sc.dt * st0["vel"] * (sc.flags != 1)[:, None]
+    margin = sc.radius.max()
+    tree = cKDTree(ph)
+    near = tree.query_pairs(2 * sc.radius.max() + margin + 1e-9, output_type="ndarray")
+    i, j = near[:, 0], near[:, 1]
+    u = ph[j] - ph[i]
+    reach = sc.radius[i] + sc.radius[j] + margin
+    keep = (u * u).sum(axis=1) < reach * reach
+    bonded = {tuple(sorted(p)) for p in sc.ij.tolist()}
+    ref = {(int(a), int(b)) for a, b in zip(i[keep], j[keep]) if (min(a, b), max(a, b)) not in bonded}
+    ref = {(min(a, b), max(a, b)) for a, b in ref}
+    log(f"  candidates GPU {len(got)} rule {len(ref)}")
+    assert got == ref and len(ref) > sc.n
+    sim.close()
+
+
+def test_batched_scenes_do_not_touch_each_other(B):
+    """Two copies of the squeezed cluster in one batch at the same place:
+    each scene's candidates and step equal those of the scene alone."""
+    a = _loose_cluster(5, 4, 3)
+    n = a.n
+    sc = a.copy()
+    for f in ("pos", "quat", "vel", "qvel", "radius", "pmat", "flags"):
+        setattr(sc, f, np.concatenate([getattr(a, f), getattr(a, f)]))
+    sc.ij = np.concatenate([a.ij, a.ij + n]).astype(np.int32)
+    sc.scene_id = np.repeat(np.arange(2, dtype=np.int32), n)
+    sc.dt_per_scene = np.array([a.dt, a.dt])
+    batch = make_sim(sc, **TIGHT)
+    rc, _ = batch.step_batched(sc.dt_per_scene)
+    alone = make_sim(a, **TIGHT)
+    alone.step(a.dt)
+    pairs = batch.contact_pairs()
+    assert np.all((pairs[:, 0] < n) == (pairs[:, 1] < n))
+    ref = _pairs_set(alone.contact_pairs())
+    assert _pairs_set(pairs[pairs[:, 0] < n]) == ref
+    assert _pairs_set(pairs[pairs[:, 0] >= n] - n) == ref
+    gb, ga = batch.get_state(), alone.get_state()
+    np.testing.assert_array_equal(gb["pos"][:n], gb["pos"][n:])
+    disp = np.abs(ga["pos"] - a.pos).max()
+    np.testing.assert_allclose(gb["pos"][:n], ga["pos"], rtol=0, atol=1e-10 * disp)
+    batch.close()
+    alone.close()
+
+
+def test_projected_blocks_of_unstrained_symmetric_bonds_are_finite(B):
+    """Rigidly translating, unrotated lattices give bond Hessians with equal
+    diagonal entries and off-diagonals at the rounding level; the FP32 clamp
+    must leave such pairs alone instead of forming 0 * inf."""
+    sc = _two_blocks()
+    sim = make_sim(sc, mixed=True, **TIGHT)
+    sim.step(1e-3)
+    st = sim.get_state()
+    ph = st["pos"] + 1e-3 * st["vel"]
+    qh = st["quat"] + 1e-3 * st["qvel"]
+    qh /= np.linalg.norm(qh, axis=1, keepdims=True)
+    what = B.BDEM_EGH_E | B.BDEM_EGH_G | B.BDEM_EGH_H | B.BDEM_EGH_PSD
+    _, _, hd, ho = sim.energy_grad_hess(1e-3, what, ph, qh)
+    assert np.isfinite(hd).all() and np.isfinite(ho).all()
+    _, _, hd_o, ho_o = oracle_for(sc, st).energy_grad_hess(1e-3, ph, qh, psd=True)
+    scale = row_scale(hd_o, ho_o, sc.ij, sc.n)
+    assert (np.linalg.norm((ho - ho_o).reshape(sc.nb, -1), axis=1) / scale[sc.ij[:, 0]]).max() <= 1e-4
+    sim.close()
