@@ -76,7 +76,7 @@ def bond_algorithmic_bytes(n, nb_alive, elt):
     return n * 64 + nb_alive * 72 + nb_alive * 36 * elt + n * 21 * elt + n * 48
 
 
-def run_path(scene, mixed, steps, warmup, profile):
+def run_path(scene, mixed, steps, warmup, profile, **opts):
     """Warm up, then time `steps` implicit steps with the library defaults.
     With profile, HIP events on the library's stream bracket every bond
     evaluation and every SpMV launch of the timed steps; PCG issues one
@@ -86,7 +86,7 @@ def run_path(scene, mixed, steps, warmup, profile):
     import torch
     from paper_2308_10459_amd import bdem as B
     prec = B.BDEM_PREC_MIXED if mixed else B.BDEM_PREC_FP64
-    sim = B.Simulator(scene, precision=prec)
+    sim = B.Simulator(scene, precision=prec, **opts)
     tuning = sim.autotune([scene.dt])
     log(f"  autotuned: {tuning}")
     if profile:   # per-launch events need ungraphed launches; the poll interval stays tuned
@@ -96,7 +96,7 @@ def run_path(scene, mixed, steps, warmup, profile):
         log(f"  warmup {k}: newton {st['newton_iters']} cg {st['cg_iters']} broken {st['bonds_broken']}")
     B.bdem_set_profiling(sim.ctx, profile)
     tot = dict(newton=0, cg=0, ls=0, bond_ms=0.0, spmv_ms=0.0, bond_launch=0, spmv_launch=0,
-               broken=0)
+               broken=0, step_ms=[], step_newton=[])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
@@ -110,6 +110,8 @@ def run_path(scene, mixed, steps, warmup, profile):
         tot["bond_launch"] += nb_launch
         tot["spmv_launch"] += sp_launch
         tot["broken"] += st["bonds_broken"]
+        tot["step_ms"].append(st["t_ms"][5])
+        tot["step_newton"].append(st["newton_iters"])
         log(f"  step {k}: newton {st['newton_iters']} cg {st['cg_iters']} ls {st['ls_backtracks']} "
             f"broken {st['bonds_broken']} rc {st['rc']} {st['t_ms'][5]:.1f} ms")
     torch.cuda.synchronize()
@@ -195,6 +197,51 @@ def run_solver_comparison(max_first_order=20000, rtol=1e-6):
     return out
 
 
+def run_integrator_comparison(scene, steps, warmup):
+    """The variational midpoint form of Section 3.1 on the bench workload
+    (mixed path), against the implicit-Euler form timed above: Newton
+    iterations per second and per step, CG iterations per Newton iteration."""
+    from paper_2308_10459_amd import bdem as B
+    r = run_path(scene, True, steps, warmup, profile=False, integrator=B.BDEM_INTEGRATOR_MIDPOINT)
+    return {"integrator": "midpoint", "steps": steps, "warmup": warmup,
+            "newton_iters_per_s": r["newton"] / r["wall_s"],
+            "ms_per_step": 1e3 * r["wall_s"] / steps,
+            "newton_iters_per_step": r["newton"] / steps,
+            "cg_iters_per_newton": r["cg"] / max(r["newton"], 1),
+            "bonds_broken": r["broken"]}
+
+
+def run_contact_comparison(scene, steps):
+    """The bench workload (mixed path) from its initial state, with and
+    without the element repulsion of Section 5.4 (k_ec = E_max r_max,
+    candidates within r_i + r_j + r_max): per-step time, Newton and CG
+    iterations, and the time per Newton iteration, which carries the cost of
+    the per-step broad phase, the per-iteration repulsion terms and the extra
+    PCG coupling kernel.  Steps are counted from the impact on, where the
+    repulsion between the pairs of bonds broken at impact (jittered rest
+    distances, so some overlap) changes the dynamics; the two columns are
+    therefore different trajectories after the first step."""
+    import torch
+    from paper_2308_10459_amd import bdem as B
+    out = {"k_self": "E_max r_max", "steps": steps}
+    for label, opts in (("without", {}), ("with", {"k_self": -1.0})):
+        sim = B.Simulator(scene, precision=B.BDEM_PREC_MIXED, **opts)
+        sim.autotune([scene.dt])
+        rows = []
+        for _ in range(steps):
+            st = sim.step(scene.dt)
+            rows.append({"ms": st["t_ms"][5], "newton": st["newton_iters"], "cg": st["cg_iters"],
+                         "broken": st["bonds_broken"], "rc": st["rc"]})
+        pairs = len(sim.contact_pairs())
+        sim.close()
+        torch.cuda.synchronize()
+        nw = sum(r["newton"] for r in rows)
+        out[label] = {"per_step": rows, "ms_per_newton_iter": sum(r["ms"] for r in rows) / max(nw, 1),
+                      "candidate_pairs_last_step": pairs}
+        log(f"  {label}: " + ", ".join(f"{r['ms']:.1f} ms / {r['newton']} Newton / {r['cg']} CG" for r in rows))
+    return out
+
+
 def cpu_baseline(target_s=15.0):
     """The FP64 oracle on a bounded sample of the same workload: a 24x24x16
     sub-plate (9,216 particles) built like the ceramic plate, same material,
@@ -246,6 +293,11 @@ def main():
     ap.add_argument("--no-solver-comparison", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=3,
                     help="steps of the 64-scene batch (0: skip)")
+    ap.add_argument("--midpoint-steps", type=int, default=5,
+                    help="steps of the bench workload with the midpoint integrator (0: skip)")
+    ap.add_argument("--contact-steps", type=int, default=2,
+                    help="steps of the bench workload from its initial state with and without "
+                         "element repulsion (0: skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -322,6 +374,13 @@ def main():
                      "traffic": recorded_traffic(),
                      "algorithmic_bytes_per_launch": rm["spmv_bytes"]},
     }
+    if args.midpoint_steps > 0:
+        log("midpoint integrator (mixed path):")
+        out["integrator_comparison"] = run_integrator_comparison(scene, args.midpoint_steps, args.warmup)
+        out["integrator_comparison"]["euler_newton_iters_per_step"] = mixed["newton"] / args.steps
+    if args.contact_steps > 0:
+        log("element repulsion on (mixed path):")
+        out["contact_comparison"] = run_contact_comparison(scene, args.contact_steps)
     if not args.no_solver_comparison:
         log("first- vs second-order manifold optimisation:")
         out["solver_comparison"] = run_solver_comparison()
