@@ -211,6 +211,21 @@ def run_integrator_comparison(scene, steps, warmup):
             "bonds_broken": r["broken"]}
 
 
+def run_precond_comparison(scene, steps, warmup):
+    """The bench workload (mixed path, same steps) with the aggregation
+    multigrid preconditioner instead of block-Jacobi (Section 5.3 solves with
+    AMG-PCG): Newton iterations per second, per step and CG iterations per
+    Newton iteration."""
+    from paper_2308_10459_amd import bdem as B
+    r = run_path(scene, True, steps, warmup, profile=False, preconditioner=B.BDEM_PRECOND_AMG)
+    return {"preconditioner": "aggregation multigrid", "steps": steps, "warmup": warmup,
+            "newton_iters_per_s": r["newton"] / r["wall_s"],
+            "ms_per_step": 1e3 * r["wall_s"] / steps,
+            "newton_iters_per_step": r["newton"] / steps,
+            "cg_iters_per_newton": r["cg"] / max(r["newton"], 1),
+            "bonds_broken": r["broken"]}
+
+
 def run_contact_comparison(scene, steps):
     """The bench workload (mixed path) from its initial state, with and
     without the element repulsion of Section 5.4 (k_ec = E_max r_max,
@@ -295,6 +310,8 @@ def main():
                     help="steps of the 64-scene batch (0: skip)")
     ap.add_argument("--midpoint-steps", type=int, default=5,
                     help="steps of the bench workload with the midpoint integrator (0: skip)")
+    ap.add_argument("--no-amg", action="store_true",
+                    help="skip the multigrid-preconditioned run of the bench workload")
     ap.add_argument("--contact-steps", type=int, default=2,
                     help="steps of the bench workload from its initial state with and without "
                          "element repulsion (0: skip)")
@@ -374,6 +391,12 @@ def main():
                      "traffic": recorded_traffic(),
                      "algorithmic_bytes_per_launch": rm["spmv_bytes"]},
     }
+    if not args.no_amg:
+        log("aggregation multigrid preconditioner (mixed path):")
+        out["precond_comparison"] = run_precond_comparison(scene, args.steps, args.warmup)
+        out["precond_comparison"]["block_jacobi"] = {
+            "newton_iters_per_s": rm["newton_iters_per_s"], "ms_per_step": rm["ms_per_step"],
+            "cg_iters_per_newton": rm["cg_iters_per_newton"]}
     if args.midpoint_steps > 0:
         log("midpoint integrator (mixed path):")
         out["integrator_comparison"] = run_integrator_comparison(scene, args.midpoint_steps, args.warmup)

@@ -142,7 +142,15 @@ typedef struct {
                               with z_hat = x_hat - dt^2/2 M_s^{-1} grad V((x_{n-1} + x_n)/2),
                               x_{n-1} = x_n - dt v_n: second order in the positions; the
                               unit-norm constraint holds at the new state */
-  int32_t pad_;            /* reserved */
+  int32_t preconditioner;  /* PCG preconditioner: BDEM_PRECOND_BLOCK_JACOBI (default, the 6x6
+                              diagonal blocks) or BDEM_PRECOND_AMG (Section 5.3 solves with AMG):
+                              aggregates = cells of side 4 r_max from each scene's initial box
+                              corner, doubled per level until a scene has at most 32; rigid-body
+                              modes of each aggregate as prolongation; Galerkin coarse operators
+                              rebuilt at every Newton iteration; omega = 0.8 block-Jacobi pre- and
+                              post-smoothing; a dense exact solve on the last level.  Built from
+                              the diagonal and bond blocks (not the element-repulsion couplings);
+                              its hierarchy is allocated by bdem_create, outside the workspace */
 } bdem_options;
 
 typedef struct {
@@ -168,6 +176,7 @@ typedef struct {
 
 enum { BDEM_SOLVER_NEWTON = 0, BDEM_SOLVER_FIRST_ORDER = 1 };
 enum { BDEM_INTEGRATOR_EULER = 0, BDEM_INTEGRATOR_MIDPOINT = 1 };
+enum { BDEM_PRECOND_BLOCK_JACOBI = 0, BDEM_PRECOND_AMG = 1 };
 
 /* Defaults: gravity (0,0,-9.81), no ground, newton_tol 0, newton_rtol 1e-8,
  * armijo_c 1e-4, cg_rtol_max 0.5, max_newton 50, max_cg 2000, max_ls 30,
@@ -207,6 +216,14 @@ int bdem_step_batched(bdem_ctx *ctx, const double *dt_per_scene,
 int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, const double *pos_eval,
                           const double *quat_eval, double *energy, double *grad6,
                           double *hdiag36, double *hoff36);
+
+/* One application of the configured PCG preconditioner M^-1 (Section 5.3) to
+ * in6 (6n, host, reduced coordinates per particle), with M built from the
+ * projected reduced Hessian at the evaluation state (as bdem_energy_grad_hess
+ * with BDEM_EGH_H | BDEM_EGH_PSD; NULL: the current state); the result goes
+ * to out6 (6n, host).  Errors as bdem_energy_grad_hess. */
+int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_eval, const double *quat_eval,
+                       const double *in6, double *out6);
 
 /* Section 3.3 stress test of every alive bond at the current state; bonds
  * with sigma > sigma_c or tau > tau_c break permanently.  n_broken (nullable)

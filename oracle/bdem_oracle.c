@@ -56,6 +56,8 @@ struct orc_sys {
   int32_t *cp;                          /* (i, j) with i < j */
   double *hcp;                          /* (i, j) 6x6 block of each pair at the last Hessian */
   int hcp_valid;
+  /* multigrid aggregation: cells of size 4 r_max from the initial box corner */
+  int64_t *cell;                        /* 3 per particle */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -190,7 +192,7 @@ void orc_destroy(orc_sys *s) {
                     s->d0, s->R0, s->kn, s->kt, s->K, s->S, s->r0, s->I, s->J, s->sigc, s->tauc};
   for (size_t k = 0; k < sizeof arrs / sizeof arrs[0]; ++k) free(arrs[k]);
   free(s->flags); free(s->ij); free(s->alive); free(s->tension_only);
-  free(s->bkey); free(s->bkey_idx); free(s->cp); free(s->hcp);
+  free(s->bkey); free(s->bkey_idx); free(s->cp); free(s->hcp); free(s->cell);
   free(s);
 }
 
@@ -290,6 +292,16 @@ orc_sys *orc_create(int32_t n, const double *pos, const double *quat, const doub
   s->cmargin = env[9] < 0.0 ? rmax : env[9];
   s->mu_s = env[10];
   s->mu_r = env[11];
+  /* multigrid aggregation cells of the initial positions */
+  {
+    double lo[3] = {1e300, 1e300, 1e300};
+    for (int32_t i = 0; i < n; ++i)
+      for (int k = 0; k < 3; ++k) lo[k] = fmin(lo[k], pos[3 * i + k]);
+    double h0 = 4.0 * rmax;
+    s->cell = (int64_t *)malloc(3 * (size_t)n * sizeof(int64_t));
+    for (int32_t i = 0; i < n; ++i)
+      for (int k = 0; k < 3; ++k) s->cell[3 * i + k] = (int64_t)floor((pos[3 * i + k] - lo[k]) / h0);
+  }
   /* bond lookup by endpoint pair */
   s->bkey = (uint64_t *)malloc(B * sizeof(uint64_t));
   s->bkey_idx = (int64_t *)malloc(B * sizeof(int64_t));
@@ -1360,6 +1372,283 @@ void orc_friction(orc_sys *s, double dt) {
     for (int c = 0; c < 4; ++c) s->qvel[4 * i + c] += 0.5 * t[c];
   }
   free(dv); free(dw); free(w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Aggregation multigrid preconditioner.  Section 5.3 solves with AMG-PCG    */
+/* without giving the method; this is the variant the GPU path implements:  */
+/* aggregates = cells of side 4 r_max (from the initial box corner; cells    */
+/* of twice the side at each coarser level), prolongation from the six      */
+/* rigid-body modes of each aggregate, Galerkin coarse operators, damped    */
+/* block-Jacobi smoothing (omega = 0.8) before and after the coarse          */
+/* correction, and an exact solve on the first level with at most 32 nodes  */
+/* (always at least one coarse level).  Built from the diagonal and bond    */
+/* blocks; element-repulsion couplings are not part of it.                   */
+/* ------------------------------------------------------------------------ */
+#define AMG_OMEGA 0.8
+#define AMG_COARSE_MAX 32
+
+typedef struct {
+  int32_t n;
+  double *A;        /* levels >= 1: dense 6n x 6n */
+  double *Dinv;     /* 36 per node */
+  double *P;        /* 36 per node: block of the prolongation to the next level */
+  int32_t *parent;  /* node of the next level */
+  double *cen;      /* 3 per node */
+  int32_t *active;  /* node has a free particle below it */
+  int64_t *cell;    /* 3 per node */
+} amg_level;
+
+/* dense inverse by Gauss-Jordan with partial pivoting; returns -1 if singular */
+static int dense_inverse(int N, const double *A, double *X) {
+  double *M = (double *)malloc(sizeof(double) * N * N);
+  memcpy(M, A, sizeof(double) * N * N);
+  for (int r = 0; r < N; ++r)
+    for (int c = 0; c < N; ++c) X[r * N + c] = (r == c);
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < N; ++r) if (fabs(M[r * N + k]) > fabs(M[piv * N + k])) piv = r;
+    if (!(fabs(M[piv * N + k]) > 0.0)) { free(M); return -1; }
+    if (piv != k)
+      for (int c = 0; c < N; ++c) {
+        double t = M[k * N + c]; M[k * N + c] = M[piv * N + c]; M[piv * N + c] = t;
+        t = X[k * N + c]; X[k * N + c] = X[piv * N + c]; X[piv * N + c] = t;
+      }
+    double inv = 1.0 / M[k * N + k];
+    for (int c = 0; c < N; ++c) { M[k * N + c] *= inv; X[k * N + c] *= inv; }
+    for (int r = 0; r < N; ++r) {
+      if (r == k) continue;
+      double f = M[r * N + k];
+      if (f == 0.0) continue;
+      for (int c = 0; c < N; ++c) { M[r * N + c] -= f * M[k * N + c]; X[r * N + c] -= f * X[k * N + c]; }
+    }
+  }
+  free(M);
+  return 0;
+}
+
+static int cmp_key(const void *a, const void *b) {
+  const int64_t *x = (const int64_t *)a, *y = (const int64_t *)b;
+  return x[0] < y[0] ? -1 : (x[0] > y[0] ? 1 : (x[1] < y[1] ? -1 : (x[1] > y[1])));
+}
+
+/* next level: group the nodes of lv by cell >> 1 (or by their own cell for
+ * the particles, whose cells are already the first aggregation cells) */
+static void amg_coarsen(const amg_level *lv, int first, amg_level *nx) {
+  int32_t n = lv->n;
+  int64_t *kv = (int64_t *)malloc(2 * sizeof(int64_t) * n);
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t c[3];
+    for (int k = 0; k < 3; ++k) c[k] = first ? lv->cell[3 * i + k] : (lv->cell[3 * i + k] >> 1);
+    kv[2 * i] = (c[0] << 42) | (c[1] << 21) | c[2];
+    kv[2 * i + 1] = i;
+  }
+  qsort(kv, n, 2 * sizeof(int64_t), cmp_key);
+  int32_t m = 0;
+  for (int32_t k = 0; k < n; ++k) if (k == 0 || kv[2 * k] != kv[2 * k - 2]) ++m;
+  nx->n = m;
+  nx->cell = (int64_t *)malloc(3 * sizeof(int64_t) * m);
+  nx->cen = (double *)calloc(3 * (size_t)m, sizeof(double));
+  nx->active = (int32_t *)calloc(m, sizeof(int32_t));
+  int32_t a = -1;
+  for (int32_t k = 0; k < n; ++k) {
+    if (k == 0 || kv[2 * k] != kv[2 * k - 2]) {
+      ++a;
+      int32_t i = (int32_t)kv[2 * k + 1];
+      for (int c = 0; c < 3; ++c) nx->cell[3 * a + c] = first ? lv->cell[3 * i + c] : (lv->cell[3 * i + c] >> 1);
+    }
+    lv->parent[kv[2 * k + 1]] = a;
+  }
+  free(kv);
+  /* centroids over active children (all children when none is active) */
+  int32_t *cnt = (int32_t *)calloc(m, sizeof(int32_t));
+  for (int32_t i = 0; i < n; ++i) if (lv->active[i]) nx->active[lv->parent[i]] = 1;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t p = lv->parent[i];
+    if (nx->active[p] && !lv->active[i]) continue;
+    for (int c = 0; c < 3; ++c) nx->cen[3 * p + c] += lv->cen[3 * i + c];
+    cnt[p]++;
+  }
+  for (int32_t p = 0; p < m; ++p)
+    for (int c = 0; c < 3; ++c) nx->cen[3 * p + c] /= cnt[p];
+  free(cnt);
+}
+
+/* P block of node i of lv (already coarsened into nx): rows (dp, y) of the
+ * node, columns (t, w) of the parent: dp = t + w x (x_i - c), y = S w */
+static void amg_prolong_blocks(amg_level *lv, const amg_level *nx, const double *quat, int fine) {
+  lv->P = (double *)calloc(36 * (size_t)lv->n, sizeof(double));
+  for (int32_t i = 0; i < lv->n; ++i) {
+    if (!lv->active[i]) continue;
+    double *P = lv->P + 36 * i;
+    const double *c = nx->cen + 3 * lv->parent[i];
+    double d[3] = {lv->cen[3 * i] - c[0], lv->cen[3 * i + 1] - c[1], lv->cen[3 * i + 2] - c[2]};
+    double X[9];
+    cross_matrix(d, X);   /* w x d = -d x w = -[d]x w */
+    for (int r = 0; r < 3; ++r) {
+      P[r * 6 + r] = 1.0;
+      for (int k = 0; k < 3; ++k) P[r * 6 + 3 + k] = -X[r * 3 + k];
+    }
+    double S[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (fine) {   /* y = 1/2 R(q)^T w: dq = G_l(q)^T y = q (y, 0) equals 1/2 (w, 0) q */
+      double R[9];
+      rotmat(quat + 4 * i, R);
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) S[r * 3 + k] = 0.5 * R[k * 3 + r];
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) P[(3 + r) * 6 + 3 + k] = S[r * 3 + k];
+  }
+}
+
+/* C += P_a^T B P_b for 6x6 blocks */
+static void ptbp_add(const double *Pa, const double *Bm, const double *Pb, double *C, int ldc) {
+  double T[36], U[36];
+  mm(6, 6, 6, Bm, Pb, T);
+  mtm(6, 6, 6, Pa, T, U);
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) C[r * ldc + c] += U[r * 6 + c];
+}
+
+static void amg_diag_inverse(amg_level *lv, const double *hdiag) {
+  lv->Dinv = (double *)malloc(36 * sizeof(double) * lv->n);
+  int32_t N = 6 * lv->n;
+  for (int32_t i = 0; i < lv->n; ++i) {
+    double B[36];
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) B[r * 6 + c] = hdiag ? hdiag[36 * i + r * 6 + c] : lv->A[(6 * i + r) * N + 6 * i + c];
+    if (dense_inverse(6, B, lv->Dinv + 36 * i)) memset(lv->Dinv + 36 * i, 0, 36 * sizeof(double));
+  }
+}
+
+/* y = A x on level l (level 0: diagonal and bond blocks) */
+static void amg_apply_A(const orc_sys *s, const amg_level *lv, int l, const double *hdiag,
+                        const double *hoff, const double *x, double *y) {
+  if (l == 0) {
+    for (int32_t i = 0; i < s->n; ++i) mm(6, 6, 1, hdiag + 36 * i, x + 6 * i, y + 6 * i);
+    for (int64_t b = 0; b < s->nb; ++b) {
+      if (!s->alive[b]) continue;
+      int32_t i = s->ij[2 * b], j = s->ij[2 * b + 1];
+      const double *Hb = hoff + 36 * b;
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+          y[6 * i + r] += Hb[r * 6 + c] * x[6 * j + c];
+          y[6 * j + c] += Hb[r * 6 + c] * x[6 * i + r];
+        }
+    }
+  } else {
+    int32_t N = 6 * lv[l].n;
+    mm(N, N, 1, lv[l].A, x, y);
+  }
+}
+
+static void amg_vcycle(const orc_sys *s, const amg_level *lv, int l, int L, const double *Ainv,
+                       const double *hdiag, const double *hoff, const double *b, double *x) {
+  int32_t n = lv[l].n, N = 6 * n;
+  if (l == L) { mm(N, N, 1, Ainv, b, x); return; }
+  double *t = (double *)calloc(N, sizeof(double)), *r = (double *)calloc(N, sizeof(double));
+  int32_t nc = lv[l + 1].n;
+  double *bc = (double *)calloc(6 * (size_t)nc, sizeof(double)), *ec = (double *)malloc(sizeof(double) * 6 * nc);
+  /* pre-smoothing from zero */
+  for (int32_t i = 0; i < n; ++i) {
+    mm(6, 6, 1, lv[l].Dinv + 36 * i, b + 6 * i, t + 6 * i);
+    for (int k = 0; k < 6; ++k) t[6 * i + k] *= AMG_OMEGA;
+  }
+  /* restricted residual */
+  amg_apply_A(s, lv, l, hdiag, hoff, t, r);
+  for (int32_t k = 0; k < N; ++k) r[k] = b[k] - r[k];
+  for (int32_t i = 0; i < n; ++i) {
+    double u[6];
+    mtm(6, 6, 1, lv[l].P + 36 * i, r + 6 * i, u);
+    for (int k = 0; k < 6; ++k) bc[6 * lv[l].parent[i] + k] += u[k];
+  }
+  amg_vcycle(s, lv, l + 1, L, Ainv, hdiag, hoff, bc, ec);
+  /* coarse correction */
+  for (int32_t i = 0; i < n; ++i) {
+    double u[6];
+    mm(6, 6, 1, lv[l].P + 36 * i, ec + 6 * lv[l].parent[i], u);
+    for (int k = 0; k < 6; ++k) t[6 * i + k] += u[k];
+  }
+  /* post-smoothing */
+  amg_apply_A(s, lv, l, hdiag, hoff, t, r);
+  for (int32_t i = 0; i < n; ++i) {
+    double e[6], u[6];
+    for (int k = 0; k < 6; ++k) e[k] = b[6 * i + k] - r[6 * i + k];
+    mm(6, 6, 1, lv[l].Dinv + 36 * i, e, u);
+    for (int k = 0; k < 6; ++k) x[6 * i + k] = t[6 * i + k] + AMG_OMEGA * u[k];
+  }
+  free(t); free(r); free(bc); free(ec);
+}
+
+int orc_amg_apply(const orc_sys *s, const double *pos, const double *quat, const double *hdiag,
+                  const double *hoff, const double *b, double *x) {
+  enum { MAXL = 24 };
+  amg_level lv[MAXL];
+  memset(lv, 0, sizeof lv);
+  int32_t n = s->n;
+  lv[0].n = n;
+  lv[0].cell = (int64_t *)malloc(3 * sizeof(int64_t) * n);
+  memcpy(lv[0].cell, s->cell, 3 * sizeof(int64_t) * n);
+  lv[0].cen = (double *)malloc(3 * sizeof(double) * n);
+  memcpy(lv[0].cen, pos, 3 * sizeof(double) * n);
+  lv[0].active = (int32_t *)malloc(sizeof(int32_t) * n);
+  for (int32_t i = 0; i < n; ++i) lv[0].active[i] = s->flags[i] == 0;
+  amg_diag_inverse(&lv[0], hdiag);
+  int L = 0;
+  do {
+    amg_level *f = &lv[L], *c = &lv[L + 1];
+    f->parent = (int32_t *)malloc(sizeof(int32_t) * f->n);
+    amg_coarsen(f, L == 0, c);
+    amg_prolong_blocks(f, c, quat, L == 0);
+    /* Galerkin product */
+    int32_t Nc = 6 * c->n;
+    c->A = (double *)calloc((size_t)Nc * Nc, sizeof(double));
+    if (L == 0) {
+      for (int32_t i = 0; i < n; ++i) {
+        int32_t a = f->parent[i];
+        ptbp_add(f->P + 36 * i, hdiag + 36 * i, f->P + 36 * i, c->A + (size_t)(6 * a) * Nc + 6 * a, Nc);
+      }
+      for (int64_t bb = 0; bb < s->nb; ++bb) {
+        if (!s->alive[bb]) continue;
+        int32_t i = s->ij[2 * bb], j = s->ij[2 * bb + 1], a = f->parent[i], cc = f->parent[j];
+        double Ht[36];
+        for (int r = 0; r < 6; ++r)
+          for (int q = 0; q < 6; ++q) Ht[r * 6 + q] = hoff[36 * bb + q * 6 + r];
+        ptbp_add(f->P + 36 * i, hoff + 36 * bb, f->P + 36 * j, c->A + (size_t)(6 * a) * Nc + 6 * cc, Nc);
+        ptbp_add(f->P + 36 * j, Ht, f->P + 36 * i, c->A + (size_t)(6 * cc) * Nc + 6 * a, Nc);
+      }
+    } else {
+      int32_t Nf = 6 * f->n;
+      for (int32_t i = 0; i < f->n; ++i)
+        for (int32_t j = 0; j < f->n; ++j) {
+          double B[36];
+          int nz = 0;
+          for (int r = 0; r < 6; ++r)
+            for (int q = 0; q < 6; ++q) {
+              B[r * 6 + q] = f->A[(size_t)(6 * i + r) * Nf + 6 * j + q];
+              nz |= B[r * 6 + q] != 0.0;
+            }
+          if (!nz) continue;
+          int32_t a = f->parent[i], cc = f->parent[j];
+          ptbp_add(f->P + 36 * i, B, f->P + 36 * j, c->A + (size_t)(6 * a) * Nc + 6 * cc, Nc);
+        }
+    }
+    for (int32_t a = 0; a < c->n; ++a)
+      if (!c->active[a])
+        for (int r = 0; r < 6; ++r) c->A[(size_t)(6 * a + r) * Nc + 6 * a + r] = 1.0;
+    amg_diag_inverse(c, NULL);
+    ++L;
+  } while (lv[L].n > AMG_COARSE_MAX && L < MAXL - 1);
+  int32_t NL = 6 * lv[L].n;
+  double *Ainv = (double *)malloc(sizeof(double) * NL * NL);
+  int rc = dense_inverse(NL, lv[L].A, Ainv) ? -1 : L;
+  if (rc >= 0) amg_vcycle(s, lv, 0, L, Ainv, hdiag, hoff, b, x);
+  free(Ainv);
+  for (int l = 0; l <= L; ++l) {
+    free(lv[l].A); free(lv[l].Dinv); free(lv[l].P); free(lv[l].parent); free(lv[l].cen);
+    free(lv[l].active); free(lv[l].cell);
+  }
+  return rc;
 }
 
 void orc_default_options(orc_options *o) {

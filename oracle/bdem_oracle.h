@@ -108,6 +108,17 @@ int64_t orc_contacts(const orc_sys *s, int32_t *pairs, int64_t cap);
 /* friction of Section 5.4 applied to the current velocities */
 void orc_friction(orc_sys *s, double dt);
 
+/* One V-cycle of the aggregation multigrid preconditioner on b (6n): x (6n)
+ * ~ H^-1 b with H the diagonal (hdiag) and bond (hoff) blocks of
+ * orc_energy_grad_hess at the state (pos, quat) the prolongation is built
+ * from.  Aggregates: cells of side 4 r_max from the initial box corner
+ * (doubled per level); rigid-body-mode prolongation; Galerkin coarse
+ * operators; omega = 0.8 block-Jacobi pre- and post-smoothing; exact solve
+ * on the first level with <= 32 nodes.  Returns the number of coarse levels,
+ * -1 if the coarsest operator is singular. */
+int orc_amg_apply(const orc_sys *s, const double *pos, const double *quat, const double *hdiag,
+                  const double *hoff, const double *b, double *x);
+
 /* y = H x with the blocks of orc_energy_grad_hess */
 void orc_hess_apply(const orc_sys *s, const double *hdiag, const double *hoff,
                     const double *x, double *y);

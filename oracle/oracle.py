@@ -75,6 +75,7 @@ def lib():
         L.orc_contacts.restype = C.c_int64
         L.orc_contacts.argtypes = [C.c_void_p, _i32p, C.c_int64]
         L.orc_friction.argtypes = [C.c_void_p, C.c_double]
+        L.orc_amg_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_hess_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
         L.orc_pcg.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp]
         L.orc_psd_project.argtypes = [C.c_int, _dp, _dp]
@@ -208,6 +209,15 @@ class Oracle:
 
     def friction(self, dt):
         lib().orc_friction(self.h, dt)
+
+    def amg_apply(self, pos, quat, hdiag, hoff, b):
+        """One V-cycle of the aggregation multigrid preconditioner; returns
+        (x, number of coarse levels)."""
+        x = np.empty((self.n, 6))
+        hd, ho = _f64(hdiag), _f64(hoff if self.nb else np.zeros((1, 6, 6)))
+        L = lib().orc_amg_apply(self.h, _p(_f64(pos)), _p(_f64(quat)), _p(hd), _p(ho),
+                                _p(_f64(b)), _p(x))
+        return x, L
 
     def midpoint_target(self, dt):
         zp, zq = np.empty((self.n, 3)), np.empty((self.n, 4))

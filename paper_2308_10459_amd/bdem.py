@@ -27,6 +27,7 @@ BDEM_FREE, BDEM_FIXED, BDEM_KINEMATIC = 0, 1, 2
 BDEM_PREC_FP64, BDEM_PREC_MIXED = 0, 1
 BDEM_SOLVER_NEWTON, BDEM_SOLVER_FIRST_ORDER = 0, 1
 BDEM_INTEGRATOR_EULER, BDEM_INTEGRATOR_MIDPOINT = 0, 1
+BDEM_PRECOND_BLOCK_JACOBI, BDEM_PRECOND_AMG = 0, 1
 BDEM_EGH_E, BDEM_EGH_G, BDEM_EGH_H, BDEM_EGH_PSD, BDEM_EGH_POTENTIAL_ONLY = 1, 2, 4, 8, 16
 
 _dp = C.POINTER(C.c_double)
@@ -58,7 +59,7 @@ class bdem_options(C.Structure):
                 ("armijo_c", C.c_double), ("cg_rtol_max", C.c_double), ("max_newton", C.c_int32),
                 ("max_cg", C.c_int32), ("max_ls", C.c_int32), ("precision", C.c_int32),
                 ("break_each_step", C.c_int32), ("cg_chunk", C.c_int32), ("use_graph", C.c_int32),
-                ("solver", C.c_int32), ("integrator", C.c_int32), ("pad_", C.c_int32)]
+                ("solver", C.c_int32), ("integrator", C.c_int32), ("preconditioner", C.c_int32)]
 
 
 class bdem_step_stats(C.Structure):
@@ -95,6 +96,7 @@ _sig = {
                                         _dp, _dp]),
     "bdem_break_bonds": (C.c_int, [_ctx_p, _i64p, _u8p]),
     "bdem_contact_pairs": (C.c_int, [_ctx_p, C.c_int64, _i32p, _i64p]),
+    "bdem_precond_apply": (C.c_int, [_ctx_p, C.c_double, _dp, _dp, _dp, _dp]),
     "bdem_get_state": (C.c_int, [_ctx_p, _dp, _dp, _dp, _dp, _u8p]),
     "bdem_set_state": (C.c_int, [_ctx_p, _dp, _dp, _dp, _dp, _u8p]),
     "bdem_sizes": (C.c_int, [_ctx_p, _i32p, _i64p, _i32p]),
@@ -239,6 +241,17 @@ def bdem_energy_grad_hess(ctx, dt, what, pos=None, quat=None):
     return e.value, g, hd, (None if ho is None else ho[:nb])
 
 
+def bdem_precond_apply(ctx, dt, vec6, pos=None, quat=None):
+    """M^-1 vec6 with the configured preconditioner at the evaluation state."""
+    n = bdem_sizes(ctx)[0]
+    x = _f64(np.asarray(vec6).reshape(n, 6))
+    out = np.empty((n, 6))
+    pe = None if pos is None else _f64(pos)
+    qe = None if quat is None else _f64(quat)
+    _check(_lib.bdem_precond_apply(ctx, dt, _p(pe), _p(qe), _p(x), _p(out)), ctx)
+    return out
+
+
 def bdem_contact_pairs(ctx):
     """Element-repulsion candidate pairs of the last step (user indices, i < j)."""
     k = C.c_int64()
@@ -341,6 +354,9 @@ class Simulator:
 
     def contact_pairs(self):
         return bdem_contact_pairs(self.ctx)
+
+    def precond_apply(self, dt, vec6, pos=None, quat=None):
+        return bdem_precond_apply(self.ctx, dt, vec6, pos, quat)
 
     def autotune(self, dts=None):
         if dts is None:

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libbdem.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["bdem_capi.cpp", "k_bond.hip", "k_particle.hip", "k_solve.hip", "k_contact.hip"]
+SOURCES = ["bdem_capi.cpp", "bdem_amg.cpp", "k_bond.hip", "k_particle.hip", "k_solve.hip",
+           "k_contact.hip", "k_amg.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

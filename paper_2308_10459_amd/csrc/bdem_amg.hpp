@@ -1,0 +1,89 @@
+// Aggregation multigrid preconditioner for the block-CSR reduced Hessian
+// (Section 5.3 solves with AMG-PCG; the variant is this project's choice).
+//
+// Aggregates are cells of side h0 = 4 r_max of the scene, counted from the
+// corner of the scene's initial bounding box; a coarser level groups the
+// cells of the level below by doubling the side.  The hierarchy (which nodes
+// belong together, every coarse sparsity pattern and the list of fine blocks
+// that sum into each coarse block) is built once on the host at create; the
+// numbers are recomputed on the device at every Newton iteration:
+//   P_i = [[I, -[x_i - c_a]x], [0, S_i]]  (rigid-body modes t, w of the
+//         aggregate a: dp = t + w x (x_i - c_a), y = S_i w; S_i = 1/2 R(q_i)^T
+//         for particles, I above), zero for particles that are not unknowns;
+//   A_{l+1} = P^T A_l P (Galerkin), identity on nodes without unknowns;
+//   smoothing: omega = 0.8 block Jacobi before and after the coarse
+//   correction; an exact dense solve per scene on the last level (at most
+//   AMG_COARSE_MAX nodes per scene).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "bdem_internal.hpp"
+
+namespace bdem {
+
+constexpr int AMG_COARSE_MAX = 32;
+constexpr double AMG_OMEGA = 0.8;
+
+// device view of one coarse level (level >= 1)
+struct AmgLevel {
+  int n = 0, nslots = 0;
+  int *row_ptr = nullptr, *col = nullptr, *slot_row = nullptr, *dslot = nullptr;
+  void *val = nullptr;              // 36 T per slot (rows of the row node)
+  void *dinv = nullptr;             // 36 T per node
+  int *gptr = nullptr, *gsrc = nullptr;   // contributions per slot, sources in the finer level
+  int *mbeg = nullptr, *mlist = nullptr;  // children (finer-level nodes) of each node
+  int *active = nullptr, *scene = nullptr;
+  double *cen = nullptr;            // 3 per node
+  double *pd = nullptr;             // 3 per node: x_node - c_parent (towards the next level)
+  int *parent = nullptr;            // node of the next level
+  double *b = nullptr, *t = nullptr, *r = nullptr, *e = nullptr;   // 6 per node
+};
+
+// device view of the whole hierarchy
+struct AmgDev {
+  int L = 0;                        // coarse levels (>= 1)
+  // fine level (particles, internal order)
+  int *slot_row0 = nullptr;         // row of each fine off-diagonal slot
+  int *parent0 = nullptr;           // level-1 node of each particle (-1: padding)
+  double *pd0 = nullptr;            // 12 per particle: x_i - c_a (3), S_i (9)
+  double *t0 = nullptr, *r0 = nullptr;   // 6 per particle
+  const AmgLevel *lv = nullptr;     // device array lv[0..L] (lv[0] unused)
+  // coarsest level: dense inverse per scene
+  int *cbeg = nullptr;              // n_scenes + 1: node range per scene on level L
+  int64_t *coff = nullptr;          // n_scenes: offset of the scene's (6m)^2 block
+  double *cmat = nullptr;           // dense operator, then its inverse
+  double *cwork = nullptr;          // Gauss-Jordan work
+};
+
+// host-side symbolic hierarchy
+struct AmgHostLevel {
+  int n = 0;
+  std::vector<int> row_ptr, col, slot_row, dslot, gptr, gsrc, mbeg, mlist, active, scene, parent;
+};
+struct AmgHost {
+  int L = 0;
+  std::vector<int> parent0, slot_row0;
+  std::vector<AmgHostLevel> lv;     // lv[1..L]
+  std::vector<int> cbeg;
+  std::vector<int64_t> coff;
+  int64_t cdense = 0;               // total doubles of the dense blocks
+};
+
+// Builds the symbolic hierarchy.  pos: 4 doubles per internal row (initial
+// positions), flags per row (255 = padding), psid per row, scene_pbeg,
+// fine CSR (row_ptr over rows, col per slot), per-scene box corner and h0.
+void amg_build(int n_pad, int n_scenes, const std::vector<double> &pos4,
+               const std::vector<uint8_t> &flags, const std::vector<int> &psid,
+               const std::vector<int> &scene_pbeg, const std::vector<int> &row_ptr,
+               const std::vector<int> &col, const std::vector<double> &lo3,
+               const std::vector<double> &h0, AmgHost &H);
+
+// kernels (k_amg.hip)
+// hl: host copy of the level array (sizes for the launches)
+void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
+                      hipStream_t s);
+void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
+                       hipStream_t s);
+
+}  // namespace bdem

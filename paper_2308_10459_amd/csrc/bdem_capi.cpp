@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/bdem.h"
+#include "bdem_amg.hpp"
 #include "bdem_internal.hpp"
 
 using namespace bdem;
@@ -188,6 +189,11 @@ struct bdem_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;   // (kind, index of start event)
+  // aggregation multigrid preconditioner (bdem_options.preconditioner)
+  bool amg = false;
+  AmgDev amg_d;
+  std::vector<AmgLevel> amg_hl;   // host copy of the level array (device pointers)
+  void *amg_mem = nullptr;
 };
 
 #define HIP_TRY(expr)                                                                 \
@@ -224,9 +230,9 @@ extern "C" void bdem_default_options(bdem_options *o) {
   o->use_graph = 0;
   o->solver = BDEM_SOLVER_NEWTON;
   o->integrator = BDEM_INTEGRATOR_EULER;
-  o->pad_ = 0;
   o->k_self = 0.0;
   o->contact_margin = -1.0;
+  o->preconditioner = BDEM_PRECOND_BLOCK_JACOBI;
 }
 
 extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
@@ -257,6 +263,7 @@ static void destroy_resources(bdem_ctx *ctx) {
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
   if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
   if (ctx->own_mem && ctx->mem) (void)hipFree(ctx->mem);
+  if (ctx->amg_mem) (void)hipFree(ctx->amg_mem);
 }
 
 extern "C" void bdem_destroy(bdem_ctx *ctx) {
@@ -276,6 +283,100 @@ extern "C" int bdem_sizes(const bdem_ctx *ctx, int32_t *n, int64_t *nb, int32_t 
   if (n) *n = ctx->S.n;
   if (nb) *nb = ctx->S.nb;
   if (ns) *ns = ctx->S.n_scenes;
+  return BDEM_OK;
+}
+
+// Symbolic multigrid hierarchy: built on the host, uploaded into one
+// allocation owned by the handle (freed by bdem_destroy).
+static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std::vector<uint8_t> &flags,
+                      const std::vector<int> &psid, const std::vector<int> &rp,
+                      const std::vector<int> &col, const std::vector<double> &lo3,
+                      const std::vector<double> &h0) {
+  const Sizes &S = ctx->S;
+  const int NP = S.n_pad, NS = S.n_scenes;
+  const size_t T = S.mixed ? 4 : 8;
+  AmgHost H;
+  amg_build(NP, NS, pos4, flags, psid, ctx->scene_pbeg, rp, col, lo3, h0, H);
+  for (int sc = 0; sc < NS; ++sc)
+    if (H.cbeg[sc + 1] - H.cbeg[sc] > AMG_COARSE_MAX) {
+      ctx->err = "multigrid: a scene does not coarsen to 32 aggregates within 15 levels";
+      return BDEM_E_INVALID;
+    }
+  for (int l = 1; l <= H.L; ++l)
+    for (int v : H.lv[l].dslot)
+      if (v < 0) { ctx->err = "multigrid: a coarse row without a diagonal block"; return BDEM_E_INVALID; }
+  // one allocation carved into the arrays
+  Layout L;
+  AmgDev &a = ctx->amg_d;
+  a = AmgDev();
+  a.L = H.L;
+  ctx->amg_hl.assign(H.L + 1, AmgLevel());
+  auto addi = [&](int **p, size_t n) { L.add(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(int)); };
+  auto addd = [&](double **p, size_t n) { L.add(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(double)); };
+  addi(&a.slot_row0, H.slot_row0.size());
+  addi(&a.parent0, NP);
+  addd(&a.pd0, 12 * (size_t)NP);
+  addd(&a.t0, 6 * (size_t)NP);
+  addd(&a.r0, 6 * (size_t)NP);
+  for (int l = 1; l <= H.L; ++l) {
+    AmgLevel &V = ctx->amg_hl[l];
+    const AmgHostLevel &h = H.lv[l];
+    V.n = h.n;
+    V.nslots = (int)h.col.size();
+    addi(&V.row_ptr, h.row_ptr.size());
+    addi(&V.col, h.col.size());
+    addi(&V.slot_row, h.slot_row.size());
+    addi(&V.dslot, h.dslot.size());
+    L.add(&V.val, std::max<size_t>(h.col.size(), 1) * 36 * T);
+    L.add(&V.dinv, std::max<size_t>(h.n, 1) * 36 * T);
+    addi(&V.gptr, h.gptr.size());
+    addi(&V.gsrc, h.gsrc.size());
+    addi(&V.mbeg, h.mbeg.size());
+    addi(&V.mlist, h.mlist.size());
+    addi(&V.active, h.n);
+    addi(&V.scene, h.n);
+    addi(&V.parent, h.n);
+    addd(&V.cen, 3 * (size_t)h.n);
+    addd(&V.pd, 3 * (size_t)h.n);
+    for (double **v : {&V.b, &V.t, &V.r, &V.e}) addd(v, 6 * (size_t)h.n);
+  }
+  addi(&a.cbeg, NS + 1);
+  L.add(reinterpret_cast<void **>(&a.coff), NS * sizeof(int64_t));
+  addd(&a.cmat, (size_t)H.cdense);
+  addd(&a.cwork, (size_t)H.cdense);
+  AmgLevel *lvdev = nullptr;
+  L.add(reinterpret_cast<void **>(&lvdev), (H.L + 1) * sizeof(AmgLevel));
+  if (hipMalloc(&ctx->amg_mem, L.total + ALIGN) != hipSuccess) {
+    ctx->amg_mem = nullptr;
+    ctx->err = "hipMalloc failed for the multigrid hierarchy";
+    return BDEM_E_NOMEM;
+  }
+  char *base = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(ctx->amg_mem) + ALIGN - 1) / ALIGN * ALIGN);
+  L.bind(base);
+  a.lv = lvdev;
+  hipStream_t st = ctx->stream;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  auto upi = [&](int *dst, const std::vector<int> &v) {
+    if (!v.empty()) chk(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  };
+  upi(a.slot_row0, H.slot_row0);
+  upi(a.parent0, H.parent0);
+  for (int l = 1; l <= H.L; ++l) {
+    const AmgLevel &V = ctx->amg_hl[l];
+    const AmgHostLevel &h = H.lv[l];
+    upi(V.row_ptr, h.row_ptr); upi(V.col, h.col); upi(V.slot_row, h.slot_row); upi(V.dslot, h.dslot);
+    upi(V.gptr, h.gptr); upi(V.gsrc, h.gsrc); upi(V.mbeg, h.mbeg); upi(V.mlist, h.mlist);
+    upi(V.active, h.active); upi(V.scene, h.scene); upi(V.parent, h.parent);
+    for (double *v : {V.b, V.t, V.r, V.e, V.cen, V.pd}) chk(hipMemsetAsync(v, 0, std::max<size_t>(6 * (size_t)h.n, 1) * sizeof(double) / (v == V.cen || v == V.pd ? 2 : 1), st));
+  }
+  upi(a.cbeg, H.cbeg);
+  chk(hipMemcpyAsync(a.coff, H.coff.data(), NS * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  chk(hipMemcpyAsync(lvdev, ctx->amg_hl.data(), (H.L + 1) * sizeof(AmgLevel), hipMemcpyHostToDevice, st));
+  for (double *v : {a.pd0, a.t0, a.r0}) chk(hipMemsetAsync(v, 0, (v == a.pd0 ? 12 : 6) * (size_t)NP * sizeof(double), st));
+  chk(hipStreamSynchronize(st));
+  if (e != hipSuccess) { ctx->err = std::string("HIP error during multigrid setup: ") + hipGetErrorString(e); return BDEM_E_HIP; }
+  ctx->amg = true;
   return BDEM_OK;
 }
 
@@ -301,6 +402,8 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     return fail(nullptr, BDEM_E_INVALID, "k_self and contact_margin must be finite");
   if (o.solver != BDEM_SOLVER_NEWTON && o.solver != BDEM_SOLVER_FIRST_ORDER)
     return fail(nullptr, BDEM_E_INVALID, "solver must be BDEM_SOLVER_NEWTON or BDEM_SOLVER_FIRST_ORDER");
+  if (o.preconditioner != BDEM_PRECOND_BLOCK_JACOBI && o.preconditioner != BDEM_PRECOND_AMG)
+    return fail(nullptr, BDEM_E_INVALID, "preconditioner must be BDEM_PRECOND_BLOCK_JACOBI or BDEM_PRECOND_AMG");
   if (o.integrator != BDEM_INTEGRATOR_EULER && o.integrator != BDEM_INTEGRATOR_MIDPOINT)
     return fail(nullptr, BDEM_E_INVALID, "integrator must be BDEM_INTEGRATOR_EULER or BDEM_INTEGRATOR_MIDPOINT");
   if (o.max_newton < 0 || o.max_cg <= 0 || o.max_ls < 0 || o.cg_chunk <= 0)
@@ -630,6 +733,26 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     delete ctx;
     return fail(nullptr, BDEM_E_HIP, m);
   }
+  if (o.preconditioner == BDEM_PRECOND_AMG) {
+    // aggregation cells of side 4 r_max from each scene's initial box corner
+    std::vector<double> pos4((size_t)NP * 4), lo3(3 * NS, 1e300), h0(NS);
+    for (int r = 0; r < NP; ++r) {
+      pos4[4 * (size_t)r] = h_pn[r].x; pos4[4 * (size_t)r + 1] = h_pn[r].y; pos4[4 * (size_t)r + 2] = h_pn[r].z;
+      if (h_flags[r] == 255) continue;
+      const int sc = h_psid[r];
+      lo3[3 * sc] = std::min(lo3[3 * sc], h_pn[r].x);
+      lo3[3 * sc + 1] = std::min(lo3[3 * sc + 1], h_pn[r].y);
+      lo3[3 * sc + 2] = std::min(lo3[3 * sc + 2], h_pn[r].z);
+    }
+    for (int sc = 0; sc < NS; ++sc) h0[sc] = 4.0 * s_rmax[sc];
+    const int rc = amg_upload(ctx, pos4, h_flags, h_psid, rp, h_col, lo3, h0);
+    if (rc) {
+      const std::string m = ctx->err;
+      destroy_resources(ctx);
+      delete ctx;
+      return fail(nullptr, rc, m);
+    }
+  }
   *out = ctx;
   return BDEM_OK;
 }
@@ -699,6 +822,8 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
 static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   const bool mixed = ctx->S.mixed;
   launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream);
+  // multigrid: u = V(r) replaces the block-Jacobi u the update wrote
+  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, false);
@@ -739,6 +864,7 @@ static int run_pcg(bdem_ctx *ctx) {
   ctx->h_counters[1] = 1;
   ctx->h_counters[5] = 1;
   launch_cg_init(ctx->d, mixed, st);
+  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, st);
   if (ctx->profiling) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling) prof_mark(ctx, 1, false);
@@ -858,6 +984,7 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     launch_bond_eval(d, mixed, true, hess, ctx->P.midpoint != 0, st);
     prof_mark(ctx, 0, false);
     launch_particle_eval(d, ctx->P, mixed, hess, false, st);
+    if (hess && ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
     launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, st);
     launch_count_active(d, NS, 0, st);
     int rc = read_counters(ctx);
@@ -1173,6 +1300,42 @@ extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, con
   return BDEM_OK;
 }
 
+extern "C" int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_eval,
+                                  const double *quat_eval, const double *in6, double *out6) {
+  if (!ctx || !in6 || !out6) return BDEM_E_INVALID;
+  const int n = ctx->S.n, NS = ctx->S.n_scenes, NP = ctx->S.n_pad;
+  // the projected reduced Hessian at the evaluation state (as bdem_energy_grad_hess)
+  int rc = bdem_energy_grad_hess(ctx, dt, BDEM_EGH_H | BDEM_EGH_PSD, pos_eval, quat_eval, nullptr,
+                                 nullptr, nullptr, nullptr);
+  if (rc < 0) return rc;
+  hipStream_t st = ctx->stream;
+  DevPtrs &d = ctx->d;
+  if (ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, st);
+  // r = in (internal order), every scene active, then u = M^-1 r
+  std::vector<double> r((size_t)NP * 6, 0.0), u((size_t)NP * 6);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 6; ++c) r[(size_t)ctx->p_int[i] * 6 + c] = in6[6 * (size_t)i + c];
+  HIP_TRY(hipMemcpyAsync(d.cr, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ctx->h_ctl, d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int sc = 0; sc < NS; ++sc) ctx->h_ctl[sc].cg_active = 1;
+  HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
+  if (ctx->amg) {
+    launch_amg_vcycle(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, st);
+  } else {
+    // block-Jacobi: the PCG initialisation computes u = D^-1 r from r = -z
+    HIP_TRY(hipMemcpyAsync(d.z, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_cg_init(d, ctx->S.mixed, st);
+  }
+  HIP_TRY(hipMemcpyAsync(u.data(), d.cs, u.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 6; ++c) out6[6 * (size_t)i + c] = u[(size_t)ctx->p_int[i] * 6 + c];
+  if (!ctx->amg)   // k_cg_init took r = -z
+    for (size_t k = 0; k < 6 * (size_t)n; ++k) out6[k] = -out6[k];
+  return BDEM_OK;
+}
+
 extern "C" int bdem_break_bonds(bdem_ctx *ctx, int64_t *n_broken, uint8_t *alive_out) {
   if (!ctx) return BDEM_E_INVALID;
   hipStream_t st = ctx->stream;
@@ -1295,6 +1458,7 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
   launch_step_target(d, ctx->P, st);
   launch_bond_eval(d, mixed, true, true, ctx->P.midpoint != 0, st);
   launch_particle_eval(d, ctx->P, mixed, true, false, st);
+  if (ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
   launch_newton_check(d, ctx->P, 1, st);
   launch_count_active(d, NS, 0, st);
   int rc = read_counters(ctx);

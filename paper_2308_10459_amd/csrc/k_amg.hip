@@ -1,0 +1,569 @@
+// Aggregation multigrid preconditioner: numeric setup at every Newton
+// iteration (rigid-body-mode prolongation, Galerkin coarse operators,
+// block-Jacobi inverses, dense inverse of the last level per scene) and the
+// V-cycle applied to the PCG residual.  The symbolic hierarchy and its
+// definitions are described in bdem_amg.hpp.  All sums run in a fixed order
+// (contribution and child lists are sorted at create), so results are
+// reproducible run to run.
+#include "bdem_amg.hpp"
+#include "bdem_math.hpp"
+
+namespace bdem {
+
+// ---------------------------------------------------------------------------
+// small dense helpers (FP64)
+// ---------------------------------------------------------------------------
+
+// y = P x for P = [[I, -[d]x], [0, S]]: (t - d x w, S w)
+__device__ __forceinline__ void p_apply(const double (&dd)[3], const double (&S)[9], const double (&x)[6],
+                                        double (&y)[6]) {
+  const double w[3] = {x[3], x[4], x[5]};
+  y[0] = x[0] - (dd[1] * w[2] - dd[2] * w[1]);
+  y[1] = x[1] - (dd[2] * w[0] - dd[0] * w[2]);
+  y[2] = x[2] - (dd[0] * w[1] - dd[1] * w[0]);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) y[3 + r] = S[r * 3] * w[0] + S[r * 3 + 1] * w[1] + S[r * 3 + 2] * w[2];
+}
+// y = P^T x: (x_p, d x x_p + S^T x_y)
+__device__ __forceinline__ void pt_apply(const double (&dd)[3], const double (&S)[9], const double (&x)[6],
+                                         double (&y)[6]) {
+  y[0] = x[0]; y[1] = x[1]; y[2] = x[2];
+  y[3] = (dd[1] * x[2] - dd[2] * x[1]) + S[0] * x[3] + S[3] * x[4] + S[6] * x[5];
+  y[4] = (dd[2] * x[0] - dd[0] * x[2]) + S[1] * x[3] + S[4] * x[4] + S[7] * x[5];
+  y[5] = (dd[0] * x[1] - dd[1] * x[0]) + S[2] * x[3] + S[5] * x[4] + S[8] * x[5];
+}
+
+__device__ __forceinline__ void ident3(double (&S)[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) S[k] = (k % 4 == 0) ? 1.0 : 0.0;
+}
+
+// 6x6 SPD inverse (full storage) by Cholesky; false if not positive definite
+__device__ __forceinline__ bool spd_inv36(const double (&A)[36], double (&X)[36]) {
+  double L[6][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    double dj = A[j * 6 + j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k];
+    if (!(dj > 0.0)) return false;
+    dj = sqrt(dj);
+    L[j][j] = dj;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      double v = A[i * 6 + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[i][k] * L[j][k];
+      L[i][j] = v / dj;
+    }
+  }
+  double Y[6][6];   // L^-1
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i < c) { Y[i][c] = 0.0; continue; }
+      double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k)
+        if (k >= c) v -= L[i][k] * Y[k][c];
+      Y[i][c] = v / L[i][i];
+    }
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v += Y[k][r] * Y[k][c];
+      X[r * 6 + c] = v;
+    }
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void mat36_apply(const T *M, const double (&x)[6], double (&y)[6]) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a += double(M[r * 6 + c]) * x[c];
+    y[r] = a;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void sym21_apply(const T *M, const double (&x)[6], double (&y)[6]) {
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a += double(M[up6(r, c)]) * x[c];
+    y[r] = a;
+  }
+}
+__device__ __forceinline__ void ld6(const double *p, double (&v)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = p[k];
+}
+__device__ __forceinline__ void st6(double *p, const double (&v)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p[k] = v[k];
+}
+
+// ---------------------------------------------------------------------------
+// numeric setup
+// ---------------------------------------------------------------------------
+
+// level 1: centroids of the aggregates (iterate positions of their free
+// particles), and each particle's (x_i - c_a, S_i = 1/2 R(q_i)^T)
+__global__ __launch_bounds__(256) void k_amg_geom1(DevPtrs d, AmgDev a) {
+  const AmgLevel &L = a.lv[1];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= L.n) return;
+  const int mb = L.mbeg[A], me = L.mbeg[A + 1];
+  const bool act = L.active[A] != 0;
+  double c[3] = {0.0, 0.0, 0.0};
+  int cnt = 0;
+  for (int k = mb; k < me; ++k) {
+    const int i = L.mlist[k];
+    if (act && d.flags[i] != 0) continue;
+    const double4 p = d.px[i];
+    c[0] += p.x; c[1] += p.y; c[2] += p.z;
+    ++cnt;
+  }
+  c[0] /= cnt; c[1] /= cnt; c[2] /= cnt;
+  L.cen[3 * A] = c[0]; L.cen[3 * A + 1] = c[1]; L.cen[3 * A + 2] = c[2];
+  for (int k = mb; k < me; ++k) {
+    const int i = L.mlist[k];
+    const double4 p = d.px[i], q = d.qx[i];
+    double *o = a.pd0 + (size_t)i * 12;
+    o[0] = p.x - c[0]; o[1] = p.y - c[1]; o[2] = p.z - c[2];
+    // R(q) for q = (x, y, z, w); S = 1/2 R^T
+    const double x = q.x, y = q.y, z = q.z, w = q.w;
+    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                         2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                         2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) o[3 + r * 3 + cc] = 0.5 * R[cc * 3 + r];
+  }
+}
+
+// level l >= 2: centroids of the active children's centroids, children's offsets
+__global__ __launch_bounds__(256) void k_amg_geom(AmgDev a, int l) {
+  const AmgLevel &L = a.lv[l], &F = a.lv[l - 1];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= L.n) return;
+  const int mb = L.mbeg[A], me = L.mbeg[A + 1];
+  const bool act = L.active[A] != 0;
+  double c[3] = {0.0, 0.0, 0.0};
+  int cnt = 0;
+  for (int k = mb; k < me; ++k) {
+    const int i = L.mlist[k];
+    if (act && !F.active[i]) continue;
+    c[0] += F.cen[3 * i]; c[1] += F.cen[3 * i + 1]; c[2] += F.cen[3 * i + 2];
+    ++cnt;
+  }
+  c[0] /= cnt; c[1] /= cnt; c[2] /= cnt;
+  L.cen[3 * A] = c[0]; L.cen[3 * A + 1] = c[1]; L.cen[3 * A + 2] = c[2];
+  for (int k = mb; k < me; ++k) {
+    const int i = L.mlist[k];
+    F.pd[3 * i] = F.cen[3 * i] - c[0];
+    F.pd[3 * i + 1] = F.cen[3 * i + 1] - c[1];
+    F.pd[3 * i + 2] = F.cen[3 * i + 2] - c[2];
+  }
+}
+
+// acc += P_r^T H P_c, column by column (H: 36 values, row-major)
+template <typename T>
+__device__ __forceinline__ void add_ptap(double (&acc)[36], const T *H, bool sym21, const double (&dr)[3],
+                                         const double (&Sr)[9], const double (&dc)[3], const double (&Sc)[9]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    double e[6] = {0, 0, 0, 0, 0, 0};
+    e[c] = 1.0;
+    double v[6], w[6], o[6];
+    p_apply(dc, Sc, e, v);
+    if (sym21) sym21_apply(H, v, w);
+    else mat36_apply(H, v, w);
+    pt_apply(dr, Sr, w, o);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) acc[r * 6 + c] += o[r];
+  }
+}
+
+// Galerkin block of every level-1 slot from the fine diagonal (packed) and
+// off-diagonal blocks of its contribution list
+template <typename T> __global__ __launch_bounds__(128) void k_amg_galerkin1(DevPtrs d, AmgDev a) {
+  const AmgLevel &L = a.lv[1];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= L.nslots) return;
+  double acc[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+  const T *hd = reinterpret_cast<const T *>(d.hdiag), *ho = reinterpret_cast<const T *>(d.hoff);
+  for (int k = L.gptr[s]; k < L.gptr[s + 1]; ++k) {
+    const int src = L.gsrc[k];
+    const bool diag = src < 0;
+    const int i = diag ? -1 - src : a.slot_row0[src];
+    const int j = diag ? i : d.col[src];
+    if (d.flags[i] != 0 || d.flags[j] != 0) continue;   // P is zero on non-unknowns
+    double dr[3], Sr[9], dc[3], Sc[9];
+    const double *pi = a.pd0 + (size_t)i * 12, *pj = a.pd0 + (size_t)j * 12;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) { dr[m] = pi[m]; dc[m] = pj[m]; }
+#pragma unroll
+    for (int m = 0; m < 9; ++m) { Sr[m] = pi[3 + m]; Sc[m] = pj[3 + m]; }
+    if (diag) add_ptap<T>(acc, hd + (size_t)i * 21, true, dr, Sr, dc, Sc);
+    else add_ptap<T>(acc, ho + (size_t)src * 36, false, dr, Sr, dc, Sc);
+  }
+  const int A = L.slot_row[s];
+  if (!L.active[A] && L.dslot[A] == s) {
+#pragma unroll
+    for (int k = 0; k < 36; ++k) acc[k] = (k % 7 == 0) ? 1.0 : 0.0;
+  }
+  T *o = reinterpret_cast<T *>(L.val) + (size_t)s * 36;
+#pragma unroll
+  for (int k = 0; k < 36; ++k) o[k] = T(acc[k]);
+}
+
+template <typename T> __global__ __launch_bounds__(128) void k_amg_galerkin(AmgDev a, int l) {
+  const AmgLevel &L = a.lv[l], &F = a.lv[l - 1];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= L.nslots) return;
+  double acc[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) acc[k] = 0.0;
+  double S[9];
+  ident3(S);
+  const T *fv = reinterpret_cast<const T *>(F.val);
+  for (int k = L.gptr[s]; k < L.gptr[s + 1]; ++k) {
+    const int src = L.gsrc[k];
+    const int i = F.slot_row[src], j = F.col[src];
+    if (!F.active[i] || !F.active[j]) continue;
+    const double dr[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
+    const double dc[3] = {F.pd[3 * j], F.pd[3 * j + 1], F.pd[3 * j + 2]};
+    add_ptap<T>(acc, fv + (size_t)src * 36, false, dr, S, dc, S);
+  }
+  const int A = L.slot_row[s];
+  if (!L.active[A] && L.dslot[A] == s) {
+#pragma unroll
+    for (int k = 0; k < 36; ++k) acc[k] = (k % 7 == 0) ? 1.0 : 0.0;
+  }
+  T *o = reinterpret_cast<T *>(L.val) + (size_t)s * 36;
+#pragma unroll
+  for (int k = 0; k < 36; ++k) o[k] = T(acc[k]);
+}
+
+// block-Jacobi inverse of every node of a coarse level
+template <typename T> __global__ __launch_bounds__(128) void k_amg_dinv(AmgDev a, int l) {
+  const AmgLevel &L = a.lv[l];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= L.n) return;
+  const T *B = reinterpret_cast<const T *>(L.val) + (size_t)L.dslot[A] * 36;
+  double M[36], X[36];
+#pragma unroll
+  for (int k = 0; k < 36; ++k) M[k] = double(B[k]);
+  // symmetrise: FP32 Galerkin sums are symmetric only to rounding
+#pragma unroll
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = r + 1; c < 6; ++c) { const double v = 0.5 * (M[r * 6 + c] + M[c * 6 + r]); M[r * 6 + c] = v; M[c * 6 + r] = v; }
+  if (!spd_inv36(M, X)) {
+#pragma unroll
+    for (int k = 0; k < 36; ++k) X[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) X[r * 7] = M[r * 7] > 0.0 ? 1.0 / M[r * 7] : 1.0;
+  }
+  T *o = reinterpret_cast<T *>(L.dinv) + (size_t)A * 36;
+#pragma unroll
+  for (int k = 0; k < 36; ++k) o[k] = T(X[k]);
+}
+
+// dense inverse of the last level of each scene (one workgroup per scene):
+// Gauss-Jordan without pivoting on the symmetric positive definite operator
+template <typename T> __global__ __launch_bounds__(1024) void k_amg_coarse_inverse(AmgDev a) {
+  __shared__ double fcol[6 * AMG_COARSE_MAX];
+  const int sc = blockIdx.x;
+  const AmgLevel &L = a.lv[a.L];
+  const int nb = a.cbeg[sc], ne = a.cbeg[sc + 1], m = ne - nb, N = 6 * m;
+  if (m == 0) return;
+  double *M = a.cmat + a.coff[sc], *X = a.cwork + a.coff[sc];
+  const T *v = reinterpret_cast<const T *>(L.val);
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) { M[e] = 0.0; X[e] = (e / N == e % N) ? 1.0 : 0.0; }
+  __syncthreads();
+  for (int A = nb; A < ne; ++A)
+    for (int s = L.row_ptr[A]; s < L.row_ptr[A + 1]; ++s) {
+      const int B = L.col[s];
+      for (int e = threadIdx.x; e < 36; e += blockDim.x)
+        M[(size_t)(6 * (A - nb) + e / 6) * N + 6 * (B - nb) + e % 6] = double(v[(size_t)s * 36 + e]);
+    }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    const double piv = M[(size_t)k * N + k];
+    __syncthreads();
+    for (int c = threadIdx.x; c < N; c += blockDim.x) { M[(size_t)k * N + c] /= piv; X[(size_t)k * N + c] /= piv; }
+    __syncthreads();
+    for (int r = threadIdx.x; r < N; r += blockDim.x) fcol[r] = M[(size_t)r * N + k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+      const int r = e / N, c = e % N;
+      if (r == k) continue;
+      const double f = fcol[r];
+      M[(size_t)r * N + c] -= f * M[(size_t)k * N + c];
+      X[(size_t)r * N + c] -= f * X[(size_t)k * N + c];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+
+// fine pre-smoothing from zero: t0 = omega D^-1 r
+template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_pre(DevPtrs d, AmgDev a) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
+  double x[6], y[6];
+  ld6(d.cr + (size_t)r * 6, x);
+  sym21_apply(reinterpret_cast<const T *>(d.dinv) + (size_t)r * 21, x, y);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] *= AMG_OMEGA;
+  st6(a.t0 + (size_t)r * 6, y);
+}
+
+// (H v)_r over the fine block-CSR
+template <typename T>
+__device__ __forceinline__ void fine_row_apply(const DevPtrs &d, int r, const double *v, double (&y)[6]) {
+  double x[6];
+  ld6(v + (size_t)r * 6, x);
+  sym21_apply(reinterpret_cast<const T *>(d.hdiag) + (size_t)r * 21, x, y);
+  const T *ho = reinterpret_cast<const T *>(d.hoff);
+  for (int s = d.row_ptr[r]; s < d.row_ptr[r + 1]; ++s) {
+    double xj[6], t[6];
+    ld6(v + (size_t)d.col[s] * 6, xj);
+    mat36_apply(ho + (size_t)s * 36, xj, t);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] += t[k];
+  }
+}
+
+// fine residual r0 = r - H t0
+template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_resid(DevPtrs d, AmgDev a) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
+  double y[6], b[6];
+  fine_row_apply<T>(d, r, a.t0, y);
+  ld6(d.cr + (size_t)r * 6, b);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
+  st6(a.r0 + (size_t)r * 6, y);
+}
+
+// b_1 = P^T r0 (level-1 node: sum over its particles)
+__global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a) {
+  const AmgLevel &L = a.lv[1];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= L.n) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = L.mbeg[A]; k < L.mbeg[A + 1]; ++k) {
+    const int i = L.mlist[k];
+    if (d.flags[i] != 0) continue;
+    const double *p = a.pd0 + (size_t)i * 12;
+    const double dd[3] = {p[0], p[1], p[2]};
+    double S[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
+    double x[6], y[6];
+    ld6(a.r0 + (size_t)i * 6, x);
+    pt_apply(dd, S, x, y);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc[m] += y[m];
+  }
+  st6(L.b + (size_t)A * 6, acc);
+}
+
+// coarse level l: t = omega D^-1 b, then r = b - A t
+template <typename T> __global__ __launch_bounds__(256) void k_amg_pre(AmgDev a, int l) {
+  const AmgLevel &L = a.lv[l];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= L.n) return;
+  double x[6], y[6];
+  ld6(L.b + (size_t)A * 6, x);
+  mat36_apply(reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36, x, y);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] *= AMG_OMEGA;
+  st6(L.t + (size_t)A * 6, y);
+}
+
+template <typename T>
+__device__ __forceinline__ void coarse_row_apply(const AmgLevel &L, int A, const double *v, double (&y)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] = 0.0;
+  const T *val = reinterpret_cast<const T *>(L.val);
+  for (int s = L.row_ptr[A]; s < L.row_ptr[A + 1]; ++s) {
+    double x[6], t[6];
+    ld6(v + (size_t)L.col[s] * 6, x);
+    mat36_apply(val + (size_t)s * 36, x, t);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] += t[k];
+  }
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_amg_resid(AmgDev a, int l) {
+  const AmgLevel &L = a.lv[l];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= L.n) return;
+  double y[6], b[6];
+  coarse_row_apply<T>(L, A, L.t, y);
+  ld6(L.b + (size_t)A * 6, b);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
+  st6(L.r + (size_t)A * 6, y);
+}
+
+// b_{l+1} = P^T r_l (S = I above the particles)
+__global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l) {
+  const AmgLevel &C = a.lv[l + 1], &F = a.lv[l];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= C.n) return;
+  double acc[6] = {0, 0, 0, 0, 0, 0}, S[9];
+  ident3(S);
+  for (int k = C.mbeg[A]; k < C.mbeg[A + 1]; ++k) {
+    const int i = C.mlist[k];
+    if (!F.active[i]) continue;
+    const double dd[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
+    double x[6], y[6];
+    ld6(F.r + (size_t)i * 6, x);
+    pt_apply(dd, S, x, y);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) acc[m] += y[m];
+  }
+  st6(C.b + (size_t)A * 6, acc);
+}
+
+// last level: e = A^-1 b per scene (dense)
+__global__ __launch_bounds__(256) void k_amg_coarse_solve(AmgDev a) {
+  const int sc = blockIdx.x;
+  const AmgLevel &L = a.lv[a.L];
+  const int nb = a.cbeg[sc], N = 6 * (a.cbeg[sc + 1] - nb);
+  const double *X = a.cwork + a.coff[sc];
+  for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < N; ++c) acc += X[(size_t)r * N + c] * L.b[(size_t)6 * nb + c];
+    L.e[(size_t)6 * nb + r] = acc;
+  }
+}
+
+// t_l += P e_{l+1}, then e_l = t_l + omega D^-1 (b_l - A t_l)
+__global__ __launch_bounds__(256) void k_amg_prolong(AmgDev a, int l) {
+  const AmgLevel &F = a.lv[l], &C = a.lv[l + 1];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= F.n || !F.active[i]) return;
+  double S[9], x[6], y[6];
+  ident3(S);
+  const double dd[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
+  ld6(C.e + (size_t)F.parent[i] * 6, x);
+  p_apply(dd, S, x, y);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) F.t[(size_t)i * 6 + k] += y[k];
+}
+
+template <typename T> __global__ __launch_bounds__(256) void k_amg_post(AmgDev a, int l) {
+  const AmgLevel &L = a.lv[l];
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= L.n) return;
+  double y[6], b[6], u[6], t[6];
+  coarse_row_apply<T>(L, A, L.t, y);
+  ld6(L.b + (size_t)A * 6, b);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
+  mat36_apply(reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36, y, u);
+  ld6(L.t + (size_t)A * 6, t);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) t[k] += AMG_OMEGA * u[k];
+  st6(L.e + (size_t)A * 6, t);
+}
+
+// fine: t0 += P e_1, then u = t0 + omega D^-1 (r - H t0) into the PCG's u
+template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_prolong(DevPtrs d, AmgDev a) {
+  const int i = blockIdx.x * TILE + threadIdx.x;
+  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
+  if (d.flags[i] != 0) return;
+  const double *p = a.pd0 + (size_t)i * 12;
+  const double dd[3] = {p[0], p[1], p[2]};
+  double S[9], x[6], y[6];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
+  ld6(a.lv[1].e + (size_t)a.parent0[i] * 6, x);
+  p_apply(dd, S, x, y);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) a.t0[(size_t)i * 6 + k] += y[k];
+}
+
+template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_post(DevPtrs d, AmgDev a) {
+  const int r = blockIdx.x * TILE + threadIdx.x;
+  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
+  double y[6], b[6], u[6], t[6];
+  fine_row_apply<T>(d, r, a.t0, y);
+  ld6(d.cr + (size_t)r * 6, b);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
+  sym21_apply(reinterpret_cast<const T *>(d.dinv) + (size_t)r * 21, y, u);
+  ld6(a.t0 + (size_t)r * 6, t);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) t[k] += AMG_OMEGA * u[k];
+  st6(d.cs + (size_t)r * 6, t);
+}
+
+// ---------------------------------------------------------------------------
+
+static inline int nblk(int n, int b) { return (n + b - 1) / b; }
+
+template <typename T>
+static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, hipStream_t s) {
+  k_amg_geom1<<<nblk(hl[1].n, 256), 256, 0, s>>>(d, a);
+  for (int l = 2; l <= a.L; ++l) k_amg_geom<<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
+  k_amg_galerkin1<T><<<nblk(hl[1].nslots, 128), 128, 0, s>>>(d, a);
+  k_amg_dinv<T><<<nblk(hl[1].n, 128), 128, 0, s>>>(a, 1);
+  for (int l = 2; l <= a.L; ++l) {
+    k_amg_galerkin<T><<<nblk(hl[l].nslots, 128), 128, 0, s>>>(a, l);
+    k_amg_dinv<T><<<nblk(hl[l].n, 128), 128, 0, s>>>(a, l);
+  }
+  k_amg_coarse_inverse<T><<<n_scenes, 1024, 0, s>>>(a);
+}
+
+template <typename T>
+static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, hipStream_t s) {
+  const int np = d.n_pad / TILE;
+  k_amg_fine_pre<T><<<np, TILE, 0, s>>>(d, a);
+  k_amg_fine_resid<T><<<np, TILE, 0, s>>>(d, a);
+  k_amg_restrict1<<<nblk(hl[1].n, 256), 256, 0, s>>>(d, a);
+  for (int l = 1; l < a.L; ++l) {
+    k_amg_pre<T><<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
+    k_amg_resid<T><<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
+    k_amg_restrict<<<nblk(hl[l + 1].n, 256), 256, 0, s>>>(a, l);
+  }
+  k_amg_coarse_solve<<<n_scenes, 256, 0, s>>>(a);
+  for (int l = a.L - 1; l >= 1; --l) {
+    k_amg_prolong<<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
+    k_amg_post<T><<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
+  }
+  k_amg_fine_prolong<T><<<np, TILE, 0, s>>>(d, a);
+  k_amg_fine_post<T><<<np, TILE, 0, s>>>(d, a);
+}
+
+void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
+                      hipStream_t s) {
+  if (mixed) setup_t<float>(d, a, hl, n_scenes, s);
+  else setup_t<double>(d, a, hl, n_scenes, s);
+}
+void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
+                       hipStream_t s) {
+  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, s);
+  else vcycle_t<double>(d, a, hl, n_scenes, s);
+}
+
+}  // namespace bdem

@@ -54,6 +54,7 @@ def test_default_options(B):
     assert o.precision == B.BDEM_PREC_FP64 and o.break_each_step == 1
     assert o.solver == B.BDEM_SOLVER_NEWTON
     assert o.integrator == B.BDEM_INTEGRATOR_EULER
+    assert o.preconditioner == B.BDEM_PRECOND_BLOCK_JACOBI
 
 
 def test_workspace_bytes_scales_with_problem(B):
@@ -112,3 +113,4 @@ def test_create_rejects_friction_and_bad_limits(B):
     assert _create_error(B, sc, precision=5) == -1
     assert _create_error(B, sc, solver=2) == -1
     assert _create_error(B, sc, integrator=2) == -1
+    assert _create_error(B, sc, preconditioner=2) == -1
