@@ -145,7 +145,7 @@ typedef struct {
   int32_t preconditioner;  /* PCG preconditioner: BDEM_PRECOND_BLOCK_JACOBI (default, the 6x6
                               diagonal blocks) or BDEM_PRECOND_AMG (Section 5.3 solves with AMG):
                               aggregates = cells of side 4 r_max from each scene's initial box
-                              corner, doubled per level until a scene has at most 32; rigid-body
+                              corner, doubled per level until a scene has at most 12; rigid-body
                               modes of each aggregate as prolongation; Galerkin coarse operators
                               rebuilt at every Newton iteration; omega = 0.8 block-Jacobi pre- and
                               post-smoothing; a dense exact solve on the last level.  Built from

@@ -114,7 +114,7 @@ void orc_friction(orc_sys *s, double dt);
  * from.  Aggregates: cells of side 4 r_max from the initial box corner
  * (doubled per level); rigid-body-mode prolongation; Galerkin coarse
  * operators; omega = 0.8 block-Jacobi pre- and post-smoothing; exact solve
- * on the first level with <= 32 nodes.  Returns the number of coarse levels,
+ * on the first level with <= 12 nodes.  Returns the number of coarse levels,
  * -1 if the coarsest operator is singular. */
 int orc_amg_apply(const orc_sys *s, const double *pos, const double *quat, const double *hdiag,
                   const double *hoff, const double *b, double *x);

@@ -13,7 +13,7 @@
 //   A_{l+1} = P^T A_l P (Galerkin), identity on nodes without unknowns;
 //   smoothing: omega = 0.8 block Jacobi before and after the coarse
 //   correction; an exact dense solve per scene on the last level (at most
-//   AMG_COARSE_MAX nodes per scene).
+//   AMG_COARSE_MAX nodes per scene, in LDS).
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -22,7 +22,7 @@
 
 namespace bdem {
 
-constexpr int AMG_COARSE_MAX = 32;
+constexpr int AMG_COARSE_MAX = 12;
 constexpr double AMG_OMEGA = 0.8;
 
 // device view of one coarse level (level >= 1)
@@ -84,6 +84,6 @@ void amg_build(int n_pad, int n_scenes, const std::vector<double> &pos4,
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
                       hipStream_t s);
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       hipStream_t s);
+                       int spmv_variant, hipStream_t s);
 
 }  // namespace bdem

@@ -299,7 +299,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   amg_build(NP, NS, pos4, flags, psid, ctx->scene_pbeg, rp, col, lo3, h0, H);
   for (int sc = 0; sc < NS; ++sc)
     if (H.cbeg[sc + 1] - H.cbeg[sc] > AMG_COARSE_MAX) {
-      ctx->err = "multigrid: a scene does not coarsen to 32 aggregates within 15 levels";
+      ctx->err = "multigrid: a scene does not coarsen to 12 aggregates within 15 levels";
       return BDEM_E_INVALID;
     }
   for (int l = 1; l <= H.L; ++l)
@@ -823,7 +823,7 @@ static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   const bool mixed = ctx->S.mixed;
   launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream);
   // multigrid: u = V(r) replaces the block-Jacobi u the update wrote
-  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->stream);
+  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, false);
@@ -864,7 +864,7 @@ static int run_pcg(bdem_ctx *ctx) {
   ctx->h_counters[1] = 1;
   ctx->h_counters[5] = 1;
   launch_cg_init(ctx->d, mixed, st);
-  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, st);
+  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, st);
   if (ctx->profiling) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling) prof_mark(ctx, 1, false);
@@ -1321,7 +1321,7 @@ extern "C" int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_ev
   for (int sc = 0; sc < NS; ++sc) ctx->h_ctl[sc].cg_active = 1;
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   if (ctx->amg) {
-    launch_amg_vcycle(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, st);
+    launch_amg_vcycle(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, ctx->spmv_variant, st);
   } else {
     // block-Jacobi: the PCG initialisation computes u = D^-1 r from r = -z
     HIP_TRY(hipMemcpyAsync(d.z, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, st));

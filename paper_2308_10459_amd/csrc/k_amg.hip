@@ -175,18 +175,37 @@ __global__ __launch_bounds__(256) void k_amg_geom(AmgDev a, int l) {
   }
 }
 
-// acc += P_r^T H P_c, column by column (H: 36 values, row-major)
+// acc += P_r^T H P_c, column by column (H: 36 values, row-major, or the
+// packed upper triangle of a symmetric block), the block read once
 template <typename T>
 __device__ __forceinline__ void add_ptap(double (&acc)[36], const T *H, bool sym21, const double (&dr)[3],
                                          const double (&Sr)[9], const double (&dc)[3], const double (&Sc)[9]) {
+  double Hm[36];
+  if (sym21) {
+    T h[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) h[k] = H[k];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Hm[r * 6 + c] = double(h[up6(r, c)]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 36; ++k) Hm[k] = double(H[k]);
+  }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     double e[6] = {0, 0, 0, 0, 0, 0};
     e[c] = 1.0;
     double v[6], w[6], o[6];
     p_apply(dc, Sc, e, v);
-    if (sym21) sym21_apply(H, v, w);
-    else mat36_apply(H, v, w);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) t += Hm[r * 6 + k] * v[k];
+      w[r] = t;
+    }
     pt_apply(dr, Sr, w, o);
 #pragma unroll
     for (int r = 0; r < 6; ++r) acc[r * 6 + c] += o[r];
@@ -282,14 +301,15 @@ template <typename T> __global__ __launch_bounds__(128) void k_amg_dinv(AmgDev a
 }
 
 // dense inverse of the last level of each scene (one workgroup per scene):
-// Gauss-Jordan without pivoting on the symmetric positive definite operator
-template <typename T> __global__ __launch_bounds__(1024) void k_amg_coarse_inverse(AmgDev a) {
-  __shared__ double fcol[6 * AMG_COARSE_MAX];
+// Gauss-Jordan without pivoting on the symmetric positive definite operator,
+// in LDS (at most 6 * AMG_COARSE_MAX rows); the inverse goes to cwork
+template <typename T> __global__ __launch_bounds__(256) void k_amg_coarse_inverse(AmgDev a) {
+  constexpr int NMAX = 6 * AMG_COARSE_MAX;
+  __shared__ double M[NMAX * NMAX], X[NMAX * NMAX], fcol[NMAX];
   const int sc = blockIdx.x;
   const AmgLevel &L = a.lv[a.L];
   const int nb = a.cbeg[sc], ne = a.cbeg[sc + 1], m = ne - nb, N = 6 * m;
   if (m == 0) return;
-  double *M = a.cmat + a.coff[sc], *X = a.cwork + a.coff[sc];
   const T *v = reinterpret_cast<const T *>(L.val);
   for (int e = threadIdx.x; e < N * N; e += blockDim.x) { M[e] = 0.0; X[e] = (e / N == e % N) ? 1.0 : 0.0; }
   __syncthreads();
@@ -297,25 +317,27 @@ template <typename T> __global__ __launch_bounds__(1024) void k_amg_coarse_inver
     for (int s = L.row_ptr[A]; s < L.row_ptr[A + 1]; ++s) {
       const int B = L.col[s];
       for (int e = threadIdx.x; e < 36; e += blockDim.x)
-        M[(size_t)(6 * (A - nb) + e / 6) * N + 6 * (B - nb) + e % 6] = double(v[(size_t)s * 36 + e]);
+        M[(6 * (A - nb) + e / 6) * N + 6 * (B - nb) + e % 6] = double(v[(size_t)s * 36 + e]);
     }
   __syncthreads();
   for (int k = 0; k < N; ++k) {
-    const double piv = M[(size_t)k * N + k];
+    const double piv = M[k * N + k];
     __syncthreads();
-    for (int c = threadIdx.x; c < N; c += blockDim.x) { M[(size_t)k * N + c] /= piv; X[(size_t)k * N + c] /= piv; }
+    for (int c = threadIdx.x; c < N; c += blockDim.x) { M[k * N + c] /= piv; X[k * N + c] /= piv; }
     __syncthreads();
-    for (int r = threadIdx.x; r < N; r += blockDim.x) fcol[r] = M[(size_t)r * N + k];
+    for (int r = threadIdx.x; r < N; r += blockDim.x) fcol[r] = M[r * N + k];
     __syncthreads();
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-      const int r = e / N, c = e % N;
+      const int r = e / N, c = e - (e / N) * N;
       if (r == k) continue;
       const double f = fcol[r];
-      M[(size_t)r * N + c] -= f * M[(size_t)k * N + c];
-      X[(size_t)r * N + c] -= f * X[(size_t)k * N + c];
+      M[r * N + c] -= f * M[k * N + c];
+      X[r * N + c] -= f * X[k * N + c];
     }
     __syncthreads();
   }
+  double *out = a.cwork + a.coff[sc];
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) out[e] = X[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -334,35 +356,7 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_pre(Dev
   st6(a.t0 + (size_t)r * 6, y);
 }
 
-// (H v)_r over the fine block-CSR
-template <typename T>
-__device__ __forceinline__ void fine_row_apply(const DevPtrs &d, int r, const double *v, double (&y)[6]) {
-  double x[6];
-  ld6(v + (size_t)r * 6, x);
-  sym21_apply(reinterpret_cast<const T *>(d.hdiag) + (size_t)r * 21, x, y);
-  const T *ho = reinterpret_cast<const T *>(d.hoff);
-  for (int s = d.row_ptr[r]; s < d.row_ptr[r + 1]; ++s) {
-    double xj[6], t[6];
-    ld6(v + (size_t)d.col[s] * 6, xj);
-    mat36_apply(ho + (size_t)s * 36, xj, t);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) y[k] += t[k];
-  }
-}
-
-// fine residual r0 = r - H t0
-template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_resid(DevPtrs d, AmgDev a) {
-  const int r = blockIdx.x * TILE + threadIdx.x;
-  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
-  double y[6], b[6];
-  fine_row_apply<T>(d, r, a.t0, y);
-  ld6(d.cr + (size_t)r * 6, b);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
-  st6(a.r0 + (size_t)r * 6, y);
-}
-
-// b_1 = P^T r0 (level-1 node: sum over its particles)
+// b_1 = P^T (r - H t0) (level-1 node: sum over its particles); r0 holds H t0
 __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a) {
   const AmgLevel &L = a.lv[1];
   const int A = blockIdx.x * blockDim.x + threadIdx.x;
@@ -376,8 +370,11 @@ __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a) {
     double S[9];
 #pragma unroll
     for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
-    double x[6], y[6];
-    ld6(a.r0 + (size_t)i * 6, x);
+    double x[6], h[6], y[6];
+    ld6(d.cr + (size_t)i * 6, x);
+    ld6(a.r0 + (size_t)i * 6, h);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) x[m] -= h[m];
     pt_apply(dd, S, x, y);
 #pragma unroll
     for (int m = 0; m < 6; ++m) acc[m] += y[m];
@@ -398,30 +395,36 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_pre(AmgDev a,
   st6(L.t + (size_t)A * 6, y);
 }
 
+// component (lane mod 6) of A_row x by one wavefront: lane (g, c) with
+// g = lane / 6 < 10 takes the row's slots g, g + 10, ... for output
+// component c; the ten partials of a component are then added in lane order
 template <typename T>
-__device__ __forceinline__ void coarse_row_apply(const AmgLevel &L, int A, const double *v, double (&y)[6]) {
-#pragma unroll
-  for (int k = 0; k < 6; ++k) y[k] = 0.0;
+__device__ __forceinline__ double wave_row_apply(const AmgLevel &L, int A, const double *x, int lane) {
   const T *val = reinterpret_cast<const T *>(L.val);
-  for (int s = L.row_ptr[A]; s < L.row_ptr[A + 1]; ++s) {
-    double x[6], t[6];
-    ld6(v + (size_t)L.col[s] * 6, x);
-    mat36_apply(val + (size_t)s * 36, x, t);
+  const int s0 = L.row_ptr[A], s1 = L.row_ptr[A + 1];
+  const int g = lane / 6, c = lane - g * 6;
+  double part = 0.0;
+  if (lane < 60)
+    for (int sl = s0 + g; sl < s1; sl += 10) {
+      const T *blk = val + (size_t)sl * 36 + c * 6;
+      const double *xj = x + (size_t)L.col[sl] * 6;
+      double acc = 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) y[k] += t[k];
-  }
+      for (int e = 0; e < 6; ++e) acc += double(blk[e]) * xj[e];
+      part += acc;
+    }
+  double y = 0.0;
+  for (int k = 0; k < 10; ++k) y += __shfl(part, k * 6 + (lane % 6), 64);
+  return y;
 }
 
+// r = b - A t, one wavefront per row
 template <typename T> __global__ __launch_bounds__(256) void k_amg_resid(AmgDev a, int l) {
   const AmgLevel &L = a.lv[l];
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= L.n) return;
-  double y[6], b[6];
-  coarse_row_apply<T>(L, A, L.t, y);
-  ld6(L.b + (size_t)A * 6, b);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
-  st6(L.r + (size_t)A * 6, y);
+  const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (A >= L.n) return;   // uniform over the wavefront
+  const double y = wave_row_apply<T>(L, A, L.t, lane);
+  if (lane < 6) L.r[(size_t)A * 6 + lane] = L.b[(size_t)A * 6 + lane] - y;
 }
 
 // b_{l+1} = P^T r_l (S = I above the particles)
@@ -471,20 +474,23 @@ __global__ __launch_bounds__(256) void k_amg_prolong(AmgDev a, int l) {
   for (int k = 0; k < 6; ++k) F.t[(size_t)i * 6 + k] += y[k];
 }
 
+// e = t + omega D^-1 (b - A t), one wavefront per row
 template <typename T> __global__ __launch_bounds__(256) void k_amg_post(AmgDev a, int l) {
   const AmgLevel &L = a.lv[l];
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= L.n) return;
-  double y[6], b[6], u[6], t[6];
-  coarse_row_apply<T>(L, A, L.t, y);
-  ld6(L.b + (size_t)A * 6, b);
+  const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (A >= L.n) return;   // uniform over the wavefront
+  const double y = wave_row_apply<T>(L, A, L.t, lane);
+  const double rb = (lane < 6) ? L.b[(size_t)A * 6 + lane] - y : 0.0;
+  double rv[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
-  mat36_apply(reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36, y, u);
-  ld6(L.t + (size_t)A * 6, t);
+  for (int k = 0; k < 6; ++k) rv[k] = __shfl(rb, k, 64);
+  if (lane < 6) {
+    const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + lane * 6;
+    double u = 0.0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) t[k] += AMG_OMEGA * u[k];
-  st6(L.e + (size_t)A * 6, t);
+    for (int k = 0; k < 6; ++k) u += double(Di[k]) * rv[k];
+    L.e[(size_t)A * 6 + lane] = L.t[(size_t)A * 6 + lane] + AMG_OMEGA * u;
+  }
 }
 
 // fine: t0 += P e_1, then u = t0 + omega D^-1 (r - H t0) into the PCG's u
@@ -503,11 +509,12 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_prolong
   for (int k = 0; k < 6; ++k) a.t0[(size_t)i * 6 + k] += y[k];
 }
 
-template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_post(DevPtrs d, AmgDev a) {
+// u = t0 + omega D^-1 (r - H t0) into the PCG's u; r0 holds H t0
+template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_final(DevPtrs d, AmgDev a) {
   const int r = blockIdx.x * TILE + threadIdx.x;
   if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
   double y[6], b[6], u[6], t[6];
-  fine_row_apply<T>(d, r, a.t0, y);
+  ld6(a.r0 + (size_t)r * 6, y);
   ld6(d.cr + (size_t)r * 6, b);
 #pragma unroll
   for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
@@ -532,27 +539,34 @@ static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n
     k_amg_galerkin<T><<<nblk(hl[l].nslots, 128), 128, 0, s>>>(a, l);
     k_amg_dinv<T><<<nblk(hl[l].n, 128), 128, 0, s>>>(a, l);
   }
-  k_amg_coarse_inverse<T><<<n_scenes, 1024, 0, s>>>(a);
+  k_amg_coarse_inverse<T><<<n_scenes, 256, 0, s>>>(a);
 }
 
 template <typename T>
-static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, hipStream_t s) {
+static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
+                     int spmv_variant, hipStream_t s) {
   const int np = d.n_pad / TILE;
+  // the fine products H t0 run through the PCG's own SpMV kernel (its dot
+  // partials are overwritten by the PCG's next SpMV)
+  DevPtrs dt = d;
+  dt.cs = a.t0;
+  dt.cAp = a.r0;
   k_amg_fine_pre<T><<<np, TILE, 0, s>>>(d, a);
-  k_amg_fine_resid<T><<<np, TILE, 0, s>>>(d, a);
+  launch_spmv(dt, mixed, spmv_variant, s);
   k_amg_restrict1<<<nblk(hl[1].n, 256), 256, 0, s>>>(d, a);
   for (int l = 1; l < a.L; ++l) {
     k_amg_pre<T><<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
-    k_amg_resid<T><<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
+    k_amg_resid<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
     k_amg_restrict<<<nblk(hl[l + 1].n, 256), 256, 0, s>>>(a, l);
   }
   k_amg_coarse_solve<<<n_scenes, 256, 0, s>>>(a);
   for (int l = a.L - 1; l >= 1; --l) {
     k_amg_prolong<<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
-    k_amg_post<T><<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
+    k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
   }
   k_amg_fine_prolong<T><<<np, TILE, 0, s>>>(d, a);
-  k_amg_fine_post<T><<<np, TILE, 0, s>>>(d, a);
+  launch_spmv(dt, mixed, spmv_variant, s);
+  k_amg_fine_final<T><<<np, TILE, 0, s>>>(d, a);
 }
 
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
@@ -561,9 +575,9 @@ void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int
   else setup_t<double>(d, a, hl, n_scenes, s);
 }
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       hipStream_t s) {
-  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, s);
-  else vcycle_t<double>(d, a, hl, n_scenes, s);
+                       int spmv_variant, hipStream_t s) {
+  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, true, spmv_variant, s);
+  else vcycle_t<double>(d, a, hl, n_scenes, false, spmv_variant, s);
 }
 
 }  // namespace bdem
