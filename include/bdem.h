@@ -165,8 +165,8 @@ typedef struct {
 /* Launch shapes of the PCG kernels (none changes a result: every shape
  * computes the same bits). */
 typedef struct {
-  int32_t spmv_threads;    /* SpMV workgroup size; 32 block rows per workgroup (192, 256, 384) */
-  int32_t spmv_trips;      /* slot products in flight per SpMV thread (1, 2, 4) */
+  int32_t spmv_threads;    /* SpMV workgroup size; 32 block rows per workgroup (192, 256, 384, 512) */
+  int32_t spmv_trips;      /* slot products per SpMV thread and pass; a pass stages threads * trips / 6 slots (1, 2, 4) */
   int32_t update_rows;     /* block rows per CG-update workgroup (32, 64, 128) */
   int32_t cg_chunk;        /* PCG iterations issued per host poll */
   int32_t use_graph;       /* 1: those iterations replay a captured HIP graph */

@@ -63,6 +63,7 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.psid), np * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.row_ptr), (np + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.col), ns * sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.sblk), ns * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.bij), std::max<size_t>(nbp, 1) * sizeof(int2));
   for (double4 **p : {&d.brest_a, &d.brest_b, &d.brest_c})
     L.add(reinterpret_cast<void **>(p), std::max<size_t>(nbp, 1) * sizeof(double4));
@@ -71,7 +72,8 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.bslot), std::max<size_t>(nbp, 1) * sizeof(int2));
   L.add(reinterpret_cast<void **>(&d.bsid), std::max<size_t>(nbp, 1) * sizeof(int));
   L.add(&d.hdiag, np * 21 * T);
-  L.add(&d.hoff, ns * 36 * T);
+  // one block per bond; k_bond_force also parks 8 doubles per slot here
+  L.add(&d.hoff, std::max(std::max<size_t>(nbp, 1) * 36 * T, ns * 8 * sizeof(double)));
   L.add(&d.hhalf, ns * 21 * T);
   L.add(&d.h9, std::max<size_t>(nbp, 1) * 45 * T);
   L.add(reinterpret_cast<void **>(&d.ghalf), ns * 6 * sizeof(double));
@@ -86,8 +88,7 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.scene_pbeg), (S.n_scenes + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.scene_bbeg), (S.n_scenes + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.degenerate), sizeof(int));
-  const size_t npc = S.contact ? np : 1, nsc = S.contact ? ns : 1;
-  L.add(reinterpret_cast<void **>(&d.slot_bond), nsc * sizeof(int));
+  const size_t npc = S.contact ? np : 1;
   for (int **p : {&d.cand, &d.cact}) L.add(reinterpret_cast<void **>(p), npc * CMAXC * sizeof(int));
   for (int **p : {&d.ncand, &d.nact, &d.gitem}) L.add(reinterpret_cast<void **>(p), npc * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.gcnt), std::max(S.n_bucket, 1) * sizeof(int));
@@ -608,7 +609,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
       const int slot = rp[r] + (int)k;
       const int bi = adj[r][k].second >> 1, end = adj[r][k].second & 1;
       h_col[slot] = adj[r][k].first;
-      h_sb[slot] = bi;
+      h_sb[slot] = 2 * bi + end;
       if (end == 0) ctx->bslot_h[bi].x = slot;
       else ctx->bslot_h[bi].y = slot;
     }
@@ -686,6 +687,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(up(d.psid, h_psid.data(), NP * sizeof(int)));
   chk(up(d.row_ptr, rp.data(), (NP + 1) * sizeof(int)));
   chk(up(d.col, h_col.data(), h_col.size() * sizeof(int)));
+  chk(up(d.sblk, h_sb.data(), h_sb.size() * sizeof(int)));
   chk(up(d.bij, h_bij.data(), h_bij.size() * sizeof(int2)));
   chk(up(d.brest_a, h_ra.data(), h_ra.size() * sizeof(double4)));
   chk(up(d.brest_b, h_rb.data(), h_rb.size() * sizeof(double4)));
@@ -698,7 +700,6 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(up(d.scene_pbeg, ctx->scene_pbeg.data(), (NS + 1) * sizeof(int)));
   chk(up(d.scene_bbeg, ctx->scene_bbeg.data(), (NS + 1) * sizeof(int)));
   if (S.contact) {
-    chk(up(d.slot_bond, h_sb.data(), h_sb.size() * sizeof(int)));
     chk(hipMemsetAsync(d.ncand, 0, NP * sizeof(int), st));
     chk(hipMemsetAsync(d.nact, 0, NP * sizeof(int), st));
   }
@@ -711,7 +712,7 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(hipMemcpyAsync(d.qt, d.qn, NP * sizeof(double4), hipMemcpyDeviceToDevice, st));
   for (double *v : {d.z, d.cx, d.cr, d.cs, d.cp, d.cAp, d.cq}) chk(hipMemsetAsync(v, 0, (size_t)NP * 6 * sizeof(double), st));
   const size_t T = S.mixed ? 4 : 8;
-  chk(hipMemsetAsync(d.hoff, 0, (size_t)std::max(S.n_slots, 1) * 36 * T, st));
+  chk(hipMemsetAsync(d.hoff, 0, (size_t)std::max(NB, 1) * 36 * T, st));
   chk(hipMemsetAsync(d.hhalf, 0, (size_t)std::max(S.n_slots, 1) * 21 * T, st));
   chk(hipMemsetAsync(d.ghalf, 0, (size_t)std::max(S.n_slots, 1) * 6 * sizeof(double), st));
   chk(hipMemsetAsync(d.hdiag, 0, (size_t)NP * 21 * T, st));
@@ -1220,8 +1221,7 @@ static void expand_blocks(const std::vector<T> &hd, const std::vector<T> &ho, bd
     }
   if (hoff36)
     for (int64_t k = 0; k < ctx->S.nb; ++k) {
-      const int slot = ctx->bslot_h[ctx->b_int[k]].x;
-      const T *src = ho.data() + (size_t)slot * 36;
+      const T *src = ho.data() + (size_t)ctx->b_int[k] * 36;
       for (int e = 0; e < 36; ++e) hoff36[36 * (size_t)k + e] = double(src[e]);
     }
 }
@@ -1271,15 +1271,15 @@ extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, con
     HIP_TRY(hipMemcpyAsync(z.data(), d.z, z.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   }
   if (hess && (hdiag36 || hoff36)) {
-    const size_t ns = std::max(ctx->S.n_slots, 1);
+    const size_t nbs = std::max(ctx->S.nb_pad, 1);
     if (mixed) {
-      std::vector<float> hd((size_t)NP * 21), ho(ns * 36);
+      std::vector<float> hd((size_t)NP * 21), ho(nbs * 36);
       HIP_TRY(hipMemcpyAsync(hd.data(), d.hdiag, hd.size() * 4, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(ho.data(), d.hoff, ho.size() * 4, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
       expand_blocks(hd, ho, ctx, hdiag36, hoff36);
     } else {
-      std::vector<double> hd((size_t)NP * 21), ho(ns * 36);
+      std::vector<double> hd((size_t)NP * 21), ho(nbs * 36);
       HIP_TRY(hipMemcpyAsync(hd.data(), d.hdiag, hd.size() * 8, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(ho.data(), d.hoff, ho.size() * 8, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));

@@ -10,8 +10,10 @@
 //               GJ/l0, EI/l0);  double4 (S, r0/I, r0/J, tension_only);
 //               double2 (sigma_c, tau_c); uint8 alive; int2 slot of the bond in rows i and j.
 //   Hessian   : diagonal blocks, 21 packed values per particle (T);
-//               off-diagonal blocks in full block-CSR, 36 values per slot (T),
-//               two slots per bond; per-slot halves of the diagonal block
+//               off-diagonal blocks stored once per bond, 36 values (T), the
+//               block (i, j) of the bond's own (i, j) order; the block-CSR
+//               pattern has two slots per bond, each naming the bond's block
+//               and whether its row reads it transposed; per-slot halves of the diagonal block
 //               (21 T) and of the reduced gradient (6 double) written by the
 //               bond kernel and summed in a fixed order by the particle kernel.
 //   solver    : 6 doubles per particle for z, CG x, r, s (= M^-1 r), p, Ap;
@@ -24,7 +26,7 @@ namespace bdem {
 
 constexpr int TILE = 256;       // particles / bonds per scene-aligned tile
 constexpr int SPMV_ROWS = 32;     // block rows per SpMV workgroup
-constexpr int SPMV_CAP = 512;     // slots staged in LDS per pass of an SpMV workgroup
+constexpr int SPMV_CAP = 384;     // slot products held in LDS per pass of an SpMV workgroup
 constexpr int CMAXC = 32;         // element-repulsion candidates per particle
 
 // per-scene control block, device resident; every decision of the Newton /
@@ -74,6 +76,8 @@ struct DevPtrs {
   int *psid;                         // scene id per particle
   int *row_ptr;                      // n_pad + 1, off-diagonal slots per row
   int *col;                          // n_slots: neighbour row of each off-diagonal slot
+  int *sblk;                         // n_slots: 2 * bond + (1 when the row is the bond's j end:
+                                     // its block is the transpose of the stored one)
   // bonds
   int2 *bij;
   double4 *brest_a, *brest_b, *brest_c;
@@ -83,7 +87,7 @@ struct DevPtrs {
   int *bsid;
   // Hessian / gradient (T = float or double, typed at the launch)
   void *hdiag;   // n_pad * 21
-  void *hoff;    // n_slots * 36: the block of every slot (both triangles)
+  void *hoff;    // nb_pad * 36: the (i, j) block of every bond (at least 64 bytes per slot)
   void *hhalf;   // n_slots * 21
   void *h9;      // nb_pad * 45: per-bond packed reduced 9x9 before projection
   double *ghalf; // n_slots * 6
@@ -102,7 +106,6 @@ struct DevPtrs {
                                       // [0] newton active, [1] cg active, [2] ls active, [3] degenerate bonds
   int *degenerate;                    // bonds with |q_i + q_j| below the threshold
   // element repulsion (Section 5.4); allocated only when enabled
-  int *slot_bond;                     // n_slots: bond of each off-diagonal slot
   int *cand, *ncand;                  // CMAXC candidates per particle (sorted), their count
   int *cact, *nact;                   // overlapping candidates at the last evaluation
   int *gcnt, *gbeg, *gitem;           // broad-phase hash grid: counts, starts, items

@@ -175,13 +175,15 @@ __global__ __launch_bounds__(256) void k_amg_geom(AmgDev a, int l) {
   }
 }
 
-// acc += P_r^T H P_c, column by column (H: 36 values, row-major, or the
-// packed upper triangle of a symmetric block), the block read once
+// acc += P_r^T H P_c, column by column (H: 36 values, row-major, the
+// transpose of such a block, or the packed upper triangle of a symmetric
+// block), the block read once
+enum BlockForm { BLK_FULL = 0, BLK_TRANSPOSED = 1, BLK_SYM21 = 2 };
 template <typename T>
-__device__ __forceinline__ void add_ptap(double (&acc)[36], const T *H, bool sym21, const double (&dr)[3],
+__device__ __forceinline__ void add_ptap(double (&acc)[36], const T *H, int form, const double (&dr)[3],
                                          const double (&Sr)[9], const double (&dc)[3], const double (&Sc)[9]) {
   double Hm[36];
-  if (sym21) {
+  if (form == BLK_SYM21) {
     T h[21];
 #pragma unroll
     for (int k = 0; k < 21; ++k) h[k] = H[k];
@@ -190,8 +192,11 @@ __device__ __forceinline__ void add_ptap(double (&acc)[36], const T *H, bool sym
 #pragma unroll
       for (int c = 0; c < 6; ++c) Hm[r * 6 + c] = double(h[up6(r, c)]);
   } else {
+    const bool tr = form == BLK_TRANSPOSED;
 #pragma unroll
-    for (int k = 0; k < 36; ++k) Hm[k] = double(H[k]);
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Hm[r * 6 + c] = double(H[tr ? c * 6 + r : r * 6 + c]);
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -234,8 +239,12 @@ template <typename T> __global__ __launch_bounds__(128) void k_amg_galerkin1(Dev
     for (int m = 0; m < 3; ++m) { dr[m] = pi[m]; dc[m] = pj[m]; }
 #pragma unroll
     for (int m = 0; m < 9; ++m) { Sr[m] = pi[3 + m]; Sc[m] = pj[3 + m]; }
-    if (diag) add_ptap<T>(acc, hd + (size_t)i * 21, true, dr, Sr, dc, Sc);
-    else add_ptap<T>(acc, ho + (size_t)src * 36, false, dr, Sr, dc, Sc);
+    if (diag) {
+      add_ptap<T>(acc, hd + (size_t)i * 21, BLK_SYM21, dr, Sr, dc, Sc);
+    } else {
+      const int sb = d.sblk[src];
+      add_ptap<T>(acc, ho + (size_t)(sb >> 1) * 36, (sb & 1) ? BLK_TRANSPOSED : BLK_FULL, dr, Sr, dc, Sc);
+    }
   }
   const int A = L.slot_row[s];
   if (!L.active[A] && L.dslot[A] == s) {
@@ -263,7 +272,7 @@ template <typename T> __global__ __launch_bounds__(128) void k_amg_galerkin(AmgD
     if (!F.active[i] || !F.active[j]) continue;
     const double dr[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
     const double dc[3] = {F.pd[3 * j], F.pd[3 * j + 1], F.pd[3 * j + 2]};
-    add_ptap<T>(acc, fv + (size_t)src * 36, false, dr, S, dc, S);
+    add_ptap<T>(acc, fv + (size_t)src * 36, BLK_FULL, dr, S, dc, S);
   }
   const int A = L.slot_row[s];
   if (!L.active[A] && L.dslot[A] == s) {

@@ -317,9 +317,10 @@ __global__ __launch_bounds__(TILE) void k_bond_eval(DevPtrs d) {
   if (threadIdx.x == 0) d.part_a[lb] = make_double2(tot.s, tot.c);
 }
 
-// Eigen-clamp of the per-bond 9x9 (Section 5.2, per bond) and scatter into
-// the bond's two off-diagonal slots and two diagonal halves.  Reads the packed
-// 9x9 written by k_bond_eval; holds only the Jacobi state in registers.
+// Eigen-clamp of the per-bond 9x9 (Section 5.2, per bond); writes the bond's
+// off-diagonal block (i, j) (row j of the matrix reads it transposed) and its
+// two diagonal halves.  Reads the packed 9x9 written by k_bond_eval; holds
+// only the Jacobi state in registers.
 template <typename T, bool PSD>
 __global__ __launch_bounds__(TILE) void k_bond_project(DevPtrs d) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
@@ -330,11 +331,11 @@ __global__ __launch_bounds__(TILE) void k_bond_project(DevPtrs d) {
   if (sl.x < 0) return;
   T *hoff = reinterpret_cast<T *>(d.hoff);
   T *hhalf = reinterpret_cast<T *>(d.hhalf);
-  T *oi = hoff + (size_t)sl.x * 36, *oj = hoff + (size_t)sl.y * 36;
+  T *oi = hoff + (size_t)b * 36;
   T *hi = hhalf + (size_t)sl.x * 21, *hj = hhalf + (size_t)sl.y * 21;
   if (!d.alive[b]) {
 #pragma unroll
-    for (int k = 0; k < 36; ++k) { oi[k] = T(0); oj[k] = T(0); }
+    for (int k = 0; k < 36; ++k) oi[k] = T(0);
 #pragma unroll
     for (int k = 0; k < 21; ++k) { hi[k] = T(0); hj[k] = T(0); }
     return;
@@ -349,8 +350,7 @@ __global__ __launch_bounds__(TILE) void k_bond_project(DevPtrs d) {
   const int2 ij = d.bij[b];
   const bool couple = d.flags[ij.x] == 0 && d.flags[ij.y] == 0;
   const T cpl = couple ? T(1) : T(0);
-  // block (i, j): rows (p_i, y_i), cols (p_j, y_j) = [[-P_uu, -P_u,rj], [P_ri,u, P_ri,rj]];
-  // block (j, i) is its transpose
+  // block (i, j): rows (p_i, y_i), cols (p_j, y_j) = [[-P_uu, -P_u,rj], [P_ri,u, P_ri,rj]]
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -363,10 +363,6 @@ __global__ __launch_bounds__(TILE) void k_bond_project(DevPtrs d) {
       oi[r * 6 + 3 + c] = uj;
       oi[(3 + r) * 6 + c] = iu;
       oi[(3 + r) * 6 + 3 + c] = ij_;
-      oj[c * 6 + r] = uu;
-      oj[(3 + c) * 6 + r] = uj;
-      oj[c * 6 + 3 + r] = iu;
-      oj[(3 + c) * 6 + 3 + r] = ij_;
     }
   // diagonal halves: i: [[P_uu, -P_u,ri], [., P_ri,ri]],  j: [[P_uu, P_u,rj], [., P_rj,rj]]
 #pragma unroll

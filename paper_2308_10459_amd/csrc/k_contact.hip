@@ -126,7 +126,7 @@ __global__ __launch_bounds__(TILE) void k_contact_candidates(DevPtrs d) {
           bool bonded = false;
           while (lo <= hi) {
             const int m = (lo + hi) >> 1, cm = d.col[m];
-            if (cm == j) { bonded = d.alive[d.slot_bond[m]] != 0; break; }
+            if (cm == j) { bonded = d.alive[d.sblk[m] >> 1] != 0; break; }
             if (cm < j) lo = m + 1; else hi = m - 1;
           }
           if (bonded) continue;

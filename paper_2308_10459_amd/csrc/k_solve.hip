@@ -150,27 +150,25 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
   store6(d.cq + (size_t)r * 6, zero);
 }
 
-// one row of a 6x6 block (6 contiguous values of type T) widened to FP64
-__device__ __forceinline__ void load_row6(const float *h, double (&v)[6]) {
-  const float2 *q = reinterpret_cast<const float2 *>(h);   // 8-byte aligned
-  const float2 a = q[0], b = q[1], c = q[2];
-  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
-}
-__device__ __forceinline__ void load_row6(const double *h, double (&v)[6]) { load6(h, v); }
-
 // w = H u plus the partial dots (r, u), (w, u), (r, r) of the workgroup.
 // Workgroup = SPMV_ROWS consecutive block rows of one scene; their slots are
-// one contiguous range of the block-CSR arrays.  Phase 1 is slot-parallel:
-// thread (slot, c) forms component c of H_slot u_j, all loads of a trip issued
-// before any use, so the matrix streams through in address order; the products
-// go to LDS in passes of SPMV_CAP slots.  Phase 2: thread (row, c) adds the
-// diagonal block times u_row and its row's slot products in slot order, so the
-// sum order is fixed and results are reproducible.  The launch shape (NT
-// threads, U trips in flight) changes neither: threads past 6 * SPMV_ROWS add
-// zeros to the dots after the row threads' waves, so every shape gives the
-// same bits.
+// one contiguous range of the block-CSR arrays, taken in passes of SPMV_CAP
+// slots.  Each bond's block is stored once: the row of the bond's i end uses
+// it as stored, the row of its j end uses the transpose.  Rows follow a
+// Morton order and bonds their first row, so a block read for one row is
+// usually still in cache when the other row reads it.
+// Phase 1 is slot-parallel, one lane per slot: the lane loads the slot's
+// whole block (16-byte pieces) and u_j, U slots in flight with every load
+// issued before any use, and writes the six components of H_slot u_j to LDS.
+// Phase 2: thread (row, c) adds the diagonal block times u_row and its row's
+// slot products in slot order, so the sum order is fixed and the launch
+// shape (NT, U) does not change a bit: threads past 6 * SPMV_ROWS add zeros
+// to the dots after the row threads' waves.
 template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d) {
-  __shared__ double prod[SPMV_CAP * 6 + 1];   // last entry absorbs clamped lanes
+  static_assert(NT >= 6 * SPMV_ROWS, "one thread per (row, component)");
+  constexpr int NQ = 36 * (int)sizeof(T) / 16;       // 16-byte pieces per block
+  __shared__ double2 prod2[SPMV_CAP * 3];
+  const double *prod = reinterpret_cast<const double *>(prod2);
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int r0 = lb * SPMV_ROWS;
   const int scene = d.psid[r0];
@@ -180,7 +178,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   const int rl = t / 6, c_out = t - (t / 6) * 6;
   const bool rowthr = t < 6 * SPMV_ROWS;
   const int row = r0 + (rowthr ? rl : 0);
-  const T *Hoff = reinterpret_cast<const T *>(d.hoff);
+  const float4 *H4 = reinterpret_cast<const float4 *>(d.hoff);
   const double *u = d.cs;
   double acc = 0.0, uc = 0.0, rc = 0.0;
   int rbeg = 0, rend = 0;
@@ -196,35 +194,45 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
     rc = d.cr[(size_t)row * 6 + c_out];
   }
   for (int cb = s0; cb < s1; cb += SPMV_CAP) {
-    const int ce = min(cb + SPMV_CAP, s1);
-    const int nsc = (ce - cb) * 6;
-    for (int base = 0; base < nsc; base += NT * U) {
-      int sl[U], cc[U], jj[U];
-      double hv[U][6], uj[U][6];
+    const int ns = min(SPMV_CAP, s1 - cb);
+    for (int base = 0; base < ns; base += NT * U) {
+      float4 hq[U][NQ];
+      double uj[U][6];
+      int tr[U];
 #pragma unroll
-      for (int m = 0; m < U; ++m) {   // lanes past the end repeat the last product
-        const int id = min(base + m * NT + t, nsc - 1);
-        sl[m] = id / 6;
-        cc[m] = id - sl[m] * 6;
+      for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last slot
+        const int sl = min(base + m * NT + t, ns - 1);
+        const int sb = d.sblk[cb + sl];
+        const int jj = d.col[cb + sl];
+        tr[m] = sb & 1;
+        const float4 *b = H4 + (size_t)(sb >> 1) * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) hq[m][q] = b[q];
+        load6(u + (size_t)jj * 6, uj[m]);
       }
 #pragma unroll
       for (int m = 0; m < U; ++m) {
-        jj[m] = d.col[cb + sl[m]];
-        load_row6(Hoff + (size_t)(cb + sl[m]) * 36 + cc[m] * 6, hv[m]);
-      }
+        const int sl = base + m * NT + t;
+        const T *h = reinterpret_cast<const T *>(hq[m]);
+        double o[6];
 #pragma unroll
-      for (int m = 0; m < U; ++m) load6(u + (size_t)jj[m] * 6, uj[m]);
+        for (int c = 0; c < 6; ++c) {
+          double a = 0.0;
 #pragma unroll
-      for (int m = 0; m < U; ++m) {
-        double a = 0.0;
-#pragma unroll
-        for (int e = 0; e < 6; ++e) a += hv[m][e] * uj[m][e];
-        prod[(base + m * NT + t < nsc) ? sl[m] * 6 + cc[m] : SPMV_CAP * 6] = a;
+          for (int e = 0; e < 6; ++e) a += double(tr[m] ? h[e * 6 + c] : h[c * 6 + e]) * uj[m][e];
+          o[c] = a;
+        }
+        if (sl < ns) {
+          double2 *pp = prod2 + sl * 3;
+          pp[0] = make_double2(o[0], o[1]);
+          pp[1] = make_double2(o[2], o[3]);
+          pp[2] = make_double2(o[4], o[5]);
+        }
       }
     }
     __syncthreads();
     if (rowthr) {
-      const int lo = max(rbeg, cb), hi = min(rend, ce);
+      const int lo = max(rbeg, cb), hi = min(rend, cb + ns);
       for (int k = lo; k < hi; ++k) acc += prod[(k - cb) * 6 + c_out];
     }
     __syncthreads();
@@ -446,7 +454,7 @@ void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s) {
   else k_cg_init<double><<<nb, TILE, 0, s>>>(d);
 }
 // launch shapes the autotuner chooses from (bitwise-identical results)
-static const int kSpmvShape[][2] = {{256, 2}, {192, 2}, {256, 1}, {256, 4}, {384, 2}, {192, 4}, {384, 1}};
+static const int kSpmvShape[][2] = {{256, 1}, {192, 1}, {256, 2}, {512, 1}, {192, 2}, {384, 1}, {384, 2}};
 static const int kUpdateRows[] = {64, 32, 128};
 int spmv_variants() { return (int)(sizeof(kSpmvShape) / sizeof(kSpmvShape[0])); }
 int update_variants() { return (int)(sizeof(kUpdateRows) / sizeof(kUpdateRows[0])); }
@@ -457,13 +465,13 @@ template <typename T> static void spmv_dispatch(const DevPtrs &d, int v, hipStre
   static_assert(TILE % SPMV_ROWS == 0, "SpMV tiling");
   const int nsp = d.n_pad / SPMV_ROWS;
   switch (v) {
-    case 1: k_spmv<T, 192, 2><<<nsp, 192, 0, s>>>(d); break;
-    case 2: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d); break;
-    case 3: k_spmv<T, 256, 4><<<nsp, 256, 0, s>>>(d); break;
-    case 4: k_spmv<T, 384, 2><<<nsp, 384, 0, s>>>(d); break;
-    case 5: k_spmv<T, 192, 4><<<nsp, 192, 0, s>>>(d); break;
-    case 6: k_spmv<T, 384, 1><<<nsp, 384, 0, s>>>(d); break;
-    default: k_spmv<T, 256, 2><<<nsp, 256, 0, s>>>(d); break;
+    case 1: k_spmv<T, 192, 1><<<nsp, 192, 0, s>>>(d); break;
+    case 2: k_spmv<T, 256, 2><<<nsp, 256, 0, s>>>(d); break;
+    case 3: k_spmv<T, 512, 1><<<nsp, 512, 0, s>>>(d); break;
+    case 4: k_spmv<T, 192, 2><<<nsp, 192, 0, s>>>(d); break;
+    case 5: k_spmv<T, 384, 1><<<nsp, 384, 0, s>>>(d); break;
+    case 6: k_spmv<T, 384, 2><<<nsp, 384, 0, s>>>(d); break;
+    default: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d); break;
   }
 }
 void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s) {

@@ -599,7 +599,7 @@ def test_launch_shapes_and_autotune_give_identical_bits(B):
     got = sim.get_state()
     for k in ("pos", "quat", "vel", "qvel"):
         assert np.array_equal(got[k], ref[k]), k
-    shapes = [(192, 2), (256, 1), (256, 2), (256, 4), (384, 2), (192, 4), (384, 1)]
+    shapes = [(192, 2), (256, 1), (256, 2), (512, 1), (384, 2), (192, 1), (384, 1)]
     for i, (threads, trips) in enumerate(shapes):
         rows = (32, 64, 128)[i % 3]
         chunk, graph = ((1, 0), (4, 1), (16, 1), (3, 0))[i % 4]
