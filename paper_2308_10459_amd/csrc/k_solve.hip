@@ -157,9 +157,12 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // it as stored, the row of its j end uses the transpose.  Rows follow a
 // Morton order and bonds their first row, so a block read for one row is
 // usually still in cache when the other row reads it.
-// Phase 1 is slot-parallel, one lane per slot: the lane loads the slot's
-// whole block (16-byte pieces) and u_j, U slots in flight with every load
-// issued before any use, and writes the six components of H_slot u_j to LDS.
+// Phase 1 is slot-parallel, every load of a trip issued before any use.
+// FP32 blocks: one lane per slot loads the slot's whole block (nine 16-byte
+// pieces) and u_j, U slots in flight, and writes the six components of
+// H_slot u_j to LDS.  FP64 blocks (twice the registers per block): lane
+// (slot, c) reads line c of the block (row c as stored, or column c for the
+// transpose) and u_j, U lines in flight, and writes component c.
 // Phase 2: thread (row, c) adds the diagonal block times u_row and its row's
 // slot products in slot order, so the sum order is fixed and the launch
 // shape (NT, U) does not change a bit: threads past 6 * SPMV_ROWS add zeros
@@ -195,38 +198,67 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   }
   for (int cb = s0; cb < s1; cb += SPMV_CAP) {
     const int ns = min(SPMV_CAP, s1 - cb);
-    for (int base = 0; base < ns; base += NT * U) {
-      float4 hq[U][NQ];
-      double uj[U][6];
-      int tr[U];
+    if constexpr (sizeof(T) == 4) {
+      for (int base = 0; base < ns; base += NT * U) {
+        float4 hq[U][NQ];
+        double uj[U][6];
+        int tr[U];
 #pragma unroll
-      for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last slot
-        const int sl = min(base + m * NT + t, ns - 1);
-        const int sb = d.sblk[cb + sl];
-        const int jj = d.col[cb + sl];
-        tr[m] = sb & 1;
-        const float4 *b = H4 + (size_t)(sb >> 1) * NQ;
+        for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last slot
+          const int sl = min(base + m * NT + t, ns - 1);
+          const int sb = d.sblk[cb + sl];
+          const int jj = d.col[cb + sl];
+          tr[m] = sb & 1;
+          const float4 *b = H4 + (size_t)(sb >> 1) * NQ;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) hq[m][q] = b[q];
-        load6(u + (size_t)jj * 6, uj[m]);
+          for (int q = 0; q < NQ; ++q) hq[m][q] = b[q];
+          load6(u + (size_t)jj * 6, uj[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+          const int sl = base + m * NT + t;
+          const T *h = reinterpret_cast<const T *>(hq[m]);
+          double o[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            double a = 0.0;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) a += double(tr[m] ? h[e * 6 + c] : h[c * 6 + e]) * uj[m][e];
+            o[c] = a;
+          }
+          if (sl < ns) {
+            double2 *pp = prod2 + sl * 3;
+            pp[0] = make_double2(o[0], o[1]);
+            pp[1] = make_double2(o[2], o[3]);
+            pp[2] = make_double2(o[4], o[5]);
+          }
+        }
       }
+    } else {
+      const T *Hb = reinterpret_cast<const T *>(d.hoff);
+      double *prodw = reinterpret_cast<double *>(prod2);
+      const int nl = ns * 6;
+      for (int base = 0; base < nl; base += NT * U) {
+        double hv[U][6], uj[U][6];
+        int id[U];
 #pragma unroll
-      for (int m = 0; m < U; ++m) {
-        const int sl = base + m * NT + t;
-        const T *h = reinterpret_cast<const T *>(hq[m]);
-        double o[6];
+        for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last line
+          id[m] = min(base + m * NT + t, nl - 1);
+          const int sl = id[m] / 6, c = id[m] - (id[m] / 6) * 6;
+          const int sb = d.sblk[cb + sl];
+          const int jj = d.col[cb + sl];
+          const T *h = Hb + (size_t)(sb >> 1) * 36 + ((sb & 1) ? c : c * 6);
+          const int st = (sb & 1) ? 6 : 1;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
+          for (int e = 0; e < 6; ++e) hv[m][e] = double(h[e * st]);
+          load6(u + (size_t)jj * 6, uj[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
           double a = 0.0;
 #pragma unroll
-          for (int e = 0; e < 6; ++e) a += double(tr[m] ? h[e * 6 + c] : h[c * 6 + e]) * uj[m][e];
-          o[c] = a;
-        }
-        if (sl < ns) {
-          double2 *pp = prod2 + sl * 3;
-          pp[0] = make_double2(o[0], o[1]);
-          pp[1] = make_double2(o[2], o[3]);
-          pp[2] = make_double2(o[4], o[5]);
+          for (int e = 0; e < 6; ++e) a += hv[m][e] * uj[m][e];
+          if (base + m * NT + t < nl) prodw[id[m]] = a;
         }
       }
     }
