@@ -160,7 +160,8 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // Phase 1 is slot-parallel, every load of a trip issued before any use.
 // FP32 blocks: one lane per slot loads the slot's whole block (nine 16-byte
 // pieces) and u_j, U slots in flight, and writes the six components of
-// H_slot u_j to LDS.  FP64 blocks (twice the registers per block): lane
+// H_slot u_j to LDS; waves take 64-slot chunks and load the next chunks'
+// indices while the current blocks are in flight.  FP64 blocks (twice the registers per block): lane
 // (slot, c) reads line c of the block (row c as stored, or column c for the
 // transpose) and u_j, U lines in flight, and writes component c.
 // Phase 2: thread (row, c) adds the diagonal block times u_row and its row's
@@ -199,24 +200,39 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   for (int cb = s0; cb < s1; cb += SPMV_CAP) {
     const int ns = min(SPMV_CAP, s1 - cb);
     if constexpr (sizeof(T) == 4) {
-      for (int base = 0; base < ns; base += NT * U) {
+      // wave w takes the pass's 64-slot chunks w, w + NW, ... (U at a time);
+      // the indices of its next chunks are loaded while the current ones'
+      // blocks are in flight
+      constexpr int NW = NT / 64;
+      const int w = t >> 6, lane = t & 63;
+      int sb[U], jj[U];
+#pragma unroll
+      for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last slot
+        const int sl = min((w + m * NW) * 64 + lane, ns - 1);
+        sb[m] = d.sblk[cb + sl];
+        jj[m] = d.col[cb + sl];
+      }
+      for (int ch = w; ch * 64 < ns; ch += NW * U) {
         float4 hq[U][NQ];
         double uj[U][6];
-        int tr[U];
+        int tr[U], sbn[U], jjn[U];
 #pragma unroll
-        for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last slot
-          const int sl = min(base + m * NT + t, ns - 1);
-          const int sb = d.sblk[cb + sl];
-          const int jj = d.col[cb + sl];
-          tr[m] = sb & 1;
-          const float4 *b = H4 + (size_t)(sb >> 1) * NQ;
+        for (int m = 0; m < U; ++m) {
+          tr[m] = sb[m] & 1;
+          const float4 *b = H4 + (size_t)(sb[m] >> 1) * NQ;
 #pragma unroll
           for (int q = 0; q < NQ; ++q) hq[m][q] = b[q];
-          load6(u + (size_t)jj * 6, uj[m]);
+          load6(u + (size_t)jj[m] * 6, uj[m]);
         }
 #pragma unroll
         for (int m = 0; m < U; ++m) {
-          const int sl = base + m * NT + t;
+          const int sl = min((ch + (U + m) * NW) * 64 + lane, ns - 1);
+          sbn[m] = d.sblk[cb + sl];
+          jjn[m] = d.col[cb + sl];
+        }
+#pragma unroll
+        for (int m = 0; m < U; ++m) {
+          const int sl = (ch + m * NW) * 64 + lane;
           const T *h = reinterpret_cast<const T *>(hq[m]);
           double o[6];
 #pragma unroll
@@ -232,6 +248,8 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
             pp[1] = make_double2(o[2], o[3]);
             pp[2] = make_double2(o[4], o[5]);
           }
+          sb[m] = sbn[m];
+          jj[m] = jjn[m];
         }
       }
     } else {
