@@ -41,7 +41,7 @@ def spmv_source_digest():
     import re
     csrc = os.path.join(ROOT, "paper_2308_10459_amd", "csrc")
     src = open(os.path.join(csrc, "k_solve.hip")).read()
-    m = re.search(r"template <typename T, int NT, int U> __global__ __launch_bounds__\(NT\) void k_spmv.*?\n}\n",
+    m = re.search(r"template <typename T, int NT, int U> __global__ __launch_bounds__\([^)]*\) void k_spmv.*?\n}\n",
                   src, re.S)
     consts = [ln for ln in open(os.path.join(csrc, "bdem_internal.hpp")) if "SPMV_" in ln]
     text = (m.group(0) if m else "") + "".join(consts)
