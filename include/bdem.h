@@ -217,6 +217,17 @@ int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, const double *
                           const double *quat_eval, double *energy, double *grad6,
                           double *hdiag36, double *hoff36);
 
+/* One product w = H u with the matrix the PCG of Section 5.3 iterates on: the
+ * projected reduced Hessian (Sections 4.2 and 5.2, as bdem_energy_grad_hess
+ * with BDEM_EGH_H | BDEM_EGH_PSD) at the evaluation state (NULL: the current
+ * state), through the step's own SpMV kernel and launch shape and, with
+ * element repulsion, its pair couplings.  in6 (6n, host): u in reduced
+ * coordinates per particle; out6 (6n, host): w.  Fixed / kinematic particles
+ * have an identity diagonal block and no couplings.  Errors as
+ * bdem_energy_grad_hess. */
+int bdem_hess_apply(bdem_ctx *ctx, double dt, const double *pos_eval, const double *quat_eval,
+                    const double *in6, double *out6);
+
 /* One application of the configured PCG preconditioner M^-1 (Section 5.3) to
  * in6 (6n, host, reduced coordinates per particle), with M built from the
  * projected reduced Hessian at the evaluation state (as bdem_energy_grad_hess

@@ -97,6 +97,7 @@ _sig = {
     "bdem_break_bonds": (C.c_int, [_ctx_p, _i64p, _u8p]),
     "bdem_contact_pairs": (C.c_int, [_ctx_p, C.c_int64, _i32p, _i64p]),
     "bdem_precond_apply": (C.c_int, [_ctx_p, C.c_double, _dp, _dp, _dp, _dp]),
+    "bdem_hess_apply": (C.c_int, [_ctx_p, C.c_double, _dp, _dp, _dp, _dp]),
     "bdem_get_state": (C.c_int, [_ctx_p, _dp, _dp, _dp, _dp, _u8p]),
     "bdem_set_state": (C.c_int, [_ctx_p, _dp, _dp, _dp, _dp, _u8p]),
     "bdem_sizes": (C.c_int, [_ctx_p, _i32p, _i64p, _i32p]),
@@ -252,6 +253,17 @@ def bdem_precond_apply(ctx, dt, vec6, pos=None, quat=None):
     return out
 
 
+def bdem_hess_apply(ctx, dt, vec6, pos=None, quat=None):
+    """H vec6 with the PCG's matrix (projected reduced Hessian) at the evaluation state."""
+    n = bdem_sizes(ctx)[0]
+    x = _f64(np.asarray(vec6).reshape(n, 6))
+    out = np.empty((n, 6))
+    pe = None if pos is None else _f64(pos)
+    qe = None if quat is None else _f64(quat)
+    _check(_lib.bdem_hess_apply(ctx, dt, _p(pe), _p(qe), _p(x), _p(out)), ctx)
+    return out
+
+
 def bdem_contact_pairs(ctx):
     """Element-repulsion candidate pairs of the last step (user indices, i < j)."""
     k = C.c_int64()
@@ -357,6 +369,9 @@ class Simulator:
 
     def precond_apply(self, dt, vec6, pos=None, quat=None):
         return bdem_precond_apply(self.ctx, dt, vec6, pos, quat)
+
+    def hess_apply(self, dt, vec6, pos=None, quat=None):
+        return bdem_hess_apply(self.ctx, dt, vec6, pos, quat)
 
     def autotune(self, dts=None):
         if dts is None:

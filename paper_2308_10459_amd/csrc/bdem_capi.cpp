@@ -1336,6 +1336,36 @@ extern "C" int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_ev
   return BDEM_OK;
 }
 
+extern "C" int bdem_hess_apply(bdem_ctx *ctx, double dt, const double *pos_eval,
+                               const double *quat_eval, const double *in6, double *out6) {
+  if (!ctx || !in6 || !out6) return BDEM_E_INVALID;
+  const int n = ctx->S.n, NS = ctx->S.n_scenes, NP = ctx->S.n_pad;
+  // the projected reduced Hessian at the evaluation state (as bdem_energy_grad_hess)
+  int rc = bdem_energy_grad_hess(ctx, dt, BDEM_EGH_H | BDEM_EGH_PSD, pos_eval, quat_eval, nullptr,
+                                 nullptr, nullptr, nullptr);
+  if (rc < 0) return rc;
+  hipStream_t st = ctx->stream;
+  DevPtrs &d = ctx->d;
+  // u = in (internal order; padding rows zero), every scene active, then w = H u
+  std::vector<double> u((size_t)NP * 6, 0.0), w((size_t)NP * 6);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 6; ++c) u[(size_t)ctx->p_int[i] * 6 + c] = in6[6 * (size_t)i + c];
+  HIP_TRY(hipMemcpyAsync(d.cs, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d.cr, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(ctx->h_ctl, d.ctl, NS * sizeof(SceneCtl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int sc = 0; sc < NS; ++sc) ctx->h_ctl[sc].cg_active = 1;
+  HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
+  launch_spmv(d, ctx->S.mixed, ctx->spmv_variant, st);
+  if (ctx->P.contact) launch_contact_spmv(d, ctx->P, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(w.data(), d.cAp, w.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < 6; ++c) out6[6 * (size_t)i + c] = w[(size_t)ctx->p_int[i] * 6 + c];
+  return BDEM_OK;
+}
+
 extern "C" int bdem_break_bonds(bdem_ctx *ctx, int64_t *n_broken, uint8_t *alive_out) {
   if (!ctx) return BDEM_E_INVALID;
   hipStream_t st = ctx->stream;
