@@ -161,9 +161,10 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // FP32 blocks: one lane per slot loads the slot's whole block (nine 16-byte
 // pieces) and u_j, U slots in flight, and writes the six components of
 // H_slot u_j to LDS; waves take 64-slot chunks and load the next chunks'
-// indices while the current blocks are in flight.  FP64 blocks (twice the registers per block): lane
-// (slot, c) reads line c of the block (row c as stored, or column c for the
-// transpose) and u_j, U lines in flight, and writes component c.
+// indices while the current blocks are in flight.  FP64 blocks (twice the
+// registers per block): lane (slot, c) reads line c of the block (row c as
+// stored, or column c for the transpose) and u_j, U lines in flight, and
+// writes component c.
 // Phase 2: thread (row, c) adds the diagonal block times u_row and its row's
 // slot products in slot order, so the sum order is fixed and the launch
 // shape (NT, U) does not change a bit: threads past 6 * SPMV_ROWS add zeros
