@@ -366,7 +366,20 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_pre(Dev
 }
 
 // b_1 = P^T (r - H t0) (level-1 node: sum over its particles); r0 holds H t0
-__global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a) {
+// pre-smoothing of one node from a zero start: t = omega D^-1 b
+template <typename T>
+__device__ __forceinline__ void pre_smooth_node(const AmgLevel &L, int A, const double (&b)[6]) {
+  double y[6];
+  mat36_apply(reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36, b, y);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) y[k] *= AMG_OMEGA;
+  st6(L.t + (size_t)A * 6, y);
+}
+
+// b of level 1 from the fine residual r - H t0; with `smooth` (level 1 is
+// not the coarsest) also its pre-smoothing
+template <typename T>
+__global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int smooth) {
   const AmgLevel &L = a.lv[1];
   const int A = blockIdx.x * blockDim.x + threadIdx.x;
   if (A >= L.n) return;
@@ -389,20 +402,11 @@ __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a) {
     for (int m = 0; m < 6; ++m) acc[m] += y[m];
   }
   st6(L.b + (size_t)A * 6, acc);
+  if (smooth) pre_smooth_node<T>(L, A, acc);
 }
 
-// coarse level l: t = omega D^-1 b, then r = b - A t
-template <typename T> __global__ __launch_bounds__(256) void k_amg_pre(AmgDev a, int l) {
-  const AmgLevel &L = a.lv[l];
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= L.n) return;
-  double x[6], y[6];
-  ld6(L.b + (size_t)A * 6, x);
-  mat36_apply(reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36, x, y);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) y[k] *= AMG_OMEGA;
-  st6(L.t + (size_t)A * 6, y);
-}
+// coarse level l: t = omega D^-1 b (done by the restriction that fills b),
+// then r = b - A t
 
 // component (lane mod 6) of A_row x by one wavefront: lane (g, c) with
 // g = lane / 6 < 10 takes the row's slots g, g + 10, ... for output
@@ -436,8 +440,10 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_resid(AmgDev 
   if (lane < 6) L.r[(size_t)A * 6 + lane] = L.b[(size_t)A * 6 + lane] - y;
 }
 
-// b_{l+1} = P^T r_l (S = I above the particles)
-__global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l) {
+// b_{l+1} = P^T r_l (S = I above the particles); with `smooth` (level l + 1
+// is not the coarsest) also its pre-smoothing
+template <typename T>
+__global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l, int smooth) {
   const AmgLevel &C = a.lv[l + 1], &F = a.lv[l];
   const int A = blockIdx.x * blockDim.x + threadIdx.x;
   if (A >= C.n) return;
@@ -454,10 +460,40 @@ __global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l) {
     for (int m = 0; m < 6; ++m) acc[m] += y[m];
   }
   st6(C.b + (size_t)A * 6, acc);
+  if (smooth) pre_smooth_node<T>(C, A, acc);
 }
 
-// last level: e = A^-1 b per scene (dense)
-__global__ __launch_bounds__(256) void k_amg_coarse_solve(AmgDev a) {
+// t_f += P_f e_A for the members f of node A of level l (level l - 1 nodes,
+// or the fine particles when l = 1; S = I above the particles)
+__device__ __forceinline__ void prolong_members(const DevPtrs &d, const AmgDev &a, int l, int A,
+                                                const double (&e)[6], int k0, int kstep) {
+  const AmgLevel &C = a.lv[l];
+  for (int k = C.mbeg[A] + k0; k < C.mbeg[A + 1]; k += kstep) {
+    const int i = C.mlist[k];
+    double dd[3], S[9], y[6];
+    double *t;
+    if (l == 1) {
+      if (d.flags[i] != 0 || !d.ctl[d.psid[i]].cg_active) continue;
+      const double *p = a.pd0 + (size_t)i * 12;
+      dd[0] = p[0]; dd[1] = p[1]; dd[2] = p[2];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
+      t = a.t0 + (size_t)i * 6;
+    } else {
+      const AmgLevel &F = a.lv[l - 1];
+      if (!F.active[i]) continue;
+      dd[0] = F.pd[3 * i]; dd[1] = F.pd[3 * i + 1]; dd[2] = F.pd[3 * i + 2];
+      ident3(S);
+      t = F.t + (size_t)i * 6;
+    }
+    p_apply(dd, S, e, y);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) t[m] += y[m];
+  }
+}
+
+// last level: e = A^-1 b per scene (dense), then prolonged into the members
+__global__ __launch_bounds__(256) void k_amg_coarse_solve(DevPtrs d, AmgDev a) {
   const int sc = blockIdx.x;
   const AmgLevel &L = a.lv[a.L];
   const int nb = a.cbeg[sc], N = 6 * (a.cbeg[sc + 1] - nb);
@@ -467,24 +503,20 @@ __global__ __launch_bounds__(256) void k_amg_coarse_solve(AmgDev a) {
     for (int c = 0; c < N; ++c) acc += X[(size_t)r * N + c] * L.b[(size_t)6 * nb + c];
     L.e[(size_t)6 * nb + r] = acc;
   }
+  __syncthreads();
+  for (int A = nb + (int)threadIdx.x; A < a.cbeg[sc + 1]; A += blockDim.x) {
+    double e[6];
+    ld6(L.e + (size_t)A * 6, e);
+    prolong_members(d, a, a.L, A, e, 0, 1);
+  }
 }
 
-// t_l += P e_{l+1}, then e_l = t_l + omega D^-1 (b_l - A t_l)
-__global__ __launch_bounds__(256) void k_amg_prolong(AmgDev a, int l) {
-  const AmgLevel &F = a.lv[l], &C = a.lv[l + 1];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= F.n || !F.active[i]) return;
-  double S[9], x[6], y[6];
-  ident3(S);
-  const double dd[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
-  ld6(C.e + (size_t)F.parent[i] * 6, x);
-  p_apply(dd, S, x, y);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) F.t[(size_t)i * 6 + k] += y[k];
-}
+// then on each level up: e_l = t_l + omega D^-1 (b_l - A t_l) (t_l already holds
+// the prolonged correction), prolonged into the members of each node
 
-// e = t + omega D^-1 (b - A t), one wavefront per row
-template <typename T> __global__ __launch_bounds__(256) void k_amg_post(AmgDev a, int l) {
+// e = t + omega D^-1 (b - A t), one wavefront per row; then t += P e on the
+// row's members one level down (the fine t0 for level 1)
+template <typename T> __global__ __launch_bounds__(256) void k_amg_post(DevPtrs d, AmgDev a, int l) {
   const AmgLevel &L = a.lv[l];
   const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (A >= L.n) return;   // uniform over the wavefront
@@ -493,30 +525,21 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_post(AmgDev a
   double rv[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) rv[k] = __shfl(rb, k, 64);
+  double ev = 0.0;
   if (lane < 6) {
     const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + lane * 6;
     double u = 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) u += double(Di[k]) * rv[k];
-    L.e[(size_t)A * 6 + lane] = L.t[(size_t)A * 6 + lane] + AMG_OMEGA * u;
+    ev = L.t[(size_t)A * 6 + lane] + AMG_OMEGA * u;
+    L.e[(size_t)A * 6 + lane] = ev;
   }
+  double e[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) e[k] = __shfl(ev, k, 64);
+  prolong_members(d, a, l, A, e, lane, 64);
 }
 
-// fine: t0 += P e_1, then u = t0 + omega D^-1 (r - H t0) into the PCG's u
-template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_prolong(DevPtrs d, AmgDev a) {
-  const int i = blockIdx.x * TILE + threadIdx.x;
-  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
-  if (d.flags[i] != 0) return;
-  const double *p = a.pd0 + (size_t)i * 12;
-  const double dd[3] = {p[0], p[1], p[2]};
-  double S[9], x[6], y[6];
-#pragma unroll
-  for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
-  ld6(a.lv[1].e + (size_t)a.parent0[i] * 6, x);
-  p_apply(dd, S, x, y);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) a.t0[(size_t)i * 6 + k] += y[k];
-}
 
 // u = t0 + omega D^-1 (r - H t0) into the PCG's u; r0 holds H t0
 template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_final(DevPtrs d, AmgDev a) {
@@ -562,18 +585,15 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   dt.cAp = a.r0;
   k_amg_fine_pre<T><<<np, TILE, 0, s>>>(d, a);
   launch_spmv(dt, mixed, spmv_variant, s);
-  k_amg_restrict1<<<nblk(hl[1].n, 256), 256, 0, s>>>(d, a);
+  // each restriction also pre-smooths the level it fills (not the coarsest)
+  k_amg_restrict1<T><<<nblk(hl[1].n, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
   for (int l = 1; l < a.L; ++l) {
-    k_amg_pre<T><<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
     k_amg_resid<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
-    k_amg_restrict<<<nblk(hl[l + 1].n, 256), 256, 0, s>>>(a, l);
+    k_amg_restrict<T><<<nblk(hl[l + 1].n, 256), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
   }
-  k_amg_coarse_solve<<<n_scenes, 256, 0, s>>>(a);
-  for (int l = a.L - 1; l >= 1; --l) {
-    k_amg_prolong<<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
-    k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
-  }
-  k_amg_fine_prolong<T><<<np, TILE, 0, s>>>(d, a);
+  // each level's kernel also prolongs its correction one level down
+  k_amg_coarse_solve<<<n_scenes, 256, 0, s>>>(d, a);
+  for (int l = a.L - 1; l >= 1; --l) k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(d, a, l);
   launch_spmv(dt, mixed, spmv_variant, s);
   k_amg_fine_final<T><<<np, TILE, 0, s>>>(d, a);
 }
