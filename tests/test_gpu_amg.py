@@ -115,3 +115,73 @@ def test_amg_ceramic_plate_first_step(B):
     assert sg["cg_iters"] * 3 < sb["cg_iters"]
     sim.close()
     bj.close()
+
+
+def test_amg_batched_scenes(B):
+    """Four uneven scenes in one context with the multigrid PCG (each scene
+    its own hierarchy and coarsest solve): a vector confined to one scene is
+    mapped to one confined to that scene, and two batched steps reach every
+    scene's own oracle fixed point (the preconditioner leaves the fixed point
+    where it is)."""
+    from tests.test_gpu_parity import _conditioning_bound, _loose_step, _mini_batch
+    batch, members = _mini_batch()
+    kc = max(m["young"] for m in batch.materials) * batch.radius.max()
+    batch.k_contact = kc
+    log(f"[amg batch] n={batch.n} scenes={len(members)}")
+    sim = make_sim(batch, preconditioner=B.BDEM_PRECOND_AMG, **TIGHT)
+    offs = np.cumsum([0] + [m.n for m, _ in members])
+    rng = np.random.default_rng(9)
+    for s in range(len(members)):
+        v = np.zeros((batch.n, 6))
+        v[offs[s]:offs[s + 1]] = rng.normal(size=(offs[s + 1] - offs[s], 6))
+        v[batch.flags != 0] = 0.0
+        x = sim.precond_apply(1e-3, v)
+        inside = np.zeros(batch.n, dtype=bool)
+        inside[offs[s]:offs[s + 1]] = True
+        assert np.all(x[~inside] == 0.0), s
+        assert np.abs(x[inside]).max() > 0.0, s
+    oracles = []
+    for m, _ in members:
+        m.k_contact = kc
+        m.gravity = batch.gravity
+        oracles.append(oracle_for(m))
+    starts = [o.get_state() for o in oracles]
+    for k in range(2):
+        rc, stats = sim.step_batched(batch.dt_per_scene)
+        got = sim.get_state()
+        for s, ((m, dt), o) in enumerate(zip(members, oracles)):
+            assert rc == 0 and stats[s]["status"] == 0, (rc, stats[s])
+            loose = _loose_step(m, starts[s], dt)
+            so = o.step(dt, tol_rel=0.0, max_newton=300)
+            ref = o.get_state()
+            cond = _conditioning_bound(m, starts[s], ref, dt, max(so["grad_final"], stats[s]["grad_final"]))
+            sl = slice(offs[s], offs[s + 1])
+            sub = {kk: got[kk][sl] for kk in ("pos", "quat", "vel", "qvel")}
+            _compare_states(m, sub, ref, starts[s], 1e-8,
+                            f"amg batch step {k} scene {s} newton {stats[s]['newton_iters']} "
+                            f"cg {stats[s]['cg_iters']}", ref2=loose, cond=cond)
+            starts[s] = ref
+    sim.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_amg_with_repulsion_and_midpoint(B, mixed):
+    """The multigrid hierarchy leaves out the element-repulsion couplings
+    (they stay in the PCG's product): steps of the squeezed cluster with
+    repulsion, in the midpoint form, still reach the oracle's fixed points."""
+    from tests.test_gpu_contact import _loose_cluster
+    sc = _loose_cluster(7, 6, 5)
+    log(f"[amg repulsion midpoint] n={sc.n} mixed={mixed}")
+    o = oracle_for(sc)
+    sim = make_sim(sc, mixed=mixed, preconditioner=B.BDEM_PRECOND_AMG,
+                   integrator=B.BDEM_INTEGRATOR_MIDPOINT, **TIGHT)
+    tol = 1e-5 if mixed else 1e-8
+    prev = o.get_state()
+    for k in range(3):
+        so = o.step(1e-3, tol_rel=0.0, max_newton=300, midpoint=1)
+        sg = sim.step(1e-3)
+        assert sg["rc"] == 0 and so["rc"] == 0, (sg, so)
+        ref, got = o.get_state(), sim.get_state()
+        _compare_states(sc, got, ref, prev, tol, f"step {k} newton {sg['newton_iters']} cg {sg['cg_iters']}")
+        prev = ref
+    sim.close()
