@@ -300,6 +300,34 @@ def test_first_order_iterations_match_oracle(B, mixed, iters):
     sim.close()
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("variant", ["midpoint", "repulsion", "both"])
+def test_first_order_iterations_with_other_options(B, mixed, variant):
+    """Algorithm 1 combined with the midpoint form and / or element repulsion:
+    five iterations take the same line-search steps as the oracle's."""
+    from tests.test_gpu_contact import _loose_cluster
+    mid = variant in ("midpoint", "both")
+    if variant == "midpoint":
+        sc, st = _perturbed_block(ground=True)
+    else:
+        sc = _loose_cluster(5, 4, 3)
+        st = dict(pos=sc.pos, quat=sc.quat, vel=sc.vel, qvel=sc.qvel)
+    iters = 5
+    o = oracle_for(sc, st)
+    so = o.step(1e-3, first_order=1, max_newton=iters, break_bonds=0, midpoint=1 if mid else 0)
+    sim = make_sim(sc, mixed=mixed, solver=B.BDEM_SOLVER_FIRST_ORDER, max_newton=iters,
+                   break_each_step=0, integrator=B.BDEM_INTEGRATOR_MIDPOINT if mid else 0)
+    sim.set_state(**st)
+    sg = sim.step(1e-3)
+    log(f"[first order {variant}] gpu ls {sg['ls_backtracks']} | oracle ls {so['ls_backtracks']}")
+    assert sg["cg_iters"] == 0 and sg["newton_iters"] == iters and sg["ls_backtracks"] == so["ls_backtracks"]
+    got, ref = sim.get_state(), o.get_state()
+    disp = np.abs(ref["pos"] - st["pos"]).max()
+    assert np.abs(got["pos"] - ref["pos"]).max() <= 1e-12 * disp
+    assert np.abs(got["quat"] - ref["quat"]).max() <= 1e-13
+    sim.close()
+
+
 def test_first_order_step_reaches_the_newton_fixed_point(B):
     """A first-order step run to a tight gradient tolerance stops at the
     second-order fixed point (oracle), within |grad f| / lambda_min."""
