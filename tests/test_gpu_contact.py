@@ -149,33 +149,44 @@ def test_colliding_blocks(B, mixed):
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-def test_friction_on_the_ground(B, mixed):
+@pytest.mark.parametrize("midpoint", [False, True])
+def test_friction_on_the_ground(B, mixed, midpoint):
     """A 3x3x2 block (no fixed layer) resting on the ground, sliding and
-    spinning, with sliding and rolling friction; velocities after each step
-    against the oracle's from the same state."""
-    log(f"[friction] mixed={mixed}")
+    spinning, with sliding and rolling friction, under either integrator;
+    velocities after each step against the oracle's from the same state."""
+    log(f"[friction] mixed={mixed} midpoint={midpoint}")
     sc = S.make_block(nx=3, ny=3, nz=2, rot_angle=0.0)
     sc.flags[:] = S.FREE
     sc.k_contact = 1e5
-    sc.ground_offset = -0.01 + 2e-4     # the bottom layer (z = 0) overlaps the ground by 0.2 mm
+    # the bottom layer (z = 0) overlaps the ground by 0.2 mm; the midpoint form
+    # conserves energy and would bounce the block off from there, so it starts
+    # at 1 um, next to the resting overlap 2 m g / k_c = 0.8 um
+    sc.ground_offset = -0.01 + (1e-6 if midpoint else 2e-4)
     sc.mu_s, sc.mu_r = 0.4, 0.02
     sc.vel = np.tile([0.3, 0.1, 0.0], (sc.n, 1))
     sc.qvel = np.tile([0.0, 0.0, 0.4, 0.0], (sc.n, 1))
-    sim = make_sim(sc, mixed=mixed, **TIGHT)
+    sim = make_sim(sc, mixed=mixed, integrator=B.BDEM_INTEGRATOR_MIDPOINT if midpoint else 0, **TIGHT)
     for k in range(6):
         prev = sim.get_state()
         o = oracle_for(sc, prev)
-        so = o.step(sc.dt, tol_rel=0.0, max_newton=300)
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300, midpoint=1 if midpoint else 0)
         sg = sim.step(sc.dt)
         ref, got = o.get_state(), sim.get_state()
         assert sg["rc"] == 0 and so["rc"] == 0
         cond = _conditioning_bound(sc, prev, ref, sc.dt, max(so["grad_final"], sg["grad_final"]))
         _compare_states(sc, got, ref, prev, 1e-5 if mixed else 1e-8, f"step {k}", cond=cond)
-        # velocities: the friction change on top of (x_{n+1} - x_n)/dt, so the
-        # states' own difference over dt bounds them too
+        # velocities: (x_{n+1} - x_n)/dt plus the friction change, whose size
+        # follows the normal force k_c |gap| at x_{n+1}; a position difference
+        # dx between the two sides therefore moves v by up to
+        # dx (1/dt + mu_s k_c dt / m) and the spin rate by up to
+        # dq / dt + dx mu_r k_c dt / (2 * 0.4 m r)
         tol = 1e-5 if mixed else 1e-8
-        dp = np.abs(got["pos"] - ref["pos"]).max() / sc.dt
-        dq = np.abs(got["quat"] - ref["quat"]).max() / sc.dt
+        dx = np.abs(got["pos"] - ref["pos"]).max()
+        m = sc.materials[0]["density"] * 4.0 / 3.0 * np.pi * sc.radius.min() ** 3
+        rr = sc.radius.min()
+        dp = dx * (1.0 / sc.dt + sc.mu_s * sc.k_contact * sc.dt / m)
+        dq = (np.abs(got["quat"] - ref["quat"]).max() / sc.dt
+              + dx * sc.mu_r * sc.k_contact * sc.dt / (2 * 0.4 * m * rr))
         ev = np.abs(got["vel"] - ref["vel"]).max()
         eq = np.abs(got["qvel"] - ref["qvel"]).max()
         bv = max(tol * np.abs(ref["vel"]).max(), 3 * dp)
