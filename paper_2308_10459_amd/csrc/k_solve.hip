@@ -388,20 +388,30 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   const double a = c.alpha, b = c.beta;
   const int t = threadIdx.x;
   const size_t o = (size_t)r0 * 6 + t;
-  const double x = d.cx[o], rv = d.cr[o], u = d.cs[o], w = d.cAp[o], p = d.cp[o], q = d.cq[o];
+  // With FP32 blocks (the mixed path) x, p, q, w and the Jacobi inverse are
+  // loaded and stored non-temporally: they are this kernel's own streams, and
+  // keeping them out of the caches leaves room there for the SpMV's matrix
+  // (about 280 MB against the 256 MB Infinity Cache) between iterations.
+  // r and u, which the SpMV reads next, are stored normally.  The FP64
+  // matrix does not fit either way and keeps plain accesses.
+  constexpr bool NT = sizeof(T) == 4;
+  auto ld = [](const auto *q) { if constexpr (NT) return __builtin_nontemporal_load(q); else return *q; };
+  auto stn = [](double v, double *q) { if constexpr (NT) __builtin_nontemporal_store(v, q); else *q = v; };
+  const double x = ld(d.cx + o), rv = d.cr[o], u = ld(d.cs + o), w = ld(d.cAp + o);
+  const double p = ld(d.cp + o), q = ld(d.cq + o);
   const double pn = u + b * p, qn = w + b * q;
   const double xn = x + a * pn, rn = rv - a * qn;
   rs[t] = rn;
-  d.cp[o] = pn;
-  d.cq[o] = qn;
-  d.cx[o] = xn;
+  stn(pn, d.cp + o);
+  stn(qn, d.cq + o);
+  stn(xn, d.cx + o);
   d.cr[o] = rn;
   __syncthreads();
   const int rl = t / 6, cc = t - rl * 6;
   const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)(r0 + rl) * 21;
   double un = 0.0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) un += double(Di[up6(cc, k)]) * rs[rl * 6 + k];
+  for (int k = 0; k < 6; ++k) un += double(ld(Di + up6(cc, k))) * rs[rl * 6 + k];
   d.cs[o] = un;
 }
 
