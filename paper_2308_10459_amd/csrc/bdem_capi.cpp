@@ -822,11 +822,13 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
 // one PCG iteration: update, SpMV with the three dots, per-scene scalars
 static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   const bool mixed = ctx->S.mixed;
-  launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream);
-  // multigrid: u = V(r) replaces the block-Jacobi u the update wrote
-  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, ctx->stream);
+  // block-Jacobi: the update forms (r, u) and (r, r) with the u it writes;
+  // multigrid: u = V(r) replaces that u, and the SpMV forms them
+  const bool amg = ctx->amg;
+  launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream, !amg);
+  if (amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, amg);
   if (profile_spmv) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, ctx->stream);
   launch_cg_scalars(ctx->d, ctx->P, ctx->stream);
@@ -1527,7 +1529,7 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
   }
   best = 1e300;
   for (int v = 0; v < update_variants(); ++v) {
-    const double us = time_it([&] { launch_cg_update(d, mixed, v, st); }, 5);
+    const double us = time_it([&] { launch_cg_update(d, mixed, v, st, !ctx->amg); }, 5);
     if (us < best) { best = us; ctx->upd_variant = v; ctx->tune_us[1] = us; }
   }
   HIP_TRY(hipGetLastError());

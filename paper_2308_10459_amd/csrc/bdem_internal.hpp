@@ -142,11 +142,13 @@ void launch_count_active(const DevPtrs &d, int n_scenes, int slot, hipStream_t s
 void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
 // PCG
 void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
-void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s);
+// rdots = false: the SpMV leaves the (r, u) and (r, r) partials to the CG
+// update that produced u (launch_cg_update with rdots = true)
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots = true);
 int spmv_variants();
 void spmv_shape(int variant, int *threads, int *trips);
 void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s);
-void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s);
+void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots = false);
 int update_variants();
 int update_rows(int variant);
 void launch_cg_slope(const DevPtrs &d, const Params &P, hipStream_t s);

@@ -168,8 +168,10 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // Phase 2: thread (row, c) adds the diagonal block times u_row and its row's
 // slot products in slot order, so the sum order is fixed and the launch
 // shape (NT, U) does not change a bit: threads past 6 * SPMV_ROWS add zeros
-// to the dots after the row threads' waves.
-template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d) {
+// to the dots after the row threads' waves.  With rdots = 0 the kernel
+// leaves (r, u) and (r, r) to the CG update that produced u (and does not
+// read r); their partials are then the update's.
+template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d, int rdots) {
   static_assert(NT >= 6 * SPMV_ROWS, "one thread per (row, component)");
   constexpr int NQ = 36 * (int)sizeof(T) / 16;       // 16-byte pieces per block
   __shared__ double2 prod2[SPMV_CAP * 3];
@@ -196,7 +198,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc += double(D[up6(c_out, k)]) * ur[k];
     uc = u[(size_t)row * 6 + c_out];
-    rc = d.cr[(size_t)row * 6 + c_out];
+    if (rdots) rc = d.cr[(size_t)row * 6 + c_out];
   }
   for (int cb = s0; cb < s1; cb += SPMV_CAP) {
     const int ns = min(SPMV_CAP, s1 - cb);
@@ -297,9 +299,11 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   }
   block_ksum3(ru, wu, rr);
   if (t == 0) {
-    d.part_a[lb] = make_double2(ru.s, ru.c);
     d.part_b[lb] = make_double2(wu.s, wu.c);
-    d.part_c[lb] = make_double2(rr.s, rr.c);
+    if (rdots) {
+      d.part_a[lb] = make_double2(ru.s, ru.c);
+      d.part_c[lb] = make_double2(rr.s, rr.c);
+    }
   }
 }
 
@@ -379,7 +383,13 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
 // p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r.
 // Thread (row, component): every vector is read and written with unit
 // stride; the new residual of the row is shared through LDS for M^-1 r.
-template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg_update(DevPtrs d) {
+// With rdots the kernel also writes the (r, u) and (r, r) partials of each
+// SPMV_ROWS-row block (the SpMV then skips them): thread (row, c) adds its
+// product, each wavefront reduces, and the block's three wavefronts merge in
+// order, the tree the SpMV uses, so the partials are bit-identical to the
+// SpMV's.
+template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg_update(DevPtrs d, int rdots) {
+  static_assert(ROWS % SPMV_ROWS == 0 && 6 * SPMV_ROWS == 192, "dot blocks of three wavefronts");
   __shared__ double rs[6 * ROWS];
   const int r0 = blockIdx.x * ROWS;
   const int scene = d.psid[r0];
@@ -388,16 +398,17 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   const double a = c.alpha, b = c.beta;
   const int t = threadIdx.x;
   const size_t o = (size_t)r0 * 6 + t;
-  // With FP32 blocks (the mixed path) x, p, q, w and the Jacobi inverse are
-  // loaded and stored non-temporally: they are this kernel's own streams, and
+  // With FP32 blocks (the mixed path) x, r, p, q, w and the Jacobi inverse
+  // are loaded and stored non-temporally: the SpMV reads none of them (it
+  // leaves the r dots to this kernel; with multigrid it reads r once), and
   // keeping them out of the caches leaves room there for the SpMV's matrix
-  // (about 280 MB against the 256 MB Infinity Cache) between iterations.
-  // r and u, which the SpMV reads next, are stored normally.  The FP64
+  // and u (about 255 MB against the 256 MB Infinity Cache) between
+  // iterations.  u, which the SpMV gathers, is stored normally.  The FP64
   // matrix does not fit either way and keeps plain accesses.
   constexpr bool NT = sizeof(T) == 4;
   auto ld = [](const auto *q) { if constexpr (NT) return __builtin_nontemporal_load(q); else return *q; };
   auto stn = [](double v, double *q) { if constexpr (NT) __builtin_nontemporal_store(v, q); else *q = v; };
-  const double x = ld(d.cx + o), rv = d.cr[o], u = ld(d.cs + o), w = ld(d.cAp + o);
+  const double x = ld(d.cx + o), rv = ld(d.cr + o), u = ld(d.cs + o), w = ld(d.cAp + o);
   const double p = ld(d.cp + o), q = ld(d.cq + o);
   const double pn = u + b * p, qn = w + b * q;
   const double xn = x + a * pn, rn = rv - a * qn;
@@ -405,7 +416,7 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   stn(pn, d.cp + o);
   stn(qn, d.cq + o);
   stn(xn, d.cx + o);
-  d.cr[o] = rn;
+  stn(rn, d.cr + o);
   __syncthreads();
   const int rl = t / 6, cc = t - rl * 6;
   const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)(r0 + rl) * 21;
@@ -413,6 +424,27 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
 #pragma unroll
   for (int k = 0; k < 6; ++k) un += double(ld(Di + up6(cc, k))) * rs[rl * 6 + k];
   d.cs[o] = un;
+  if (!rdots) return;   // uniform over the launch
+  constexpr int NWV = 6 * ROWS / 64;
+  __shared__ double wd[4][NWV];
+  KSum ru = {0.0, 0.0}, rr = {0.0, 0.0};
+  kadd(ru, rn * un);
+  kadd(rr, rn * rn);
+  ru = wave_ksum(ru);
+  rr = wave_ksum(rr);
+  const int wv = t >> 6;
+  if ((t & 63) == 0) { wd[0][wv] = ru.s; wd[1][wv] = ru.c; wd[2][wv] = rr.s; wd[3][wv] = rr.c; }
+  __syncthreads();
+  if (t < ROWS / SPMV_ROWS) {
+    KSum a = {0.0, 0.0}, c2 = {0.0, 0.0};
+    for (int k = 3 * t; k < 3 * t + 3; ++k) {
+      a = kmerge(a, KSum{wd[0][k], wd[1][k]});
+      c2 = kmerge(c2, KSum{wd[2][k], wd[3][k]});
+    }
+    const int blk = r0 / SPMV_ROWS + t;
+    d.part_a[blk] = make_double2(a.s, a.c);
+    d.part_c[blk] = make_double2(c2.s, c2.c);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -522,37 +554,37 @@ int update_variants() { return (int)(sizeof(kUpdateRows) / sizeof(kUpdateRows[0]
 void spmv_shape(int v, int *threads, int *trips) { *threads = kSpmvShape[v][0]; *trips = kSpmvShape[v][1]; }
 int update_rows(int v) { return kUpdateRows[v]; }
 
-template <typename T> static void spmv_dispatch(const DevPtrs &d, int v, hipStream_t s) {
+template <typename T> static void spmv_dispatch(const DevPtrs &d, int v, int rd, hipStream_t s) {
   static_assert(TILE % SPMV_ROWS == 0, "SpMV tiling");
   const int nsp = d.n_pad / SPMV_ROWS;
   switch (v) {
-    case 1: k_spmv<T, 192, 1><<<nsp, 192, 0, s>>>(d); break;
-    case 2: k_spmv<T, 256, 2><<<nsp, 256, 0, s>>>(d); break;
-    case 3: k_spmv<T, 512, 1><<<nsp, 512, 0, s>>>(d); break;
-    case 4: k_spmv<T, 192, 2><<<nsp, 192, 0, s>>>(d); break;
-    case 5: k_spmv<T, 384, 1><<<nsp, 384, 0, s>>>(d); break;
-    case 6: k_spmv<T, 384, 2><<<nsp, 384, 0, s>>>(d); break;
-    default: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d); break;
+    case 1: k_spmv<T, 192, 1><<<nsp, 192, 0, s>>>(d, rd); break;
+    case 2: k_spmv<T, 256, 2><<<nsp, 256, 0, s>>>(d, rd); break;
+    case 3: k_spmv<T, 512, 1><<<nsp, 512, 0, s>>>(d, rd); break;
+    case 4: k_spmv<T, 192, 2><<<nsp, 192, 0, s>>>(d, rd); break;
+    case 5: k_spmv<T, 384, 1><<<nsp, 384, 0, s>>>(d, rd); break;
+    case 6: k_spmv<T, 384, 2><<<nsp, 384, 0, s>>>(d, rd); break;
+    default: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d, rd); break;
   }
 }
-void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s) {
-  if (mixed) spmv_dispatch<float>(d, variant, s);
-  else spmv_dispatch<double>(d, variant, s);
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots) {
+  if (mixed) spmv_dispatch<float>(d, variant, rdots ? 1 : 0, s);
+  else spmv_dispatch<double>(d, variant, rdots ? 1 : 0, s);
 }
 void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s) {
   k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P);
 }
-template <typename T> static void update_dispatch(const DevPtrs &d, int v, hipStream_t s) {
+template <typename T> static void update_dispatch(const DevPtrs &d, int v, int rd, hipStream_t s) {
   static_assert(TILE % 128 == 0, "update tiling");
   switch (v) {
-    case 1: k_cg_update<T, 32><<<d.n_pad / 32, 6 * 32, 0, s>>>(d); break;
-    case 2: k_cg_update<T, 128><<<d.n_pad / 128, 6 * 128, 0, s>>>(d); break;
-    default: k_cg_update<T, 64><<<d.n_pad / 64, 6 * 64, 0, s>>>(d); break;
+    case 1: k_cg_update<T, 32><<<d.n_pad / 32, 6 * 32, 0, s>>>(d, rd); break;
+    case 2: k_cg_update<T, 128><<<d.n_pad / 128, 6 * 128, 0, s>>>(d, rd); break;
+    default: k_cg_update<T, 64><<<d.n_pad / 64, 6 * 64, 0, s>>>(d, rd); break;
   }
 }
-void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s) {
-  if (mixed) update_dispatch<float>(d, variant, s);
-  else update_dispatch<double>(d, variant, s);
+void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots) {
+  if (mixed) update_dispatch<float>(d, variant, rdots ? 1 : 0, s);
+  else update_dispatch<double>(d, variant, rdots ? 1 : 0, s);
 }
 void launch_cg_slope(const DevPtrs &d, const Params &P, hipStream_t s) {
   k_slope_part<<<d.n_pad / TILE, TILE, 0, s>>>(d);
