@@ -128,8 +128,9 @@ __device__ __forceinline__ void store6(double *p, const double (&v)[6]) {
 //   gamma = (r, u), delta = (w, u);  beta = gamma / gamma_prev;
 //   alpha = gamma / (delta - beta gamma / alpha_prev);
 //   p = u + beta p;  q = w + beta q;  x += alpha p;  r -= alpha q;  u = M^-1 r.
-// One iteration = k_cg_update, k_spmv (w = H u plus the three dots r.u, w.u,
-// r.r) and k_cg_scalars (per scene).  Buffers: cx = x, cr = r, cs = u,
+// One iteration = k_cg_update (also the dots r.u and r.r of the u it
+// writes), k_spmv (w = H u and the dot w.u; all three dots after k_cg_init
+// and with multigrid) and k_cg_scalars (per scene).  Buffers: cx = x, cr = r, cs = u,
 // cAp = w, cp = p, cq = q.
 
 // r = -z, x = 0, u = M^-1 r, p = q = 0
