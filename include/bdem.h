@@ -255,11 +255,12 @@ int bdem_set_state(bdem_ctx *ctx, const double *pos, const double *quat, const d
 
 /* Launch-shape autotuner: assembles the Hessian at the prediction of a step
  * of length dt_per_scene[s] (the first Newton iteration's matrix), times each
- * SpMV shape, each CG-update tile and each PCG polling mode (cg_chunk,
- * use_graph) on it with HIP events, keeps the fastest and reports it in out
- * (nullable).  The simulation state is not changed, and since every shape
- * computes the same bits, no later result depends on the choice.  Errors:
- * INVALID, DEGENERATE, HIP. */
+ * pair of CG-update tile and SpMV shape (the two kernels back to back, as a
+ * PCG iteration runs them) and each PCG polling mode (cg_chunk, use_graph) on
+ * it with HIP events, keeps the fastest and reports it in out (nullable;
+ * spmv_us and update_us are the chosen kernels timed alone).  The simulation
+ * state is not changed, and since every shape computes the same bits, no
+ * later result depends on the choice.  Errors: INVALID, DEGENERATE, HIP. */
 int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tuning *out);
 /* Current launch shapes / set them explicitly (INVALID if not a listed shape). */
 int bdem_get_tuning(const bdem_ctx *ctx, bdem_tuning *out);

@@ -95,6 +95,7 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.gbeg), (std::max(S.n_bucket, 1) + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.cand_over), sizeof(int));
   L.add(reinterpret_cast<void **>(&d.part_d), std::max<size_t>(ntile_p, 1) * sizeof(double2));
+  for (double2 **p : {&d.part_ag, &d.part_cg}) L.add(reinterpret_cast<void **>(p), std::max<size_t>(ntile_p, 1) * sizeof(double2));
 }
 
 // scene sizes from the particle and bond arrays (no validation beyond what
@@ -831,7 +832,7 @@ static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, amg);
   if (profile_spmv) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, ctx->stream);
-  launch_cg_scalars(ctx->d, ctx->P, ctx->stream);
+  launch_cg_scalars(ctx->d, ctx->P, ctx->stream, !amg);
 }
 
 static void drop_cg_graphs(bdem_ctx *ctx) {
@@ -872,7 +873,7 @@ static int run_pcg(bdem_ctx *ctx) {
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, st);
-  launch_cg_scalars(ctx->d, ctx->P, st);
+  launch_cg_scalars(ctx->d, ctx->P, st, false);
   if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
   int rc = read_counters(ctx);
   if (rc) return rc;
@@ -1522,16 +1523,26 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
   };
   HIP_TRY(hipMemcpyAsync(d.ctl, quiet.data(), NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   launch_cg_init(d, mixed, st);
+  // update tile and SpMV shape are timed as the pair the PCG loop runs: the
+  // update's streams decide how much of the matrix the SpMV finds in cache.
+  // Shapes differ by a few percent, so each pair keeps the better of two
+  // passes over all pairs.
+  const int nu = update_variants(), nsv = spmv_variants();
+  std::vector<double> pair_us(nu * nsv, 1e300);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int vu = 0; vu < nu; ++vu)
+      for (int vs = 0; vs < nsv; ++vs) {
+        const double us = time_it([&] {
+          launch_cg_update(d, mixed, vu, st, !ctx->amg);
+          launch_spmv(d, mixed, vs, st, ctx->amg);
+        }, 20);
+        pair_us[vu * nsv + vs] = std::min(pair_us[vu * nsv + vs], us);
+      }
   double best = 1e300;
-  for (int v = 0; v < spmv_variants(); ++v) {
-    const double us = time_it([&] { launch_spmv(d, mixed, v, st); }, 5);
-    if (us < best) { best = us; ctx->spmv_variant = v; ctx->tune_us[0] = us; }
-  }
-  best = 1e300;
-  for (int v = 0; v < update_variants(); ++v) {
-    const double us = time_it([&] { launch_cg_update(d, mixed, v, st, !ctx->amg); }, 5);
-    if (us < best) { best = us; ctx->upd_variant = v; ctx->tune_us[1] = us; }
-  }
+  for (int k = 0; k < nu * nsv; ++k)
+    if (pair_us[k] < best) { best = pair_us[k]; ctx->upd_variant = k / nsv; ctx->spmv_variant = k % nsv; }
+  ctx->tune_us[0] = time_it([&] { launch_spmv(d, mixed, ctx->spmv_variant, st, ctx->amg); }, 5);
+  ctx->tune_us[1] = time_it([&] { launch_cg_update(d, mixed, ctx->upd_variant, st, !ctx->amg); }, 5);
   HIP_TRY(hipGetLastError());
   // PCG polling: each candidate runs the same solve from x = 0
   const int modes[][2] = {{1, 0}, {4, 0}, {4, 1}, {16, 1}};

@@ -27,6 +27,7 @@ namespace bdem {
 constexpr int TILE = 256;       // particles / bonds per scene-aligned tile
 constexpr int SPMV_ROWS = 32;     // block rows per SpMV workgroup
 constexpr int SPMV_CAP = 384;     // slot products held in LDS per pass of an SpMV workgroup
+constexpr int DOT_GROUP = 64;     // SpMV blocks whose (r, u), (r, r) partials one SpMV wavefront merges
 constexpr int CMAXC = 32;         // element-repulsion candidates per particle
 
 // per-scene control block, device resident; every decision of the Newton /
@@ -97,6 +98,7 @@ struct DevPtrs {
   double *cx, *cr, *cs, *cp, *cAp, *cq;
   // reductions
   double2 *part_a, *part_b, *part_c;  // per-block compensated partials
+  double2 *part_ag, *part_cg;         // part_a, part_c merged per DOT_GROUP SpMV blocks (one slot per TILE rows)
   double *part_max;                   // per-block maxima (2 per block)
   int *part_cnt;                      // per-block integer counts
   SceneCtl *ctl;                      // n_scenes
@@ -147,7 +149,7 @@ void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
 void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots = true);
 int spmv_variants();
 void spmv_shape(int variant, int *threads, int *trips);
-void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s, bool grouped);
 void launch_cg_update(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots = false);
 int update_variants();
 int update_rows(int variant);

@@ -129,9 +129,10 @@ __device__ __forceinline__ void store6(double *p, const double (&v)[6]) {
 //   alpha = gamma / (delta - beta gamma / alpha_prev);
 //   p = u + beta p;  q = w + beta q;  x += alpha p;  r -= alpha q;  u = M^-1 r.
 // One iteration = k_cg_update (also the dots r.u and r.r of the u it
-// writes), k_spmv (w = H u and the dot w.u; all three dots after k_cg_init
-// and with multigrid) and k_cg_scalars (per scene).  Buffers: cx = x, cr = r, cs = u,
-// cAp = w, cp = p, cq = q.
+// writes), k_spmv (w = H u and the dot w.u, and it merges the update's dot
+// partials in groups; all three dots after k_cg_init and with multigrid) and
+// k_cg_scalars (per scene).  Buffers: cx = x, cr = r, cs = u, cAp = w,
+// cp = p, cq = q.
 
 // r = -z, x = 0, u = M^-1 r, p = q = 0
 template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs d) {
@@ -171,7 +172,11 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // shape (NT, U) does not change a bit: threads past 6 * SPMV_ROWS add zeros
 // to the dots after the row threads' waves.  With rdots = 0 the kernel
 // leaves (r, u) and (r, r) to the CG update that produced u (and does not
-// read r); their partials are then the update's.
+// read r); their partials are then the update's, and every DOT_GROUP-th
+// workgroup of a scene merges them for the scalars step: wavefront 0 takes
+// the partials of its own block and the next DOT_GROUP - 1 (one butterfly
+// tree per group, whatever the launch shape).  The merging workgroups are
+// spread over the scene, and so over all XCDs.
 template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d, int rdots) {
   static_assert(NT >= 6 * SPMV_ROWS, "one thread per (row, component)");
   constexpr int NQ = 36 * (int)sizeof(T) / 16;       // 16-byte pieces per block
@@ -306,12 +311,36 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
       d.part_c[lb] = make_double2(rr.s, rr.c);
     }
   }
+  // the update's dot partials this workgroup merges, if any (at the end, so
+  // that their loads do not sit ahead of the block loads)
+  const int sb0 = d.scene_pbeg[scene] / SPMV_ROWS, sb1 = d.scene_pbeg[scene + 1] / SPMV_ROWS, gl = lb - sb0;
+  if (!rdots && gl % DOT_GROUP == 0 && t < 64) {   // all of wavefront 0
+    double2 ga = make_double2(0.0, 0.0), gc = make_double2(0.0, 0.0);
+    const int k = lb + t;
+    if (t < DOT_GROUP && k < sb1) {
+      ga = d.part_a[k];
+      gc = d.part_c[k];
+    }
+    const KSum a = wave_ksum(KSum{ga.x, ga.y}), c = wave_ksum(KSum{gc.x, gc.y});
+    if (t == 0) {
+      const int slot = sb0 / (TILE / SPMV_ROWS) + gl / DOT_GROUP;
+      d.part_ag[slot] = make_double2(a.s, a.c);
+      d.part_cg[slot] = make_double2(c.s, c.c);
+    }
+  }
 }
 
 // per-scene scalars of one iteration and the stop test |r| <= eps_r |z|.
 // The partial loads do not wait for the activity flag: everything the block
 // reads is issued at once, then the three sums share one LDS round.
-__global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
+// GROUPED: (r, u) and (r, r) arrive merged per DOT_GROUP blocks by the SpMV
+// (one slot per TILE rows of the scene, the first ceil(blocks / DOT_GROUP)
+// used) and (w, u) per block; otherwise all three per block.  One workgroup
+// of SCAL_THREADS per scene: a narrow workgroup starts and reduces sooner,
+// and U loads per thread cover the plate's 6,845 blocks in two trips.
+constexpr int SCAL_THREADS = 256;
+template <bool GROUPED> __global__ __launch_bounds__(SCAL_THREADS) void k_cg_scalars(DevPtrs d, Params P) {
+  static_assert(DOT_GROUP >= TILE / SPMV_ROWS && TILE % SPMV_ROWS == 0, "one grouped slot per tile at most");
   const int s = blockIdx.x;
   SceneCtl &c = d.ctl[s];
   const int b0 = d.scene_pbeg[s] / SPMV_ROWS, b1 = d.scene_pbeg[s + 1] / SPMV_ROWS;
@@ -319,23 +348,42 @@ __global__ __launch_bounds__(1024) void k_cg_scalars(DevPtrs d, Params P) {
   // the scalars the decision needs, fetched with the partials
   const double rz_prev = c.rz, alpha_prev = c.alpha, cg_tol = c.cg_tol;
   const int cg_it = c.cg_it;
+  const int t = threadIdx.x;
   KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
-  constexpr int U = 8;   // partials per thread in flight
-  for (int k0 = b0; k0 < b1; k0 += U * (int)blockDim.x) {
-    double2 pa[U], pb[U], pc[U];
-#pragma unroll
-    for (int m = 0; m < U; ++m) {
-      const int k = min(k0 + m * (int)blockDim.x + (int)threadIdx.x, b1 - 1);
-      pa[m] = d.part_a[k];
-      pb[m] = d.part_b[k];
-      pc[m] = d.part_c[k];
+  if constexpr (GROUPED) {
+    constexpr int U = 14;
+    const int g0 = b0 / (TILE / SPMV_ROWS), g1 = g0 + (b1 - b0 + DOT_GROUP - 1) / DOT_GROUP;
+    for (int k = g0 + t; k < g1; k += SCAL_THREADS) {
+      const double2 pa = d.part_ag[k], pc = d.part_cg[k];
+      ru = kmerge(ru, KSum{pa.x, pa.y});
+      rr = kmerge(rr, KSum{pc.x, pc.y});
     }
+    for (int k0 = b0; k0 < b1; k0 += U * SCAL_THREADS) {
+      double2 pb[U];
 #pragma unroll
-    for (int m = 0; m < U; ++m) {
-      if (k0 + m * (int)blockDim.x + (int)threadIdx.x >= b1) continue;
-      ru = kmerge(ru, KSum{pa[m].x, pa[m].y});
-      wu = kmerge(wu, KSum{pb[m].x, pb[m].y});
-      rr = kmerge(rr, KSum{pc[m].x, pc[m].y});
+      for (int m = 0; m < U; ++m) pb[m] = d.part_b[min(k0 + m * SCAL_THREADS + t, b1 - 1)];
+#pragma unroll
+      for (int m = 0; m < U; ++m)
+        if (k0 + m * SCAL_THREADS + t < b1) wu = kmerge(wu, KSum{pb[m].x, pb[m].y});
+    }
+  } else {
+    constexpr int U = 14;
+    for (int k0 = b0; k0 < b1; k0 += U * SCAL_THREADS) {
+      double2 pa[U], pb[U], pc[U];
+#pragma unroll
+      for (int m = 0; m < U; ++m) {
+        const int k = min(k0 + m * SCAL_THREADS + t, b1 - 1);
+        pa[m] = d.part_a[k];
+        pb[m] = d.part_b[k];
+        pc[m] = d.part_c[k];
+      }
+#pragma unroll
+      for (int m = 0; m < U; ++m) {
+        if (k0 + m * SCAL_THREADS + t >= b1) continue;
+        ru = kmerge(ru, KSum{pa[m].x, pa[m].y});
+        wu = kmerge(wu, KSum{pb[m].x, pb[m].y});
+        rr = kmerge(rr, KSum{pc[m].x, pc[m].y});
+      }
     }
   }
   // the element repulsion's share of (w, u), added after the bond SpMV
@@ -572,8 +620,9 @@ void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool 
   if (mixed) spmv_dispatch<float>(d, variant, rdots ? 1 : 0, s);
   else spmv_dispatch<double>(d, variant, rdots ? 1 : 0, s);
 }
-void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s) {
-  k_cg_scalars<<<P.n_scenes, 1024, 0, s>>>(d, P);
+void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s, bool grouped) {
+  if (grouped) k_cg_scalars<true><<<P.n_scenes, SCAL_THREADS, 0, s>>>(d, P);
+  else k_cg_scalars<false><<<P.n_scenes, SCAL_THREADS, 0, s>>>(d, P);
 }
 template <typename T> static void update_dispatch(const DevPtrs &d, int v, int rd, hipStream_t s) {
   static_assert(TILE % 128 == 0, "update tiling");
