@@ -114,3 +114,14 @@ def test_create_rejects_friction_and_bad_limits(B):
     assert _create_error(B, sc, solver=2) == -1
     assert _create_error(B, sc, integrator=2) == -1
     assert _create_error(B, sc, preconditioner=2) == -1
+
+
+def test_empty_scene_is_rejected(B):
+    """No particles: no workspace size and INVALID from create, never a launch."""
+    sc = S.make_chain(n=2)
+    for k in ("pos", "quat", "vel", "qvel", "radius", "flags", "pmat"):
+        setattr(sc, k, getattr(sc, k)[:0])
+    sc.ij = np.zeros((0, 2), dtype=np.int32)
+    assert sc.n == 0 and sc.nb == 0
+    assert B.bdem_workspace_bytes(sc, B.scene_options(sc)) == 0
+    assert _create_error(B, sc) == -1
