@@ -128,7 +128,8 @@ def run_batch(steps, warmup):
     """The 64-scene batch (992,148 particles, seeded sizes 2K-50K, per-scene
     dt): aggregate particle-steps per second of the mixed path stepping all
     scenes in one batched call, of the FP64 path batched, and of the FP64
-    path stepping the scenes one after another (each scene alone)."""
+    path stepping the scenes one after another (each scene alone).  Every
+    handle is autotuned on its own scenes first, as in the single-scene runs."""
     import torch
     from paper_2308_10459_amd import bdem as B
     from paper_2308_10459_amd import scenes as S
@@ -137,6 +138,8 @@ def run_batch(steps, warmup):
                        "per-scene dt = 50 x the period estimate", "steps": steps}
     for label, prec in (("mixed_batched", B.BDEM_PREC_MIXED), ("fp64_batched", B.BDEM_PREC_FP64)):
         sim = B.Simulator(sc, precision=prec)
+        tuning = sim.autotune(sc.dt_per_scene)
+        log(f"  batch {label} autotuned: {tuning}")
         for _ in range(warmup):
             sim.step_batched(sc.dt_per_scene)
         torch.cuda.synchronize()
@@ -154,6 +157,7 @@ def run_batch(steps, warmup):
     for s in range(len(sc.dt_per_scene)):
         m = S.subset_scenes(sc, [s])
         sim = B.Simulator(m, precision=B.BDEM_PREC_FP64)
+        sim.autotune(m.dt_per_scene)
         for _ in range(warmup):
             sim.step_batched(m.dt_per_scene)
         torch.cuda.synchronize()

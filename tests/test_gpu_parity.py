@@ -529,6 +529,30 @@ def test_batched_scenes_match_each_scene_alone(B):
     sim.close()
 
 
+def test_batched_autotune_keeps_state_and_bits(B):
+    """Autotuning a handle of several uneven scenes (each with its own dt)
+    leaves the state alone, and a batched step afterwards gives the same bits
+    as before tuning, for both precisions."""
+    batch, _ = _mini_batch()
+    for mixed in (False, True):
+        sim = make_sim(batch, mixed=mixed)
+        st = sim.get_state()
+        sim.step_batched(batch.dt_per_scene)
+        ref = sim.get_state()
+        sim.set_state(**st)
+        t = sim.autotune(batch.dt_per_scene)
+        log(f"[batched autotune] mixed={mixed} {t}")
+        assert t["spmv_us"] > 0 and t["update_us"] > 0 and t["pcg_us_per_iter"] > 0
+        after = sim.get_state()
+        for k in ("pos", "quat", "vel", "qvel", "alive"):
+            assert np.array_equal(after[k], st[k]), k
+        rc, stats = sim.step_batched(batch.dt_per_scene)
+        got = sim.get_state()
+        for k in ("pos", "quat", "vel", "qvel", "alive"):
+            assert np.array_equal(got[k], ref[k]), (mixed, k)
+        sim.close()
+
+
 def _conditioning_bound_sparse(sc, prev, ref, dt, zfloor):
     """_conditioning_bound for scenes too large for a dense inverse: the norm
     of any row block of H^-1 is at most 1 / lambda_min(H), with the smallest
