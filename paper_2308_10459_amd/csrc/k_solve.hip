@@ -453,7 +453,8 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   // keeping them out of the caches leaves room there for the SpMV's matrix
   // and u (about 255 MB against the 256 MB Infinity Cache) between
   // iterations.  u, which the SpMV gathers, is stored normally.  The FP64
-  // matrix does not fit either way and keeps plain accesses.
+  // matrix does not fit either way and keeps plain accesses (non-temporal
+  // ones there cost the update more than they gain the SpMV).
   constexpr bool NT = sizeof(T) == 4;
   auto ld = [](const auto *q) { if constexpr (NT) return __builtin_nontemporal_load(q); else return *q; };
   auto stn = [](double v, double *q) { if constexpr (NT) __builtin_nontemporal_store(v, q); else *q = v; };
