@@ -431,7 +431,9 @@ template <bool GROUPED> __global__ __launch_bounds__(SCAL_THREADS) void k_cg_sca
 
 // p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r.
 // Thread (row, component): every vector is read and written with unit
-// stride; the new residual of the row is shared through LDS for M^-1 r.
+// stride; the new residual of the row is shared through LDS for M^-1 r, and
+// the rows' Jacobi inverses are staged there with 16-byte loads (read
+// directly, each thread would issue six scattered 4-byte loads).
 // With rdots the kernel also writes the (r, u) and (r, r) partials of each
 // SPMV_ROWS-row block (the SpMV then skips them): thread (row, c) adds its
 // product, each wavefront reduces, and the block's three wavefronts merge in
@@ -458,6 +460,16 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   constexpr bool NT = sizeof(T) == 4;
   auto ld = [](const auto *q) { if constexpr (NT) return __builtin_nontemporal_load(q); else return *q; };
   auto stn = [](double v, double *q) { if constexpr (NT) __builtin_nontemporal_store(v, q); else *q = v; };
+  // the block's Jacobi inverses (ROWS x 21 T, contiguous) staged in LDS
+  // with 16-byte loads
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  constexpr int NPC = ROWS * 21 * (int)sizeof(T) / 16;
+  static_assert(ROWS * 21 * sizeof(T) % 16 == 0, "16-byte pieces");
+  __shared__ v4f dl4[NPC];
+  {
+    const v4f *src = reinterpret_cast<const v4f *>(reinterpret_cast<const T *>(d.dinv) + (size_t)r0 * 21);
+    for (int k = t; k < NPC; k += 6 * ROWS) dl4[k] = ld(src + k);
+  }
   const double x = ld(d.cx + o), rv = ld(d.cr + o), u = ld(d.cs + o), w = ld(d.cAp + o);
   const double p = ld(d.cp + o), q = ld(d.cq + o);
   const double pn = u + b * p, qn = w + b * q;
@@ -469,10 +481,10 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   stn(rn, d.cr + o);
   __syncthreads();
   const int rl = t / 6, cc = t - rl * 6;
-  const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)(r0 + rl) * 21;
+  const T *Di = reinterpret_cast<const T *>(dl4) + rl * 21;
   double un = 0.0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) un += double(ld(Di + up6(cc, k))) * rs[rl * 6 + k];
+  for (int k = 0; k < 6; ++k) un += double(Di[up6(cc, k)]) * rs[rl * 6 + k];
   d.cs[o] = un;
   if (!rdots) return;   // uniform over the launch
   constexpr int NWV = 6 * ROWS / 64;
