@@ -193,18 +193,40 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   const int row = r0 + (rowthr ? rl : 0);
   const float4 *H4 = reinterpret_cast<const float4 *>(d.hoff);
   const double *u = d.cs;
+  // the workgroup's diagonal blocks (SPMV_ROWS x 21 T) and its rows' u
+  // (SPMV_ROWS x 6 doubles), both contiguous, staged in LDS with 16-byte
+  // loads issued first and read after the first barrier (read directly,
+  // each row thread would issue six scattered loads of its block)
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  constexpr int NDG = SPMV_ROWS * 21 * (int)sizeof(T) / 16, NUR = SPMV_ROWS * 6 * 8 / 16;
+  static_assert(SPMV_ROWS * 21 * sizeof(T) % 16 == 0, "16-byte pieces");
+  __shared__ v4f dg4[NDG + NUR];
+  {
+    const v4f *sd = reinterpret_cast<const v4f *>(reinterpret_cast<const T *>(d.hdiag) + (size_t)r0 * 21);
+    const v4f *su = reinterpret_cast<const v4f *>(u + (size_t)r0 * 6);
+    for (int k = t; k < NDG; k += NT) dg4[k] = sd[k];
+    for (int k = t; k < NUR; k += NT) dg4[NDG + k] = su[k];
+  }
   double acc = 0.0, uc = 0.0, rc = 0.0;
   int rbeg = 0, rend = 0;
   if (rowthr) {
     rbeg = d.row_ptr[row];
     rend = d.row_ptr[row + 1];
-    const T *D = reinterpret_cast<const T *>(d.hdiag) + (size_t)row * 21;
-    double ur[6];
-    load6(u + (size_t)row * 6, ur);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) acc += double(D[up6(c_out, k)]) * ur[k];
-    uc = u[(size_t)row * 6 + c_out];
     if (rdots) rc = d.cr[(size_t)row * 6 + c_out];
+  }
+  // the diagonal block times u_row, added before any slot product
+  auto add_diag = [&]() {
+    if (rowthr) {
+      const T *D = reinterpret_cast<const T *>(dg4) + rl * 21;
+      const double *ur = reinterpret_cast<const double *>(dg4 + NDG) + rl * 6;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc += double(D[up6(c_out, k)]) * ur[k];
+      uc = ur[c_out];
+    }
+  };
+  if (s1 == s0) {   // no slots: uniform over the workgroup
+    __syncthreads();
+    add_diag();
   }
   for (int cb = s0; cb < s1; cb += SPMV_CAP) {
     const int ns = min(SPMV_CAP, s1 - cb);
@@ -290,6 +312,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
       }
     }
     __syncthreads();
+    if (cb == s0) add_diag();
     if (rowthr) {
       const int lo = max(rbeg, cb), hi = min(rend, cb + ns);
       for (int k = lo; k < hi; ++k) acc += prod[(k - cb) * 6 + c_out];
