@@ -1662,6 +1662,7 @@ void orc_default_options(orc_options *o) {
   o->break_bonds = 1;
   o->first_order = 0;
   o->midpoint = 0;
+  o->cg_forcing = 0;
 }
 
 int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
@@ -1747,8 +1748,10 @@ int orc_step(orc_sys *s, double dt, const orc_options *o, orc_stats *st) {
     } else {
       /* solve (Hess' f) dx = -grad f in the reduced tangent space */
       for (size_t a = 0; a < N6; ++a) rhs[a] = -z[a];
-      double res;
-      int it = orc_pcg(s, hdiag, hoff, rhs, o->cg_rtol, max_cg, y, &res);
+      double res, rt = o->cg_rtol;
+      /* Section 5.3: relative tolerance min(eps, sqrt|grad f|) when asked for */
+      if (o->cg_forcing && sqrt(zn) < rt) rt = sqrt(zn);
+      int it = orc_pcg(s, hdiag, hoff, rhs, rt, max_cg, y, &res);
       S.cg_iters += it >= 0 ? it : -it;
     }
     double slope = vdot(z, y, N6);

@@ -145,6 +145,8 @@ typedef struct {
   int32_t max_newton, max_cg, max_ls, break_bonds;
   int32_t first_order;       /* 1: Algorithm 1 (Riemannian gradient descent) instead of Algorithm 2 */
   int32_t midpoint;          /* 1: the variational midpoint objective of Section 3.1 */
+  int32_t cg_forcing;        /* 1: each linear solve stops at the relative residual
+                                min(cg_rtol, sqrt|z|) of Section 5.3 instead of cg_rtol */
 } orc_options;
 
 typedef struct {

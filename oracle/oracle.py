@@ -26,7 +26,7 @@ class Options(C.Structure):
     _fields_ = [("tol_abs", C.c_double), ("tol_rel", C.c_double), ("cg_rtol", C.c_double),
                 ("armijo_c", C.c_double), ("max_newton", C.c_int32), ("max_cg", C.c_int32),
                 ("max_ls", C.c_int32), ("break_bonds", C.c_int32), ("first_order", C.c_int32),
-                ("midpoint", C.c_int32)]
+                ("midpoint", C.c_int32), ("cg_forcing", C.c_int32)]
 
 
 class Stats(C.Structure):

@@ -487,6 +487,40 @@ def test_linear_mass_spring_chain(oracle_mod):
     np.testing.assert_allclose(o.get_state()["pos"][:, 0], ref, rtol=0, atol=1e-12 * a)
 
 
+def test_kinematic_particle_drives_its_neighbour(oracle_mod):
+    """A KINEMATIC particle (its position prescribed at t + dt, its orientation
+    held; the pulled edges of Section 6.4's beams and sheets) moves exactly
+    dt v per step and keeps its quaternion even with a quaternion rate set;
+    the free particle bonded to it along the bond axis follows the scalar
+    backward-Euler recurrence of a mass on a spring whose anchor moves:
+    m (x_{n+1} - x_n - dt v_n) / dt^2 = -k_n (x_{n+1} - a_{n+1} - l0)."""
+    O = oracle_mod
+    E, r, l0, V, dt = 1e7, 0.01, 0.02, 0.05, 1e-3
+    sc = S.make_pair(axis=(1.0, 0.0, 0.0), length=l0, r=r, young=E)
+    sc.flags[0] = S.KINEMATIC
+    sc.vel = np.array([[V, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    sc.qvel = np.array([[0.3, -0.2, 0.1, 0.0], [0.0, 0.0, 0.0, 0.0]])
+    o = O.Oracle(sc)
+    kn = E * math.pi * r * r / l0
+    m = 1000 * 4 / 3 * math.pi * r ** 3
+    x1, v1 = sc.pos[1, 0], 0.0
+    for k in range(1, 31):
+        assert o.step(dt, tol_rel=1e-14)["rc"] == 0
+        st = o.get_state()
+        anchor = sc.pos[0, 0] + k * dt * V
+        np.testing.assert_allclose(st["pos"][0], [anchor, 0.0, 0.0], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(st["vel"][0], [V, 0.0, 0.0], rtol=0, atol=1e-12)
+        np.testing.assert_array_equal(st["quat"][0], sc.quat[0])
+        assert np.all(st["qvel"][0] == 0.0)
+        x_next = (m / dt ** 2 * (x1 + dt * v1) + kn * (anchor + l0)) / (m / dt ** 2 + kn)
+        v1, x1 = (x_next - x1) / dt, x_next
+        np.testing.assert_allclose(st["pos"][1], [x1, 0.0, 0.0], rtol=0, atol=1e-13 * l0)
+        np.testing.assert_allclose(st["vel"][1, 0], v1, rtol=0, atol=1e-10 * V)
+        assert np.abs(st["quat"][1] - [0, 0, 0, 1.0]).max() <= 1e-15
+    # the neighbour has been dragged along: it moves with the anchor's speed
+    assert abs(v1 - V) < 1e-3 * V
+
+
 def test_momentum_conserved_free_cluster(oracle_mod):
     O = oracle_mod
     sc = S.make_block(nx=3, ny=3, nz=3, rot_angle=0.01)
@@ -592,6 +626,36 @@ def test_fracture_decision_is_strict_and_permanent(oracle_mod):
         o.set_state(pos=sc.pos)
         assert o.break_bonds() == 0
         assert o.get_state()["alive"][0] == 1 - expect   # no healing
+
+
+def test_tension_only_bond_ignores_compression(oracle_mod):
+    """Section 3.3 with the tension-only option: a compressed and bent bond
+    has sigma from bending alone, E sin(phi/2) r / l0, where the plain bond
+    adds E |delta| / l0; under tension both count the stretch.  The fracture
+    decision follows: a threshold between the two values breaks the plain
+    bond and spares the tension-only one under compression, and breaks both
+    under the same stretch in tension."""
+    O = oracle_mod
+    E, r, l0, phi, delta = 1e7, 0.01, 0.02, 0.01, 2e-5
+    d0 = _unit([0.3, 1.0, 0.2])
+    b = _unit(np.cross(d0, [1.0, 0, 0]))
+    q = np.stack([_axis_angle(b, phi / 2), _axis_angle(b, -phi / 2)])
+    bend = E * math.sin(phi / 2) * r / l0
+    axial = E * delta / l0
+    for tension_only in (0, 1):
+        sc, o = _pair_oracle(O, axis=d0, young=E, tension_only=tension_only)
+        for sign in (-1.0, 1.0):
+            pos = sc.pos.copy()
+            pos[1] += sign * delta * d0
+            s_, t_ = o.bond_stress(0, pos, q)
+            expect = bend if (tension_only and sign < 0) else bend + axial
+            np.testing.assert_allclose(s_, expect, rtol=1e-9)
+            assert t_ < 1e-8 * s_
+            sc2 = S.make_pair(axis=d0, length=l0, young=E, tension_only=tension_only,
+                              sigma_c=bend + 0.5 * axial, tau_c=0.0)
+            o2 = O.Oracle(sc2)
+            o2.set_state(pos=pos, quat=q)
+            assert o2.break_bonds() == (0 if (tension_only and sign < 0) else 1)
 
 
 # --------------------------------------------------------------------------
@@ -1084,6 +1148,65 @@ def test_sliding_and_rolling_friction_on_the_ground(oracle_mod):
                                    atol=2e-6 * w0)
         assert abs(st["pos"][0, 2] - sc.pos[0, 2]) <= 1e-12
     assert vx == 0.0 and w[2] == 0.0
+
+
+def _sphere_on_sphere(O, lower_flag, k=1e4, r=0.01, g=9.81):
+    """A free sphere resting on another sphere (fixed or kinematic) at the
+    overlap where the repulsion carries its weight, so F_n = m g."""
+    m = 1000 * 4 / 3 * math.pi * r ** 3
+    sc = _loose_spheres([[0, 0, 0], [0, 0, 2 * r - m * g / k]], r=r, gravity=(0.0, 0.0, -g))
+    sc.flags[0] = lower_flag
+    sc.k_self = k
+    return sc, m
+
+
+def test_pair_rolling_friction_stops_a_spin(oracle_mod):
+    """Section 5.4 between two spheres: the upper one, resting on a fixed
+    sphere (F_n = m g through the repulsion), spins about the contact normal;
+    each step removes mu_r F_n r dt / I = 2.5 mu_r g dt / r of the relative
+    spin until it stops at exactly zero, and its centre does not move."""
+    O = oracle_mod
+    r, g, dt, w0, mu_r = 0.01, 9.81, 1e-3, 0.5, 0.005
+    sc, m = _sphere_on_sphere(O, S.FIXED, r=r, g=g)
+    sc.mu_s, sc.mu_r = 0.3, mu_r
+    sc.qvel = np.array([[0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.5 * w0, 0.0]])
+    o = O.Oracle(sc)
+    for k in range(1, 46):
+        assert o.step(dt, tol_rel=1e-14)["rc"] == 0
+        st = o.get_state()
+        q, qd = st["quat"][1], st["qvel"][1]
+        w = 2 * O.quat_mul(qd, np.array([-q[0], -q[1], -q[2], q[3]]))[:3]
+        np.testing.assert_allclose(w[2], max(0.0, w0 - k * 2.5 * mu_r * g * dt / r), rtol=0,
+                                   atol=2e-6 * w0)
+        assert np.abs(st["pos"][1] - sc.pos[1]).max() <= 1e-12
+        assert len(o.contacts()) == 1
+    assert w[2] == 0.0
+
+
+def test_pair_sliding_friction_acts_on_the_relative_velocity(oracle_mod):
+    """Section 5.4 between two spheres: the lower sphere is kinematic and
+    moves sideways at V_a; the upper one rests on it (F_n = m g) and slides
+    at V_a + v0.  Friction removes mu_s F_n dt / m = mu_s g dt of the relative
+    tangential speed per step until the two move together, then the upper
+    sphere keeps the lower one's speed (friction uses the relative velocity,
+    not the sphere's own).  The bound allows for the contact normal tilting
+    by the 1.5 um the spheres slide against each other (the tangential pull
+    of gravity there is g * 8e-5 per unit time)."""
+    O = oracle_mod
+    r, g, dt, Va, v0, mu_s = 0.01, 9.81, 1e-4, 0.02, 3e-3, 0.3
+    sc, m = _sphere_on_sphere(O, S.KINEMATIC, r=r, g=g)
+    sc.mu_s, sc.mu_r = mu_s, 0.0
+    sc.vel = np.array([[Va, 0.0, 0.0], [Va + v0, 0.0, 0.0]])
+    o = O.Oracle(sc)
+    stopped = 0
+    for k in range(1, 16):
+        assert o.step(dt, tol_rel=1e-14)["rc"] == 0
+        st = o.get_state()
+        expect = Va + max(0.0, v0 - k * mu_s * g * dt)
+        np.testing.assert_allclose(st["vel"][1, 0], expect, rtol=0, atol=1e-6)
+        np.testing.assert_allclose(st["vel"][0], [Va, 0.0, 0.0], rtol=0, atol=1e-12)
+        stopped += expect == Va
+    assert stopped >= 4
 
 
 def test_contact_objective_derivatives_along_geodesics(oracle_mod):
