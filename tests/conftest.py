@@ -18,3 +18,17 @@ def oracle_mod():
     from oracle import oracle as O
     O.lib()
     return O
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Every bounded parity comparison of the run, with its error and bound."""
+    try:
+        from tests.gpu_helpers import BOUNDS
+    except Exception:
+        return
+    if not BOUNDS:
+        return
+    tr = terminalreporter
+    tr.section("parity errors and their bounds")
+    for test, what, err, bound in BOUNDS:
+        tr.write_line(f"{err:9.2e} <= {bound:9.2e}  {what}  [{test}]")

@@ -8,9 +8,21 @@ import numpy as np
 from oracle.oracle import Oracle
 
 
+# (test, comparison, error, bound) of every bounded comparison made in this
+# process; printed in the terminal summary, so that a run's log shows how far
+# each result was from its bound even when every test passes
+BOUNDS = []
+
+
 def log(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+def record_bound(what, err, bound):
+    import os
+    test = os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
+    BOUNDS.append((test, what, float(err), float(bound)))
 
 
 def make_sim(scene, mixed=False, **opts):

@@ -17,8 +17,8 @@ import numpy as np
 import pytest
 
 from paper_2308_10459_amd import scenes as S
-from tests.gpu_helpers import (log, make_sim, oracle_for, quat_angle_err, row_scale,
-                               sampled_oracle_egh)
+from tests.gpu_helpers import (log, make_sim, oracle_for, quat_angle_err, record_bound,
+                               row_scale, sampled_oracle_egh)
 
 pytestmark = pytest.mark.gpu
 
@@ -161,19 +161,28 @@ def _compare_states(sc, got, ref, prev, tol, tag, rot_abs=1e-12, ref2=None, cond
         qtol = max(qtol, cond[1] / max(np.linalg.norm(rot), 1e-300))
     log(f"  {tag}: pos rel err {perr:.2e} (disp {disp:.3e}, bound {ptol:.1e})  rot rel err "
         f"{qrel:.2e} (bound {qtol:.1e})")
+    record_bound(f"{tag}: positions / displacement (stated {tol:.0e})", perr, ptol)
     assert perr <= ptol
+    if qrel <= qtol:
+        record_bound(f"{tag}: rotation error / step rotation (stated {tol:.0e})", qrel, qtol)
+    else:
+        record_bound(f"{tag}: max rotation error, absolute (step rotation below resolution)",
+                     np.abs(qerr).max(), rot_abs)
     assert qrel <= qtol or np.abs(qerr).max() <= rot_abs
     assert np.abs(np.linalg.norm(got["quat"], axis=1) - 1.0).max() <= 4.5e-16
 
 
+@pytest.mark.parametrize("hessian", ["gauss_newton", "eigen_clamp"])
 @pytest.mark.parametrize("mixed", [False, True])
-def test_step_block_1000(B, mixed):
+def test_step_block_1000(B, mixed, hessian):
     """The 1000-particle simple-cubic block (gravity, fixed bottom layer,
-    seeded 1e-3 rad rotations), 10 steps of dt = 1e-3."""
-    log(f"[step block] mixed={mixed}")
+    seeded 1e-3 rad rotations), 10 steps of dt = 1e-3, with either PSD form of
+    the bond Hessians (the fixed point is the same)."""
+    log(f"[step block] mixed={mixed} hessian={hessian}")
     sc = S.make_block()
     o = oracle_for(sc)
-    sim = make_sim(sc, mixed=mixed, **TIGHT)
+    hs = B.BDEM_HESS_GAUSS_NEWTON if hessian == "gauss_newton" else B.BDEM_HESS_EIGEN_CLAMP
+    sim = make_sim(sc, mixed=mixed, hessian=hs, **TIGHT)
     tol = 1e-5 if mixed else 1e-8
     prev = o.get_state()
     for k in range(10):
@@ -181,7 +190,8 @@ def test_step_block_1000(B, mixed):
         sg = sim.step(sc.dt)
         ref, got = o.get_state(), sim.get_state()
         assert sg["rc"] == 0, sg
-        _compare_states(sc, got, ref, prev, tol, f"step {k} newton {sg['newton_iters']} cg {sg['cg_iters']}")
+        _compare_states(sc, got, ref, prev, tol, f"block {hessian} mixed={mixed} step {k} newton "
+                        f"{sg['newton_iters']} cg {sg['cg_iters']}")
         np.testing.assert_allclose(got["vel"], ref["vel"], rtol=0,
                                    atol=tol * np.abs(ref["vel"]).max() * 10 + 1e-14)
         # the energy at the accepted state, evaluated by the oracle, agrees
@@ -233,6 +243,79 @@ def test_step_sheet_kinematic_edges(B):
         np.testing.assert_array_equal(got["pos"][kin], ref["pos"][kin])
         prev = ref
     sim.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_notched_sheet_tears_like_the_oracle(B, mixed):
+    """The textile workload's tearing with fracture on, at a size the oracle
+    steps in seconds: a 20x12 one-layer sheet with a notch over a quarter of
+    its height, its edge columns pulled apart at 2 m/s (kinematic), dt = 5e-5
+    as in the full-size sheet.  Thresholds sit near the 95th percentiles of
+    the oracle's bond stresses after three steps (certified: no stress of that
+    state within 1e-3 of them), so the first steps break nothing and the
+    later ones tear.  Every step is compared as a one-step map from the GPU's
+    state (positions, orientations, objective) and its broken set bit-exact
+    on the bonds whose oracle stresses are certified (Section 3.3)."""
+    log(f"[notched sheet] mixed={mixed}")
+    sc = S.make_textile(nx=20, ny=12, sigma_c=0.0, tau_c=0.0, dt=5e-5, notch=0.25)
+    o = oracle_for(sc)
+    for _ in range(3):
+        o.step(sc.dt, tol_rel=0.0, max_newton=300, break_bonds=0)
+    s3 = o.get_state()
+    sig, tau = o.stresses(s3["pos"], s3["quat"])
+    sc.materials[0]["sigma_c"], sc.materials[0]["tau_c"] = _certified_thresholds(sig, tau, 0.05)
+    sim = make_sim(sc, mixed=mixed, **TIGHT)
+    tol = 1e-5 if mixed else 1e-8
+    broken = []
+    for k in range(6):
+        prev = sim.get_state()
+        o = oracle_for(sc, prev)
+        so = o.step(sc.dt, tol_rel=0.0, max_newton=300)
+        sg = sim.step(sc.dt)
+        ref, got = o.get_state(), sim.get_state()
+        assert sg["rc"] == 0, sg
+        tag = f"notched sheet mixed={mixed} step {k} broken {so['bonds_broken']}"
+        # torn-off pieces of a sheet with 1e-2 bend / twist stiffness turn
+        # almost freely: the step's fixed point is then determined only to the
+        # conditioning of its Hessian (bound from the oracle's own Hessian)
+        cond = _conditioning_bound(sc, prev, ref, sc.dt, max(so["grad_final"], sg["grad_final"]))
+        _compare_states(sc, got, ref, prev, tol, tag, rot_abs=2e-9, ref2=_loose_step(sc, prev, sc.dt),
+                        cond=cond)
+        perr = abs(sg["phi"] - so["phi"]) / abs(so["phi"])
+        record_bound(f"{tag}: objective at the new state, relative", perr, 1e-6 if mixed else 1e-10)
+        assert perr <= (1e-6 if mixed else 1e-10), (sg["phi"], so["phi"])
+        sg_, ta_ = o.stresses(ref["pos"], ref["quat"])
+        m = sc.materials[0]
+        safe = (np.abs(sg_ / m["sigma_c"] - 1) >= 1e-3) & (np.abs(ta_ / m["tau_c"] - 1) >= 1e-3)
+        np.testing.assert_array_equal(got["alive"][safe], ref["alive"][safe])
+        log(f"  step {k}: oracle broke {so['bonds_broken']}, gpu {sg['bonds_broken']}, "
+            f"uncertified {np.count_nonzero(~safe & (prev['alive'] != 0))}")
+        broken.append(so["bonds_broken"])
+    assert sum(broken) > 0 and broken[0] == 0
+    sim.close()
+
+
+def test_textile_at_the_longer_step_stops_converging(B):
+    """Why the full-size textile runs at dt = 5e-5: at the 5e-4 the workload was
+    first specified with (about 600 times the Section 5.1 period estimate;
+    the paper recommends 20-100) the sheet tears within its first ~20 steps
+    and from then on the Newton iteration no longer reaches its tolerance in
+    50 iterations (BDEM_W_NOT_CONVERGED: torn pieces with 1e-2 bend / twist
+    stiffness spin far within one step), later also without any descent
+    (BDEM_W_LS_FAILED).  Checked: converged steps first, then the warning,
+    and bonds broken by then."""
+    sc = S.make_textile(dt=5e-4)
+    sim = make_sim(sc, mixed=True)
+    rcs, broken = [], 0
+    for k in range(40):
+        st = sim.step(sc.dt)
+        rcs.append(st["rc"])
+        broken += st["bonds_broken"]
+    sim.close()
+    log(f"[textile dt 5e-4] return codes {rcs}, bonds broken {broken}")
+    assert all(rc == B.BDEM_OK for rc in rcs[:10])
+    assert B.BDEM_W_NOT_CONVERGED in rcs[15:]
+    assert broken > 0
 
 
 def test_prediction_outside_the_domain_restarts_from_the_state(B):
@@ -497,23 +580,41 @@ def _mini_batch():
     return batch, members
 
 
-def test_batched_scenes_match_each_scene_alone(B):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_scenes_match_each_scene_alone(B, mixed):
+    """Four uneven scenes, each with its own dt, stepped together by
+    bdem_step_batched (Algorithm 3 per scene) on either path, against the
+    oracle run on each scene alone: positions and orientations at the step
+    tolerance of the path, the objective Phi(x_{n+1}) of every scene within
+    1e-6 (mixed) or 1e-10 (FP64), and the broken-bond set of the plate,
+    whose thresholds are certified against the oracle's stresses, bit-exact."""
     batch, members = _mini_batch()
     # the ground stiffness of a batch is E_max r_max over all scenes: give every
     # member that value explicitly
     kc = max(m["young"] for m in batch.materials) * batch.radius.max()
     batch.k_contact = kc
-    sim = make_sim(batch, **TIGHT)
-    oracles = []
     for m, _ in members:
         m.k_contact = kc
         m.gravity = batch.gravity
-        oracles.append(oracle_for(m))
+    # the plate (member 2) breaks: thresholds near the 95th percentiles of its
+    # oracle stresses after the first step, moved until every stress is at
+    # least 1e-3 away from them (the material dict is shared with the batch)
+    plate, pdt = members[2]
+    o = oracle_for(plate)
+    o.step(pdt, tol_rel=0.0, max_newton=300, break_bonds=0)
+    s1 = o.get_state()
+    sig, tau = o.stresses(s1["pos"], s1["quat"])
+    plate.materials[0]["sigma_c"], plate.materials[0]["tau_c"] = _certified_thresholds(sig, tau, 0.05)
+    sim = make_sim(batch, mixed=mixed, **TIGHT)
+    oracles = [oracle_for(m) for m, _ in members]
     starts = [o.get_state() for o in oracles]
+    tol = 1e-5 if mixed else 1e-8
+    ptol = 1e-6 if mixed else 1e-10
+    broken_total = 0
     for k in range(2):
         rc, stats = sim.step_batched(batch.dt_per_scene)
         got = sim.get_state()
-        off = 0
+        off, boff = 0, 0
         for s, ((m, dt), o) in enumerate(zip(members, oracles)):
             loose = _loose_step(m, starts[s], dt)
             so = o.step(dt, tol_rel=0.0, max_newton=300)
@@ -521,11 +622,30 @@ def test_batched_scenes_match_each_scene_alone(B):
             cond = _conditioning_bound(m, starts[s], ref, dt, max(so["grad_final"], stats[s]["grad_final"]))
             sl = slice(off, off + m.n)
             sub = {kk: got[kk][sl] for kk in ("pos", "quat", "vel", "qvel")}
-            _compare_states(m, sub, ref, starts[s], 1e-8,
-                            f"batch step {k} scene {s} newton {stats[s]['newton_iters']}", ref2=loose,
-                            cond=cond)
+            tag = f"batch mixed={mixed} step {k} scene {s} newton {stats[s]['newton_iters']}"
+            assert stats[s]["status"] == 0, stats[s]
+            _compare_states(m, sub, ref, starts[s], tol, tag, ref2=loose, cond=cond)
+            perr = abs(stats[s]["phi"] - so["phi"]) / abs(so["phi"])
+            record_bound(f"{tag}: objective at the new state, relative", perr, ptol)
+            assert perr <= ptol, (stats[s]["phi"], so["phi"])
+            alive = got["alive"][boff:boff + m.nb]
+            if m.materials[0]["sigma_c"] > 0:
+                sg_, ta_ = o.stresses(ref["pos"], ref["quat"])
+                mm = m.materials[0]
+                safe = (np.abs(sg_ / mm["sigma_c"] - 1) >= 1e-3) & (np.abs(ta_ / mm["tau_c"] - 1) >= 1e-3)
+                if k == 0:
+                    assert safe.all()
+                np.testing.assert_array_equal(alive[safe], ref["alive"][safe])
+                if safe.all():
+                    assert stats[s]["bonds_broken"] == so["bonds_broken"]
+                broken_total += so["bonds_broken"]
+            else:
+                assert alive.all()
             starts[s] = ref
             off += m.n
+            boff += m.nb
+    log(f"  broken bonds in the plate: {broken_total}")
+    assert broken_total > 0
     sim.close()
 
 
@@ -577,16 +697,19 @@ def _conditioning_bound_sparse(sc, prev, ref, dt, zfloor):
     return inv * 10 * zfloor, inv * 10 * zfloor * 2.0
 
 
-def test_full_batch_sampled_scenes(B):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_full_batch_sampled_scenes(B, mixed):
     """The 64-scene batch at full size (992,148 particles, 4,009,869 bonds,
-    per-scene dt and ground stiffness) stepped once in one batched call on the
-    FP64 path; the smallest box, beam and plate against the oracle run on each
-    scene alone."""
+    per-scene dt and ground stiffness) stepped once in one batched call, on
+    the FP64 path and on the mixed path the batched benchmark runs; the
+    smallest box, beam and plate against the oracle run on each scene alone
+    (positions and orientations at the path's step tolerance, the objective
+    within 1e-6 mixed or 1e-10 FP64)."""
     sc = S.make_batch()
     sizes = np.bincount(sc.scene_id)
     picks = [min((s for s in range(64) if s % 3 == shape), key=lambda k: sizes[k]) for shape in range(3)]
-    log(f"[full batch] n={sc.n} nb={sc.nb} sampled scenes {picks}")
-    sim = make_sim(sc, **TIGHT)
+    log(f"[full batch] mixed={mixed} n={sc.n} nb={sc.nb} sampled scenes {picks}")
+    sim = make_sim(sc, mixed=mixed, **TIGHT)
     start = sim.get_state()
     rc, stats = sim.step_batched(sc.dt_per_scene)
     got = sim.get_state()
@@ -608,8 +731,12 @@ def test_full_batch_sampled_scenes(B):
                                           max(so["grad_final"], stats[s]["grad_final"]))
         sub = {k: got[k][sel] for k in ("pos", "quat", "vel", "qvel")}
         assert stats[s]["status"] == 0, stats[s]
-        _compare_states(m, sub, ref, prev, 1e-8, f"scene {s} (n={m.n}) newton {stats[s]['newton_iters']} "
-                        f"cg {stats[s]['cg_iters']}", ref2=loose, cond=cond)
+        tag = f"full batch mixed={mixed} scene {s} (n={m.n}) newton {stats[s]['newton_iters']} " \
+              f"cg {stats[s]['cg_iters']}"
+        _compare_states(m, sub, ref, prev, 1e-5 if mixed else 1e-8, tag, ref2=loose, cond=cond)
+        perr = abs(stats[s]["phi"] - so["phi"]) / abs(so["phi"])
+        record_bound(f"{tag}: objective at the new state, relative", perr, 1e-6 if mixed else 1e-10)
+        assert perr <= (1e-6 if mixed else 1e-10), (stats[s]["phi"], so["phi"])
 
 
 # --------------------------------------------------------------------------
@@ -845,7 +972,8 @@ def test_midpoint_step_block_1000(B, mixed):
         sg = sim.step(sc.dt)
         ref, got = o.get_state(), sim.get_state()
         assert sg["rc"] == 0 and so["rc"] == 0, (sg, so)
-        _compare_states(sc, got, ref, prev, tol, f"step {k} newton {sg['newton_iters']} cg {sg['cg_iters']}")
+        _compare_states(sc, got, ref, prev, tol, f"midpoint block mixed={mixed} step {k} newton "
+                        f"{sg['newton_iters']} cg {sg['cg_iters']}")
         np.testing.assert_allclose(got["vel"], ref["vel"], rtol=0,
                                    atol=tol * np.abs(ref["vel"]).max() * 10 + 1e-14)
         assert abs(sg["phi"] - so["phi"]) <= (1e-6 if mixed else 1e-10) * abs(so["phi"])
