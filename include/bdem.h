@@ -71,8 +71,12 @@ enum {
   BDEM_EGH_E = 1,              /* energy */
   BDEM_EGH_G = 2,              /* reduced gradient */
   BDEM_EGH_H = 4,              /* reduced Hessian blocks */
-  BDEM_EGH_PSD = 8,            /* PSD-project the Hessian (Section 5.2) */
-  BDEM_EGH_POTENTIAL_ONLY = 16 /* V only: no inertia term */
+  BDEM_EGH_PSD = 8,            /* PSD-project the Hessian (Section 5.2): per-bond eigen-clamp */
+  BDEM_EGH_POTENTIAL_ONLY = 16, /* V only: no inertia term */
+  BDEM_EGH_GN = 32,            /* with BDEM_EGH_H: the Gauss-Newton form of the bond Hessians
+                                  (PSD by construction, see bdem_options.hessian) */
+  BDEM_EGH_PCG_MATRIX = 64     /* with BDEM_EGH_H | BDEM_EGH_PSD: the form the handle's PCG
+                                  iterates on (bdem_options.hessian) */
 };
 
 /* Particles (Section 3.1: state x = {p, q}, extended mass from m and r). */
@@ -151,6 +155,17 @@ typedef struct {
                               post-smoothing; a dense exact solve on the last level.  Built from
                               the diagonal and bond blocks (not the element-repulsion couplings);
                               its hierarchy is allocated by bdem_create, outside the workspace */
+  int32_t hessian;         /* PSD form of the bond Hessians the Newton step solves with
+                              (Section 5.2 asks only for a PSD matrix; the fixed point is that of
+                              the exact gradient either way): BDEM_HESS_EIGEN_CLAMP: the exact
+                              reduced 12x12 bond Hessian with its negative eigenvalues set to
+                              zero; BDEM_HESS_GAUSS_NEWTON (default): stretch exact with its
+                              (1 - l0/l) factor clamped at 0, shear and bend/twist in
+                              Gauss-Newton form (J^T W J, the second derivatives of the shear
+                              residual and the bend/twist cross term dropped), the bond's
+                              Weingarten share kept only where positive; PSD term by term and
+                              equal to the exact Hessian at zero strain.  It is evaluated by one
+                              row-parallel kernel (no per-slot halves in memory) */
 } bdem_options;
 
 typedef struct {
@@ -177,10 +192,12 @@ typedef struct {
 enum { BDEM_SOLVER_NEWTON = 0, BDEM_SOLVER_FIRST_ORDER = 1 };
 enum { BDEM_INTEGRATOR_EULER = 0, BDEM_INTEGRATOR_MIDPOINT = 1 };
 enum { BDEM_PRECOND_BLOCK_JACOBI = 0, BDEM_PRECOND_AMG = 1 };
+enum { BDEM_HESS_EIGEN_CLAMP = 0, BDEM_HESS_GAUSS_NEWTON = 1 };
 
 /* Defaults: gravity (0,0,-9.81), no ground, newton_tol 0, newton_rtol 1e-8,
  * armijo_c 1e-4, cg_rtol_max 0.5, max_newton 50, max_cg 2000, max_ls 30,
- * FP64, fracture on, cg_chunk 16, no graph, Newton solver, implicit-Euler form. */
+ * FP64, fracture on, cg_chunk 16, no graph, Newton solver, implicit-Euler form,
+ * block-Jacobi preconditioner, Gauss-Newton bond Hessians. */
 void bdem_default_options(bdem_options *opt);
 
 /* Device bytes bdem_create needs for this problem (0 on invalid input). */
@@ -269,10 +286,12 @@ int bdem_set_tuning(bdem_ctx *ctx, const bdem_tuning *tuning);
 /* Sizes of the handle's problem. */
 int bdem_sizes(const bdem_ctx *ctx, int32_t *n, int64_t *nb, int32_t *n_scenes);
 
-/* Measurement hook: when enabled, HIP events bracket every bond-evaluation
- * and SpMV launch of bdem_step (graphs are not used meanwhile); the summed
- * kernel milliseconds land in bdem_step_stats.t_ms[6] (bond) and t_ms[7]
- * (SpMV) and the launch counts of the last step in bdem_profile_counts. */
+/* Measurement hook.  enable = 1: HIP events bracket every bond-evaluation
+ * and SpMV launch of bdem_step (the PCG then issues plain launches, no graph);
+ * enable = 2: only the bond-evaluation launches are bracketed and the PCG
+ * runs as tuned; 0: off.  The summed kernel milliseconds land in
+ * bdem_step_stats.t_ms[6] (bond) and t_ms[7] (SpMV) and the launch counts of
+ * the last step in bdem_profile_counts.  Errors: INVALID (other levels). */
 int bdem_set_profiling(bdem_ctx *ctx, int32_t enable);
 int bdem_profile_counts(const bdem_ctx *ctx, int32_t *bond_launches, int32_t *spmv_launches);
 

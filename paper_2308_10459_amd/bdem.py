@@ -29,6 +29,8 @@ BDEM_SOLVER_NEWTON, BDEM_SOLVER_FIRST_ORDER = 0, 1
 BDEM_INTEGRATOR_EULER, BDEM_INTEGRATOR_MIDPOINT = 0, 1
 BDEM_PRECOND_BLOCK_JACOBI, BDEM_PRECOND_AMG = 0, 1
 BDEM_EGH_E, BDEM_EGH_G, BDEM_EGH_H, BDEM_EGH_PSD, BDEM_EGH_POTENTIAL_ONLY = 1, 2, 4, 8, 16
+BDEM_EGH_GN, BDEM_EGH_PCG_MATRIX = 32, 64
+BDEM_HESS_EIGEN_CLAMP, BDEM_HESS_GAUSS_NEWTON = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)
@@ -59,7 +61,8 @@ class bdem_options(C.Structure):
                 ("armijo_c", C.c_double), ("cg_rtol_max", C.c_double), ("max_newton", C.c_int32),
                 ("max_cg", C.c_int32), ("max_ls", C.c_int32), ("precision", C.c_int32),
                 ("break_each_step", C.c_int32), ("cg_chunk", C.c_int32), ("use_graph", C.c_int32),
-                ("solver", C.c_int32), ("integrator", C.c_int32), ("preconditioner", C.c_int32)]
+                ("solver", C.c_int32), ("integrator", C.c_int32), ("preconditioner", C.c_int32),
+                ("hessian", C.c_int32)]
 
 
 class bdem_step_stats(C.Structure):

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libbdem.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["bdem_capi.cpp", "bdem_amg.cpp", "k_bond.hip", "k_particle.hip", "k_solve.hip",
-           "k_contact.hip", "k_amg.hip"]
+           "k_contact.hip", "k_amg.hip", "k_rows.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -185,7 +185,7 @@ struct bdem_ctx {
   double tune_us[3] = {0.0, 0.0, 0.0};      // measured SpMV, update, PCG-iteration times
   hipGraphExec_t cg_exec[2] = {nullptr, nullptr};
   hipGraph_t cg_graph[2] = {nullptr, nullptr};
-  // profiling: events around the bond and SpMV kernels
+  // profiling: 1 = events around the bond and SpMV kernels, 2 = around the bond kernels only
   int profiling = 0;
   int trace = 0;                 // BDEM_TRACE=1: one line per Newton iteration of scene 0
   std::vector<hipEvent_t> ev_pool;
@@ -235,6 +235,7 @@ extern "C" void bdem_default_options(bdem_options *o) {
   o->k_self = 0.0;
   o->contact_margin = -1.0;
   o->preconditioner = BDEM_PRECOND_BLOCK_JACOBI;
+  o->hessian = BDEM_HESS_GAUSS_NEWTON;
 }
 
 extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
@@ -408,6 +409,8 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     return fail(nullptr, BDEM_E_INVALID, "preconditioner must be BDEM_PRECOND_BLOCK_JACOBI or BDEM_PRECOND_AMG");
   if (o.integrator != BDEM_INTEGRATOR_EULER && o.integrator != BDEM_INTEGRATOR_MIDPOINT)
     return fail(nullptr, BDEM_E_INVALID, "integrator must be BDEM_INTEGRATOR_EULER or BDEM_INTEGRATOR_MIDPOINT");
+  if (o.hessian != BDEM_HESS_EIGEN_CLAMP && o.hessian != BDEM_HESS_GAUSS_NEWTON)
+    return fail(nullptr, BDEM_E_INVALID, "hessian must be BDEM_HESS_EIGEN_CLAMP or BDEM_HESS_GAUSS_NEWTON");
   if (o.max_newton < 0 || o.max_cg <= 0 || o.max_ls < 0 || o.cg_chunk <= 0)
     return fail(nullptr, BDEM_E_INVALID, "bad iteration limits");
   // ---- validation ----
@@ -820,6 +823,36 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
   ctx->ev_used = 0;
 }
 
+// Gradient (and Hessian) of every active scene at the Newton iterate, and the
+// partials the Newton check reads.  With the Gauss-Newton Hessian one
+// row-parallel kernel forms gradient, blocks and inverse; the objective of a
+// step's first iterate then comes from the energy pass (later iterates take
+// the value of the line-search trial they accepted).  Otherwise the
+// bond-parallel kernels evaluate the exact reduced Hessian, eigen-clamped per
+// bond when psd, and the particle kernel assembles it.
+static bool rows_path(const bdem_ctx *ctx, bool hess) {
+  return hess && ctx->opt.hessian == BDEM_HESS_GAUSS_NEWTON;
+}
+static void launch_evaluation(bdem_ctx *ctx, bool hess, bool psd, bool first, bool pot) {
+  const DevPtrs &d = ctx->d;
+  hipStream_t st = ctx->stream;
+  const bool mixed = ctx->S.mixed, mid = ctx->P.midpoint != 0;
+  if (rows_path(ctx, hess)) {
+    if (first) {
+      launch_bond_energy(d, false, mid, st);
+      launch_particle_energy(d, ctx->P, pot, st);
+    }
+    prof_mark(ctx, 0, true);
+    launch_rows_eval(d, ctx->P, mixed, mid, pot, st);
+    prof_mark(ctx, 0, false);
+  } else {
+    prof_mark(ctx, 0, true);
+    launch_bond_eval(d, mixed, psd, hess, mid, st);
+    prof_mark(ctx, 0, false);
+    launch_particle_eval(d, ctx->P, mixed, hess, pot, st);
+  }
+}
+
 // one PCG iteration: update, SpMV with the three dots, per-scene scalars
 static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   const bool mixed = ctx->S.mixed;
@@ -869,9 +902,9 @@ static int run_pcg(bdem_ctx *ctx) {
   ctx->h_counters[5] = 1;
   launch_cg_init(ctx->d, mixed, st);
   if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, st);
-  if (ctx->profiling) prof_mark(ctx, 1, true);
+  if (ctx->profiling == 1) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
-  if (ctx->profiling) prof_mark(ctx, 1, false);
+  if (ctx->profiling == 1) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, st);
   launch_cg_scalars(ctx->d, ctx->P, st, false);
   if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
@@ -879,7 +912,7 @@ static int run_pcg(bdem_ctx *ctx) {
   if (rc) return rc;
   if (ctx->h_counters[1] == 0) return BDEM_OK;
   const int chunk = std::max(1, ctx->opt.cg_chunk);
-  const bool graph = ctx->opt.use_graph && st != nullptr && !ctx->profiling;
+  const bool graph = ctx->opt.use_graph && st != nullptr && ctx->profiling != 1;
   if (graph && !ctx->cg_exec[0]) {
     rc = build_cg_graphs(ctx, chunk);
     if (rc) return rc;
@@ -891,7 +924,7 @@ static int run_pcg(bdem_ctx *ctx) {
     if (graph) {
       HIP_TRY(hipGraphLaunch(ctx->cg_exec[slot], st));
     } else {
-      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling != 0);
+      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling == 1);
       if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, slot, st);
     }
     HIP_TRY(hipEventRecord(ctx->ev_slot[slot], st));
@@ -902,7 +935,7 @@ static int run_pcg(bdem_ctx *ctx) {
     pending = slot;
   }
   HIP_TRY(hipStreamSynchronize(st));
-  if (ctx->profiling && !graph) {
+  if (ctx->profiling == 1 && !graph) {
     // SpMV launches issued after every scene had converged returned at once:
     // keep the timings of the first 1 + max(cg_it) launches of this solve
     std::vector<SceneCtl> after(ctx->S.n_scenes);
@@ -984,12 +1017,9 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
   for (int k = 0; k <= ctx->opt.max_newton + 1; ++k) {
     HIP_TRY(hipEventRecord(ph[1], st));
     const bool hess = !ctx->P.first_order;   // Algorithm 1 needs the gradient only
-    prof_mark(ctx, 0, true);
-    launch_bond_eval(d, mixed, true, hess, ctx->P.midpoint != 0, st);
-    prof_mark(ctx, 0, false);
-    launch_particle_eval(d, ctx->P, mixed, hess, false, st);
+    launch_evaluation(ctx, hess, true, k == 0, false);
     if (hess && ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
-    launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, st);
+    launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, rows_path(ctx, hess), st);
     launch_count_active(d, NS, 0, st);
     int rc = read_counters(ctx);
     if (rc) return rc;
@@ -1261,9 +1291,18 @@ extern "C" int bdem_energy_grad_hess(bdem_ctx *ctx, double dt, int32_t what, con
   launch_copy_state_to_iterate(d, st);
   if (pos_eval && (rc = upload4(ctx, d.px, pos_eval, 3))) return rc;
   if (quat_eval && (rc = upload4(ctx, d.qx, quat_eval, 4))) return rc;
-  launch_bond_eval(d, mixed, psd, hess, ctx->P.midpoint != 0, st);
-  launch_particle_eval(d, ctx->P, mixed, hess, pot, st);
-  launch_newton_check(d, ctx->P, 1, st);
+  const bool gn = (what & BDEM_EGH_GN) != 0;
+  if (gn && !hess) return fail(ctx, BDEM_E_INVALID, "BDEM_EGH_GN needs BDEM_EGH_H");
+  const bool rows = gn || (hess && psd && ctx->opt.hessian == BDEM_HESS_GAUSS_NEWTON && (what & BDEM_EGH_PCG_MATRIX));
+  if (rows) {
+    launch_bond_energy(d, false, ctx->P.midpoint != 0, st);
+    launch_particle_energy(d, ctx->P, pot, st);
+    launch_rows_eval(d, ctx->P, mixed, ctx->P.midpoint != 0, pot, st);
+  } else {
+    launch_bond_eval(d, mixed, psd, hess, ctx->P.midpoint != 0, st);
+    launch_particle_eval(d, ctx->P, mixed, hess, pot, st);
+  }
+  launch_newton_check(d, ctx->P, 1, rows, st);
   launch_count_active(d, NS, 0, st);
   if ((rc = read_counters(ctx))) return rc;
   if (ctx->h_counters[3] > 0) return fail(ctx, BDEM_E_DEGENERATE, "|q_i + q_j| < 1e-6 in a bond");
@@ -1308,8 +1347,8 @@ extern "C" int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_ev
   if (!ctx || !in6 || !out6) return BDEM_E_INVALID;
   const int n = ctx->S.n, NS = ctx->S.n_scenes, NP = ctx->S.n_pad;
   // the projected reduced Hessian at the evaluation state (as bdem_energy_grad_hess)
-  int rc = bdem_energy_grad_hess(ctx, dt, BDEM_EGH_H | BDEM_EGH_PSD, pos_eval, quat_eval, nullptr,
-                                 nullptr, nullptr, nullptr);
+  int rc = bdem_energy_grad_hess(ctx, dt, BDEM_EGH_H | BDEM_EGH_PSD | BDEM_EGH_PCG_MATRIX, pos_eval,
+                                 quat_eval, nullptr, nullptr, nullptr, nullptr);
   if (rc < 0) return rc;
   hipStream_t st = ctx->stream;
   DevPtrs &d = ctx->d;
@@ -1344,8 +1383,8 @@ extern "C" int bdem_hess_apply(bdem_ctx *ctx, double dt, const double *pos_eval,
   if (!ctx || !in6 || !out6) return BDEM_E_INVALID;
   const int n = ctx->S.n, NS = ctx->S.n_scenes, NP = ctx->S.n_pad;
   // the projected reduced Hessian at the evaluation state (as bdem_energy_grad_hess)
-  int rc = bdem_energy_grad_hess(ctx, dt, BDEM_EGH_H | BDEM_EGH_PSD, pos_eval, quat_eval, nullptr,
-                                 nullptr, nullptr, nullptr);
+  int rc = bdem_energy_grad_hess(ctx, dt, BDEM_EGH_H | BDEM_EGH_PSD | BDEM_EGH_PCG_MATRIX, pos_eval,
+                                 quat_eval, nullptr, nullptr, nullptr, nullptr);
   if (rc < 0) return rc;
   hipStream_t st = ctx->stream;
   DevPtrs &d = ctx->d;
@@ -1489,10 +1528,9 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
     if (rc) return rc;
   }
   launch_step_target(d, ctx->P, st);
-  launch_bond_eval(d, mixed, true, true, ctx->P.midpoint != 0, st);
-  launch_particle_eval(d, ctx->P, mixed, true, false, st);
+  launch_evaluation(ctx, true, true, true, false);
   if (ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
-  launch_newton_check(d, ctx->P, 1, st);
+  launch_newton_check(d, ctx->P, 1, rows_path(ctx, true), st);
   launch_count_active(d, NS, 0, st);
   int rc = read_counters(ctx);
   if (rc) return rc;
@@ -1577,7 +1615,8 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
 
 extern "C" int bdem_set_profiling(bdem_ctx *ctx, int32_t enable) {
   if (!ctx) return BDEM_E_INVALID;
-  ctx->profiling = enable ? 1 : 0;
+  if (enable < 0 || enable > 2) return fail(ctx, BDEM_E_INVALID, "profiling level must be 0, 1 or 2");
+  ctx->profiling = enable;
   return BDEM_OK;
 }
 

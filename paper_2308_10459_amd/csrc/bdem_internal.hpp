@@ -29,6 +29,7 @@ constexpr int SPMV_ROWS = 32;     // block rows per SpMV workgroup
 constexpr int SPMV_CAP = 384;     // slot products held in LDS per pass of an SpMV workgroup
 constexpr int DOT_GROUP = 64;     // SpMV blocks whose (r, u), (r, r) partials one SpMV wavefront merges
 constexpr int CMAXC = 32;         // element-repulsion candidates per particle
+constexpr int ROWS_RT = 64;       // block rows per workgroup of the row-parallel evaluation
 
 // per-scene control block, device resident; every decision of the Newton /
 // PCG / line-search loops is taken on the device from these values
@@ -129,6 +130,12 @@ void launch_copy_state_to_iterate(const DevPtrs &d, hipStream_t s);
 void launch_restart_from_state(const DevPtrs &d, hipStream_t s);
 void launch_particle_eval(const DevPtrs &d, const Params &P, bool mixed, bool hess,
                           bool potential_only, hipStream_t s);
+// row-parallel evaluation with the Gauss-Newton bond Hessian (gradient,
+// diagonal and off-diagonal blocks, block-Jacobi inverse, |z|^2 per ROWS_RT
+// rows), and the particle part of the objective at the iterate
+void launch_rows_eval(const DevPtrs &d, const Params &P, bool mixed, bool midpoint,
+                      bool potential_only, hipStream_t s);
+void launch_particle_energy(const DevPtrs &d, const Params &P, bool potential_only, hipStream_t s);
 void launch_midpoint_target(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_ls_trial(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_ls_accept(const DevPtrs &d, hipStream_t s);
@@ -139,7 +146,9 @@ void launch_contact_trial_energy(const DevPtrs &d, const Params &P, hipStream_t 
 void launch_friction(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_finish_step(const DevPtrs &d, hipStream_t s);
 // per-scene decisions
-void launch_newton_check(const DevPtrs &d, const Params &P, int first, hipStream_t s);
+// rows: the iterate was evaluated by the row-parallel kernel (|z|^2 partials
+// per ROWS_RT rows; Phi of later iterates is the accepted line-search trial's)
+void launch_newton_check(const DevPtrs &d, const Params &P, int first, bool rows, hipStream_t s);
 void launch_count_active(const DevPtrs &d, int n_scenes, int slot, hipStream_t s);
 void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
 // PCG

@@ -31,6 +31,11 @@ template <typename T> __device__ __forceinline__ void qmul(const T *a, const T *
   c[3] = a[3] * b[3] - a[0] * b[0] - a[1] * b[1] - a[2] * b[2];
 }
 
+// componentwise midpoint (a + b)/2
+__device__ __forceinline__ double4 mid4(double4 a, double4 b) {
+  return make_double4(0.5 * (a.x + b.x), 0.5 * (a.y + b.y), 0.5 * (a.z + b.z), 0.5 * (a.w + b.w));
+}
+
 // G_l(q) = [s I - v^x, -v] as a 3x4 row-major matrix.
 template <typename T> __device__ __forceinline__ void gleft(const T *q, T *G) {
   const T x = q[0], y = q[1], z = q[2], s = q[3];

@@ -31,18 +31,23 @@ __device__ __forceinline__ double range_max(const double *part, int stride, int 
 // Newton stop test (Algorithm 2 / 3: |grad f| < eps), CG tolerance
 // eps_r = min(0.5, sqrt|grad f|) (Section 5.3).  One workgroup per scene.
 // ---------------------------------------------------------------------------
-__global__ void k_newton_check(DevPtrs d, Params P, int first) {
+// rows: the reduced gradient came from the row-parallel evaluation (one |z|^2
+// partial per ROWS_RT rows), which forms no energy: Phi of the first iterate
+// comes from the energy pass at the iterate, Phi of a later one is that of
+// the line-search trial it accepted (the same kernels, the same state).
+__global__ void k_newton_check(DevPtrs d, Params P, int first, int rows) {
   const int s = blockIdx.x;
   SceneCtl &c = d.ctl[s];
   if (!c.newton_active) return;
   const int pb = d.scene_pbeg[s] / TILE, pe = d.scene_pbeg[s + 1] / TILE;
   const int bb = d.scene_bbeg[s] / TILE, be = d.scene_bbeg[s + 1] / TILE;
+  const int zg = rows ? ROWS_RT : TILE;
   const KSum eb = range_ksum(d.part_a, bb, be);
   const KSum ep = range_ksum(d.part_b, pb, pe);
-  const KSum g2 = range_ksum(d.part_c, pb, pe);
+  const KSum g2 = range_ksum(d.part_c, d.scene_pbeg[s] / zg, d.scene_pbeg[s + 1] / zg);
   if (threadIdx.x != 0) return;
   const KSum et = kmerge(eb, ep);
-  const double phi = et.s + et.c;
+  const double phi = (rows && !first) ? c.phi_trial : et.s + et.c;
   const double gn = sqrt(g2.s + g2.c);
   c.phi = phi;
   c.gnorm = gn;
@@ -620,8 +625,8 @@ __global__ void k_ls_decide(DevPtrs d, Params P) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-void launch_newton_check(const DevPtrs &d, const Params &P, int first, hipStream_t s) {
-  k_newton_check<<<P.n_scenes, 256, 0, s>>>(d, P, first);
+void launch_newton_check(const DevPtrs &d, const Params &P, int first, bool rows, hipStream_t s) {
+  k_newton_check<<<P.n_scenes, 256, 0, s>>>(d, P, first, rows ? 1 : 0);
 }
 void launch_count_active(const DevPtrs &d, int n_scenes, int slot, hipStream_t s) {
   k_count_active<<<1, 256, 0, s>>>(d, n_scenes, slot);

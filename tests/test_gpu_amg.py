@@ -39,7 +39,7 @@ def test_vcycle_matches_oracle(B, mixed, dims):
     b = rng.normal(size=(sc.n, 6))
     b[sc.flags != 0] = 0.0
     x_o, L = o.amg_apply(ev_pos, ev_quat, hd, ho, b)
-    sim = make_sim(sc, mixed=mixed, preconditioner=B.BDEM_PRECOND_AMG)
+    sim = make_sim(sc, mixed=mixed, preconditioner=B.BDEM_PRECOND_AMG, hessian=B.BDEM_HESS_EIGEN_CLAMP)
     sim.set_state(**st)
     x = sim.precond_apply(dt, b, ev_pos, ev_quat)
     err = np.abs(x - x_o).max() / np.abs(x_o).max()
@@ -53,7 +53,7 @@ def test_vcycle_matches_oracle(B, mixed, dims):
         s1, s2 = float((a2 * x).sum()), float((b * y).sum())
         assert abs(s1 - s2) <= 1e-10 * abs(s1)
         # block-Jacobi through the same entry point: D^-1 b
-        sj = make_sim(sc, mixed=False)
+        sj = make_sim(sc, mixed=False, hessian=B.BDEM_HESS_EIGEN_CLAMP)
         sj.set_state(**st)
         xj = sj.precond_apply(dt, b, ev_pos, ev_quat)
         ref = np.einsum("nij,nj->ni", np.linalg.inv(hd), b)

@@ -60,7 +60,7 @@ def test_hess_apply_matches_oracle(B, mixed, ground, dims):
     _, _, hd, ho = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=True)
     u = np.random.default_rng(3).normal(size=(sc.n, 6))
     ref = o.hess_apply(hd, ho, u)
-    sim = make_sim(sc, mixed=mixed)
+    sim = make_sim(sc, mixed=mixed, hessian=B.BDEM_HESS_EIGEN_CLAMP)
     sim.set_state(**st)
     w = sim.hess_apply(dt, u, ev_pos, ev_quat)
     bound = _row_bound(sc.n, sc.ij, hd, ho, u)
@@ -92,7 +92,7 @@ def test_hess_apply_with_repulsion_couplings(B, mixed):
     np.add.at(ref0, sc.ij[:, 1], np.einsum("bji,bj->bi", ho, u[sc.ij[:, 0]]))
     # the couplings are there: the bond blocks alone give another product
     assert np.abs(ref - ref0).max() > 1e-3 * np.abs(ref).max()
-    sim = make_sim(sc, mixed=mixed)
+    sim = make_sim(sc, mixed=mixed, hessian=B.BDEM_HESS_EIGEN_CLAMP)
     w = sim.hess_apply(dt, u)
     pairs = [(i, j, sc.k_self) for i, j in o.contacts()]
     bound = _row_bound(sc.n, sc.ij, hd, ho, u, pairs)
@@ -109,7 +109,7 @@ def test_hess_apply_ceramic_plate_sampled_rows(B, mixed):
     oracle's blocks of the sampled particles and their bonds."""
     sc = S.make_ceramic_plate()
     log(f"[hess apply ceramic plate] n={sc.n} nb={sc.nb} mixed={mixed}")
-    sim = make_sim(sc, mixed=mixed)
+    sim = make_sim(sc, mixed=mixed, hessian=B.BDEM_HESS_EIGEN_CLAMP)
     sim.autotune([sc.dt])
     sg = sim.step(sc.dt)
     assert sg["rc"] == 0 and sg["bonds_broken"] > 0
