@@ -30,16 +30,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "spmv_ceramic_plate_219k.md")
+# committed counter summaries, one per kernel
+PROFILES = {"k_spmv<float>": os.path.join(ROOT, "profiles", "spmv_ceramic_plate_219k.md"),
+            "k_rows_eval<float>": os.path.join(ROOT, "profiles", "rows_eval_ceramic_plate_219k.md")}
 
 
-def spmv_source_digest():
-    """sha256 of the SpMV kernel's source text (the k_spmv template and the
-    SPMV_* tiling constants): HBM counter figures recorded for one digest are
-    stale once it changes."""
+def source_digest(kernel="k_spmv<float>"):
+    """sha256 of the kernel's source text: HBM counter figures recorded for one
+    digest are stale once it changes.  k_spmv: its template and the SPMV_*
+    tiling constants; k_rows_eval: its file and the headers it inlines (bond
+    geometry, particle terms) and the ROWS_* tiling constant."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_2308_10459_amd", "csrc")
+    if kernel.startswith("k_rows_eval"):
+        text = "".join(open(os.path.join(csrc, f)).read()
+                       for f in ("k_rows.hip", "bdem_bond.hpp", "bdem_particle.hpp"))
+        text += "".join(ln for ln in open(os.path.join(csrc, "bdem_internal.hpp")) if "ROWS_" in ln)
+        return hashlib.sha256(text.encode()).hexdigest()[:16]
     src = open(os.path.join(csrc, "k_solve.hip")).read()
     m = re.search(r"template <typename T, int NT, int U> __global__ __launch_bounds__\([^)]*\) void k_spmv.*?\n}\n",
                   src, re.S)
@@ -48,18 +56,42 @@ def spmv_source_digest():
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per SpMV launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+def spmv_source_digest():
+    return source_digest("k_spmv<float>")
+
+
+def recorded_traffic(kernel="k_spmv<float>"):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    they were taken on the current source of the kernels; else None."""
     import re
     try:
-        txt = open(PROFILE).read()
-    except OSError:
+        txt = open(PROFILES[kernel]).read()
+    except (OSError, KeyError):
         return None
-    m = re.search(r"TRAFFIC kernel=k_spmv<float> digest=(\w+) fetch_bytes=(\d+) write_bytes=(\d+)", txt)
-    if not m or m.group(1) != spmv_source_digest():
+    pat = r"TRAFFIC kernel=" + re.escape(kernel) + r" digest=(\w+) fetch_bytes=(\d+) write_bytes=(\d+)"
+    m = re.search(pat, txt)
+    if not m or m.group(1) != source_digest(kernel):
         return None
     return int(m.group(2)) + int(m.group(3))
+
+
+def recorded_valu(kernel):
+    """VALU wave-instructions per launch of `kernel` from its committed counter
+    summary (SQ_INSTS_VALU), if taken on the current source; else None."""
+    import re
+    try:
+        txt = open(PROFILES[kernel]).read()
+    except (OSError, KeyError):
+        return None
+    m = re.search(r"VALU kernel=" + re.escape(kernel) + r" digest=(\w+) insts_valu=(\d+)", txt)
+    if not m or m.group(1) != source_digest(kernel):
+        return None
+    return int(m.group(2))
+
+
+# wave64 VALU instructions the chip can issue per second: 256 CUs x 4 SIMDs,
+# one wave64 instruction per SIMD every 4 cycles (16 lanes), 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def spmv_algorithmic_bytes(n, nb_alive, elt):
@@ -69,18 +101,26 @@ def spmv_algorithmic_bytes(n, nb_alive, elt):
     return nb_alive * 36 * elt + n * 21 * elt + nb_alive * 8 + 2 * 6 * n * 8
 
 
-def bond_algorithmic_bytes(n, nb_alive, elt):
-    """Bytes of one bond evaluation (both bond kernels): state read once
-    (p, q: 64 B per particle), bond topology and rest data (8 + 64 B), unique
-    Hessian blocks written (36 per bond, 21 per diagonal) and the FP64 gradient."""
-    return n * 64 + nb_alive * 72 + nb_alive * 36 * elt + n * 21 * elt + n * 48
+def bond_algorithmic_bytes(n, nb_alive, elt, inverse=False):
+    """Bytes one bond evaluation must move at least (the K1 figure of the
+    measurement plan): the state read once (p, q: 56 B per particle), each
+    bond's topology and rest data (i, j, l0, d0: 24 B), the unique Hessian
+    blocks written (36 values per bond, 21 per diagonal block) and the FP64
+    reduced gradient (48 B per particle).  The row-parallel evaluation also
+    writes the block-Jacobi inverse (21 values per particle): inverse=True
+    counts it."""
+    b = n * 56 + nb_alive * 24 + nb_alive * 36 * elt + n * 21 * elt + n * 48
+    return b + (n * 21 * elt if inverse else 0)
 
 
 def run_path(scene, mixed, steps, warmup, profile, **opts):
-    """Warm up, then time `steps` implicit steps with the library defaults.
-    With profile, HIP events on the library's stream bracket every bond
-    evaluation and every SpMV launch of the timed steps; PCG issues one
-    iteration ahead of its convergence poll and the timings of the one
+    """Warm up, then time `steps` implicit steps in the autotuned launch
+    configuration.  With profile, HIP events on the library's stream bracket
+    every bond-evaluation launch of the timed steps, and every SpMV launch too
+    when the tuned PCG mode issues plain launches; when it replays captured
+    graphs (whose launches cannot be bracketed) the SpMV average comes from
+    three further steps with plain launches, and the result says so.  PCG
+    issues one iteration ahead of its convergence poll; the timings of the one
     iteration issued after convergence (whose kernels return at once) are
     dropped, so the SpMV average covers working launches only."""
     import torch
@@ -89,12 +129,11 @@ def run_path(scene, mixed, steps, warmup, profile, **opts):
     sim = B.Simulator(scene, precision=prec, **opts)
     tuning = sim.autotune([scene.dt])
     log(f"  autotuned: {tuning}")
-    if profile:   # per-launch events need ungraphed launches; the poll interval stays tuned
-        sim.set_tuning(use_graph=0)
+    plain = not tuning["use_graph"]
     for k in range(warmup):
         st = sim.step(scene.dt)
         log(f"  warmup {k}: newton {st['newton_iters']} cg {st['cg_iters']} broken {st['bonds_broken']}")
-    B.bdem_set_profiling(sim.ctx, profile)
+    B.bdem_set_profiling(sim.ctx, (1 if plain else 2) if profile else 0)
     tot = dict(newton=0, cg=0, ls=0, bond_ms=0.0, spmv_ms=0.0, bond_launch=0, spmv_launch=0,
                broken=0, step_ms=[], step_newton=[])
     torch.cuda.synchronize()
@@ -116,6 +155,15 @@ def run_path(scene, mixed, steps, warmup, profile, **opts):
             f"broken {st['bonds_broken']} rc {st['rc']} {st['t_ms'][5]:.1f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    tot["spmv_timing"] = "timed steps"
+    if profile and not plain:
+        B.bdem_set_profiling(sim.ctx, 1)
+        for k in range(3):
+            st = sim.step(scene.dt)
+            tot["spmv_ms"] += st["t_ms"][7]
+            tot["spmv_launch"] += B.bdem_profile_counts(sim.ctx)[1]
+        tot["spmv_timing"] = ("3 steps after the timed ones with plain launches (the tuned PCG mode "
+                              "replays captured graphs)")
     alive = int(sim.get_state()["alive"].sum())
     sim.close()
     tot["wall_s"] = wall
@@ -261,48 +309,98 @@ def run_contact_comparison(scene, steps):
     return out
 
 
-def cpu_baseline(target_s=15.0):
-    """The FP64 oracle on a bounded sample of the same workload: a 24x24x16
-    sub-plate (9,216 particles) built like the ceramic plate, same material,
-    velocity, ground and dt.  One oracle step; Newton iterations per second
-    scaled to 219,024 particles by the particle ratio (optimistic for the
-    oracle: its PCG iteration count would grow with size), and oracle bond
-    Hessian evaluations per second (exact per-bond work)."""
+def _omp_threads(n=None):
+    """OpenMP threads of this process (the oracle's runtime); with n, set them."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cg_per_newton=None):
+    """The FP64 oracle on the bench workload itself (the 219,024-particle
+    plate, its own initial state), on the host cores:
+      * one Newton iteration of the oracle's Algorithm 3 step (its evaluation
+        with the eigen-clamped Hessian, PCG with the Section 5.3 forcing
+        min(0.5, sqrt|grad f|), line search): the step limited to one
+        iteration, minus the closing evaluation of the new iterate, timed
+        separately;
+      * one evaluation (energy, gradient, projected Hessian of every bond) at
+        all threads and at one thread (the oracle parallelises its bond and
+        particle loops; its PCG is sequential);
+      * 20 PCG iterations on that Hessian, for the seconds per iteration.
+    value: Newton iterations per second of the first iteration of the impact
+    step (the oracle's first PCG solve stops at half the residual, so few
+    iterations); modelled_at_bench_cg_per_newton: one evaluation plus the GPU
+    run's CG iterations per Newton iteration at the measured cost each."""
     import numpy as np
-    from oracle.oracle import Oracle
+    from oracle.oracle import Oracle, lib
     from paper_2308_10459_amd import scenes as S
-    full_n = 117 * 117 * 16
-    sc = S.make_ceramic_plate(nx=24, ny=24, nl=16)
+    lib()
+    threads = _omp_threads()
+    sc = S.make_ceramic_plate()
     o = Oracle(sc)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    st = o.step(sc.dt, tol_rel=1e-10, max_newton=20)
+    phi, z, hd, ho = o.energy_grad_hess(sc.dt)
+    t_eval = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, it, _ = o.pcg(hd, ho, -z, rtol=0.0, max_iter=20)
+    t_cg = (time.perf_counter() - t0) / max(it, 1)
+    del hd, ho
+    t0 = time.perf_counter()
+    st = o.step(sc.dt, max_newton=1, tol_rel=1e-8, cg_rtol=0.5, cg_forcing=1, break_bonds=0)
     t_step = time.perf_counter() - t0
-    # bond Hessian evaluations: energy/gradient/projected Hessian of every bond
-    t0 = time.perf_counter()
-    reps = 0
-    while True:
-        o.energy_grad_hess(sc.dt)
-        reps += 1
-        if time.perf_counter() - t0 > min(5.0, target_s / 3):
-            break
-    t_egh = (time.perf_counter() - t0) / reps
-    iters = max(st["newton_iters"], 1)
-    return {
-        "value": iters / t_step * sc.n / full_n, "unit": "Newton iters/s", "cores": threads,
-        "kind": "oracle",
-        "sample": f"one oracle step of a 24x24x16 sub-plate ({sc.n} particles, {sc.nb} bonds): "
-                  f"{st['newton_iters']} Newton iterations, {st['cg_iters']} PCG iterations in "
-                  f"{t_step:.1f} s, rate scaled by {sc.n}/{full_n} particles",
-        "bond_hessian_evals_per_s": sc.nb / t_egh,
+    t_iter = max(t_step - t_eval, 1e-9)
+    t_eval1 = None
+    if threads and threads > 1:
+        _omp_threads(1)
+        try:
+            t0 = time.perf_counter()
+            o.energy_grad_hess(sc.dt, hess=True)
+            t_eval1 = time.perf_counter() - t0
+        finally:
+            _omp_threads(threads)
+    nb = sc.nb
+    out = {
+        "value": 1.0 / t_iter, "unit": "Newton iters/s", "cores": threads, "kind": "oracle",
+        "cpu_model": _cpu_model(),
+        "sample": (f"the bench workload itself ({sc.n} particles, {nb} bonds): the first Newton "
+                   f"iteration of the oracle's impact step ({st['cg_iters']} PCG iterations, forcing "
+                   f"min(0.5, sqrt|grad f|)) in {t_iter:.1f} s = step limited to one iteration "
+                   f"({t_step:.1f} s) minus one evaluation ({t_eval:.1f} s)"),
+        "seconds_per_evaluation": t_eval,
+        "seconds_per_pcg_iteration": t_cg,
+        "bond_hessian_evals_per_s": nb / t_eval,
     }
+    if t_eval1 is not None:
+        out["seconds_per_evaluation_1_thread"] = t_eval1
+        out["bond_hessian_evals_per_s_1_thread"] = nb / t_eval1
+    if cg_per_newton:
+        out["modelled_at_bench_cg_per_newton"] = {
+            "cg_per_newton": cg_per_newton,
+            "newton_iters_per_s": 1.0 / (t_eval + cg_per_newton * t_cg)}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="ceramic_plate")
@@ -310,7 +408,9 @@ def main():
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--mixed-only", action="store_true")
     ap.add_argument("--no-solver-comparison", action="store_true")
-    ap.add_argument("--batch-steps", type=int, default=3,
+    ap.add_argument("--no-hessian-comparison", action="store_true",
+                    help="skip the run with eigen-clamped bond Hessians")
+    ap.add_argument("--batch-steps", type=int, default=20,
                     help="steps of the 64-scene batch (0: skip)")
     ap.add_argument("--midpoint-steps", type=int, default=5,
                     help="steps of the bench workload with the midpoint integrator (0: skip)")
@@ -325,10 +425,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); the multi-GPU "
               "path of this method is a design, not a build", file=sys.stderr)
         sys.exit(2)
+    from paper_2308_10459_amd import bdem as B
     from paper_2308_10459_amd import scenes as S
     scene = S.WORKLOADS[args.workload]()
     log(f"workload {scene.name}: n={scene.n} nb={scene.nb} dt={scene.dt}")
-    log("mixed path:")
+    log("mixed path (Gauss-Newton bond Hessians):")
     mixed = run_path(scene, True, args.steps, args.warmup, profile=True)
     fsteps = args.steps if args.fp64_steps is None else args.fp64_steps
     if args.mixed_only:
@@ -337,6 +438,11 @@ def main():
     if fsteps:
         log("fp64 path:")
         fp64 = run_path(scene, False, fsteps, args.warmup, profile=True)
+    eig = None
+    if not args.no_hessian_comparison:
+        log("mixed path, eigen-clamped bond Hessians:")
+        eig = run_path(scene, True, args.steps, args.warmup, profile=True,
+                       hessian=B.BDEM_HESS_EIGEN_CLAMP)
     if args.copy_probe:
         import torch
         src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -346,29 +452,35 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: 3 x 1 GiB device-to-device copies")
 
-    def rates(r, elt, steps):
-        if steps == 0:
+    def rates(r, elt, steps, rows):
+        if steps == 0 or r is None:
             return None
         nwt = r["newton"] / r["wall_s"] if r["wall_s"] > 0 and r["newton"] else 0.0
         be = r["alive_bonds"] * r["bond_launch"] / (r["bond_ms"] * 1e-3) if r["bond_ms"] > 0 else 0.0
         spmv_avg_ms = r["spmv_ms"] / max(r["spmv_launch"], 1)
         bytes_spmv = spmv_algorithmic_bytes(scene.n, r["alive_bonds"], elt)
         bond_avg_ms = r["bond_ms"] / max(r["bond_launch"], 1)
-        bytes_bond = bond_algorithmic_bytes(scene.n, r["alive_bonds"], elt)
+        bytes_bond = bond_algorithmic_bytes(scene.n, r["alive_bonds"], elt, inverse=rows)
         return dict(newton_iters_per_s=nwt, bond_hessian_evals_per_s=be,
                     bond_hessian_evals_per_wall_s=r["alive_bonds"] * r["newton"] / r["wall_s"],
                     ms_per_step=1e3 * r["wall_s"] / steps,
+                    newton_iters_per_step=r["newton"] / steps,
                     cg_iters_per_newton=r["cg"] / max(r["newton"], 1),
                     ls_backtracks_per_newton=r["ls"] / max(r["newton"], 1),
                     spmv_launches=r["spmv_launch"], spmv_avg_ms=spmv_avg_ms,
                     spmv_gbs=bytes_spmv / (spmv_avg_ms * 1e-3) / 1e9 if spmv_avg_ms > 0 else 0.0,
-                    spmv_bytes=bytes_spmv, bond_launches=r["bond_launch"], bond_avg_ms=bond_avg_ms,
+                    spmv_bytes=bytes_spmv, spmv_timing=r["spmv_timing"],
+                    bond_kernels=("k_rows_eval (row-parallel, Gauss-Newton blocks, assembly and "
+                                  "block-Jacobi inverse)" if rows else
+                                  "k_bond_eval + k_bond_project (bond-parallel, eigen-clamp)"),
+                    bond_launches=r["bond_launch"], bond_avg_ms=bond_avg_ms,
                     bond_gbs=bytes_bond / (bond_avg_ms * 1e-3) / 1e9 if bond_avg_ms > 0 else 0.0,
                     bond_bytes=bytes_bond,
                     newton_iters=r["newton"], cg_iters=r["cg"], bonds_broken=r["broken"],
                     alive_bonds=r["alive_bonds"], tuning=r["tuning"])
 
-    rm, rf = rates(mixed, 4, args.steps), rates(fp64, 8, fsteps)
+    rm, rf = rates(mixed, 4, args.steps, True), rates(fp64, 8, fsteps, True)
+    re_ = rates(eig, 4, args.steps, False)
     out = {
         "metric": METRIC,
         "value": rm["newton_iters_per_s"],
@@ -384,17 +496,36 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{scene.name}: {scene.n} particles, {scene.nb} bonds, E=5e10 Pa, "
                                f"v0=-8 m/s onto the ground, dt={scene.dt}",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "hessian": "Gauss-Newton bond Hessians (PSD by construction)"},
         "bond_hessian_evals_per_s": rm["bond_hessian_evals_per_s"],
         "mixed": rm,
         "fp64": rf,
         "mixed_over_fp64_newton_iters_per_s": (rm["newton_iters_per_s"] / rf["newton_iters_per_s"]
                                                if rf and rf["newton_iters_per_s"] > 0 else None),
+        "mixed_over_fp64_ms_per_step": (rf["ms_per_step"] / rm["ms_per_step"] if rf else None),
         "roofline": {"bound": "hbm", "kernel": "k_spmv<float>", "achieved": rm["spmv_gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rm["spmv_gbs"] / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(),
                      "algorithmic_bytes_per_launch": rm["spmv_bytes"]},
+        "roofline_bond_eval": {"bound": "hbm", "kernel": "k_rows_eval<float>",
+                               "achieved": rm["bond_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": rm["bond_gbs"] / HBM_PEAK_GBS,
+                               "traffic": recorded_traffic("k_rows_eval<float>"),
+                               "algorithmic_bytes_per_launch": rm["bond_bytes"]},
     }
+    valu = recorded_valu("k_rows_eval<float>")
+    if valu and rm["bond_avg_ms"] > 0:
+        rate = valu / (rm["bond_avg_ms"] * 1e-3)
+        out["roofline_bond_eval"]["valu_issue"] = {
+            "insts_valu_per_launch": valu, "achieved": rate, "peak": VALU_ISSUE_PEAK,
+            "unit": "wave64 VALU instructions/s", "frac": rate / VALU_ISSUE_PEAK}
+    if re_:
+        out["hessian_comparison"] = {
+            "hessian": "eigen-clamped exact bond Hessians (bond-parallel evaluation + projection)",
+            **{k: re_[k] for k in ("newton_iters_per_s", "ms_per_step", "newton_iters_per_step",
+                                   "cg_iters_per_newton", "bond_avg_ms", "bond_gbs",
+                                   "bond_hessian_evals_per_s", "bond_kernels")}}
     if not args.no_amg:
         log("aggregation multigrid preconditioner (mixed path):")
         out["precond_comparison"] = run_precond_comparison(scene, args.steps, args.warmup)
@@ -416,7 +547,7 @@ def main():
         out["batch"] = run_batch(args.batch_steps, 1)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle):")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(cg_per_newton=rm["cg_iters_per_newton"])
     print(json.dumps(out), flush=True)
 
 

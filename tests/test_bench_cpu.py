@@ -32,8 +32,23 @@ def test_spmv_algorithmic_bytes_per_unit():
 
 
 def test_bond_algorithmic_bytes_per_unit():
-    """Per particle: state (64 B), the diagonal block (21 values) and the FP64
-    gradient (48 B); per bond: topology and rest data (72 B) and its block."""
+    """The bond-evaluation (K1) figure of the measurement plan: per particle
+    the state read once (p and q: 56 B), the diagonal block (21 values) and
+    the FP64 gradient (48 B); per bond its topology and rest data (i, j, l0,
+    d0: 24 B) and its block (36 values); the row-parallel kernel also writes
+    the block-Jacobi inverse (21 values per particle)."""
     for elt in (4, 8):
-        assert bench.bond_algorithmic_bytes(1, 0, elt) == 64 + 21 * elt + 48
-        assert bench.bond_algorithmic_bytes(0, 1, elt) == 72 + 36 * elt
+        assert bench.bond_algorithmic_bytes(1, 0, elt) == 56 + 21 * elt + 48
+        assert bench.bond_algorithmic_bytes(0, 1, elt) == 24 + 36 * elt
+        assert bench.bond_algorithmic_bytes(1, 0, elt, inverse=True) == 56 + 42 * elt + 48
+    # the 219,024-particle plate, 1,336,336 alive bonds, FP32 blocks: 265.7 MB
+    assert bench.bond_algorithmic_bytes(219024, 1336336, 4) == 265_680_960
+
+
+def test_counter_figures_are_tied_to_the_kernel_source():
+    """A counter summary names the digest of the kernel source it was taken
+    on; a different digest means the figures are stale and are not reported."""
+    for k in ("k_spmv<float>", "k_rows_eval<float>"):
+        d = bench.source_digest(k)
+        assert len(d) == 16 and d == bench.source_digest(k)
+    assert bench.source_digest("k_spmv<float>") != bench.source_digest("k_rows_eval<float>")
