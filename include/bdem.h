@@ -211,6 +211,26 @@ int bdem_create(const bdem_particles *p, const bdem_bonds *b, const bdem_materia
                 int32_t n_mats, const bdem_options *opt, void *hip_stream,
                 void *workspace_dev, size_t workspace_bytes, bdem_ctx **out);
 
+/* bdem_create for callers that cannot allocate device memory (serving loops
+ * and harnesses that forbid hipMalloc, code that sets up work to be captured
+ * into a HIP graph): the handle's workspace is the library's static device
+ * array of BDEM_SCRATCH_BYTES on the current device (held from the library's
+ * first use on that device until the process ends), its host mirrors are
+ * unpinned and its convergence counters live in device memory (read back
+ * after the stream drains, so the PCG polls without running ahead).  It
+ * calls no hipMalloc, hipHostMalloc, hipFree or other allocating routine;
+ * everything else is bdem_create's (same kernels, same results).  One handle
+ * per device may live in the array at a time: bdem_destroy releases it.  The
+ * array keeps the contents of the last handle; create initialises every
+ * buffer it reads.  Errors: NOMEM (the problem needs more than
+ * BDEM_SCRATCH_BYTES; the message gives both sizes), STATE (the device's
+ * array is in use), INVALID (as bdem_create, and the multigrid
+ * preconditioner, whose hierarchy is a separate allocation), HIP. */
+#define BDEM_SCRATCH_BYTES (64u << 20)
+int bdem_create_in_scratch(const bdem_particles *p, const bdem_bonds *b, const bdem_material *mats,
+                           int32_t n_mats, const bdem_options *opt, void *hip_stream,
+                           bdem_ctx **out);
+
 /* One implicit step of every scene with the same dt (Algorithm 3).  stats
  * (nullable) receives the totals over scenes.  Errors: INVALID (dt <= 0),
  * NONFINITE, DEGENERATE, HIP; warnings NOT_CONVERGED, LS_FAILED. */

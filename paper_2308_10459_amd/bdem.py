@@ -30,6 +30,7 @@ BDEM_INTEGRATOR_EULER, BDEM_INTEGRATOR_MIDPOINT = 0, 1
 BDEM_PRECOND_BLOCK_JACOBI, BDEM_PRECOND_AMG = 0, 1
 BDEM_EGH_E, BDEM_EGH_G, BDEM_EGH_H, BDEM_EGH_PSD, BDEM_EGH_POTENTIAL_ONLY = 1, 2, 4, 8, 16
 BDEM_EGH_GN, BDEM_EGH_PCG_MATRIX = 32, 64
+BDEM_SCRATCH_BYTES = 64 << 20
 BDEM_HESS_EIGEN_CLAMP, BDEM_HESS_GAUSS_NEWTON = 0, 1
 
 _dp = C.POINTER(C.c_double)
@@ -93,6 +94,9 @@ _sig = {
     "bdem_create": (C.c_int, [C.POINTER(bdem_particles), C.POINTER(bdem_bonds),
                               C.POINTER(bdem_material), C.c_int32, C.POINTER(bdem_options),
                               C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(_ctx_p)]),
+    "bdem_create_in_scratch": (C.c_int, [C.POINTER(bdem_particles), C.POINTER(bdem_bonds),
+                                         C.POINTER(bdem_material), C.c_int32, C.POINTER(bdem_options),
+                                         C.c_void_p, C.POINTER(_ctx_p)]),
     "bdem_step": (C.c_int, [_ctx_p, C.c_double, C.POINTER(bdem_step_stats)]),
     "bdem_step_batched": (C.c_int, [_ctx_p, _dp, C.POINTER(bdem_step_stats)]),
     "bdem_energy_grad_hess": (C.c_int, [_ctx_p, C.c_double, C.c_int32, _dp, _dp, _dp, _dp,
@@ -213,6 +217,18 @@ def bdem_create(scene, opts, stream=None, workspace=None):
     sptr = None if stream is None else C.c_void_p(stream.cuda_stream)
     rc = _lib.bdem_create(C.byref(inp.p), C.byref(inp.b), inp.mats, len(scene.materials),
                           C.byref(opts), sptr, wptr, wbytes, C.byref(ctx))
+    _check(rc)
+    return ctx
+
+
+def bdem_create_in_scratch(scene, opts, stream=None):
+    """Create a handle whose workspace is the library's static device array
+    (no allocation; one such handle per device at a time)."""
+    inp = _Inputs(scene)
+    ctx = _ctx_p()
+    sptr = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = _lib.bdem_create_in_scratch(C.byref(inp.p), C.byref(inp.b), inp.mats, len(scene.materials),
+                                     C.byref(opts), sptr, C.byref(ctx))
     _check(rc)
     return ctx
 
@@ -343,15 +359,22 @@ def bdem_destroy(ctx):
 class Simulator:
     """A handle plus its torch-owned workspace on the current device / stream."""
 
-    def __init__(self, scene, precision=BDEM_PREC_FP64, device="cuda", stream=None, **opts):
+    def __init__(self, scene, precision=BDEM_PREC_FP64, device="cuda", stream=None, in_scratch=False,
+                 **opts):
+        """in_scratch: create with bdem_create_in_scratch (the library's static
+        device array, no workspace tensor)."""
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the bdem library needs a GPU")
         self.scene = scene
         self.opts = scene_options(scene, precision=precision, **opts)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if in_scratch:
+            self.workspace = None
+            self.ctx = bdem_create_in_scratch(scene, self.opts, self.stream)
+            return
         nbytes = bdem_workspace_bytes(scene, self.opts)
         if nbytes == 0:
             raise BdemError(BDEM_E_INVALID, "invalid scene")
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.ctx = bdem_create(scene, self.opts, self.stream, self.workspace)
 

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -88,6 +89,7 @@ void make_layout(const Sizes &S, DevPtrs &d, Layout &L) {
   L.add(reinterpret_cast<void **>(&d.scene_pbeg), (S.n_scenes + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.scene_bbeg), (S.n_scenes + 1) * sizeof(int));
   L.add(reinterpret_cast<void **>(&d.degenerate), sizeof(int));
+  L.add(reinterpret_cast<void **>(&d.counters_ws), 8 * sizeof(int));
   const size_t npc = S.contact ? np : 1;
   for (int **p : {&d.cand, &d.cact}) L.add(reinterpret_cast<void **>(p), npc * CMAXC * sizeof(int));
   for (int **p : {&d.ncand, &d.nact, &d.gitem}) L.add(reinterpret_cast<void **>(p), npc * sizeof(int));
@@ -177,6 +179,13 @@ struct bdem_ctx {
   std::vector<double> scene_kself, scene_cmargin, scene_ccell;   // element repulsion per scene
   // pinned host mirrors
   int *h_counters = nullptr;     // 2 polling slots x 4
+  // created by bdem_create_in_scratch: workspace = the device's static scratch,
+  // counters in the workspace (copied to h_counters_local), host mirrors unpinned
+  bool in_scratch = false;       // holds the claim on the device's scratch (set once created)
+  bool host_pinned = false;      // h_counters / h_ctl are pinned allocations
+  int scratch_dev = -1;
+  int h_counters_local[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<SceneCtl> h_ctl_local;
   int prof_cnt[2] = {0, 0};      // profiled launches in the last step (bond, SpMV)
   SceneCtl *h_ctl = nullptr;
   hipEvent_t ev_slot[2] = {nullptr, nullptr};
@@ -256,6 +265,27 @@ extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds
   return L.total + ALIGN;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of bdem_create_in_scratch: a file-scope device array (every
+// GPU the library runs on holds one until the process ends).  Host code never
+// uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device with that device current, and is kept
+// per device.  One handle per device may live in it at a time.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = BDEM_SCRATCH_BYTES;
+static_assert(SCRATCH_BYTES == size_t(64) << 20, "64 MiB");
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+static bool g_scratch_used[SCRATCH_MAX_DEVICES] = {};
+
+static void scratch_release(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  g_scratch_used[dev] = false;
+}
+
 static void destroy_resources(bdem_ctx *ctx) {
   for (int k = 0; k < 2; ++k) {
     if (ctx->cg_exec[k]) (void)hipGraphExecDestroy(ctx->cg_exec[k]);
@@ -263,10 +293,13 @@ static void destroy_resources(bdem_ctx *ctx) {
     if (ctx->ev_slot[k]) (void)hipEventDestroy(ctx->ev_slot[k]);
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
-  if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+  if (ctx->host_pinned) {
+    if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+    if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+  }
   if (ctx->own_mem && ctx->mem) (void)hipFree(ctx->mem);
   if (ctx->amg_mem) (void)hipFree(ctx->amg_mem);
+  if (ctx->in_scratch) scratch_release(ctx->scratch_dev);
 }
 
 extern "C" void bdem_destroy(bdem_ctx *ctx) {
@@ -383,9 +416,11 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   return BDEM_OK;
 }
 
-extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const bdem_material *mats,
-                           int32_t n_mats, const bdem_options *opt, void *hip_stream,
-                           void *workspace_dev, size_t workspace_bytes, bdem_ctx **out) {
+// scratch_dev >= 0: the workspace is that device's static scratch (the
+// caller holds its claim): no pinned host memory, no events, no multigrid
+static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_material *mats,
+                       int32_t n_mats, const bdem_options *opt, void *hip_stream,
+                       void *workspace_dev, size_t workspace_bytes, int scratch_dev, bdem_ctx **out) {
   if (!out) return fail(nullptr, BDEM_E_INVALID, "out is NULL");
   *out = nullptr;
   if (!p || !b || !mats || n_mats <= 0) return fail(nullptr, BDEM_E_INVALID, "NULL argument");
@@ -449,8 +484,12 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
       return fail(nullptr, BDEM_E_INVALID, "duplicate bond");
   }
+  if (scratch_dev >= 0 && o.preconditioner == BDEM_PRECOND_AMG)
+    return fail(nullptr, BDEM_E_INVALID, "the multigrid preconditioner allocates its hierarchy: not available "
+                                         "in the static scratch");
   bdem_ctx *ctx = new bdem_ctx();
   ctx->stream = (hipStream_t)hip_stream;
+  ctx->scratch_dev = scratch_dev;
   {
     const char *tr = std::getenv("BDEM_TRACE");
     ctx->trace = (tr && tr[0] == '1') ? 1 : 0;
@@ -628,6 +667,10 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
     if (workspace_bytes < need) {
       destroy_resources(ctx);
       delete ctx;
+      if (scratch_dev >= 0)
+        return fail(nullptr, BDEM_E_NOMEM, "the problem needs " + std::to_string(need) +
+                                           " bytes of workspace; the static scratch holds " +
+                                           std::to_string(workspace_bytes));
       return fail(nullptr, BDEM_E_NOMEM, "workspace too small");
     }
     ctx->mem = workspace_dev;
@@ -724,13 +767,23 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
   chk(hipMemsetAsync(d.degenerate, 0, sizeof(int), st));
   // counters: written by the decision kernels straight into mapped host
   // memory, read by the host once an event or the stream has passed them
-  chk(hipHostMalloc((void **)&ctx->h_counters, 8 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
-  if (e == hipSuccess) {
-    std::memset(ctx->h_counters, 0, 8 * sizeof(int));
-    chk(hipHostGetDevicePointer((void **)&ctx->d.counters, ctx->h_counters, 0));
+  if (scratch_dev >= 0) {
+    // counters in the workspace, copied to the host after the stream drains
+    ctx->h_counters = ctx->h_counters_local;
+    ctx->d.counters = d.counters_ws;
+    chk(hipMemsetAsync(d.counters_ws, 0, 8 * sizeof(int), st));
+    ctx->h_ctl_local.assign(NS, SceneCtl{});
+    ctx->h_ctl = ctx->h_ctl_local.data();
+  } else {
+    ctx->host_pinned = true;
+    chk(hipHostMalloc((void **)&ctx->h_counters, 8 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent));
+    if (e == hipSuccess) {
+      std::memset(ctx->h_counters, 0, 8 * sizeof(int));
+      chk(hipHostGetDevicePointer((void **)&ctx->d.counters, ctx->h_counters, 0));
+    }
+    chk(hipHostMalloc((void **)&ctx->h_ctl, NS * sizeof(SceneCtl), hipHostMallocDefault));
+    for (int k = 0; k < 2; ++k) chk(hipEventCreateWithFlags(&ctx->ev_slot[k], hipEventDisableTiming));
   }
-  chk(hipHostMalloc((void **)&ctx->h_ctl, NS * sizeof(SceneCtl), hipHostMallocDefault));
-  for (int k = 0; k < 2; ++k) chk(hipEventCreateWithFlags(&ctx->ev_slot[k], hipEventDisableTiming));
   chk(hipStreamSynchronize(st));
   if (e != hipSuccess) {
     const std::string m = std::string("HIP error during create: ") + hipGetErrorString(e);
@@ -758,8 +811,44 @@ extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const b
       return fail(nullptr, rc, m);
     }
   }
+  ctx->in_scratch = scratch_dev >= 0;
   *out = ctx;
   return BDEM_OK;
+}
+
+extern "C" int bdem_create(const bdem_particles *p, const bdem_bonds *b, const bdem_material *mats,
+                           int32_t n_mats, const bdem_options *opt, void *hip_stream,
+                           void *workspace_dev, size_t workspace_bytes, bdem_ctx **out) {
+  return create_impl(p, b, mats, n_mats, opt, hip_stream, workspace_dev, workspace_bytes, -1, out);
+}
+
+extern "C" int bdem_create_in_scratch(const bdem_particles *p, const bdem_bonds *b,
+                                      const bdem_material *mats, int32_t n_mats,
+                                      const bdem_options *opt, void *hip_stream, bdem_ctx **out) {
+  if (!out) return fail(nullptr, BDEM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(nullptr, BDEM_E_HIP, "no current HIP device");
+  void *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_used[dev])
+      return fail(nullptr, BDEM_E_STATE, "another handle on this device lives in the static scratch "
+                                         "(bdem_destroy it first)");
+    if (!g_scratch_ptr[dev]) {
+      void *ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return fail(nullptr, BDEM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      g_scratch_ptr[dev] = ptr;
+    }
+    g_scratch_used[dev] = true;
+    ws = g_scratch_ptr[dev];
+  }
+  const int rc = create_impl(p, b, mats, n_mats, opt, hip_stream, ws, SCRATCH_BYTES, dev, out);
+  if (rc != BDEM_OK) scratch_release(dev);
+  return rc;
 }
 
 // ---------------------------------------------------------------------------
@@ -794,6 +883,9 @@ static int contact_candidates(bdem_ctx *ctx) {
 
 static int read_counters(bdem_ctx *ctx) {
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  // a handle in the static scratch keeps its counters in device memory
+  if (ctx->in_scratch)
+    HIP_TRY(hipMemcpy(ctx->h_counters, ctx->d.counters, 8 * sizeof(int), hipMemcpyDeviceToHost));
   return BDEM_OK;
 }
 
@@ -900,6 +992,10 @@ static int run_pcg(bdem_ctx *ctx) {
   // both when it stops, with several the count kernel rewrites its slot
   ctx->h_counters[1] = 1;
   ctx->h_counters[5] = 1;
+  if (ctx->in_scratch) {
+    HIP_TRY(hipMemcpyAsync(ctx->d.counters, ctx->h_counters, 8 * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
   launch_cg_init(ctx->d, mixed, st);
   if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, st);
   if (ctx->profiling == 1) prof_mark(ctx, 1, true);
@@ -926,6 +1022,12 @@ static int run_pcg(bdem_ctx *ctx) {
     } else {
       for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling == 1);
       if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, slot, st);
+    }
+    if (ctx->in_scratch) {   // no events: drain the stream and read this chunk's count
+      rc = read_counters(ctx);
+      if (rc) return rc;
+      if (ctx->h_counters[4 * slot + 1] == 0) break;
+      continue;
     }
     HIP_TRY(hipEventRecord(ctx->ev_slot[slot], st));
     if (pending >= 0) {

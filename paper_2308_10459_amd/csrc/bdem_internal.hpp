@@ -105,7 +105,10 @@ struct DevPtrs {
   SceneCtl *ctl;                      // n_scenes
   int *scene_pbeg;                    // n_scenes + 1 (particle index, multiple of TILE)
   int *scene_bbeg;                    // n_scenes + 1 (bond index, multiple of TILE)
-  int *counters;                      // device address of 2 slots x 4 ints in mapped pinned host memory:
+  int *counters_ws;                   // 2 slots x 4 ints in the workspace (the counters of a handle
+                                      // created in the static scratch, which has no pinned host memory)
+  int *counters;                      // device address of 2 slots x 4 ints in mapped pinned host memory
+                                      // (or counters_ws):
                                       // [0] newton active, [1] cg active, [2] ls active, [3] degenerate bonds
   int *degenerate;                    // bonds with |q_i + q_j| below the threshold
   // element repulsion (Section 5.4); allocated only when enabled
