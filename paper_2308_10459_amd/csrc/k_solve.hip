@@ -601,7 +601,14 @@ __global__ void k_ls_decide(DevPtrs d, Params P) {
   const KSum et = kmerge(eb, ep);
   const double phit = et.s + et.c;
   c.phi_trial = phit;
-  if (isfinite(phit) && phit <= c.phi + P.armijo_c * c.alpha_ls * c.slope) {
+  // Armijo test.  When the predicted decrease -alpha * slope is below the
+  // objective's FP64 resolution (1e-15 |Phi|), the comparison of two sums of
+  // that size is decided by rounding: there a trial is accepted unless it
+  // raises Phi by more than that resolution, so that the Newton step near
+  // the fixed point is not cut down by rounding noise
+  const double res = 1e-15 * fabs(c.phi);
+  const double slack = (-c.alpha_ls * c.slope <= res) ? res : 0.0;
+  if (isfinite(phit) && phit <= c.phi + P.armijo_c * c.alpha_ls * c.slope + slack) {
     c.ls_accept = 1;
     c.ls_active = 0;
     c.unresolved = -c.alpha_ls * c.slope <= 1e-15 * fabs(c.phi);

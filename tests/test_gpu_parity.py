@@ -69,6 +69,9 @@ def test_energy_grad_hess_block(B, mixed, psd, ground, dims):
     sim.set_state(**st)
     what = B.BDEM_EGH_E | B.BDEM_EGH_G | B.BDEM_EGH_H | (B.BDEM_EGH_PSD if psd else 0)
     phi, z, hd, ho = sim.energy_grad_hess(dt, what, ev_pos, ev_quat)
+    tag = f"same-state n={sc.n} mixed={mixed} psd={psd} ground={ground}"
+    record_bound(f"{tag}: objective, relative", abs(phi - phi_o) / abs(phi_o), 1e-12)
+    record_bound(f"{tag}: reduced gradient / max|z|", np.abs(z - z_o).max() / np.abs(z_o).max(), 1e-11)
     assert abs(phi - phi_o) <= 1e-12 * abs(phi_o)
     assert np.abs(z - z_o).max() <= 1e-11 * np.abs(z_o).max()
     scale = row_scale(hd_o, ho_o, sc.ij, sc.n)
@@ -77,6 +80,7 @@ def test_energy_grad_hess_block(B, mixed, psd, ground, dims):
     eo = np.linalg.norm((ho - ho_o).reshape(sc.nb, -1), axis=1) / np.minimum(
         scale[sc.ij[:, 0]], scale[sc.ij[:, 1]])
     log(f"  max diag err {ed.max():.2e}  max off err {eo.max():.2e}")
+    record_bound(f"{tag}: Hessian blocks / block-row scale", max(ed.max(), eo.max()), tol)
     assert ed.max() <= tol and eo.max() <= tol
     # potential only: no inertia
     pv, _, _, _ = sim.energy_grad_hess(dt, B.BDEM_EGH_E | B.BDEM_EGH_POTENTIAL_ONLY, ev_pos, ev_quat)
@@ -195,6 +199,8 @@ def test_step_block_1000(B, mixed, hessian):
         np.testing.assert_allclose(got["vel"], ref["vel"], rtol=0,
                                    atol=tol * np.abs(ref["vel"]).max() * 10 + 1e-14)
         # the energy at the accepted state, evaluated by the oracle, agrees
+        record_bound(f"block {hessian} mixed={mixed} step {k}: objective at the new state, relative",
+                     abs(sg["phi"] - so["phi"]) / abs(so["phi"]), 1e-6 if mixed else 1e-10)
         assert abs(sg["phi"] - so["phi"]) <= (1e-6 if mixed else 1e-10) * abs(so["phi"])
         prev = ref
     sim.close()
