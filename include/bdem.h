@@ -166,6 +166,12 @@ typedef struct {
                               Weingarten share kept only where positive; PSD term by term and
                               equal to the exact Hessian at zero strain.  It is evaluated by one
                               row-parallel kernel (no per-slot halves in memory) */
+  int32_t amg_refresh;     /* multigrid only: 0 rebuilds the coarse levels (prolongators, Galerkin
+                              products, inverses) at every Newton iteration; 1 (default) at the
+                              first Newton iteration of each step and reuses them for the rest of
+                              the step (the fine level, its smoother and the PCG's matrix are
+                              always current; any such V-cycle is a fixed SPD operator within a
+                              PCG solve, so only the iteration count can change) */
 } bdem_options;
 
 typedef struct {

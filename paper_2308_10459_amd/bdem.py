@@ -63,7 +63,7 @@ class bdem_options(C.Structure):
                 ("max_cg", C.c_int32), ("max_ls", C.c_int32), ("precision", C.c_int32),
                 ("break_each_step", C.c_int32), ("cg_chunk", C.c_int32), ("use_graph", C.c_int32),
                 ("solver", C.c_int32), ("integrator", C.c_int32), ("preconditioner", C.c_int32),
-                ("hessian", C.c_int32)]
+                ("hessian", C.c_int32), ("amg_refresh", C.c_int32)]
 
 
 class bdem_step_stats(C.Structure):

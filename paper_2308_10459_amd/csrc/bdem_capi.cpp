@@ -245,6 +245,7 @@ extern "C" void bdem_default_options(bdem_options *o) {
   o->contact_margin = -1.0;
   o->preconditioner = BDEM_PRECOND_BLOCK_JACOBI;
   o->hessian = BDEM_HESS_GAUSS_NEWTON;
+  o->amg_refresh = 1;
 }
 
 extern "C" size_t bdem_workspace_bytes(const bdem_particles *p, const bdem_bonds *b,
@@ -446,6 +447,8 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
     return fail(nullptr, BDEM_E_INVALID, "integrator must be BDEM_INTEGRATOR_EULER or BDEM_INTEGRATOR_MIDPOINT");
   if (o.hessian != BDEM_HESS_EIGEN_CLAMP && o.hessian != BDEM_HESS_GAUSS_NEWTON)
     return fail(nullptr, BDEM_E_INVALID, "hessian must be BDEM_HESS_EIGEN_CLAMP or BDEM_HESS_GAUSS_NEWTON");
+  if (o.amg_refresh != 0 && o.amg_refresh != 1)
+    return fail(nullptr, BDEM_E_INVALID, "amg_refresh must be 0 or 1");
   if (o.max_newton < 0 || o.max_cg <= 0 || o.max_ls < 0 || o.cg_chunk <= 0)
     return fail(nullptr, BDEM_E_INVALID, "bad iteration limits");
   // ---- validation ----
@@ -1120,7 +1123,9 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     HIP_TRY(hipEventRecord(ph[1], st));
     const bool hess = !ctx->P.first_order;   // Algorithm 1 needs the gradient only
     launch_evaluation(ctx, hess, true, k == 0, false);
-    if (hess && ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
+    // the multigrid hierarchy: every Newton iteration, or once per step
+    if (hess && ctx->amg && (k == 0 || ctx->opt.amg_refresh == 0))
+      launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
     launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, rows_path(ctx, hess), st);
     launch_count_active(d, NS, 0, st);
     int rc = read_counters(ctx);

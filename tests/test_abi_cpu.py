@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(B):
 
 def test_struct_sizes_match_header_layout(B):
     # doubles first then int32s, natural alignment: the ctypes mirror must not pad differently
-    assert C.sizeof(B.bdem_options) == 8 * (3 + 3 + 1 + 1 + 2 + 2 + 4) + 4 * 11 + 4  # tail padding
+    assert C.sizeof(B.bdem_options) == 8 * (3 + 3 + 1 + 1 + 2 + 2 + 4) + 4 * 12
     assert C.sizeof(B.bdem_material) == 8 * 9 + 4 * 2
     assert C.sizeof(B.bdem_step_stats) == 4 * 4 + 8 + 8 * 3 + 8 * 8
     assert C.sizeof(B.bdem_tuning) == 4 * 6 + 8 * 3
@@ -56,6 +56,7 @@ def test_default_options(B):
     assert o.integrator == B.BDEM_INTEGRATOR_EULER
     assert o.preconditioner == B.BDEM_PRECOND_BLOCK_JACOBI
     assert o.hessian == B.BDEM_HESS_GAUSS_NEWTON
+    assert o.amg_refresh == 1
 
 
 def test_workspace_bytes_scales_with_problem(B):
