@@ -6,7 +6,8 @@
 // cells of the level below by doubling the side.  The hierarchy (which nodes
 // belong together, every coarse sparsity pattern and the list of fine blocks
 // that sum into each coarse block) is built once on the host at create; the
-// numbers are recomputed on the device at every Newton iteration:
+// numbers are recomputed on the device at the first Newton iteration of each
+// step (or at every one, bdem_options.amg_refresh = 0):
 //   P_i = [[I, -[x_i - c_a]x], [0, S_i]]  (rigid-body modes t, w of the
 //         aggregate a: dp = t + w x (x_i - c_a), y = S_i w; S_i = 1/2 R(q_i)^T
 //         for particles, I above), zero for particles that are not unknowns;
@@ -24,6 +25,12 @@ namespace bdem {
 
 constexpr int AMG_COARSE_MAX = 12;
 constexpr double AMG_OMEGA = 0.8;
+// levels whose every scene has at most AMG_TAIL_ROWS nodes and
+// AMG_TAIL_SLOTS blocks (and all coarser ones) are cycled by one workgroup
+// per scene in a single launch, their products held in LDS
+constexpr int AMG_TAIL_ROWS = 256;
+constexpr int AMG_TAIL_SLOTS = 1024;
+constexpr int AMG_TAIL_THREADS = 1024;
 
 // device view of one coarse level (level >= 1)
 struct AmgLevel {
@@ -43,6 +50,9 @@ struct AmgLevel {
 // device view of the whole hierarchy
 struct AmgDev {
   int L = 0;                        // coarse levels (>= 1)
+  int Lt = 0;                       // first level of the single-launch tail (1 <= Lt <= L)
+  int *tbeg = nullptr;              // (L - Lt + 1) x (n_scenes + 1): node range per scene on the
+                                    // tail levels, level l at (l - Lt) * (n_scenes + 1)
   // fine level (particles, internal order)
   int *slot_row0 = nullptr;         // row of each fine off-diagonal slot
   int *parent0 = nullptr;           // level-1 node of each particle (-1: padding)
@@ -63,6 +73,8 @@ struct AmgHostLevel {
 };
 struct AmgHost {
   int L = 0;
+  int Lt = 0;
+  std::vector<int> tbeg;
   std::vector<int> parent0, slot_row0;
   std::vector<AmgHostLevel> lv;     // lv[1..L]
   std::vector<int> cbeg;
@@ -83,7 +95,10 @@ void amg_build(int n_pad, int n_scenes, const std::vector<double> &pos4,
 // hl: host copy of the level array (sizes for the launches)
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
                       hipStream_t s);
+// t0_ready: the CG update already wrote t0 = omega D^-1 r (DevPtrs::amg_t0);
+// the cycle writes u = M^-1 r into d.cs and the (r, u), (r, r) partials of
+// each SPMV_ROWS-row block
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       int spmv_variant, hipStream_t s);
+                       int spmv_variant, bool t0_ready, hipStream_t s);
 
 }  // namespace bdem

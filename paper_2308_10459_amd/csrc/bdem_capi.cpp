@@ -347,6 +347,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   AmgDev &a = ctx->amg_d;
   a = AmgDev();
   a.L = H.L;
+  a.Lt = H.Lt;
   ctx->amg_hl.assign(H.L + 1, AmgLevel());
   auto addi = [&](int **p, size_t n) { L.add(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(int)); };
   auto addd = [&](double **p, size_t n) { L.add(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(double)); };
@@ -378,6 +379,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
     for (double **v : {&V.b, &V.t, &V.r, &V.e}) addd(v, 6 * (size_t)h.n);
   }
   addi(&a.cbeg, NS + 1);
+  addi(&a.tbeg, H.tbeg.size());
   L.add(reinterpret_cast<void **>(&a.coff), NS * sizeof(int64_t));
   addd(&a.cmat, (size_t)H.cdense);
   addd(&a.cwork, (size_t)H.cdense);
@@ -408,12 +410,14 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
     for (double *v : {V.b, V.t, V.r, V.e, V.cen, V.pd}) chk(hipMemsetAsync(v, 0, std::max<size_t>(6 * (size_t)h.n, 1) * sizeof(double) / (v == V.cen || v == V.pd ? 2 : 1), st));
   }
   upi(a.cbeg, H.cbeg);
+  upi(a.tbeg, H.tbeg);
   chk(hipMemcpyAsync(a.coff, H.coff.data(), NS * sizeof(int64_t), hipMemcpyHostToDevice, st));
   chk(hipMemcpyAsync(lvdev, ctx->amg_hl.data(), (H.L + 1) * sizeof(AmgLevel), hipMemcpyHostToDevice, st));
   for (double *v : {a.pd0, a.t0, a.r0}) chk(hipMemsetAsync(v, 0, (v == a.pd0 ? 12 : 6) * (size_t)NP * sizeof(double), st));
   chk(hipStreamSynchronize(st));
   if (e != hipSuccess) { ctx->err = std::string("HIP error during multigrid setup: ") + hipGetErrorString(e); return BDEM_E_HIP; }
   ctx->amg = true;
+  ctx->d.amg_t0 = a.t0;   // the CG update writes the cycle's first step there
   return BDEM_OK;
 }
 
@@ -952,15 +956,18 @@ static void launch_evaluation(bdem_ctx *ctx, bool hess, bool psd, bool first, bo
 static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   const bool mixed = ctx->S.mixed;
   // block-Jacobi: the update forms (r, u) and (r, r) with the u it writes;
-  // multigrid: u = V(r) replaces that u, and the SpMV forms them
+  // multigrid: the update writes the cycle's first step, and the cycle's last
+  // kernel writes u = V(r) and forms them
   const bool amg = ctx->amg;
   launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream, !amg);
-  if (amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, ctx->stream);
+  if (amg)
+    launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, true,
+                      ctx->stream);
   if (profile_spmv) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, amg);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, SPMV_DOTS_WU);
   if (profile_spmv) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, ctx->stream);
-  launch_cg_scalars(ctx->d, ctx->P, ctx->stream, !amg);
+  launch_cg_scalars(ctx->d, ctx->P, ctx->stream, true);
 }
 
 static void drop_cg_graphs(bdem_ctx *ctx) {
@@ -1000,7 +1007,7 @@ static int run_pcg(bdem_ctx *ctx) {
     HIP_TRY(hipStreamSynchronize(st));
   }
   launch_cg_init(ctx->d, mixed, st);
-  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, st);
+  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, false, st);
   if (ctx->profiling == 1) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling == 1) prof_mark(ctx, 1, false);
@@ -1470,7 +1477,7 @@ extern "C" int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_ev
   for (int sc = 0; sc < NS; ++sc) ctx->h_ctl[sc].cg_active = 1;
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   if (ctx->amg) {
-    launch_amg_vcycle(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, ctx->spmv_variant, st);
+    launch_amg_vcycle(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, ctx->spmv_variant, false, st);
   } else {
     // block-Jacobi: the PCG initialisation computes u = D^-1 r from r = -z
     HIP_TRY(hipMemcpyAsync(d.z, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1679,14 +1686,14 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
       for (int vs = 0; vs < nsv; ++vs) {
         const double us = time_it([&] {
           launch_cg_update(d, mixed, vu, st, !ctx->amg);
-          launch_spmv(d, mixed, vs, st, ctx->amg);
+          launch_spmv(d, mixed, vs, st, SPMV_DOTS_WU);
         }, 20);
         pair_us[vu * nsv + vs] = std::min(pair_us[vu * nsv + vs], us);
       }
   double best = 1e300;
   for (int k = 0; k < nu * nsv; ++k)
     if (pair_us[k] < best) { best = pair_us[k]; ctx->upd_variant = k / nsv; ctx->spmv_variant = k % nsv; }
-  ctx->tune_us[0] = time_it([&] { launch_spmv(d, mixed, ctx->spmv_variant, st, ctx->amg); }, 5);
+  ctx->tune_us[0] = time_it([&] { launch_spmv(d, mixed, ctx->spmv_variant, st, SPMV_DOTS_WU); }, 5);
   ctx->tune_us[1] = time_it([&] { launch_cg_update(d, mixed, ctx->upd_variant, st, !ctx->amg); }, 5);
   HIP_TRY(hipGetLastError());
   // PCG polling: each candidate runs the same solve from x = 0

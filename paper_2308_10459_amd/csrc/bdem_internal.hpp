@@ -97,6 +97,8 @@ struct DevPtrs {
   double *z;     // 6 n_pad
   // CG
   double *cx, *cr, *cs, *cp, *cAp, *cq;
+  double *amg_t0;                     // multigrid only: the CG update writes the cycle's pre-smoothed
+                                      // start omega D^-1 r here in place of u (null otherwise)
   // reductions
   double2 *part_a, *part_b, *part_c;  // per-block compensated partials
   double2 *part_ag, *part_cg;         // part_a, part_c merged per DOT_GROUP SpMV blocks (one slot per TILE rows)
@@ -156,9 +158,12 @@ void launch_count_active(const DevPtrs &d, int n_scenes, int slot, hipStream_t s
 void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
 // PCG
 void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
-// rdots = false: the SpMV leaves the (r, u) and (r, r) partials to the CG
-// update that produced u (launch_cg_update with rdots = true)
-void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots = true);
+// dots: SPMV_DOTS_ALL forms the (r, u), (w, u) and (r, r) partials;
+// SPMV_DOTS_WU leaves (r, u) and (r, r) to the kernel that produced u (the CG
+// update with rdots = true, or the multigrid cycle's last kernel) and merges
+// theirs; SPMV_DOTS_NONE writes w only (the products inside the cycle)
+enum SpmvDots { SPMV_DOTS_WU = 0, SPMV_DOTS_ALL = 1, SPMV_DOTS_NONE = 2 };
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, int dots = SPMV_DOTS_ALL);
 int spmv_variants();
 void spmv_shape(int variant, int *threads, int *trips);
 void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s, bool grouped);

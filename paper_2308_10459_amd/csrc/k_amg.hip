@@ -1,7 +1,7 @@
-// Aggregation multigrid preconditioner: numeric setup at every Newton
-// iteration (rigid-body-mode prolongation, Galerkin coarse operators,
-// block-Jacobi inverses, dense inverse of the last level per scene) and the
-// V-cycle applied to the PCG residual.  The symbolic hierarchy and its
+// Aggregation multigrid preconditioner: numeric setup at the first Newton
+// iteration of a step, or at every one (rigid-body-mode prolongation,
+// Galerkin coarse operators, block-Jacobi inverses, dense inverse of the
+// last level per scene) and the V-cycle applied to the PCG residual.  The symbolic hierarchy and its
 // definitions are described in bdem_amg.hpp.  All sums run in a fixed order
 // (contribution and child lists are sorted at create), so results are
 // reproducible run to run.
@@ -365,49 +365,67 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_pre(Dev
   st6(a.t0 + (size_t)r * 6, y);
 }
 
-// b_1 = P^T (r - H t0) (level-1 node: sum over its particles); r0 holds H t0
-// pre-smoothing of one node from a zero start: t = omega D^-1 b
-template <typename T>
-__device__ __forceinline__ void pre_smooth_node(const AmgLevel &L, int A, const double (&b)[6]) {
-  double y[6];
-  mat36_apply(reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36, b, y);
+// b of level 1 from the fine residual r - H t0 (r0 holds H t0), and with
+// `smooth` (level 1 is not the coarsest) its pre-smoothing t = omega D^-1 b.
+// R1_LANES lanes per level-1 node: lane k takes the node's particles k,
+// k + R1_LANES, ...; the lanes' sums then meet in a fixed butterfly, and six
+// of them write b and t.
+constexpr int R1_LANES = 16;   // a cell of side 4 r holds about 11 close-packed particles
+constexpr int RC_LANES = 8;    // a coarser cell holds at most 8 cells
+
+template <int G> __device__ __forceinline__ void lanes_sum6(double (&v)[6]) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) y[k] *= AMG_OMEGA;
-  st6(L.t + (size_t)A * 6, y);
+  for (int off = G / 2; off >= 1; off >>= 1)
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v[m] += __shfl_xor(v[m], off, 64);
 }
 
-// b of level 1 from the fine residual r - H t0; with `smooth` (level 1 is
-// not the coarsest) also its pre-smoothing
+// lane c < 6 of a node's group: b_c, and with `smooth` t_c = omega (D^-1 b)_c
+template <typename T>
+__device__ __forceinline__ void store_b_and_smooth(const AmgLevel &L, int A, int c, const double (&acc)[6],
+                                                   int smooth) {
+  double bc = 0.0;
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+    if (m == c) bc = acc[m];
+  L.b[(size_t)A * 6 + c] = bc;
+  if (!smooth) return;
+  const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + c * 6;
+  double y = 0.0;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) y += double(Di[m]) * acc[m];
+  L.t[(size_t)A * 6 + c] = AMG_OMEGA * y;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int smooth) {
   const AmgLevel &L = a.lv[1];
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= L.n) return;
+  const int A = (blockIdx.x * 256 + (int)threadIdx.x) / R1_LANES, k0 = threadIdx.x % R1_LANES;
+  const bool live = A < L.n;   // the same for the whole group
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = L.mbeg[A]; k < L.mbeg[A + 1]; ++k) {
-    const int i = L.mlist[k];
-    if (d.flags[i] != 0) continue;
-    const double *p = a.pd0 + (size_t)i * 12;
-    const double dd[3] = {p[0], p[1], p[2]};
-    double S[9];
+  if (live)
+    for (int k = L.mbeg[A] + k0; k < L.mbeg[A + 1]; k += R1_LANES) {
+      const int i = L.mlist[k];
+      if (d.flags[i] != 0) continue;
+      const double *p = a.pd0 + (size_t)i * 12;
+      const double dd[3] = {p[0], p[1], p[2]};
+      double S[9];
 #pragma unroll
-    for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
-    double x[6], h[6], y[6];
-    ld6(d.cr + (size_t)i * 6, x);
-    ld6(a.r0 + (size_t)i * 6, h);
+      for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
+      double x[6], h[6], y[6];
+      ld6(d.cr + (size_t)i * 6, x);
+      ld6(a.r0 + (size_t)i * 6, h);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) x[m] -= h[m];
-    pt_apply(dd, S, x, y);
+      for (int m = 0; m < 6; ++m) x[m] -= h[m];
+      pt_apply(dd, S, x, y);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) acc[m] += y[m];
-  }
-  st6(L.b + (size_t)A * 6, acc);
-  if (smooth) pre_smooth_node<T>(L, A, acc);
+      for (int m = 0; m < 6; ++m) acc[m] += y[m];
+    }
+  lanes_sum6<R1_LANES>(acc);
+  if (live && k0 < 6) store_b_and_smooth<T>(L, A, k0, acc, smooth);
 }
 
-// coarse level l: t = omega D^-1 b (done by the restriction that fills b),
-// then r = b - A t
-
+// r = b - A t on a level above the tail, one wavefront per row
 // component (lane mod 6) of A_row x by one wavefront: lane (g, c) with
 // g = lane / 6 < 10 takes the row's slots g, g + 10, ... for output
 // component c; the ten partials of a component are then added in lane order
@@ -431,7 +449,6 @@ __device__ __forceinline__ double wave_row_apply(const AmgLevel &L, int A, const
   return y;
 }
 
-// r = b - A t, one wavefront per row
 template <typename T> __global__ __launch_bounds__(256) void k_amg_resid(AmgDev a, int l) {
   const AmgLevel &L = a.lv[l];
   const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -440,82 +457,58 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_resid(AmgDev 
   if (lane < 6) L.r[(size_t)A * 6 + lane] = L.b[(size_t)A * 6 + lane] - y;
 }
 
-// b_{l+1} = P^T r_l (S = I above the particles); with `smooth` (level l + 1
-// is not the coarsest) also its pre-smoothing
+// b_{l+1} = P^T r_l (S = I above the particles) and, with `smooth` (level
+// l + 1 is not the coarsest), its pre-smoothing; RC_LANES lanes per node
 template <typename T>
 __global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l, int smooth) {
   const AmgLevel &C = a.lv[l + 1], &F = a.lv[l];
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= C.n) return;
+  const int A = (blockIdx.x * 256 + (int)threadIdx.x) / RC_LANES, k0 = threadIdx.x % RC_LANES;
+  const bool live = A < C.n;
   double acc[6] = {0, 0, 0, 0, 0, 0}, S[9];
   ident3(S);
-  for (int k = C.mbeg[A]; k < C.mbeg[A + 1]; ++k) {
-    const int i = C.mlist[k];
-    if (!F.active[i]) continue;
-    const double dd[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
-    double x[6], y[6];
-    ld6(F.r + (size_t)i * 6, x);
-    pt_apply(dd, S, x, y);
-#pragma unroll
-    for (int m = 0; m < 6; ++m) acc[m] += y[m];
-  }
-  st6(C.b + (size_t)A * 6, acc);
-  if (smooth) pre_smooth_node<T>(C, A, acc);
-}
-
-// t_f += P_f e_A for the members f of node A of level l (level l - 1 nodes,
-// or the fine particles when l = 1; S = I above the particles)
-__device__ __forceinline__ void prolong_members(const DevPtrs &d, const AmgDev &a, int l, int A,
-                                                const double (&e)[6], int k0, int kstep) {
-  const AmgLevel &C = a.lv[l];
-  for (int k = C.mbeg[A] + k0; k < C.mbeg[A + 1]; k += kstep) {
-    const int i = C.mlist[k];
-    double dd[3], S[9], y[6];
-    double *t;
-    if (l == 1) {
-      if (d.flags[i] != 0 || !d.ctl[d.psid[i]].cg_active) continue;
-      const double *p = a.pd0 + (size_t)i * 12;
-      dd[0] = p[0]; dd[1] = p[1]; dd[2] = p[2];
-#pragma unroll
-      for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
-      t = a.t0 + (size_t)i * 6;
-    } else {
-      const AmgLevel &F = a.lv[l - 1];
+  if (live)
+    for (int k = C.mbeg[A] + k0; k < C.mbeg[A + 1]; k += RC_LANES) {
+      const int i = C.mlist[k];
       if (!F.active[i]) continue;
-      dd[0] = F.pd[3 * i]; dd[1] = F.pd[3 * i + 1]; dd[2] = F.pd[3 * i + 2];
-      ident3(S);
-      t = F.t + (size_t)i * 6;
-    }
-    p_apply(dd, S, e, y);
+      const double dd[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
+      double x[6], y[6];
+      ld6(F.r + (size_t)i * 6, x);
+      pt_apply(dd, S, x, y);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) t[m] += y[m];
-  }
+      for (int m = 0; m < 6; ++m) acc[m] += y[m];
+    }
+  lanes_sum6<RC_LANES>(acc);
+  if (live && k0 < 6) store_b_and_smooth<T>(C, A, k0, acc, smooth);
 }
 
-// last level: e = A^-1 b per scene (dense), then prolonged into the members
-__global__ __launch_bounds__(256) void k_amg_coarse_solve(DevPtrs d, AmgDev a) {
-  const int sc = blockIdx.x;
-  const AmgLevel &L = a.lv[a.L];
-  const int nb = a.cbeg[sc], N = 6 * (a.cbeg[sc + 1] - nb);
-  const double *X = a.cwork + a.coff[sc];
-  for (int r = threadIdx.x; r < N; r += blockDim.x) {
-    double acc = 0.0;
-    for (int c = 0; c < N; ++c) acc += X[(size_t)r * N + c] * L.b[(size_t)6 * nb + c];
-    L.e[(size_t)6 * nb + r] = acc;
+// t_f += P_f e for one member f of a level-l node (a level l - 1 node, or a
+// fine particle when l = 1; S = I above the particles)
+__device__ __forceinline__ void prolong_one(const DevPtrs &d, const AmgDev &a, int l, int i,
+                                            const double (&e)[6]) {
+  double dd[3], S[9], y[6];
+  double *t;
+  if (l == 1) {
+    if (d.flags[i] != 0 || !d.ctl[d.psid[i]].cg_active) return;
+    const double *p = a.pd0 + (size_t)i * 12;
+    dd[0] = p[0]; dd[1] = p[1]; dd[2] = p[2];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
+    t = a.t0 + (size_t)i * 6;
+  } else {
+    const AmgLevel &F = a.lv[l - 1];
+    if (!F.active[i]) return;
+    dd[0] = F.pd[3 * i]; dd[1] = F.pd[3 * i + 1]; dd[2] = F.pd[3 * i + 2];
+    ident3(S);
+    t = F.t + (size_t)i * 6;
   }
-  __syncthreads();
-  for (int A = nb + (int)threadIdx.x; A < a.cbeg[sc + 1]; A += blockDim.x) {
-    double e[6];
-    ld6(L.e + (size_t)A * 6, e);
-    prolong_members(d, a, a.L, A, e, 0, 1);
-  }
+  p_apply(dd, S, e, y);
+#pragma unroll
+  for (int m = 0; m < 6; ++m) t[m] += y[m];
 }
 
-// then on each level up: e_l = t_l + omega D^-1 (b_l - A t_l) (t_l already holds
-// the prolonged correction), prolonged into the members of each node
-
-// e = t + omega D^-1 (b - A t), one wavefront per row; then t += P e on the
-// row's members one level down (the fine t0 for level 1)
+// on each level going up: e_l = t_l + omega D^-1 (b_l - A t_l) (t_l already
+// holds the prolonged correction), prolonged into the members of each node.
+// One wavefront per row; its lanes then take the row's members.
 template <typename T> __global__ __launch_bounds__(256) void k_amg_post(DevPtrs d, AmgDev a, int l) {
   const AmgLevel &L = a.lv[l];
   const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -537,24 +530,191 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_post(DevPtrs 
   double e[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) e[k] = __shfl(ev, k, 64);
-  prolong_members(d, a, l, A, e, lane, 64);
+  for (int k = L.mbeg[A] + lane; k < L.mbeg[A + 1]; k += 64) prolong_one(d, a, l, L.mlist[k], e);
 }
 
+// ---------------------------------------------------------------------------
+// The tail: levels Lt..L of one scene in one workgroup, in LDS.  The same
+// cycle as the per-level kernels: going down, r_l = b_l - A t_l and the
+// restriction into l + 1 with its pre-smoothing; the dense solve of the last
+// level; going up, e_l = t_l + omega D^-1 (b_l - A t_l) prolonged into the
+// level below (the last of them into level Lt - 1, or the fine t0, which the
+// next launch reads).  A product A x takes one thread per block (its six
+// components into LDS), then one thread per (row, component) adds its row's
+// blocks in slot order.
+// ---------------------------------------------------------------------------
 
-// u = t0 + omega D^-1 (r - H t0) into the PCG's u; r0 holds H t0
-template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_final(DevPtrs d, AmgDev a) {
-  const int r = blockIdx.x * TILE + threadIdx.x;
-  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
-  double y[6], b[6], u[6], t[6];
-  ld6(a.r0 + (size_t)r * 6, y);
-  ld6(d.cr + (size_t)r * 6, b);
+// res[(A - nb) * 6 + c] = (b - A t)_c for the scene's rows [nb, ne) of level L
+template <typename T>
+__device__ __forceinline__ void tail_residual(const AmgLevel &L, int nb, int ne, double *prod, double *res) {
+  const T *val = reinterpret_cast<const T *>(L.val);
+  const int s0 = L.row_ptr[nb], s1 = L.row_ptr[ne];
+  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
+    const T *blk = val + (size_t)s * 36;
+    double x[6];
+    ld6(L.t + (size_t)L.col[s] * 6, x);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) y[k] = b[k] - y[k];
-  sym21_apply(reinterpret_cast<const T *>(d.dinv) + (size_t)r * 21, y, u);
-  ld6(a.t0 + (size_t)r * 6, t);
+    for (int c = 0; c < 6; ++c) {
+      double acc = 0.0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) t[k] += AMG_OMEGA * u[k];
-  st6(d.cs + (size_t)r * 6, t);
+      for (int e = 0; e < 6; ++e) acc += double(blk[c * 6 + e]) * x[e];
+      prod[(s - s0) * 6 + c] = acc;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x) {
+    const int A = nb + q / 6, c = q - (q / 6) * 6;
+    double y = 0.0;
+    for (int s = L.row_ptr[A]; s < L.row_ptr[A + 1]; ++s) y += prod[(s - s0) * 6 + c];
+    res[q] = L.b[(size_t)A * 6 + c] - y;
+  }
+  __syncthreads();
+}
+
+// e of the rows [nb, ne) (6 values per row in ev) prolonged into their
+// members one level down
+__device__ __forceinline__ void tail_prolong(const DevPtrs &d, const AmgDev &a, int l, int nb, int ne,
+                                             const double *ev) {
+  const AmgLevel &L = a.lv[l];
+  const int *parent = (l == 1) ? a.parent0 : a.lv[l - 1].parent;
+  for (int k = L.mbeg[nb] + (int)threadIdx.x; k < L.mbeg[ne]; k += blockDim.x) {
+    const int i = L.mlist[k];
+    const double *ep = ev + (parent[i] - nb) * 6;
+    const double e[6] = {ep[0], ep[1], ep[2], ep[3], ep[4], ep[5]};
+    prolong_one(d, a, l, i, e);
+  }
+  __syncthreads();
+}
+
+template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_tail(DevPtrs d, AmgDev a) {
+  __shared__ double prod[AMG_TAIL_SLOTS * 6];
+  __shared__ double res[AMG_TAIL_ROWS * 6];
+  const int sc = blockIdx.x, NS = gridDim.x;
+  if (!d.ctl[sc].cg_active) return;   // uniform over the workgroup
+  auto range = [&](int l, int &nb, int &ne) {
+    const int *tb = a.tbeg + (size_t)(l - a.Lt) * (NS + 1);
+    nb = tb[sc];
+    ne = tb[sc + 1];
+  };
+  // going down
+  for (int l = a.Lt; l < a.L; ++l) {
+    int nb, ne, cb, ce;
+    range(l, nb, ne);
+    range(l + 1, cb, ce);
+    const AmgLevel &F = a.lv[l], &C = a.lv[l + 1];
+    tail_residual<T>(F, nb, ne, prod, res);
+    // b_{l+1} = P^T r_l, one thread per (node, component), members in order
+    for (int q = threadIdx.x; q < 6 * (ce - cb); q += blockDim.x) {
+      const int A = cb + q / 6, c = q - (q / 6) * 6;
+      double acc = 0.0;
+      for (int k = C.mbeg[A]; k < C.mbeg[A + 1]; ++k) {
+        const int i = C.mlist[k];
+        if (!F.active[i]) continue;
+        const double *x = res + (i - nb) * 6;
+        if (c < 3) {
+          acc += x[c];
+        } else {   // (d x x_p + x_y)_{c-3}, d = x_i - c_A
+          const double *dd = F.pd + 3 * (size_t)i;
+          const int u = (c - 2) % 3, v = (c - 1) % 3;
+          acc += (dd[u] * x[v] - dd[v] * x[u]) + x[c];
+        }
+      }
+      prod[q] = acc;
+      C.b[(size_t)A * 6 + c] = acc;
+    }
+    __syncthreads();
+    if (l + 1 < a.L)   // pre-smoothing from zero
+      for (int q = threadIdx.x; q < 6 * (ce - cb); q += blockDim.x) {
+        const int A = cb + q / 6, c = q - (q / 6) * 6;
+        const T *Di = reinterpret_cast<const T *>(C.dinv) + (size_t)A * 36 + c * 6;
+        double y = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) y += double(Di[m]) * prod[(A - cb) * 6 + m];
+        C.t[(size_t)A * 6 + c] = AMG_OMEGA * y;
+      }
+    __syncthreads();
+  }
+  // the last level: e = A^-1 b (dense), prolonged one level down
+  {
+    int nb, ne;
+    range(a.L, nb, ne);
+    const AmgLevel &L = a.lv[a.L];
+    const int N = 6 * (ne - nb);
+    const double *X = a.cwork + a.coff[sc];
+    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+      double acc = 0.0;
+      for (int c = 0; c < N; ++c) acc += X[(size_t)r * N + c] * L.b[(size_t)6 * nb + c];
+      res[r] = acc;
+      L.e[(size_t)6 * nb + r] = acc;
+    }
+    __syncthreads();
+    tail_prolong(d, a, a.L, nb, ne, res);
+  }
+  // going up
+  for (int l = a.L - 1; l >= a.Lt; --l) {
+    int nb, ne;
+    range(l, nb, ne);
+    const AmgLevel &L = a.lv[l];
+    tail_residual<T>(L, nb, ne, prod, res);
+    double ev[(6 * AMG_TAIL_ROWS + AMG_TAIL_THREADS - 1) / AMG_TAIL_THREADS];
+    int m = 0;
+    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x, ++m) {
+      const int A = nb + q / 6, c = q - (q / 6) * 6;
+      const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + c * 6;
+      double u = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) u += double(Di[k]) * res[(A - nb) * 6 + k];
+      ev[m] = L.t[(size_t)A * 6 + c] + AMG_OMEGA * u;
+    }
+    __syncthreads();   // every thread has read res
+    m = 0;
+    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x, ++m) {
+      res[q] = ev[m];
+      L.e[(size_t)nb * 6 + q] = ev[m];
+    }
+    __syncthreads();
+    tail_prolong(d, a, l, nb, ne, res);
+  }
+}
+
+// u = t0 + omega D^-1 (r - H t0) into the PCG's u (r0 holds H t0), and the
+// (r, u), (r, r) partials of the SPMV_ROWS-row block for the PCG's scalars
+// (thread (row, component); the block's three wavefronts merge in order, as
+// the CG update's do)
+template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) void k_amg_fine_final(DevPtrs d, AmgDev a) {
+  static_assert(6 * SPMV_ROWS == 192, "three wavefronts per block");
+  __shared__ double ys[6 * SPMV_ROWS];
+  __shared__ double wd[4][3];
+  const int r0 = blockIdx.x * SPMV_ROWS;
+  if (!d.ctl[d.psid[r0]].cg_active) return;   // uniform over the workgroup
+  const int t = threadIdx.x, rl = t / 6, c = t - rl * 6;
+  const size_t o = (size_t)r0 * 6 + t;
+  const double rv = d.cr[o];
+  ys[t] = rv - a.r0[o];
+  __syncthreads();
+  const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)(r0 + rl) * 21;
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v += double(Di[up6(c, k)]) * ys[rl * 6 + k];
+  const double un = a.t0[o] + AMG_OMEGA * v;
+  d.cs[o] = un;
+  KSum ru = {0.0, 0.0}, rr = {0.0, 0.0};
+  kadd(ru, rv * un);
+  kadd(rr, rv * rv);
+  ru = wave_ksum(ru);
+  rr = wave_ksum(rr);
+  const int wv = t >> 6;
+  if ((t & 63) == 0) { wd[0][wv] = ru.s; wd[1][wv] = ru.c; wd[2][wv] = rr.s; wd[3][wv] = rr.c; }
+  __syncthreads();
+  if (t == 0) {
+    KSum x = {0.0, 0.0}, y = {0.0, 0.0};
+    for (int k = 0; k < 3; ++k) {
+      x = kmerge(x, KSum{wd[0][k], wd[1][k]});
+      y = kmerge(y, KSum{wd[2][k], wd[3][k]});
+    }
+    d.part_a[blockIdx.x] = make_double2(x.s, x.c);
+    d.part_c[blockIdx.x] = make_double2(y.s, y.c);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -576,26 +736,26 @@ static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n
 
 template <typename T>
 static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                     int spmv_variant, hipStream_t s) {
-  const int np = d.n_pad / TILE;
-  // the fine products H t0 run through the PCG's own SpMV kernel (its dot
-  // partials are overwritten by the PCG's next SpMV)
+                     int spmv_variant, bool t0_ready, hipStream_t s) {
+  // the fine products H t0 run through the PCG's own SpMV kernel, without
+  // its dots
   DevPtrs dt = d;
   dt.cs = a.t0;
   dt.cAp = a.r0;
-  k_amg_fine_pre<T><<<np, TILE, 0, s>>>(d, a);
-  launch_spmv(dt, mixed, spmv_variant, s);
+  if (!t0_ready) k_amg_fine_pre<T><<<d.n_pad / TILE, TILE, 0, s>>>(d, a);
+  launch_spmv(dt, mixed, spmv_variant, s, SPMV_DOTS_NONE);
   // each restriction also pre-smooths the level it fills (not the coarsest)
-  k_amg_restrict1<T><<<nblk(hl[1].n, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
-  for (int l = 1; l < a.L; ++l) {
+  k_amg_restrict1<T><<<nblk(hl[1].n * R1_LANES, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
+  for (int l = 1; l < a.Lt; ++l) {
     k_amg_resid<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
-    k_amg_restrict<T><<<nblk(hl[l + 1].n, 256), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
+    k_amg_restrict<T><<<nblk(hl[l + 1].n * RC_LANES, 256), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
   }
+  // levels Lt..L in one launch; it prolongs into level Lt - 1 (or t0)
+  k_amg_tail<T><<<n_scenes, AMG_TAIL_THREADS, 0, s>>>(d, a);
   // each level's kernel also prolongs its correction one level down
-  k_amg_coarse_solve<<<n_scenes, 256, 0, s>>>(d, a);
-  for (int l = a.L - 1; l >= 1; --l) k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(d, a, l);
-  launch_spmv(dt, mixed, spmv_variant, s);
-  k_amg_fine_final<T><<<np, TILE, 0, s>>>(d, a);
+  for (int l = a.Lt - 1; l >= 1; --l) k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(d, a, l);
+  launch_spmv(dt, mixed, spmv_variant, s, SPMV_DOTS_NONE);
+  k_amg_fine_final<T><<<d.n_pad / SPMV_ROWS, 6 * SPMV_ROWS, 0, s>>>(d, a);
 }
 
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
@@ -604,9 +764,9 @@ void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int
   else setup_t<double>(d, a, hl, n_scenes, s);
 }
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       int spmv_variant, hipStream_t s) {
-  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, true, spmv_variant, s);
-  else vcycle_t<double>(d, a, hl, n_scenes, false, spmv_variant, s);
+                       int spmv_variant, bool t0_ready, hipStream_t s) {
+  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, true, spmv_variant, t0_ready, s);
+  else vcycle_t<double>(d, a, hl, n_scenes, false, spmv_variant, t0_ready, s);
 }
 
 }  // namespace bdem

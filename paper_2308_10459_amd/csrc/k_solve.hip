@@ -11,6 +11,7 @@
 // control blocks on the device, so one CG iteration is a fixed sequence of
 // launches that can be replayed from a captured graph; the host only polls
 // the number of scenes still iterating.
+#include "bdem_amg.hpp"
 #include "bdem_internal.hpp"
 #include "bdem_math.hpp"
 
@@ -175,13 +176,15 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // Phase 2: thread (row, c) adds the diagonal block times u_row and its row's
 // slot products in slot order, so the sum order is fixed and the launch
 // shape (NT, U) does not change a bit: threads past 6 * SPMV_ROWS add zeros
-// to the dots after the row threads' waves.  With rdots = 0 the kernel
-// leaves (r, u) and (r, r) to the CG update that produced u (and does not
-// read r); their partials are then the update's, and every DOT_GROUP-th
+// to the dots after the row threads' waves.  With rdots = SPMV_DOTS_WU the
+// kernel leaves (r, u) and (r, r) to the kernel that produced u (the CG
+// update, or the multigrid cycle's last kernel) and does not read r; their
+// partials are then that kernel's, and every DOT_GROUP-th
 // workgroup of a scene merges them for the scalars step: wavefront 0 takes
 // the partials of its own block and the next DOT_GROUP - 1 (one butterfly
 // tree per group, whatever the launch shape).  The merging workgroups are
-// spread over the scene, and so over all XCDs.
+// spread over the scene, and so over all XCDs.  SPMV_DOTS_NONE (the
+// products inside the multigrid cycle) writes w and nothing else.
 template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d, int rdots) {
   static_assert(NT >= 6 * SPMV_ROWS, "one thread per (row, component)");
   constexpr int NQ = 36 * (int)sizeof(T) / 16;       // 16-byte pieces per block
@@ -217,7 +220,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   if (rowthr) {
     rbeg = d.row_ptr[row];
     rend = d.row_ptr[row + 1];
-    if (rdots) rc = d.cr[(size_t)row * 6 + c_out];
+    if (rdots == SPMV_DOTS_ALL) rc = d.cr[(size_t)row * 6 + c_out];
   }
   // the diagonal block times u_row, added before any slot product
   auto add_diag = [&]() {
@@ -325,6 +328,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
     __syncthreads();
   }
   if (rowthr) d.cAp[(size_t)row * 6 + c_out] = acc;
+  if (rdots == SPMV_DOTS_NONE) return;   // uniform over the launch
   KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
   if (rowthr) {
     kadd(ru, rc * uc);
@@ -334,7 +338,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   block_ksum3(ru, wu, rr);
   if (t == 0) {
     d.part_b[lb] = make_double2(wu.s, wu.c);
-    if (rdots) {
+    if (rdots == SPMV_DOTS_ALL) {
       d.part_a[lb] = make_double2(ru.s, ru.c);
       d.part_c[lb] = make_double2(rr.s, rr.c);
     }
@@ -342,7 +346,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   // the update's dot partials this workgroup merges, if any (at the end, so
   // that their loads do not sit ahead of the block loads)
   const int sb0 = d.scene_pbeg[scene] / SPMV_ROWS, sb1 = d.scene_pbeg[scene + 1] / SPMV_ROWS, gl = lb - sb0;
-  if (!rdots && gl % DOT_GROUP == 0 && t < 64) {   // all of wavefront 0
+  if (rdots == SPMV_DOTS_WU && gl % DOT_GROUP == 0 && t < 64) {   // all of wavefront 0
     double2 ga = make_double2(0.0, 0.0), gc = make_double2(0.0, 0.0);
     const int k = lb + t;
     if (t < DOT_GROUP && k < sb1) {
@@ -457,8 +461,9 @@ template <bool GROUPED> __global__ __launch_bounds__(SCAL_THREADS) void k_cg_sca
   }
 }
 
-// p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r.
-// Thread (row, component): every vector is read and written with unit
+// p = u + beta p ; q = w + beta q ; x += alpha p ; r -= alpha q ; u = M^-1 r
+// (with multigrid t0 = omega D^-1 r, the first step of the V-cycle, in place
+// of u).  Thread (row, component): every vector is read and written with unit
 // stride; the new residual of the row is shared through LDS for M^-1 r, and
 // the rows' Jacobi inverses are staged there with 16-byte loads (read
 // directly, each thread would issue six scattered 4-byte loads).
@@ -513,6 +518,11 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   double un = 0.0;
 #pragma unroll
   for (int k = 0; k < 6; ++k) un += double(Di[up6(cc, k)]) * rs[rl * 6 + k];
+  if (d.amg_t0) {   // multigrid (uniform over the launch): the cycle's pre-smoothed
+                    // start; the cycle's last kernel writes u and the r dots
+    d.amg_t0[o] = AMG_OMEGA * un;
+    return;
+  }
   d.cs[o] = un;
   if (!rdots) return;   // uniform over the launch
   constexpr int NWV = 6 * ROWS / 64;
@@ -664,9 +674,9 @@ template <typename T> static void spmv_dispatch(const DevPtrs &d, int v, int rd,
     default: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d, rd); break;
   }
 }
-void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, bool rdots) {
-  if (mixed) spmv_dispatch<float>(d, variant, rdots ? 1 : 0, s);
-  else spmv_dispatch<double>(d, variant, rdots ? 1 : 0, s);
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, int dots) {
+  if (mixed) spmv_dispatch<float>(d, variant, dots, s);
+  else spmv_dispatch<double>(d, variant, dots, s);
 }
 void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s, bool grouped) {
   if (grouped) k_cg_scalars<true><<<P.n_scenes, SCAL_THREADS, 0, s>>>(d, P);
