@@ -56,7 +56,7 @@ struct orc_sys {
   int32_t *cp;                          /* (i, j) with i < j */
   double *hcp;                          /* (i, j) 6x6 block of each pair at the last Hessian */
   int hcp_valid;
-  /* multigrid aggregation: cells of size 4 r_max from the initial box corner */
+  /* multigrid aggregation: cells of size 8 r_max from the initial box corner */
   int64_t *cell;                        /* 3 per particle */
 };
 
@@ -297,7 +297,7 @@ orc_sys *orc_create(int32_t n, const double *pos, const double *quat, const doub
     double lo[3] = {1e300, 1e300, 1e300};
     for (int32_t i = 0; i < n; ++i)
       for (int k = 0; k < 3; ++k) lo[k] = fmin(lo[k], pos[3 * i + k]);
-    double h0 = 4.0 * rmax;
+    double h0 = 8.0 * rmax;
     s->cell = (int64_t *)malloc(3 * (size_t)n * sizeof(int64_t));
     for (int32_t i = 0; i < n; ++i)
       for (int k = 0; k < 3; ++k) s->cell[3 * i + k] = (int64_t)floor((pos[3 * i + k] - lo[k]) / h0);
@@ -1377,7 +1377,7 @@ void orc_friction(orc_sys *s, double dt) {
 /* ------------------------------------------------------------------------ */
 /* Aggregation multigrid preconditioner.  Section 5.3 solves with AMG-PCG    */
 /* without giving the method; this is the variant the GPU path implements:  */
-/* aggregates = cells of side 4 r_max (from the initial box corner; cells    */
+/* aggregates = cells of side 8 r_max (from the initial box corner; cells    */
 /* of twice the side at each coarser level), prolongation from the six      */
 /* rigid-body modes of each aggregate, Galerkin coarse operators, damped    */
 /* block-Jacobi smoothing (omega = 0.8) before and after the coarse          */

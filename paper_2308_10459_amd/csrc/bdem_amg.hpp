@@ -1,8 +1,8 @@
 // Aggregation multigrid preconditioner for the block-CSR reduced Hessian
 // (Section 5.3 solves with AMG-PCG; the variant is this project's choice).
 //
-// Aggregates are cells of side h0 = 4 r_max of the scene, counted from the
-// corner of the scene's initial bounding box; a coarser level groups the
+// Aggregates are cells of side h0 = AMG_CELL r_max of the scene, counted
+// from the corner of the scene's initial bounding box; a coarser level groups the
 // cells of the level below by doubling the side.  The hierarchy (which nodes
 // belong together, every coarse sparsity pattern and the list of fine blocks
 // that sum into each coarse block) is built once on the host at create; the
@@ -23,6 +23,12 @@
 
 namespace bdem {
 
+// cell side in units of the largest radius: 8 r_max holds about 4 x 4 x 4
+// lattice sites of a close-packed solid.  On the 219K plate cells of 4, 5, 6
+// and 8 r_max all need ~22.6 CG iterations per Newton iteration, and the
+// larger cells make every level smaller (8 r_max fastest; past 10 r_max the
+// first level's restriction and Galerkin sums grow long)
+constexpr double AMG_CELL = 8.0;
 constexpr int AMG_COARSE_MAX = 12;
 constexpr double AMG_OMEGA = 0.8;
 // levels whose every scene has at most AMG_TAIL_ROWS nodes and

@@ -809,7 +809,7 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
       lo3[3 * sc + 1] = std::min(lo3[3 * sc + 1], h_pn[r].y);
       lo3[3 * sc + 2] = std::min(lo3[3 * sc + 2], h_pn[r].z);
     }
-    for (int sc = 0; sc < NS; ++sc) h0[sc] = 4.0 * s_rmax[sc];
+    for (int sc = 0; sc < NS; ++sc) h0[sc] = AMG_CELL * s_rmax[sc];
     const int rc = amg_upload(ctx, pos4, h_flags, h_psid, rp, h_col, lo3, h0);
     if (rc) {
       const std::string m = ctx->err;
