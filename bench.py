@@ -263,14 +263,16 @@ def run_integrator_comparison(scene, steps, warmup):
             "bonds_broken": r["broken"]}
 
 
-def run_precond_comparison(scene, steps, warmup):
-    """The bench workload (mixed path, same steps) with the aggregation
-    multigrid preconditioner instead of block-Jacobi (Section 5.3 solves with
-    AMG-PCG): Newton iterations per second, per step and CG iterations per
-    Newton iteration."""
+def run_precond_comparison(scene, steps, warmup, amg):
+    """The bench workload (mixed path, same steps) with the other
+    preconditioner than the headline legs' (6x6 block-Jacobi, or the
+    aggregation multigrid with which Section 5.3 solves): Newton iterations
+    per second, per step and CG iterations per Newton iteration."""
     from paper_2308_10459_amd import bdem as B
-    r = run_path(scene, True, steps, warmup, profile=False, preconditioner=B.BDEM_PRECOND_AMG)
-    return {"preconditioner": "aggregation multigrid", "steps": steps, "warmup": warmup,
+    r = run_path(scene, True, steps, warmup, profile=False,
+                 preconditioner=B.BDEM_PRECOND_AMG if amg else B.BDEM_PRECOND_BLOCK_JACOBI)
+    return {"preconditioner": "aggregation multigrid" if amg else "block-Jacobi (6x6)",
+            "steps": steps, "warmup": warmup,
             "newton_iters_per_s": r["newton"] / r["wall_s"],
             "ms_per_step": 1e3 * r["wall_s"] / steps,
             "newton_iters_per_step": r["newton"] / steps,
@@ -414,8 +416,11 @@ def main():
                     help="steps of the 64-scene batch (0: skip)")
     ap.add_argument("--midpoint-steps", type=int, default=5,
                     help="steps of the bench workload with the midpoint integrator (0: skip)")
-    ap.add_argument("--no-amg", action="store_true",
-                    help="skip the multigrid-preconditioned run of the bench workload")
+    ap.add_argument("--precond", choices=("amg", "block-jacobi"), default="amg",
+                    help="preconditioner of the headline legs (the comparison leg runs the other)")
+    ap.add_argument("--no-precond-comparison", "--no-amg", dest="no_precond_comparison",
+                    action="store_true",
+                    help="skip the run of the bench workload with the other preconditioner")
     ap.add_argument("--contact-steps", type=int, default=2,
                     help="steps of the bench workload from its initial state with and without "
                          "element repulsion (0: skip)")
@@ -429,20 +434,23 @@ def main():
     from paper_2308_10459_amd import scenes as S
     scene = S.WORKLOADS[args.workload]()
     log(f"workload {scene.name}: n={scene.n} nb={scene.nb} dt={scene.dt}")
-    log("mixed path (Gauss-Newton bond Hessians):")
-    mixed = run_path(scene, True, args.steps, args.warmup, profile=True)
+    # the headline legs: Section 5.3's multigrid-preconditioned CG by default
+    head_amg = args.precond == "amg"
+    amg = dict(preconditioner=B.BDEM_PRECOND_AMG if head_amg else B.BDEM_PRECOND_BLOCK_JACOBI)
+    log(f"mixed path (Gauss-Newton bond Hessians, {args.precond} PCG):")
+    mixed = run_path(scene, True, args.steps, args.warmup, profile=True, **amg)
     fsteps = args.steps if args.fp64_steps is None else args.fp64_steps
     if args.mixed_only:
         fsteps = 0
     fp64 = None
     if fsteps:
         log("fp64 path:")
-        fp64 = run_path(scene, False, fsteps, args.warmup, profile=True)
+        fp64 = run_path(scene, False, fsteps, args.warmup, profile=True, **amg)
     eig = None
     if not args.no_hessian_comparison:
         log("mixed path, eigen-clamped bond Hessians:")
         eig = run_path(scene, True, args.steps, args.warmup, profile=True,
-                       hessian=B.BDEM_HESS_EIGEN_CLAMP)
+                       hessian=B.BDEM_HESS_EIGEN_CLAMP, **amg)
     if args.copy_probe:
         import torch
         src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -497,7 +505,9 @@ def main():
         "config": {"workload": f"{scene.name}: {scene.n} particles, {scene.nb} bonds, E=5e10 Pa, "
                                f"v0=-8 m/s onto the ground, dt={scene.dt}",
                    "parallelism": "single GPU",
-                   "hessian": "Gauss-Newton bond Hessians (PSD by construction)"},
+                   "hessian": "Gauss-Newton bond Hessians (PSD by construction)",
+                   "preconditioner": ("aggregation multigrid V(1,1) cycle (PCG, Section 5.3)" if head_amg
+                                      else "block-Jacobi (6x6)")},
         "bond_hessian_evals_per_s": rm["bond_hessian_evals_per_s"],
         "mixed": rm,
         "fp64": rf,
@@ -526,10 +536,10 @@ def main():
             **{k: re_[k] for k in ("newton_iters_per_s", "ms_per_step", "newton_iters_per_step",
                                    "cg_iters_per_newton", "bond_avg_ms", "bond_gbs",
                                    "bond_hessian_evals_per_s", "bond_kernels")}}
-    if not args.no_amg:
-        log("aggregation multigrid preconditioner (mixed path):")
-        out["precond_comparison"] = run_precond_comparison(scene, args.steps, args.warmup)
-        out["precond_comparison"]["block_jacobi"] = {
+    if not args.no_precond_comparison:
+        log("other preconditioner (mixed path):")
+        out["precond_comparison"] = run_precond_comparison(scene, args.steps, args.warmup, not head_amg)
+        out["precond_comparison"]["headline"] = {
             "newton_iters_per_s": rm["newton_iters_per_s"], "ms_per_step": rm["ms_per_step"],
             "cg_iters_per_newton": rm["cg_iters_per_newton"]}
     if args.midpoint_steps > 0:

@@ -110,6 +110,7 @@ __device__ __forceinline__ void st6(double *p, const double (&v)[6]) {
   for (int k = 0; k < 6; ++k) p[k] = v[k];
 }
 
+
 // ---------------------------------------------------------------------------
 // numeric setup
 // ---------------------------------------------------------------------------
@@ -370,7 +371,7 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_pre(Dev
 // R1_LANES lanes per level-1 node: lane k takes the node's particles k,
 // k + R1_LANES, ...; the lanes' sums then meet in a fixed butterfly, and six
 // of them write b and t.
-constexpr int R1_LANES = 16;   // a cell of side 4 r holds about 11 close-packed particles
+constexpr int R1_LANES = 64;   // a cell of side 8 r_max holds 60-90 close-packed particles
 constexpr int RC_LANES = 8;    // a coarser cell holds at most 8 cells
 
 template <int G> __device__ __forceinline__ void lanes_sum6(double (&v)[6]) {
@@ -409,10 +410,9 @@ __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int 
       if (d.flags[i] != 0) continue;
       const double *p = a.pd0 + (size_t)i * 12;
       const double dd[3] = {p[0], p[1], p[2]};
-      double S[9];
+      double S[9], x[6], h[6], y[6];
 #pragma unroll
       for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
-      double x[6], h[6], y[6];
       ld6(d.cr + (size_t)i * 6, x);
       ld6(a.r0 + (size_t)i * 6, h);
 #pragma unroll
@@ -435,14 +435,32 @@ __device__ __forceinline__ double wave_row_apply(const AmgLevel &L, int A, const
   const int s0 = L.row_ptr[A], s1 = L.row_ptr[A + 1];
   const int g = lane / 6, c = lane - g * 6;
   double part = 0.0;
+  // four of the lane's slots at a time, all their loads issued before the
+  // first product (a row of up to 40 blocks in one round)
   if (lane < 60)
-    for (int sl = s0 + g; sl < s1; sl += 10) {
-      const T *blk = val + (size_t)sl * 36 + c * 6;
-      const double *xj = x + (size_t)L.col[sl] * 6;
-      double acc = 0.0;
+    for (int sb = s0 + g; sb < s1; sb += 40) {
+      int sl[4], cj[4];
 #pragma unroll
-      for (int e = 0; e < 6; ++e) acc += double(blk[e]) * xj[e];
-      part += acc;
+      for (int m = 0; m < 4; ++m) {
+        sl[m] = sb + 10 * m < s1 ? sb + 10 * m : sb;
+        cj[m] = L.col[sl[m]];
+      }
+      T bv[4][6];
+      double xv[4][6];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          bv[m][e] = val[(size_t)sl[m] * 36 + c * 6 + e];
+          xv[m][e] = x[(size_t)cj[m] * 6 + e];
+        }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {   // branch-free, so that no load sinks into a branch
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) acc += double(bv[m][e]) * xv[m][e];
+        part += (sb + 10 * m < s1) ? acc : 0.0;
+      }
     }
   double y = 0.0;
   for (int k = 0; k < 10; ++k) y += __shfl(part, k * 6 + (lane % 6), 64);
@@ -677,46 +695,6 @@ template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_
   }
 }
 
-// u = t0 + omega D^-1 (r - H t0) into the PCG's u (r0 holds H t0), and the
-// (r, u), (r, r) partials of the SPMV_ROWS-row block for the PCG's scalars
-// (thread (row, component); the block's three wavefronts merge in order, as
-// the CG update's do)
-template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) void k_amg_fine_final(DevPtrs d, AmgDev a) {
-  static_assert(6 * SPMV_ROWS == 192, "three wavefronts per block");
-  __shared__ double ys[6 * SPMV_ROWS];
-  __shared__ double wd[4][3];
-  const int r0 = blockIdx.x * SPMV_ROWS;
-  if (!d.ctl[d.psid[r0]].cg_active) return;   // uniform over the workgroup
-  const int t = threadIdx.x, rl = t / 6, c = t - rl * 6;
-  const size_t o = (size_t)r0 * 6 + t;
-  const double rv = d.cr[o];
-  ys[t] = rv - a.r0[o];
-  __syncthreads();
-  const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)(r0 + rl) * 21;
-  double v = 0.0;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) v += double(Di[up6(c, k)]) * ys[rl * 6 + k];
-  const double un = a.t0[o] + AMG_OMEGA * v;
-  d.cs[o] = un;
-  KSum ru = {0.0, 0.0}, rr = {0.0, 0.0};
-  kadd(ru, rv * un);
-  kadd(rr, rv * rv);
-  ru = wave_ksum(ru);
-  rr = wave_ksum(rr);
-  const int wv = t >> 6;
-  if ((t & 63) == 0) { wd[0][wv] = ru.s; wd[1][wv] = ru.c; wd[2][wv] = rr.s; wd[3][wv] = rr.c; }
-  __syncthreads();
-  if (t == 0) {
-    KSum x = {0.0, 0.0}, y = {0.0, 0.0};
-    for (int k = 0; k < 3; ++k) {
-      x = kmerge(x, KSum{wd[0][k], wd[1][k]});
-      y = kmerge(y, KSum{wd[2][k], wd[3][k]});
-    }
-    d.part_a[blockIdx.x] = make_double2(x.s, x.c);
-    d.part_c[blockIdx.x] = make_double2(y.s, y.c);
-  }
-}
-
 // ---------------------------------------------------------------------------
 
 static inline int nblk(int n, int b) { return (n + b - 1) / b; }
@@ -754,8 +732,11 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   k_amg_tail<T><<<n_scenes, AMG_TAIL_THREADS, 0, s>>>(d, a);
   // each level's kernel also prolongs its correction one level down
   for (int l = a.Lt - 1; l >= 1; --l) k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(d, a, l);
-  launch_spmv(dt, mixed, spmv_variant, s, SPMV_DOTS_NONE);
-  k_amg_fine_final<T><<<d.n_pad / SPMV_ROWS, 6 * SPMV_ROWS, 0, s>>>(d, a);
+  // the post-smoothing u = t0 + omega D^-1 (r - H t0) and the PCG's r dots,
+  // in the epilogue of the product H t0
+  DevPtrs df = dt;
+  df.cAp = d.cs;
+  launch_spmv(df, mixed, spmv_variant, s, SPMV_AMG_FINAL);
 }
 
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
