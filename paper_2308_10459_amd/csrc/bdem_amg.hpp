@@ -104,7 +104,13 @@ void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int
 // t0_ready: the CG update already wrote t0 = omega D^-1 r (DevPtrs::amg_t0);
 // the cycle writes u = M^-1 r into d.cs and the (r, u), (r, r) partials of
 // each SPMV_ROWS-row block
+// mark (optional): called with true before and false after each of the
+// cycle's two fine SpMV launches (the profiler's event brackets)
+struct SpmvMark {
+  void (*fn)(void *arg, bool start) = nullptr;
+  void *arg = nullptr;
+};
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       int spmv_variant, bool t0_ready, hipStream_t s);
+                       int spmv_variant, bool t0_ready, hipStream_t s, SpmvMark mark = SpmvMark());
 
 }  // namespace bdem

@@ -910,6 +910,17 @@ static void prof_mark(bdem_ctx *ctx, int kind, bool start) {
   (void)hipEventRecord(ctx->ev_pool[ctx->ev_used++], ctx->stream);
 }
 
+// the multigrid cycle's SpMV launches, bracketed like the PCG's own
+static void prof_mark_spmv(void *arg, bool start) { prof_mark(static_cast<bdem_ctx *>(arg), 1, start); }
+static SpmvMark cycle_marks(bdem_ctx *ctx, bool on) {
+  SpmvMark m;
+  if (on) {
+    m.fn = prof_mark_spmv;
+    m.arg = ctx;
+  }
+  return m;
+}
+
 static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
   for (auto &m : ctx->ev_marks) {
     float ms = 0.f;
@@ -962,7 +973,7 @@ static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream, !amg);
   if (amg)
     launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, true,
-                      ctx->stream);
+                      ctx->stream, cycle_marks(ctx, profile_spmv));
   if (profile_spmv) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, SPMV_DOTS_WU);
   if (profile_spmv) prof_mark(ctx, 1, false);
@@ -1007,7 +1018,9 @@ static int run_pcg(bdem_ctx *ctx) {
     HIP_TRY(hipStreamSynchronize(st));
   }
   launch_cg_init(ctx->d, mixed, st);
-  if (ctx->amg) launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, false, st);
+  if (ctx->amg)
+    launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, false, st,
+                      cycle_marks(ctx, ctx->profiling == 1));
   if (ctx->profiling == 1) prof_mark(ctx, 1, true);
   launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
   if (ctx->profiling == 1) prof_mark(ctx, 1, false);
@@ -1049,12 +1062,13 @@ static int run_pcg(bdem_ctx *ctx) {
   HIP_TRY(hipStreamSynchronize(st));
   if (ctx->profiling == 1 && !graph) {
     // SpMV launches issued after every scene had converged returned at once:
-    // keep the timings of the first 1 + max(cg_it) launches of this solve
+    // keep the timings of the first 1 + max(cg_it) iterations' launches of
+    // this solve (three per iteration with multigrid: two in the cycle)
     std::vector<SceneCtl> after(ctx->S.n_scenes);
     HIP_TRY(hipMemcpy(after.data(), ctx->d.ctl, after.size() * sizeof(SceneCtl), hipMemcpyDeviceToHost));
     int real = 0;
     for (const auto &c : after) real = std::max(real, c.cg_it);
-    real += 1;
+    real = (real + 1) * (ctx->amg ? 3 : 1);
     std::vector<std::pair<int, size_t>> kept(ctx->ev_marks.begin(), ctx->ev_marks.begin() + mark0);
     int seen = 0;
     for (size_t k = mark0; k < ctx->ev_marks.size(); ++k) {

@@ -116,25 +116,29 @@ __device__ __forceinline__ void st6(double *p, const double (&v)[6]) {
 // ---------------------------------------------------------------------------
 
 // level 1: centroids of the aggregates (iterate positions of their free
-// particles), and each particle's (x_i - c_a, S_i = 1/2 R(q_i)^T)
+// particles), and each particle's (x_i - c_a, S_i = 1/2 R(q_i)^T).  One
+// wavefront per aggregate: lane k takes members k, k + 64, ...; the lanes'
+// sums meet in a fixed butterfly.
 __global__ __launch_bounds__(256) void k_amg_geom1(DevPtrs d, AmgDev a) {
   const AmgLevel &L = a.lv[1];
-  const int A = blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= L.n) return;
+  const int A = (blockIdx.x * 256 + (int)threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (A >= L.n) return;   // uniform over the wavefront
   const int mb = L.mbeg[A], me = L.mbeg[A + 1];
   const bool act = L.active[A] != 0;
-  double c[3] = {0.0, 0.0, 0.0};
-  int cnt = 0;
-  for (int k = mb; k < me; ++k) {
+  double c[4] = {0.0, 0.0, 0.0, 0.0};   // position sum, count
+  for (int k = mb + lane; k < me; k += 64) {
     const int i = L.mlist[k];
     if (act && d.flags[i] != 0) continue;
     const double4 p = d.px[i];
-    c[0] += p.x; c[1] += p.y; c[2] += p.z;
-    ++cnt;
+    c[0] += p.x; c[1] += p.y; c[2] += p.z; c[3] += 1.0;
   }
-  c[0] /= cnt; c[1] /= cnt; c[2] /= cnt;
-  L.cen[3 * A] = c[0]; L.cen[3 * A + 1] = c[1]; L.cen[3 * A + 2] = c[2];
-  for (int k = mb; k < me; ++k) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) c[m] += __shfl_xor(c[m], off, 64);
+  c[0] /= c[3]; c[1] /= c[3]; c[2] /= c[3];
+  if (lane == 0) { L.cen[3 * A] = c[0]; L.cen[3 * A + 1] = c[1]; L.cen[3 * A + 2] = c[2]; }
+  for (int k = mb + lane; k < me; k += 64) {
     const int i = L.mlist[k];
     const double4 p = d.px[i], q = d.qx[i];
     double *o = a.pd0 + (size_t)i * 12;
@@ -219,16 +223,19 @@ __device__ __forceinline__ void add_ptap(double (&acc)[36], const T *H, int form
 }
 
 // Galerkin block of every level-1 slot from the fine diagonal (packed) and
-// off-diagonal blocks of its contribution list
-template <typename T> __global__ __launch_bounds__(128) void k_amg_galerkin1(DevPtrs d, AmgDev a) {
+// off-diagonal blocks of its contribution list.  One wavefront per slot (an
+// aggregate of ~60-90 particles has ~1,000 contributions on its diagonal
+// slot): lane k takes contributions k, k + 64, ...; the lanes' 36 sums are
+// then added in lane order through LDS.
+template <typename T> __global__ __launch_bounds__(64) void k_amg_galerkin1(DevPtrs d, AmgDev a) {
+  __shared__ double part[64][37];
   const AmgLevel &L = a.lv[1];
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= L.nslots) return;
+  const int s = blockIdx.x, lane = threadIdx.x;
   double acc[36];
 #pragma unroll
   for (int k = 0; k < 36; ++k) acc[k] = 0.0;
   const T *hd = reinterpret_cast<const T *>(d.hdiag), *ho = reinterpret_cast<const T *>(d.hoff);
-  for (int k = L.gptr[s]; k < L.gptr[s + 1]; ++k) {
+  for (int k = L.gptr[s] + lane; k < L.gptr[s + 1]; k += 64) {
     const int src = L.gsrc[k];
     const bool diag = src < 0;
     const int i = diag ? -1 - src : a.slot_row0[src];
@@ -247,14 +254,15 @@ template <typename T> __global__ __launch_bounds__(128) void k_amg_galerkin1(Dev
       add_ptap<T>(acc, ho + (size_t)(sb >> 1) * 36, (sb & 1) ? BLK_TRANSPOSED : BLK_FULL, dr, Sr, dc, Sc);
     }
   }
+#pragma unroll
+  for (int k = 0; k < 36; ++k) part[lane][k] = acc[k];
+  __syncthreads();
+  if (lane >= 36) return;
+  double v = 0.0;
+  for (int m = 0; m < 64; ++m) v += part[m][lane];
   const int A = L.slot_row[s];
-  if (!L.active[A] && L.dslot[A] == s) {
-#pragma unroll
-    for (int k = 0; k < 36; ++k) acc[k] = (k % 7 == 0) ? 1.0 : 0.0;
-  }
-  T *o = reinterpret_cast<T *>(L.val) + (size_t)s * 36;
-#pragma unroll
-  for (int k = 0; k < 36; ++k) o[k] = T(acc[k]);
+  if (!L.active[A] && L.dslot[A] == s) v = (lane % 7 == 0) ? 1.0 : 0.0;
+  reinterpret_cast<T *>(L.val)[(size_t)s * 36 + lane] = T(v);
 }
 
 template <typename T> __global__ __launch_bounds__(128) void k_amg_galerkin(AmgDev a, int l) {
@@ -701,9 +709,9 @@ static inline int nblk(int n, int b) { return (n + b - 1) / b; }
 
 template <typename T>
 static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, hipStream_t s) {
-  k_amg_geom1<<<nblk(hl[1].n, 256), 256, 0, s>>>(d, a);
+  k_amg_geom1<<<nblk(hl[1].n * 64, 256), 256, 0, s>>>(d, a);
   for (int l = 2; l <= a.L; ++l) k_amg_geom<<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
-  k_amg_galerkin1<T><<<nblk(hl[1].nslots, 128), 128, 0, s>>>(d, a);
+  if (hl[1].nslots > 0) k_amg_galerkin1<T><<<hl[1].nslots, 64, 0, s>>>(d, a);
   k_amg_dinv<T><<<nblk(hl[1].n, 128), 128, 0, s>>>(a, 1);
   for (int l = 2; l <= a.L; ++l) {
     k_amg_galerkin<T><<<nblk(hl[l].nslots, 128), 128, 0, s>>>(a, l);
@@ -714,14 +722,19 @@ static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n
 
 template <typename T>
 static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                     int spmv_variant, bool t0_ready, hipStream_t s) {
+                     int spmv_variant, bool t0_ready, hipStream_t s, SpmvMark mark) {
+  auto spmv = [&](const DevPtrs &dd, int mode) {
+    if (mark.fn) mark.fn(mark.arg, true);
+    launch_spmv(dd, mixed, spmv_variant, s, mode);
+    if (mark.fn) mark.fn(mark.arg, false);
+  };
   // the fine products H t0 run through the PCG's own SpMV kernel, without
   // its dots
   DevPtrs dt = d;
   dt.cs = a.t0;
   dt.cAp = a.r0;
   if (!t0_ready) k_amg_fine_pre<T><<<d.n_pad / TILE, TILE, 0, s>>>(d, a);
-  launch_spmv(dt, mixed, spmv_variant, s, SPMV_DOTS_NONE);
+  spmv(dt, SPMV_DOTS_NONE);
   // each restriction also pre-smooths the level it fills (not the coarsest)
   k_amg_restrict1<T><<<nblk(hl[1].n * R1_LANES, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
   for (int l = 1; l < a.Lt; ++l) {
@@ -736,7 +749,7 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   // in the epilogue of the product H t0
   DevPtrs df = dt;
   df.cAp = d.cs;
-  launch_spmv(df, mixed, spmv_variant, s, SPMV_AMG_FINAL);
+  spmv(df, SPMV_AMG_FINAL);
 }
 
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
@@ -745,9 +758,9 @@ void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int
   else setup_t<double>(d, a, hl, n_scenes, s);
 }
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       int spmv_variant, bool t0_ready, hipStream_t s) {
-  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, true, spmv_variant, t0_ready, s);
-  else vcycle_t<double>(d, a, hl, n_scenes, false, spmv_variant, t0_ready, s);
+                       int spmv_variant, bool t0_ready, hipStream_t s, SpmvMark mark) {
+  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, true, spmv_variant, t0_ready, s, mark);
+  else vcycle_t<double>(d, a, hl, n_scenes, false, spmv_variant, t0_ready, s, mark);
 }
 
 }  // namespace bdem
