@@ -62,7 +62,7 @@ struct AmgDev {
   // fine level (particles, internal order)
   int *slot_row0 = nullptr;         // row of each fine off-diagonal slot
   int *parent0 = nullptr;           // level-1 node of each particle (-1: padding)
-  double *pd0 = nullptr;            // 12 per particle: x_i - c_a (3), S_i (9)
+  void *pd0 = nullptr;              // 12 T per particle: x_i - c_a (3), S_i (9)
   double *t0 = nullptr, *r0 = nullptr;   // 6 per particle
   const AmgLevel *lv = nullptr;     // device array lv[0..L] (lv[0] unused)
   // coarsest level: dense inverse per scene

@@ -353,7 +353,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   auto addd = [&](double **p, size_t n) { L.add(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(double)); };
   addi(&a.slot_row0, H.slot_row0.size());
   addi(&a.parent0, NP);
-  addd(&a.pd0, 12 * (size_t)NP);
+  L.add(&a.pd0, 12 * (size_t)NP * T);
   addd(&a.t0, 6 * (size_t)NP);
   addd(&a.r0, 6 * (size_t)NP);
   for (int l = 1; l <= H.L; ++l) {
@@ -413,7 +413,8 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   upi(a.tbeg, H.tbeg);
   chk(hipMemcpyAsync(a.coff, H.coff.data(), NS * sizeof(int64_t), hipMemcpyHostToDevice, st));
   chk(hipMemcpyAsync(lvdev, ctx->amg_hl.data(), (H.L + 1) * sizeof(AmgLevel), hipMemcpyHostToDevice, st));
-  for (double *v : {a.pd0, a.t0, a.r0}) chk(hipMemsetAsync(v, 0, (v == a.pd0 ? 12 : 6) * (size_t)NP * sizeof(double), st));
+  chk(hipMemsetAsync(a.pd0, 0, 12 * (size_t)NP * T, st));
+  for (double *v : {a.t0, a.r0}) chk(hipMemsetAsync(v, 0, 6 * (size_t)NP * sizeof(double), st));
   chk(hipStreamSynchronize(st));
   if (e != hipSuccess) { ctx->err = std::string("HIP error during multigrid setup: ") + hipGetErrorString(e); return BDEM_E_HIP; }
   ctx->amg = true;

@@ -109,6 +109,15 @@ __device__ __forceinline__ void st6(double *p, const double (&v)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) p[k] = v[k];
 }
+// a particle's prolongator block (x_i - c_a, S_i), stored in T: 12 values
+template <typename T>
+__device__ __forceinline__ void load_pd0(const AmgDev &a, int i, double (&dd)[3], double (&S)[9]) {
+  const T *p = reinterpret_cast<const T *>(a.pd0) + (size_t)i * 12;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) dd[m] = double(p[m]);
+#pragma unroll
+  for (int m = 0; m < 9; ++m) S[m] = double(p[3 + m]);
+}
 
 
 // ---------------------------------------------------------------------------
@@ -119,7 +128,7 @@ __device__ __forceinline__ void st6(double *p, const double (&v)[6]) {
 // particles), and each particle's (x_i - c_a, S_i = 1/2 R(q_i)^T).  One
 // wavefront per aggregate: lane k takes members k, k + 64, ...; the lanes'
 // sums meet in a fixed butterfly.
-__global__ __launch_bounds__(256) void k_amg_geom1(DevPtrs d, AmgDev a) {
+template <typename T> __global__ __launch_bounds__(256) void k_amg_geom1(DevPtrs d, AmgDev a) {
   const AmgLevel &L = a.lv[1];
   const int A = (blockIdx.x * 256 + (int)threadIdx.x) >> 6, lane = threadIdx.x & 63;
   if (A >= L.n) return;   // uniform over the wavefront
@@ -141,8 +150,8 @@ __global__ __launch_bounds__(256) void k_amg_geom1(DevPtrs d, AmgDev a) {
   for (int k = mb + lane; k < me; k += 64) {
     const int i = L.mlist[k];
     const double4 p = d.px[i], q = d.qx[i];
-    double *o = a.pd0 + (size_t)i * 12;
-    o[0] = p.x - c[0]; o[1] = p.y - c[1]; o[2] = p.z - c[2];
+    T *o = reinterpret_cast<T *>(a.pd0) + (size_t)i * 12;
+    o[0] = T(p.x - c[0]); o[1] = T(p.y - c[1]); o[2] = T(p.z - c[2]);
     // R(q) for q = (x, y, z, w); S = 1/2 R^T
     const double x = q.x, y = q.y, z = q.z, w = q.w;
     const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(256) void k_amg_geom1(DevPtrs d, AmgDev a) {
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) o[3 + r * 3 + cc] = 0.5 * R[cc * 3 + r];
+      for (int cc = 0; cc < 3; ++cc) o[3 + r * 3 + cc] = T(0.5 * R[cc * 3 + r]);
   }
 }
 
@@ -242,11 +251,8 @@ template <typename T> __global__ __launch_bounds__(64) void k_amg_galerkin1(DevP
     const int j = diag ? i : d.col[src];
     if (d.flags[i] != 0 || d.flags[j] != 0) continue;   // P is zero on non-unknowns
     double dr[3], Sr[9], dc[3], Sc[9];
-    const double *pi = a.pd0 + (size_t)i * 12, *pj = a.pd0 + (size_t)j * 12;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) { dr[m] = pi[m]; dc[m] = pj[m]; }
-#pragma unroll
-    for (int m = 0; m < 9; ++m) { Sr[m] = pi[3 + m]; Sc[m] = pj[3 + m]; }
+    load_pd0<T>(a, i, dr, Sr);
+    load_pd0<T>(a, j, dc, Sc);
     if (diag) {
       add_ptap<T>(acc, hd + (size_t)i * 21, BLK_SYM21, dr, Sr, dc, Sc);
     } else {
@@ -416,11 +422,8 @@ __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int 
     for (int k = L.mbeg[A] + k0; k < L.mbeg[A + 1]; k += R1_LANES) {
       const int i = L.mlist[k];
       if (d.flags[i] != 0) continue;
-      const double *p = a.pd0 + (size_t)i * 12;
-      const double dd[3] = {p[0], p[1], p[2]};
-      double S[9], x[6], h[6], y[6];
-#pragma unroll
-      for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
+      double dd[3], S[9], x[6], h[6], y[6];
+      load_pd0<T>(a, i, dd, S);
       ld6(d.cr + (size_t)i * 6, x);
       ld6(a.r0 + (size_t)i * 6, h);
 #pragma unroll
@@ -509,16 +512,14 @@ __global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l, int smoot
 
 // t_f += P_f e for one member f of a level-l node (a level l - 1 node, or a
 // fine particle when l = 1; S = I above the particles)
+template <typename T>
 __device__ __forceinline__ void prolong_one(const DevPtrs &d, const AmgDev &a, int l, int i,
                                             const double (&e)[6]) {
   double dd[3], S[9], y[6];
   double *t;
   if (l == 1) {
     if (d.flags[i] != 0 || !d.ctl[d.psid[i]].cg_active) return;
-    const double *p = a.pd0 + (size_t)i * 12;
-    dd[0] = p[0]; dd[1] = p[1]; dd[2] = p[2];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) S[m] = p[3 + m];
+    load_pd0<T>(a, i, dd, S);
     t = a.t0 + (size_t)i * 6;
   } else {
     const AmgLevel &F = a.lv[l - 1];
@@ -556,7 +557,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_post(DevPtrs 
   double e[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) e[k] = __shfl(ev, k, 64);
-  for (int k = L.mbeg[A] + lane; k < L.mbeg[A + 1]; k += 64) prolong_one(d, a, l, L.mlist[k], e);
+  for (int k = L.mbeg[A] + lane; k < L.mbeg[A + 1]; k += 64) prolong_one<T>(d, a, l, L.mlist[k], e);
 }
 
 // ---------------------------------------------------------------------------
@@ -599,6 +600,7 @@ __device__ __forceinline__ void tail_residual(const AmgLevel &L, int nb, int ne,
 
 // e of the rows [nb, ne) (6 values per row in ev) prolonged into their
 // members one level down
+template <typename T>
 __device__ __forceinline__ void tail_prolong(const DevPtrs &d, const AmgDev &a, int l, int nb, int ne,
                                              const double *ev) {
   const AmgLevel &L = a.lv[l];
@@ -607,7 +609,7 @@ __device__ __forceinline__ void tail_prolong(const DevPtrs &d, const AmgDev &a, 
     const int i = L.mlist[k];
     const double *ep = ev + (parent[i] - nb) * 6;
     const double e[6] = {ep[0], ep[1], ep[2], ep[3], ep[4], ep[5]};
-    prolong_one(d, a, l, i, e);
+    prolong_one<T>(d, a, l, i, e);
   }
   __syncthreads();
 }
@@ -674,7 +676,7 @@ template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_
       L.e[(size_t)6 * nb + r] = acc;
     }
     __syncthreads();
-    tail_prolong(d, a, a.L, nb, ne, res);
+    tail_prolong<T>(d, a, a.L, nb, ne, res);
   }
   // going up
   for (int l = a.L - 1; l >= a.Lt; --l) {
@@ -699,7 +701,7 @@ template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_
       L.e[(size_t)nb * 6 + q] = ev[m];
     }
     __syncthreads();
-    tail_prolong(d, a, l, nb, ne, res);
+    tail_prolong<T>(d, a, l, nb, ne, res);
   }
 }
 
@@ -709,7 +711,7 @@ static inline int nblk(int n, int b) { return (n + b - 1) / b; }
 
 template <typename T>
 static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, hipStream_t s) {
-  k_amg_geom1<<<nblk(hl[1].n * 64, 256), 256, 0, s>>>(d, a);
+  k_amg_geom1<T><<<nblk(hl[1].n * 64, 256), 256, 0, s>>>(d, a);
   for (int l = 2; l <= a.L; ++l) k_amg_geom<<<nblk(hl[l].n, 256), 256, 0, s>>>(a, l);
   if (hl[1].nslots > 0) k_amg_galerkin1<T><<<hl[1].nslots, 64, 0, s>>>(d, a);
   k_amg_dinv<T><<<nblk(hl[1].n, 128), 128, 0, s>>>(a, 1);
