@@ -181,20 +181,27 @@ def run_path(scene, mixed, steps, warmup, profile, **opts):
     return tot
 
 
-def run_batch(steps, warmup):
+def run_batch(steps, warmup, amg=True):
     """The 64-scene batch (992,148 particles, seeded sizes 2K-50K, per-scene
     dt): aggregate particle-steps per second of the mixed path stepping all
     scenes in one batched call, of the FP64 path batched, and of the FP64
-    path stepping the scenes one after another (each scene alone).  Every
-    handle is autotuned on its own scenes first, as in the single-scene runs."""
+    path stepping the scenes one after another (each scene alone), all with
+    the headline legs' preconditioner; then the mixed batched call with the
+    other preconditioner.  Every handle is autotuned on its own scenes first,
+    as in the single-scene runs."""
     import torch
     from paper_2308_10459_amd import bdem as B
     from paper_2308_10459_amd import scenes as S
     sc = S.make_batch()
+    pc, other = ((B.BDEM_PRECOND_AMG, B.BDEM_PRECOND_BLOCK_JACOBI) if amg else
+                 (B.BDEM_PRECOND_BLOCK_JACOBI, B.BDEM_PRECOND_AMG))
     out = {"workload": f"{sc.name}: {sc.n} particles, {sc.nb} bonds, 64 scenes of 2K-50K particles, "
-                       "per-scene dt = 50 x the period estimate", "steps": steps}
-    for label, prec in (("mixed_batched", B.BDEM_PREC_MIXED), ("fp64_batched", B.BDEM_PREC_FP64)):
-        sim = B.Simulator(sc, precision=prec)
+                       "per-scene dt = 50 x the period estimate", "steps": steps,
+           "preconditioner": "aggregation multigrid" if amg else "block-Jacobi (6x6)"}
+    other_label = "mixed_batched_block_jacobi" if amg else "mixed_batched_multigrid"
+    for label, prec, p in (("mixed_batched", B.BDEM_PREC_MIXED, pc), ("fp64_batched", B.BDEM_PREC_FP64, pc),
+                           (other_label, B.BDEM_PREC_MIXED, other)):
+        sim = B.Simulator(sc, precision=prec, preconditioner=p)
         tuning = sim.autotune(sc.dt_per_scene)
         log(f"  batch {label} autotuned: {tuning}")
         for _ in range(warmup):
@@ -213,7 +220,7 @@ def run_batch(steps, warmup):
     wall = 0.0
     for s in range(len(sc.dt_per_scene)):
         m = S.subset_scenes(sc, [s])
-        sim = B.Simulator(m, precision=B.BDEM_PREC_FP64)
+        sim = B.Simulator(m, precision=B.BDEM_PREC_FP64, preconditioner=pc)
         sim.autotune(m.dt_per_scene)
         for _ in range(warmup):
             sim.step_batched(m.dt_per_scene)
@@ -566,7 +573,7 @@ def main():
         out["solver_comparison"] = run_solver_comparison()
     if args.batch_steps > 0:
         log("64-scene batch:")
-        out["batch"] = run_batch(args.batch_steps, 1)
+        out["batch"] = run_batch(args.batch_steps, 1, amg=head_amg)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle):")
         out["cpu_baseline"] = cpu_baseline(cg_per_newton=rm["cg_iters_per_newton"])

@@ -4,8 +4,9 @@ Section 3.3 at the end of every step), stored by
 tests/golden/make_trajectories.py, which calls only the oracle:
 
   * the 219,024-particle ceramic plate (the benchmark workload), steps 1-10,
-    on the mixed path the benchmark runs;
-  * the 32,768-particle plate drop, steps 1-3, on both paths.
+    on the mixed path the benchmark runs, with either preconditioner;
+  * the 32,768-particle plate drop, steps 1-3, on both paths (and with the
+    multigrid preconditioner on the mixed one).
 
 Per step: positions and orientations of 2,048 seeded sample particles against
 the oracle's (relative to the step's own displacement / rotation at the
@@ -46,17 +47,24 @@ def _golden(name):
     return z, json.loads(str(z["meta"]))
 
 
-@pytest.mark.parametrize("name,mixed", [("ceramic_plate", True), ("plate_drop", True),
-                                        ("plate_drop", False)])
-def test_full_size_trajectory_matches_the_oracle(B, name, mixed):
+@pytest.mark.parametrize("name,mixed,precond", [("ceramic_plate", True, "block_jacobi"),
+                                                ("ceramic_plate", True, "amg"),
+                                                ("plate_drop", True, "block_jacobi"),
+                                                ("plate_drop", False, "block_jacobi"),
+                                                ("plate_drop", True, "amg")])
+def test_full_size_trajectory_matches_the_oracle(B, name, mixed, precond):
+    """precond: the PCG's preconditioner (the multigrid one is the benchmark's
+    headline configuration); the fixed point of each step does not depend on
+    it."""
     z, meta = _golden(name)
     sc = getattr(S, "make_" + name)()
     assert (sc.n, sc.nb, sc.dt) == (meta["n"], meta["nb"], meta["dt"])
     sample = z["sample"]
     nsteps = int(meta["steps_stored"])
-    log(f"[trajectory] {name} mixed={mixed}: n={sc.n} nb={sc.nb}, {nsteps} steps, "
+    log(f"[trajectory] {name} mixed={mixed} precond={precond}: n={sc.n} nb={sc.nb}, {nsteps} steps, "
         f"{len(sample)} sample particles")
-    sim = make_sim(sc, mixed=mixed, **TIGHT)
+    pc = B.BDEM_PRECOND_AMG if precond == "amg" else B.BDEM_PRECOND_BLOCK_JACOBI
+    sim = make_sim(sc, mixed=mixed, preconditioner=pc, **TIGHT)
     tol = 1e-5 if mixed else 1e-9
     ptol = 1e-6 if mixed else 1e-12
     prev_p, prev_q = sc.pos[sample], sc.quat[sample]
@@ -89,7 +97,7 @@ def test_full_size_trajectory_matches_the_oracle(B, name, mixed):
         qrel = np.linalg.norm(qerr) / max(np.linalg.norm(rot), 1e-300)
         phi_o = float(z[f"s{k}_phi"])
         eerr = abs(sg["phi"] - phi_o) / abs(phi_o)
-        tag = f"{name} mixed={mixed} step {k}"
+        tag = f"{name} mixed={mixed} {precond} step {k}"
         log(f"  step {k}: newton {sg['newton_iters']} cg {sg['cg_iters']} broken {sg['bonds_broken']} "
             f"(oracle {int(broken.sum())}, uncertified {len(z[f's{k}_uncert'])}, adopted {diff}) "
             f"pos {perr:.2e} rot {qrel:.2e} phi {eerr:.2e}")
