@@ -200,6 +200,8 @@ struct bdem_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;   // (kind, index of start event)
+  std::vector<int> ev_iter;     // PCG iteration of each mark (-1: outside the iterations)
+  int prof_iter = -1;           // the PCG iteration being issued
   // aggregation multigrid preconditioner (bdem_options.preconditioner)
   bool amg = false;
   AmgDev amg_d;
@@ -897,6 +899,10 @@ static int read_counters(bdem_ctx *ctx) {
   return BDEM_OK;
 }
 
+// with profiling, the SpMV launches of one PCG iteration in this many are
+// bracketed by events (and the initial product of every solve)
+constexpr int PROF_SPMV_EVERY = 8;
+
 static void prof_mark(bdem_ctx *ctx, int kind, bool start) {
   if (!ctx->profiling) return;
   if (ctx->ev_used + 1 >= ctx->ev_pool.size()) {
@@ -907,7 +913,10 @@ static void prof_mark(bdem_ctx *ctx, int kind, bool start) {
       ctx->ev_pool.push_back(ev);
     }
   }
-  if (start) ctx->ev_marks.push_back({kind, ctx->ev_used});
+  if (start) {
+    ctx->ev_marks.push_back({kind, ctx->ev_used});
+    ctx->ev_iter.push_back(ctx->prof_iter);
+  }
   (void)hipEventRecord(ctx->ev_pool[ctx->ev_used++], ctx->stream);
 }
 
@@ -931,6 +940,7 @@ static void prof_collect(bdem_ctx *ctx, double *ms_kind, int *cnt_kind) {
     }
   }
   ctx->ev_marks.clear();
+  ctx->ev_iter.clear();
   ctx->ev_used = 0;
 }
 
@@ -1044,7 +1054,14 @@ static int run_pcg(bdem_ctx *ctx) {
     if (graph) {
       HIP_TRY(hipGraphLaunch(ctx->cg_exec[slot], st));
     } else {
-      for (int k = 0; k < chunk; ++k) launch_cg_iteration(ctx, ctx->profiling == 1);
+      for (int k = 0; k < chunk; ++k) {
+        // profiling: the SpMV launches of every PROF_SPMV_EVERY-th iteration
+        // are bracketed (events between launches lengthen the timed steps)
+        const int it = c * chunk + k;
+        ctx->prof_iter = it;
+        launch_cg_iteration(ctx, ctx->profiling == 1 && it % PROF_SPMV_EVERY == 0);
+      }
+      ctx->prof_iter = -1;
       if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, slot, st);
     }
     if (ctx->in_scratch) {   // no events: drain the stream and read this chunk's count
@@ -1063,20 +1080,21 @@ static int run_pcg(bdem_ctx *ctx) {
   HIP_TRY(hipStreamSynchronize(st));
   if (ctx->profiling == 1 && !graph) {
     // SpMV launches issued after every scene had converged returned at once:
-    // keep the timings of the first 1 + max(cg_it) iterations' launches of
-    // this solve (three per iteration with multigrid: two in the cycle)
+    // keep the timings of the initial product(s) and of iterations
+    // 0 .. max(cg_it) - 1 of this solve
     std::vector<SceneCtl> after(ctx->S.n_scenes);
     HIP_TRY(hipMemcpy(after.data(), ctx->d.ctl, after.size() * sizeof(SceneCtl), hipMemcpyDeviceToHost));
     int real = 0;
     for (const auto &c : after) real = std::max(real, c.cg_it);
-    real = (real + 1) * (ctx->amg ? 3 : 1);
     std::vector<std::pair<int, size_t>> kept(ctx->ev_marks.begin(), ctx->ev_marks.begin() + mark0);
-    int seen = 0;
-    for (size_t k = mark0; k < ctx->ev_marks.size(); ++k) {
-      const auto &m = ctx->ev_marks[k];
-      if (m.first != 1 || seen++ < real) kept.push_back(m);
-    }
+    std::vector<int> kept_it(ctx->ev_iter.begin(), ctx->ev_iter.begin() + mark0);
+    for (size_t k = mark0; k < ctx->ev_marks.size(); ++k)
+      if (ctx->ev_marks[k].first != 1 || ctx->ev_iter[k] < real) {
+        kept.push_back(ctx->ev_marks[k]);
+        kept_it.push_back(ctx->ev_iter[k]);
+      }
     ctx->ev_marks.swap(kept);
+    ctx->ev_iter.swap(kept_it);
   }
   return BDEM_OK;
 }
