@@ -247,7 +247,7 @@ __device__ __forceinline__ void rows_slot(const DevPtrs &d, int b, bool tr, int 
 }
 
 template <typename T, bool MID>
-__global__ __launch_bounds__(ROWS_NT, sizeof(T) == 4 ? 3 : 2) void k_rows_eval(DevPtrs d, Params P, int potential_only) {
+__global__ __launch_bounds__(ROWS_NT) void k_rows_eval(DevPtrs d, Params P, int potential_only) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int r0 = lb * ROWS_RT;
   const int scene = d.psid[r0];
