@@ -1381,12 +1381,12 @@ void orc_friction(orc_sys *s, double dt) {
 /* of twice the side at each coarser level), prolongation from the six      */
 /* rigid-body modes of each aggregate, Galerkin coarse operators, damped    */
 /* block-Jacobi smoothing (omega = 0.8) before and after the coarse          */
-/* correction, and an exact solve on the first level with at most 12 nodes  */
+/* correction, and an exact solve on the first level with at most 16 nodes  */
 /* (always at least one coarse level).  Built from the diagonal and bond    */
 /* blocks; element-repulsion couplings are not part of it.                   */
 /* ------------------------------------------------------------------------ */
 #define AMG_OMEGA 0.8
-#define AMG_COARSE_MAX 12
+#define AMG_COARSE_MAX 16
 
 typedef struct {
   int32_t n;

@@ -29,7 +29,7 @@ namespace bdem {
 // larger cells make every level smaller (8 r_max fastest; past 10 r_max the
 // first level's restriction and Galerkin sums grow long)
 constexpr double AMG_CELL = 8.0;
-constexpr int AMG_COARSE_MAX = 12;
+constexpr int AMG_COARSE_MAX = 16;
 constexpr double AMG_OMEGA = 0.8;
 // levels whose every scene has at most AMG_TAIL_ROWS nodes and
 // AMG_TAIL_SLOTS blocks (and all coarser ones) are cycled by one workgroup

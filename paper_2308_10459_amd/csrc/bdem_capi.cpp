@@ -338,7 +338,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   amg_build(NP, NS, pos4, flags, psid, ctx->scene_pbeg, rp, col, lo3, h0, H);
   for (int sc = 0; sc < NS; ++sc)
     if (H.cbeg[sc + 1] - H.cbeg[sc] > AMG_COARSE_MAX) {
-      ctx->err = "multigrid: a scene does not coarsen to 12 aggregates within 15 levels";
+      ctx->err = "multigrid: a scene does not coarsen to 16 aggregates within 15 levels";
       return BDEM_E_INVALID;
     }
   for (int l = 1; l <= H.L; ++l)

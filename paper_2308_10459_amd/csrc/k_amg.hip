@@ -327,7 +327,7 @@ template <typename T> __global__ __launch_bounds__(128) void k_amg_dinv(AmgDev a
 // dense inverse of the last level of each scene (one workgroup per scene):
 // Gauss-Jordan without pivoting on the symmetric positive definite operator,
 // in LDS (at most 6 * AMG_COARSE_MAX rows); the inverse goes to cwork
-template <typename T> __global__ __launch_bounds__(256) void k_amg_coarse_inverse(AmgDev a) {
+template <typename T> __global__ __launch_bounds__(1024) void k_amg_coarse_inverse(AmgDev a) {
   constexpr int NMAX = 6 * AMG_COARSE_MAX;
   __shared__ double M[NMAX * NMAX], X[NMAX * NMAX], fcol[NMAX];
   const int sc = blockIdx.x;
@@ -662,18 +662,38 @@ template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_
       }
     __syncthreads();
   }
-  // the last level: e = A^-1 b (dense), prolonged one level down
+  // the last level: e = A^-1 b (dense), prolonged one level down.  b is in
+  // prod (the last restriction left it there; loaded when the tail is the
+  // last level alone); thread (row, chunk) forms its part of a row, every
+  // load of the dense inverse issued at once, and the parts are added in
+  // chunk order
   {
     int nb, ne;
     range(a.L, nb, ne);
     const AmgLevel &L = a.lv[a.L];
     const int N = 6 * (ne - nb);
+    if (a.Lt == a.L) {
+      for (int q = threadIdx.x; q < N; q += blockDim.x) prod[q] = L.b[(size_t)6 * nb + q];
+      __syncthreads();
+    }
     const double *X = a.cwork + a.coff[sc];
+    const int nch = AMG_TAIL_THREADS / N, len = (N + nch - 1) / nch;   // N <= 6 AMG_COARSE_MAX < threads
+    double *part = prod + N;   // nch x N partial sums
+    {
+      const int r = threadIdx.x % N, ch = threadIdx.x / N;
+      if (ch < nch) {
+        const int c0 = ch * len, c1 = min(N, c0 + len);
+        double acc = 0.0;
+#pragma unroll 4
+        for (int c = c0; c < c1; ++c) acc += X[(size_t)r * N + c] * prod[c];
+        part[ch * N + r] = acc;
+      }
+    }
+    __syncthreads();
     for (int r = threadIdx.x; r < N; r += blockDim.x) {
       double acc = 0.0;
-      for (int c = 0; c < N; ++c) acc += X[(size_t)r * N + c] * L.b[(size_t)6 * nb + c];
+      for (int ch = 0; ch < nch; ++ch) acc += part[ch * N + r];
       res[r] = acc;
-      L.e[(size_t)6 * nb + r] = acc;
     }
     __syncthreads();
     tail_prolong<T>(d, a, a.L, nb, ne, res);
@@ -719,7 +739,7 @@ static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n
     k_amg_galerkin<T><<<nblk(hl[l].nslots, 128), 128, 0, s>>>(a, l);
     k_amg_dinv<T><<<nblk(hl[l].n, 128), 128, 0, s>>>(a, l);
   }
-  k_amg_coarse_inverse<T><<<n_scenes, 256, 0, s>>>(a);
+  k_amg_coarse_inverse<T><<<n_scenes, 1024, 0, s>>>(a);
 }
 
 template <typename T>
