@@ -511,14 +511,16 @@ __global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l, int smoot
 }
 
 // t_f += P_f e for one member f of a level-l node (a level l - 1 node, or a
-// fine particle when l = 1; S = I above the particles)
+// fine particle when l = 1; S = I above the particles).  Scenes whose PCG
+// has stopped are prolonged too: their t0 is not read again before the next
+// solve's first cycle rewrites it.
 template <typename T>
 __device__ __forceinline__ void prolong_one(const DevPtrs &d, const AmgDev &a, int l, int i,
                                             const double (&e)[6]) {
   double dd[3], S[9], y[6];
   double *t;
   if (l == 1) {
-    if (d.flags[i] != 0 || !d.ctl[d.psid[i]].cg_active) return;
+    if (d.flags[i] != 0) return;
     load_pd0<T>(a, i, dd, S);
     t = a.t0 + (size_t)i * 6;
   } else {
