@@ -1038,11 +1038,18 @@ static int run_pcg(bdem_ctx *ctx) {
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, st);
   launch_cg_scalars(ctx->d, ctx->P, st, false);
   if (ctx->S.n_scenes > 1) launch_count_active(ctx->d, ctx->S.n_scenes, 0, st);
-  int rc = read_counters(ctx);
-  if (rc) return rc;
-  if (ctx->h_counters[1] == 0) return BDEM_OK;
   const int chunk = std::max(1, ctx->opt.cg_chunk);
   const bool graph = ctx->opt.use_graph && st != nullptr && ctx->profiling != 1;
+  int rc = BDEM_OK;
+  // The first chunk is issued without waiting for the initial scalars: every
+  // kernel of an iteration returns at once for a scene whose solve stopped,
+  // and the first poll sees it.  (A handle in the static scratch reads its
+  // counters synchronously, and capturing the chunk graphs waits as well.)
+  if (ctx->in_scratch || (graph && !ctx->cg_exec[0])) {
+    rc = read_counters(ctx);
+    if (rc) return rc;
+    if (ctx->h_counters[1] == 0) return BDEM_OK;
+  }
   if (graph && !ctx->cg_exec[0]) {
     rc = build_cg_graphs(ctx, chunk);
     if (rc) return rc;
@@ -1077,8 +1084,10 @@ static int run_pcg(bdem_ctx *ctx) {
     }
     pending = slot;
   }
-  HIP_TRY(hipStreamSynchronize(st));
+  // no wait for the chunk still in flight: what follows is issued behind it
+  // on the same stream
   if (ctx->profiling == 1 && !graph) {
+    HIP_TRY(hipStreamSynchronize(st));
     // SpMV launches issued after every scene had converged returned at once:
     // keep the timings of the initial product(s) and of iterations
     // 0 .. max(cg_it) - 1 of this solve
