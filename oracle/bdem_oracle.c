@@ -1380,12 +1380,12 @@ void orc_friction(orc_sys *s, double dt) {
 /* aggregates = cells of side 8 r_max (from the initial box corner; cells    */
 /* of twice the side at each coarser level), prolongation from the six      */
 /* rigid-body modes of each aggregate, Galerkin coarse operators, damped    */
-/* block-Jacobi smoothing (omega = 0.8) before and after the coarse          */
+/* block-Jacobi smoothing (omega = 0.9) before and after the coarse          */
 /* correction, and an exact solve on the first level with at most 16 nodes  */
 /* (always at least one coarse level).  Built from the diagonal and bond    */
 /* blocks; element-repulsion couplings are not part of it.                   */
 /* ------------------------------------------------------------------------ */
-#define AMG_OMEGA 0.8
+#define AMG_OMEGA 0.9
 #define AMG_COARSE_MAX 16
 
 typedef struct {

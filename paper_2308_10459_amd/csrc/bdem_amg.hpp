@@ -12,7 +12,7 @@
 //         aggregate a: dp = t + w x (x_i - c_a), y = S_i w; S_i = 1/2 R(q_i)^T
 //         for particles, I above), zero for particles that are not unknowns;
 //   A_{l+1} = P^T A_l P (Galerkin), identity on nodes without unknowns;
-//   smoothing: omega = 0.8 block Jacobi before and after the coarse
+//   smoothing: omega = 0.9 block Jacobi before and after the coarse
 //   correction; an exact dense solve per scene on the last level (at most
 //   AMG_COARSE_MAX nodes per scene, in LDS).
 #pragma once
@@ -30,7 +30,7 @@ namespace bdem {
 // first level's restriction and Galerkin sums grow long)
 constexpr double AMG_CELL = 8.0;
 constexpr int AMG_COARSE_MAX = 16;
-constexpr double AMG_OMEGA = 0.8;
+constexpr double AMG_OMEGA = 0.9;
 // levels whose every scene has at most AMG_TAIL_ROWS nodes and
 // AMG_TAIL_SLOTS blocks (and all coarser ones) are cycled by one workgroup
 // per scene in a single launch, their products held in LDS
