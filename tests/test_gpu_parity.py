@@ -912,11 +912,15 @@ def test_ceramic_plate_step_is_a_fixed_point(B, check_step):
     z_o, _, _, _ = sampled_oracle_egh(sc, st0, got["pos"], got["quat"], sc.dt, sample, psd=True,
                                       alive=st0["alive"])
     log(f"  oracle |z| at sampled particles: {np.abs(z_o).max():.3e} (z0 {sg['grad0']:.3e}, rc {sg['rc']})")
-    # Newton ran down to the tolerance or to the objective's rounding floor
-    # (the Armijo test cannot see a decrease below ~1e-15 J of a ~10 J
-    # objective), and the residual it reports is the one the oracle finds
+    # Newton was asked for 1e-10 of the initial gradient, below what the
+    # mixed path resolves; it stops at the objective's rounding floor (the
+    # Armijo test cannot see a decrease below ~1e-15 J of a ~10 J objective),
+    # which must lie at least 1e-5 below the initial gradient; the residual it
+    # reports is the one the oracle finds
     assert sg["rc"] == 0
-    assert sg["grad_final"] <= max(1e-10 * sg["grad0"], 1e-5 * sg["grad0"])
+    record_bound(f"ceramic plate step {check_step}: final / initial reduced gradient",
+                 sg["grad_final"] / sg["grad0"], 1e-5)
+    assert sg["grad_final"] <= 1e-5 * sg["grad0"]
     assert np.abs(z_o).max() <= sg["grad_final"] * (1 + 1e-6) + 1e-10 * sg["grad0"]
     o = Oracle(sc)
     o.set_state(pos=st0["pos"], quat=st0["quat"], vel=st0["vel"], qvel=st0["qvel"], alive=st0["alive"])
