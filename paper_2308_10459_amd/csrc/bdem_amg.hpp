@@ -110,7 +110,8 @@ struct SpmvMark {
   void (*fn)(void *arg, bool start) = nullptr;
   void *arg = nullptr;
 };
+// rev: the block order of the cycle's first SpMV (its second takes the other)
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       int spmv_variant, bool t0_ready, hipStream_t s, SpmvMark mark = SpmvMark());
+                       int spmv_variant, bool t0_ready, bool rev, hipStream_t s, SpmvMark mark = SpmvMark());
 
 }  // namespace bdem

@@ -201,6 +201,7 @@ struct bdem_ctx {
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;   // (kind, index of start event)
   std::vector<int> ev_iter;     // PCG iteration of each mark (-1: outside the iterations)
+  bool spmv_rev = false;        // block order of the next PCG iteration's first SpMV
   int prof_iter = -1;           // the PCG iteration being issued
   // aggregation multigrid preconditioner (bdem_options.preconditioner)
   bool amg = false;
@@ -981,12 +982,16 @@ static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   // multigrid: the update writes the cycle's first step, and the cycle's last
   // kernel writes u = V(r) and forms them
   const bool amg = ctx->amg;
+  // consecutive SpMVs walk the row blocks in opposite orders (an iteration
+  // with multigrid has three: r, !r, r; the next one starts with !r)
+  const bool rev = ctx->spmv_rev;
+  ctx->spmv_rev = !rev;
   launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream, !amg);
   if (amg)
     launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, true,
-                      ctx->stream, cycle_marks(ctx, profile_spmv));
+                      rev, ctx->stream, cycle_marks(ctx, profile_spmv));
   if (profile_spmv) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, SPMV_DOTS_WU);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, SPMV_DOTS_WU, rev);
   if (profile_spmv) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, ctx->stream);
   launch_cg_scalars(ctx->d, ctx->P, ctx->stream, true);
@@ -1029,11 +1034,13 @@ static int run_pcg(bdem_ctx *ctx) {
     HIP_TRY(hipStreamSynchronize(st));
   }
   launch_cg_init(ctx->d, mixed, st);
+  const bool rev = ctx->spmv_rev;
+  ctx->spmv_rev = !rev;
   if (ctx->amg)
-    launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, false, st,
-                      cycle_marks(ctx, ctx->profiling == 1));
+    launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, false, rev,
+                      st, cycle_marks(ctx, ctx->profiling == 1));
   if (ctx->profiling == 1) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, ctx->spmv_variant, st);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, st, SPMV_DOTS_ALL, rev);
   if (ctx->profiling == 1) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, st);
   launch_cg_scalars(ctx->d, ctx->P, st, false);
@@ -1519,7 +1526,7 @@ extern "C" int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_ev
   for (int sc = 0; sc < NS; ++sc) ctx->h_ctl[sc].cg_active = 1;
   HIP_TRY(hipMemcpyAsync(d.ctl, ctx->h_ctl, NS * sizeof(SceneCtl), hipMemcpyHostToDevice, st));
   if (ctx->amg) {
-    launch_amg_vcycle(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, ctx->spmv_variant, false, st);
+    launch_amg_vcycle(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, ctx->spmv_variant, false, false, st);
   } else {
     // block-Jacobi: the PCG initialisation computes u = D^-1 r from r = -z
     HIP_TRY(hipMemcpyAsync(d.z, r.data(), r.size() * sizeof(double), hipMemcpyHostToDevice, st));

@@ -165,7 +165,12 @@ void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
 // SPMV_AMG_FINAL ends the multigrid cycle: with t in u it writes
 // t + omega D^-1 (r - H t) to cAp and the (r, .) and (r, r) partials
 enum SpmvDots { SPMV_DOTS_WU = 0, SPMV_DOTS_ALL = 1, SPMV_DOTS_NONE = 2, SPMV_AMG_FINAL = 3 };
-void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, int dots = SPMV_DOTS_ALL);
+// reverse: workgroups take the row blocks of each XCD's range from its end
+// (consecutive products alternate, so that the rows a product reads first
+// are the ones the product before read last, still in the caches); the
+// results do not depend on it
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, int dots = SPMV_DOTS_ALL,
+                 bool reverse = false);
 int spmv_variants();
 void spmv_shape(int variant, int *threads, int *trips);
 void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s, bool grouped);

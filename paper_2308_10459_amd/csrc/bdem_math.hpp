@@ -199,6 +199,12 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
   const int xcd = b & 7, k = b >> 3;
   return (xcd < rem) ? xcd * (q + 1) + k : rem * (q + 1) + (xcd - rem) * q + k;
 }
+// the same ranges per XCD, each walked from its end
+__device__ __forceinline__ int xcd_block_rev(int b, int nblk) {
+  const int q = nblk >> 3, rem = nblk & 7;
+  const int xcd = b & 7, k = b >> 3;
+  return (xcd < rem) ? xcd * (q + 1) + (q - k) : rem * (q + 1) + (xcd - rem) * q + (q - 1 - k);
+}
 
 // ---------------------------------------------------------------------------
 // Symmetric 9x9 eigen-clamp by cyclic Jacobi, register resident.

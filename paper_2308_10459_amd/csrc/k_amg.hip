@@ -746,10 +746,10 @@ static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n
 
 template <typename T>
 static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                     int spmv_variant, bool t0_ready, hipStream_t s, SpmvMark mark) {
-  auto spmv = [&](const DevPtrs &dd, int mode) {
+                     int spmv_variant, bool t0_ready, bool rev, hipStream_t s, SpmvMark mark) {
+  auto spmv = [&](const DevPtrs &dd, int mode, bool r) {
     if (mark.fn) mark.fn(mark.arg, true);
-    launch_spmv(dd, mixed, spmv_variant, s, mode);
+    launch_spmv(dd, mixed, spmv_variant, s, mode, r);
     if (mark.fn) mark.fn(mark.arg, false);
   };
   // the fine products H t0 run through the PCG's own SpMV kernel, without
@@ -758,7 +758,7 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   dt.cs = a.t0;
   dt.cAp = a.r0;
   if (!t0_ready) k_amg_fine_pre<T><<<d.n_pad / TILE, TILE, 0, s>>>(d, a);
-  spmv(dt, SPMV_DOTS_NONE);
+  spmv(dt, SPMV_DOTS_NONE, rev);
   // each restriction also pre-smooths the level it fills (not the coarsest)
   k_amg_restrict1<T><<<nblk(hl[1].n * R1_LANES, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
   for (int l = 1; l < a.Lt; ++l) {
@@ -773,7 +773,7 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   // in the epilogue of the product H t0
   DevPtrs df = dt;
   df.cAp = d.cs;
-  spmv(df, SPMV_AMG_FINAL);
+  spmv(df, SPMV_AMG_FINAL, !rev);
 }
 
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
@@ -782,9 +782,9 @@ void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int
   else setup_t<double>(d, a, hl, n_scenes, s);
 }
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
-                       int spmv_variant, bool t0_ready, hipStream_t s, SpmvMark mark) {
-  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, true, spmv_variant, t0_ready, s, mark);
-  else vcycle_t<double>(d, a, hl, n_scenes, false, spmv_variant, t0_ready, s, mark);
+                       int spmv_variant, bool t0_ready, bool rev, hipStream_t s, SpmvMark mark) {
+  if (mixed) vcycle_t<float>(d, a, hl, n_scenes, true, spmv_variant, t0_ready, rev, s, mark);
+  else vcycle_t<double>(d, a, hl, n_scenes, false, spmv_variant, t0_ready, rev, s, mark);
 }
 
 }  // namespace bdem

@@ -188,12 +188,12 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // SPMV_AMG_FINAL (the cycle's second product, u holding its iterate t)
 // writes the cycle's result t + omega D^-1 (r - H t) in place of w, with the
 // (r, .) partials of that result for the PCG's scalars.
-template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d, int rdots) {
+template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d, int rdots, int rev) {
   static_assert(NT >= 6 * SPMV_ROWS, "one thread per (row, component)");
   constexpr int NQ = 36 * (int)sizeof(T) / 16;       // 16-byte pieces per block
   __shared__ double2 prod2[SPMV_CAP * 3];
   const double *prod = reinterpret_cast<const double *>(prod2);
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int lb = rev ? xcd_block_rev(blockIdx.x, gridDim.x) : xcd_block(blockIdx.x, gridDim.x);
   const int r0 = lb * SPMV_ROWS;
   const int scene = d.psid[r0];
   if (!d.ctl[scene].cg_active) return;
@@ -688,22 +688,22 @@ int update_variants() { return (int)(sizeof(kUpdateRows) / sizeof(kUpdateRows[0]
 void spmv_shape(int v, int *threads, int *trips) { *threads = kSpmvShape[v][0]; *trips = kSpmvShape[v][1]; }
 int update_rows(int v) { return kUpdateRows[v]; }
 
-template <typename T> static void spmv_dispatch(const DevPtrs &d, int v, int rd, hipStream_t s) {
+template <typename T> static void spmv_dispatch(const DevPtrs &d, int v, int rd, int rev, hipStream_t s) {
   static_assert(TILE % SPMV_ROWS == 0, "SpMV tiling");
   const int nsp = d.n_pad / SPMV_ROWS;
   switch (v) {
-    case 1: k_spmv<T, 192, 1><<<nsp, 192, 0, s>>>(d, rd); break;
-    case 2: k_spmv<T, 256, 2><<<nsp, 256, 0, s>>>(d, rd); break;
-    case 3: k_spmv<T, 512, 1><<<nsp, 512, 0, s>>>(d, rd); break;
-    case 4: k_spmv<T, 192, 2><<<nsp, 192, 0, s>>>(d, rd); break;
-    case 5: k_spmv<T, 384, 1><<<nsp, 384, 0, s>>>(d, rd); break;
-    case 6: k_spmv<T, 384, 2><<<nsp, 384, 0, s>>>(d, rd); break;
-    default: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d, rd); break;
+    case 1: k_spmv<T, 192, 1><<<nsp, 192, 0, s>>>(d, rd, rev); break;
+    case 2: k_spmv<T, 256, 2><<<nsp, 256, 0, s>>>(d, rd, rev); break;
+    case 3: k_spmv<T, 512, 1><<<nsp, 512, 0, s>>>(d, rd, rev); break;
+    case 4: k_spmv<T, 192, 2><<<nsp, 192, 0, s>>>(d, rd, rev); break;
+    case 5: k_spmv<T, 384, 1><<<nsp, 384, 0, s>>>(d, rd, rev); break;
+    case 6: k_spmv<T, 384, 2><<<nsp, 384, 0, s>>>(d, rd, rev); break;
+    default: k_spmv<T, 256, 1><<<nsp, 256, 0, s>>>(d, rd, rev); break;
   }
 }
-void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, int dots) {
-  if (mixed) spmv_dispatch<float>(d, variant, dots, s);
-  else spmv_dispatch<double>(d, variant, dots, s);
+void launch_spmv(const DevPtrs &d, bool mixed, int variant, hipStream_t s, int dots, bool reverse) {
+  if (mixed) spmv_dispatch<float>(d, variant, dots, reverse ? 1 : 0, s);
+  else spmv_dispatch<double>(d, variant, dots, reverse ? 1 : 0, s);
 }
 void launch_cg_scalars(const DevPtrs &d, const Params &P, hipStream_t s, bool grouped) {
   if (grouped) k_cg_scalars<true><<<P.n_scenes, SCAL_THREADS, 0, s>>>(d, P);
