@@ -9,15 +9,17 @@
 
 namespace bdem {
 
-namespace {
-
-uint64_t morton3(int64_t x, int64_t y, int64_t z) {
+uint64_t amg_cell_key(int64_t x, int64_t y, int64_t z) {
   uint64_t c = 0;
   for (int bit = 20; bit >= 0; --bit)
     c = (c << 3) | ((uint64_t)((x >> bit) & 1) << 2) | ((uint64_t)((y >> bit) & 1) << 1) |
         (uint64_t)((z >> bit) & 1);
   return c;
 }
+
+namespace {
+
+uint64_t morton3(int64_t x, int64_t y, int64_t z) { return amg_cell_key(x, y, z); }
 
 // nodes of a level from keys (scene, cell) of the finer nodes: unique keys in
 // (scene, Morton(cell)) order; parent of each finer node; children lists

@@ -88,6 +88,10 @@ struct AmgHost {
   int64_t cdense = 0;               // total doubles of the dense blocks
 };
 
+// Morton (Z-order) key of an aggregation cell (x, y, z >= 0): the order of
+// the nodes of every level within a scene
+uint64_t amg_cell_key(int64_t x, int64_t y, int64_t z);
+
 // Builds the symbolic hierarchy.  pos: 4 doubles per internal row (initial
 // positions), flags per row (255 = padding), psid per row, scene_pbeg,
 // fine CSR (row_ptr over rows, col per slot), per-scene box corner and h0.

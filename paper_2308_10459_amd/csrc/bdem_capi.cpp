@@ -517,12 +517,17 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
     ctx->scene_pbeg[s + 1] = ctx->scene_pbeg[s] + (pcnt[s] + TILE - 1) / TILE * TILE;
     ctx->scene_bbeg[s + 1] = ctx->scene_bbeg[s] + (int)((bcnt[s] + TILE - 1) / TILE * TILE);
   }
-  // internal particle order: within each scene, along a Morton (Z-order)
-  // curve of the initial positions, so bonded particles sit in nearby rows
-  // (locality of the bond gathers, the assembly and the symmetric SpMV)
+  // internal particle order: within each scene, by the multigrid's
+  // first-level aggregation cell (side AMG_CELL r_max from the scene's
+  // initial box corner, cells in the hierarchy's Morton order), and inside a
+  // cell along a Morton (Z-order) curve of the initial positions.  Bonded
+  // particles sit in nearby rows (locality of the bond gathers, the
+  // assembly and the symmetric SpMV), and the members of an aggregate are
+  // one contiguous range of rows (the restriction and prolongation read
+  // them with unit stride).
   ctx->p_int.resize(n);
   {
-    std::vector<uint64_t> code(n);
+    std::vector<uint64_t> code(n), cell(n);
     int i0 = 0;
     while (i0 < n) {
       const int s = p->scene ? p->scene[i0] : 0;
@@ -535,7 +540,13 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
           hi[k] = std::max(hi[k], p->pos[3 * i + k]);
         }
       const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+      double rmax = 0.0;
+      for (int i = i0; i < i1; ++i) rmax = std::max(rmax, p->radius[i]);
+      const double h0 = AMG_CELL * std::max(rmax, 1e-300);
       for (int i = i0; i < i1; ++i) {
+        int64_t ck[3];
+        for (int k = 0; k < 3; ++k) ck[k] = (int64_t)std::floor((p->pos[3 * i + k] - lo[k]) / h0);
+        cell[i] = amg_cell_key(ck[0], ck[1], ck[2]);
         uint64_t c = 0;
         uint32_t q[3];
         for (int k = 0; k < 3; ++k)
@@ -546,7 +557,9 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
       }
       std::vector<int> idx(i1 - i0);
       std::iota(idx.begin(), idx.end(), i0);
-      std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return code[a] < code[c]; });
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+        return cell[a] != cell[c] ? cell[a] < cell[c] : code[a] < code[c];
+      });
       for (int k = 0; k < (int)idx.size(); ++k) ctx->p_int[idx[k]] = ctx->scene_pbeg[s] + k;
       i0 = i1;
     }
@@ -803,7 +816,7 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
     return fail(nullptr, BDEM_E_HIP, m);
   }
   if (o.preconditioner == BDEM_PRECOND_AMG) {
-    // aggregation cells of side 4 r_max from each scene's initial box corner
+    // aggregation cells of side AMG_CELL r_max from each scene's initial box corner
     std::vector<double> pos4((size_t)NP * 4), lo3(3 * NS, 1e300), h0(NS);
     for (int r = 0; r < NP; ++r) {
       pos4[4 * (size_t)r] = h_pn[r].x; pos4[4 * (size_t)r + 1] = h_pn[r].y; pos4[4 * (size_t)r + 2] = h_pn[r].z;
