@@ -204,6 +204,18 @@ def run_batch(steps, warmup, amg=True):
         sim = B.Simulator(sc, precision=prec, preconditioner=p)
         tuning = sim.autotune(sc.dt_per_scene)
         log(f"  batch {label} autotuned: {tuning}")
+        if label == "mixed_batched":
+            # the batched SpMV's roofline: the autotuner times the tuned SpMV
+            # shape with every scene active (back-to-back launches on the
+            # batch's initial matrix, all bonds alive)
+            nbytes = spmv_algorithmic_bytes(sc.n, sc.nb, 4)
+            us = tuning["spmv_us"]
+            out["roofline_spmv"] = {
+                "bound": "hbm", "kernel": "k_spmv<float> (all 64 scenes in one launch)",
+                "achieved": nbytes / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "launch_us": us,
+                "algorithmic_bytes_per_launch": nbytes,
+                "timing": "autotuner: mean of back-to-back launches, every scene active"}
         for _ in range(warmup):
             sim.step_batched(sc.dt_per_scene)
         torch.cuda.synchronize()
