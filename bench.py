@@ -96,18 +96,13 @@ def recorded_valu(kernel):
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
-def spmv_algorithmic_bytes(n, nb_alive, elt, multigrid=False):
+def spmv_algorithmic_bytes(n, nb_alive, elt):
     """Bytes one SpMV must move at least: every unique block once (one 6x6 per
     bond, the 21 packed values of each diagonal block), the bond's index pair,
-    the input vector read once and the output written once (FP64).  With
-    multigrid, the average over a PCG iteration's three SpMV launches: the
-    cycle's first product and the PCG's own move that much, the cycle's last
-    also reads r (48 B) and the Jacobi inverse (21 values) per particle, in its
-    smoothing epilogue."""
-    base = nb_alive * 36 * elt + n * 21 * elt + nb_alive * 8 + 2 * 6 * n * 8
-    if multigrid:
-        return base + (n * 48 + n * 21 * elt) / 3
-    return base
+    the input vector read once and the output written once (FP64).  Both
+    launches of a multigrid PCG iteration (the cycle's fine product and the
+    PCG's own) are such products."""
+    return nb_alive * 36 * elt + n * 21 * elt + nb_alive * 8 + 2 * 6 * n * 8
 
 
 def bond_algorithmic_bytes(n, nb_alive, elt, inverse=False):
@@ -494,7 +489,7 @@ def main():
         nwt = r["newton"] / r["wall_s"] if r["wall_s"] > 0 and r["newton"] else 0.0
         be = r["alive_bonds"] * r["bond_launch"] / (r["bond_ms"] * 1e-3) if r["bond_ms"] > 0 else 0.0
         spmv_avg_ms = r["spmv_ms"] / max(r["spmv_launch"], 1)
-        bytes_spmv = spmv_algorithmic_bytes(scene.n, r["alive_bonds"], elt, multigrid=head_amg)
+        bytes_spmv = spmv_algorithmic_bytes(scene.n, r["alive_bonds"], elt)
         bond_avg_ms = r["bond_ms"] / max(r["bond_launch"], 1)
         bytes_bond = bond_algorithmic_bytes(scene.n, r["alive_bonds"], elt, inverse=rows)
         return dict(newton_iters_per_s=nwt, bond_hessian_evals_per_s=be,
@@ -543,7 +538,7 @@ def main():
                                                if rf and rf["newton_iters_per_s"] > 0 else None),
         "mixed_over_fp64_ms_per_step": (rf["ms_per_step"] / rm["ms_per_step"] if rf else None),
         "roofline": {"bound": "hbm",
-                     "kernel": ("k_spmv<float> (every launch: the multigrid cycle's two and the PCG's)"
+                     "kernel": ("k_spmv<float> (every launch: the multigrid cycle's and the PCG's)"
                                 if head_amg else "k_spmv<float>"),
                      "achieved": rm["spmv_gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": rm["spmv_gbs"] / HBM_PEAK_GBS,

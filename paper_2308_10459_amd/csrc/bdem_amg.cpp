@@ -117,6 +117,29 @@ void amg_build(int n_pad, int n_scenes, const std::vector<double> &pos4,
   // level 1
   Grouping g = group(fscene, fcell, real);
   H.parent0 = g.parent;
+  // fine coupling H P: the distinct aggregates of each row's diagonal and
+  // off-diagonal columns that are unknowns (P is zero elsewhere), ascending;
+  // the sources of an entry in slot order, the diagonal first
+  H.hp_ptr.assign(n_pad + 1, 0);
+  H.hp_gptr.assign(1, 0);
+  {
+    std::vector<std::pair<int, int>> src;   // (aggregate, source)
+    for (int r = 0; r < n_pad; ++r) {
+      src.clear();
+      if (g.parent[r] >= 0 && factive[r]) src.push_back({g.parent[r], -1 - r});
+      for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k)
+        if (g.parent[col[k]] >= 0 && factive[col[k]]) src.push_back({g.parent[col[k]], k});
+      std::stable_sort(src.begin(), src.end(),
+                       [](const std::pair<int, int> &x, const std::pair<int, int> &y) { return x.first < y.first; });
+      for (size_t k = 0; k < src.size(); ++k) {
+        if (k > 0 && src[k].first != src[k - 1].first) H.hp_gptr.push_back((int)H.hp_gsrc.size());
+        if (k == 0 || src[k].first != src[k - 1].first) H.hp_agg.push_back(src[k].first);
+        H.hp_gsrc.push_back(src[k].second);
+      }
+      if (!src.empty()) H.hp_gptr.push_back((int)H.hp_gsrc.size());
+      H.hp_ptr[r + 1] = (int)H.hp_agg.size();
+    }
+  }
   int level = 0;
   std::vector<int> prev_scene = fscene, prev_active = factive;
   std::vector<int64_t> prev_cell = fcell;

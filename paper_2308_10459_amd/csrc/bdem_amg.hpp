@@ -15,6 +15,12 @@
 //   smoothing: omega = 0.9 block Jacobi before and after the coarse
 //   correction; an exact dense solve per scene on the last level (at most
 //   AMG_COARSE_MAX nodes per scene, in LDS).
+// The fine level's post-smoothing needs H t for t = t0 + P e (e the level-1
+// correction).  It is formed as H t0 (the cycle's first fine product) plus
+// (H P) e: the fine coupling H P, one 6x6 block per fine row and level-1
+// aggregate that the row's blocks reach (about 2.7 per row on close-packed
+// solids against ~13 Hessian blocks per row), is recomputed whenever the
+// Hessian changes, so the cycle runs one fine product instead of two.
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -65,6 +71,14 @@ struct AmgDev {
   void *pd0 = nullptr;              // 12 T per particle: x_i - c_a (3), S_i (9)
   double *t0 = nullptr, *r0 = nullptr;   // 6 per particle
   const AmgLevel *lv = nullptr;     // device array lv[0..L] (lv[0] unused)
+  // fine coupling H P: per fine row its level-1 aggregates in ascending order
+  // (hp_ptr over rows, hp_agg per entry, 36 T per entry, row-major), and per
+  // entry the fine blocks that sum into it, in slot order (hp_gptr; per
+  // source hp_src: the slot's block code, (bond block << 1) | transposed, or
+  // -1 for the row's diagonal block; hp_col: the block's column j)
+  int nhp = 0;
+  int *hp_ptr = nullptr, *hp_agg = nullptr, *hp_gptr = nullptr, *hp_src = nullptr, *hp_col = nullptr;
+  void *hp_val = nullptr;
   // coarsest level: dense inverse per scene
   int *cbeg = nullptr;              // n_scenes + 1: node range per scene on level L
   int64_t *coff = nullptr;          // n_scenes: offset of the scene's (6m)^2 block
@@ -82,6 +96,9 @@ struct AmgHost {
   int Lt = 0;
   std::vector<int> tbeg;
   std::vector<int> parent0, slot_row0;
+  // fine coupling pattern (AmgDev); hp_gsrc per source: the slot, or
+  // -1 - row for the diagonal block
+  std::vector<int> hp_ptr, hp_agg, hp_gptr, hp_gsrc;
   std::vector<AmgHostLevel> lv;     // lv[1..L]
   std::vector<int> cbeg;
   std::vector<int64_t> coff;
@@ -105,16 +122,20 @@ void amg_build(int n_pad, int n_scenes, const std::vector<double> &pos4,
 // hl: host copy of the level array (sizes for the launches)
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
                       hipStream_t s);
+// the fine coupling H P from the current Hessian blocks and the prolongator
+// of the last setup: after every setup and every Hessian evaluation that
+// the cycle will use
+void launch_amg_couple(const DevPtrs &d, const AmgDev &a, bool mixed, hipStream_t s);
 // t0_ready: the CG update already wrote t0 = omega D^-1 r (DevPtrs::amg_t0);
 // the cycle writes u = M^-1 r into d.cs and the (r, u), (r, r) partials of
 // each SPMV_ROWS-row block
-// mark (optional): called with true before and false after each of the
-// cycle's two fine SpMV launches (the profiler's event brackets)
+// mark (optional): called with true before and false after the cycle's
+// fine SpMV launch (the profiler's event brackets)
 struct SpmvMark {
   void (*fn)(void *arg, bool start) = nullptr;
   void *arg = nullptr;
 };
-// rev: the block order of the cycle's first SpMV (its second takes the other)
+// rev: the block order of the cycle's fine SpMV
 void launch_amg_vcycle(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
                        int spmv_variant, bool t0_ready, bool rev, hipStream_t s, SpmvMark mark = SpmvMark());
 

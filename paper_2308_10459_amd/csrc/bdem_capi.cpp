@@ -330,8 +330,8 @@ extern "C" int bdem_sizes(const bdem_ctx *ctx, int32_t *n, int64_t *nb, int32_t 
 // allocation owned by the handle (freed by bdem_destroy).
 static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std::vector<uint8_t> &flags,
                       const std::vector<int> &psid, const std::vector<int> &rp,
-                      const std::vector<int> &col, const std::vector<double> &lo3,
-                      const std::vector<double> &h0) {
+                      const std::vector<int> &col, const std::vector<int> &sblk,
+                      const std::vector<double> &lo3, const std::vector<double> &h0) {
   const Sizes &S = ctx->S;
   const int NP = S.n_pad, NS = S.n_scenes;
   const size_t T = S.mixed ? 4 : 8;
@@ -359,6 +359,20 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   L.add(&a.pd0, 12 * (size_t)NP * T);
   addd(&a.t0, 6 * (size_t)NP);
   addd(&a.r0, 6 * (size_t)NP);
+  // the coupling's sources as the kernel reads them: block code and column
+  std::vector<int> hp_src(H.hp_gsrc.size()), hp_col(H.hp_gsrc.size());
+  for (size_t m = 0; m < H.hp_gsrc.size(); ++m) {
+    const int g = H.hp_gsrc[m];
+    hp_src[m] = g < 0 ? -1 : sblk[g];
+    hp_col[m] = g < 0 ? -1 - g : col[g];
+  }
+  a.nhp = (int)H.hp_agg.size();
+  addi(&a.hp_ptr, H.hp_ptr.size());
+  addi(&a.hp_agg, H.hp_agg.size());
+  addi(&a.hp_gptr, H.hp_gptr.size());
+  addi(&a.hp_src, hp_src.size());
+  addi(&a.hp_col, hp_col.size());
+  L.add(&a.hp_val, std::max<size_t>(H.hp_agg.size(), 1) * 36 * T);
   for (int l = 1; l <= H.L; ++l) {
     AmgLevel &V = ctx->amg_hl[l];
     const AmgHostLevel &h = H.lv[l];
@@ -404,6 +418,11 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   };
   upi(a.slot_row0, H.slot_row0);
   upi(a.parent0, H.parent0);
+  upi(a.hp_ptr, H.hp_ptr);
+  upi(a.hp_agg, H.hp_agg);
+  upi(a.hp_gptr, H.hp_gptr);
+  upi(a.hp_src, hp_src);
+  upi(a.hp_col, hp_col);
   for (int l = 1; l <= H.L; ++l) {
     const AmgLevel &V = ctx->amg_hl[l];
     const AmgHostLevel &h = H.lv[l];
@@ -827,7 +846,7 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
       lo3[3 * sc + 2] = std::min(lo3[3 * sc + 2], h_pn[r].z);
     }
     for (int sc = 0; sc < NS; ++sc) h0[sc] = AMG_CELL * s_rmax[sc];
-    const int rc = amg_upload(ctx, pos4, h_flags, h_psid, rp, h_col, lo3, h0);
+    const int rc = amg_upload(ctx, pos4, h_flags, h_psid, rp, h_col, h_sb, lo3, h0);
     if (rc) {
       const std::string m = ctx->err;
       destroy_resources(ctx);
@@ -995,16 +1014,17 @@ static void launch_cg_iteration(bdem_ctx *ctx, bool profile_spmv) {
   // multigrid: the update writes the cycle's first step, and the cycle's last
   // kernel writes u = V(r) and forms them
   const bool amg = ctx->amg;
-  // consecutive SpMVs walk the row blocks in opposite orders (an iteration
-  // with multigrid has three: r, !r, r; the next one starts with !r)
+  // consecutive SpMVs walk the row blocks in opposite orders: block-Jacobi
+  // has one per iteration (the next iteration takes the other order),
+  // multigrid two (the cycle's r, the PCG's !r; every iteration starts with r)
   const bool rev = ctx->spmv_rev;
-  ctx->spmv_rev = !rev;
+  if (!amg) ctx->spmv_rev = !rev;
   launch_cg_update(ctx->d, mixed, ctx->upd_variant, ctx->stream, !amg);
   if (amg)
     launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, true,
                       rev, ctx->stream, cycle_marks(ctx, profile_spmv));
   if (profile_spmv) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, SPMV_DOTS_WU, rev);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, ctx->stream, SPMV_DOTS_WU, amg ? !rev : rev);
   if (profile_spmv) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, ctx->stream);
   launch_cg_scalars(ctx->d, ctx->P, ctx->stream, true);
@@ -1048,12 +1068,12 @@ static int run_pcg(bdem_ctx *ctx) {
   }
   launch_cg_init(ctx->d, mixed, st);
   const bool rev = ctx->spmv_rev;
-  ctx->spmv_rev = !rev;
+  if (!ctx->amg) ctx->spmv_rev = !rev;
   if (ctx->amg)
     launch_amg_vcycle(ctx->d, ctx->amg_d, ctx->amg_hl.data(), ctx->S.n_scenes, mixed, ctx->spmv_variant, false, rev,
                       st, cycle_marks(ctx, ctx->profiling == 1));
   if (ctx->profiling == 1) prof_mark(ctx, 1, true);
-  launch_spmv(ctx->d, mixed, ctx->spmv_variant, st, SPMV_DOTS_ALL, rev);
+  launch_spmv(ctx->d, mixed, ctx->spmv_variant, st, SPMV_DOTS_ALL, ctx->amg ? !rev : rev);
   if (ctx->profiling == 1) prof_mark(ctx, 1, false);
   if (ctx->P.contact) launch_contact_spmv(ctx->d, ctx->P, st);
   launch_cg_scalars(ctx->d, ctx->P, st, false);
@@ -1193,8 +1213,10 @@ static int step_impl(bdem_ctx *ctx, const double *dts, bdem_step_stats *stats, b
     const bool hess = !ctx->P.first_order;   // Algorithm 1 needs the gradient only
     launch_evaluation(ctx, hess, true, k == 0, false);
     // the multigrid hierarchy: every Newton iteration, or once per step
-    if (hess && ctx->amg && (k == 0 || ctx->opt.amg_refresh == 0))
-      launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
+    if (hess && ctx->amg) {
+      if (k == 0 || ctx->opt.amg_refresh == 0) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
+      launch_amg_couple(d, ctx->amg_d, mixed, st);   // H P of this iterate's Hessian
+    }
     launch_newton_check(d, ctx->P, k == 0 ? 1 : 0, rows_path(ctx, hess), st);
     launch_count_active(d, NS, 0, st);
     int rc = read_counters(ctx);
@@ -1528,7 +1550,10 @@ extern "C" int bdem_precond_apply(bdem_ctx *ctx, double dt, const double *pos_ev
   if (rc < 0) return rc;
   hipStream_t st = ctx->stream;
   DevPtrs &d = ctx->d;
-  if (ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, st);
+  if (ctx->amg) {
+    launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, ctx->S.mixed, st);
+    launch_amg_couple(d, ctx->amg_d, ctx->S.mixed, st);
+  }
   // r = in (internal order), every scene active, then u = M^-1 r
   std::vector<double> r((size_t)NP * 6, 0.0), u((size_t)NP * 6);
   for (int i = 0; i < n; ++i)
@@ -1705,7 +1730,10 @@ extern "C" int bdem_autotune(bdem_ctx *ctx, const double *dt_per_scene, bdem_tun
   }
   launch_step_target(d, ctx->P, st);
   launch_evaluation(ctx, true, true, true, false);
-  if (ctx->amg) launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
+  if (ctx->amg) {
+    launch_amg_setup(d, ctx->amg_d, ctx->amg_hl.data(), NS, mixed, st);
+    launch_amg_couple(d, ctx->amg_d, mixed, st);
+  }
   launch_newton_check(d, ctx->P, 1, rows_path(ctx, true), st);
   launch_count_active(d, NS, 0, st);
   int rc = read_counters(ctx);

@@ -160,11 +160,9 @@ void launch_ls_decide(const DevPtrs &d, const Params &P, hipStream_t s);
 void launch_cg_init(const DevPtrs &d, bool mixed, hipStream_t s);
 // dots: SPMV_DOTS_ALL forms the (r, u), (w, u) and (r, r) partials;
 // SPMV_DOTS_WU leaves (r, u) and (r, r) to the kernel that produced u (the CG
-// update with rdots = true, or the multigrid cycle's last product) and
-// merges theirs; SPMV_DOTS_NONE writes w only (the cycle's first product);
-// SPMV_AMG_FINAL ends the multigrid cycle: with t in u it writes
-// t + omega D^-1 (r - H t) to cAp and the (r, .) and (r, r) partials
-enum SpmvDots { SPMV_DOTS_WU = 0, SPMV_DOTS_ALL = 1, SPMV_DOTS_NONE = 2, SPMV_AMG_FINAL = 3 };
+// update with rdots = true, or the multigrid cycle's last kernel) and
+// merges theirs; SPMV_DOTS_NONE writes w only (the cycle's fine product)
+enum SpmvDots { SPMV_DOTS_WU = 0, SPMV_DOTS_ALL = 1, SPMV_DOTS_NONE = 2 };
 // reverse: workgroups take the row blocks of each XCD's range from its end
 // (consecutive products alternate, so that the rows a product reads first
 // are the ones the product before read last, still in the caches); the

@@ -510,35 +510,26 @@ __global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l, int smoot
   if (live && k0 < 6) store_b_and_smooth<T>(C, A, k0, acc, smooth);
 }
 
-// t_f += P_f e for one member f of a level-l node (a level l - 1 node, or a
-// fine particle when l = 1; S = I above the particles).  Scenes whose PCG
-// has stopped are prolonged too: their t0 is not read again before the next
-// solve's first cycle rewrites it.
-template <typename T>
-__device__ __forceinline__ void prolong_one(const DevPtrs &d, const AmgDev &a, int l, int i,
-                                            const double (&e)[6]) {
-  double dd[3], S[9], y[6];
-  double *t;
-  if (l == 1) {
-    if (d.flags[i] != 0) return;
-    load_pd0<T>(a, i, dd, S);
-    t = a.t0 + (size_t)i * 6;
-  } else {
-    const AmgLevel &F = a.lv[l - 1];
-    if (!F.active[i]) return;
-    dd[0] = F.pd[3 * i]; dd[1] = F.pd[3 * i + 1]; dd[2] = F.pd[3 * i + 2];
-    ident3(S);
-    t = F.t + (size_t)i * 6;
-  }
+// t_f += P_f e for one member f of a level-l node, l >= 2 (a level l - 1
+// node; S = I above the particles).  Level 1's correction is not prolonged
+// here: the cycle's last kernel applies it to the particles.
+__device__ __forceinline__ void prolong_one(const AmgDev &a, int l, int i, const double (&e)[6]) {
+  const AmgLevel &F = a.lv[l - 1];
+  if (!F.active[i]) return;
+  const double dd[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
+  double S[9], y[6];
+  ident3(S);
+  double *t = F.t + (size_t)i * 6;
   p_apply(dd, S, e, y);
 #pragma unroll
   for (int m = 0; m < 6; ++m) t[m] += y[m];
 }
 
 // on each level going up: e_l = t_l + omega D^-1 (b_l - A t_l) (t_l already
-// holds the prolonged correction), prolonged into the members of each node.
-// One wavefront per row; its lanes then take the row's members.
-template <typename T> __global__ __launch_bounds__(256) void k_amg_post(DevPtrs d, AmgDev a, int l) {
+// holds the prolonged correction), prolonged into the members of each node
+// (level 1 keeps e_1 for the cycle's last kernel).  One wavefront per row;
+// its lanes then take the row's members.
+template <typename T> __global__ __launch_bounds__(256) void k_amg_post(AmgDev a, int l) {
   const AmgLevel &L = a.lv[l];
   const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (A >= L.n) return;   // uniform over the wavefront
@@ -554,12 +545,13 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_post(DevPtrs 
 #pragma unroll
     for (int k = 0; k < 6; ++k) u += double(Di[k]) * rv[k];
     ev = L.t[(size_t)A * 6 + lane] + AMG_OMEGA * u;
-    L.e[(size_t)A * 6 + lane] = ev;
+    if (l == 1) L.e[(size_t)A * 6 + lane] = ev;
   }
+  if (l == 1) return;   // uniform over the launch
   double e[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) e[k] = __shfl(ev, k, 64);
-  for (int k = L.mbeg[A] + lane; k < L.mbeg[A + 1]; k += 64) prolong_one<T>(d, a, l, L.mlist[k], e);
+  for (int k = L.mbeg[A] + lane; k < L.mbeg[A + 1]; k += 64) prolong_one(a, l, L.mlist[k], e);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,8 +559,8 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_post(DevPtrs 
 // cycle as the per-level kernels: going down, r_l = b_l - A t_l and the
 // restriction into l + 1 with its pre-smoothing; the dense solve of the last
 // level; going up, e_l = t_l + omega D^-1 (b_l - A t_l) prolonged into the
-// level below (the last of them into level Lt - 1, or the fine t0, which the
-// next launch reads).  A product A x takes one thread per block (its six
+// level below (the last of them into level Lt - 1, which the next launch
+// reads; level 1's e_1 is kept for the cycle's last kernel).  A product A x takes one thread per block (its six
 // components into LDS), then one thread per (row, component) adds its row's
 // blocks in slot order.
 // ---------------------------------------------------------------------------
@@ -601,17 +593,19 @@ __device__ __forceinline__ void tail_residual(const AmgLevel &L, int nb, int ne,
 }
 
 // e of the rows [nb, ne) (6 values per row in ev) prolonged into their
-// members one level down
-template <typename T>
-__device__ __forceinline__ void tail_prolong(const DevPtrs &d, const AmgDev &a, int l, int nb, int ne,
-                                             const double *ev) {
+// members one level down; on level 1 stored for the cycle's last kernel
+__device__ __forceinline__ void tail_prolong(const AmgDev &a, int l, int nb, int ne, const double *ev) {
   const AmgLevel &L = a.lv[l];
-  const int *parent = (l == 1) ? a.parent0 : a.lv[l - 1].parent;
-  for (int k = L.mbeg[nb] + (int)threadIdx.x; k < L.mbeg[ne]; k += blockDim.x) {
-    const int i = L.mlist[k];
-    const double *ep = ev + (parent[i] - nb) * 6;
-    const double e[6] = {ep[0], ep[1], ep[2], ep[3], ep[4], ep[5]};
-    prolong_one<T>(d, a, l, i, e);
+  if (l == 1) {
+    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x) L.e[(size_t)nb * 6 + q] = ev[q];
+  } else {
+    const int *parent = a.lv[l - 1].parent;
+    for (int k = L.mbeg[nb] + (int)threadIdx.x; k < L.mbeg[ne]; k += blockDim.x) {
+      const int i = L.mlist[k];
+      const double *ep = ev + (parent[i] - nb) * 6;
+      const double e[6] = {ep[0], ep[1], ep[2], ep[3], ep[4], ep[5]};
+      prolong_one(a, l, i, e);
+    }
   }
   __syncthreads();
 }
@@ -698,7 +692,7 @@ template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_
       res[r] = acc;
     }
     __syncthreads();
-    tail_prolong<T>(d, a, a.L, nb, ne, res);
+    tail_prolong(a, a.L, nb, ne, res);
   }
   // going up
   for (int l = a.L - 1; l >= a.Lt; --l) {
@@ -718,12 +712,195 @@ template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_
     }
     __syncthreads();   // every thread has read res
     m = 0;
-    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x, ++m) {
-      res[q] = ev[m];
-      L.e[(size_t)nb * 6 + q] = ev[m];
+    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x, ++m) res[q] = ev[m];
+    __syncthreads();
+    tail_prolong(a, l, nb, ne, res);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fine level's end of the cycle
+// ---------------------------------------------------------------------------
+
+// fine coupling (H P)_{i,a} = sum of H_ij P_j over the blocks of row i whose
+// column j is an unknown of aggregate a.  Row r of H_ij P_j, with h = row r
+// of H_ij split into (h_t, h_w): columns 0-2 are h_t, columns 3-5 are
+// d_j x h_t + S_j^T h_w.  Thread (entry, r); its sources HP_U at a time,
+// every load of those issued before the first product, in the fixed order
+// of the pattern.
+constexpr int HP_U = 2;   // sources in flight per thread (about five per entry)
+template <typename T> __global__ __launch_bounds__(256) void k_amg_hp(DevPtrs d, AmgDev a) {
+  const int q = blockIdx.x * 256 + (int)threadIdx.x;
+  const int k = q / 6, r = q - (q / 6) * 6;
+  if (k >= a.nhp) return;
+  const T *hd = reinterpret_cast<const T *>(d.hdiag), *ho = reinterpret_cast<const T *>(d.hoff);
+  const T *pd = reinterpret_cast<const T *>(a.pd0);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int m0 = a.hp_gptr[k], m1 = a.hp_gptr[k + 1];
+  constexpr int U = HP_U;
+  constexpr int NP4 = 12 * (int)sizeof(T) / 16;   // 16-byte pieces of a prolongator record
+  for (int mb = m0; mb < m1; mb += U) {
+    int src[U], j[U];
+#pragma unroll
+    for (int m = 0; m < U; ++m) {   // past the entry: its last source again
+      const int mm = min(mb + m, m1 - 1);
+      src[m] = a.hp_src[mm];
+      j[m] = a.hp_col[mm];
+    }
+    T h[U][6], p[U][12];
+#pragma unroll
+    for (int m = 0; m < U; ++m) {
+      // diagonal: packed upper triangle of row j; off-diagonal: row r of the
+      // stored block, or its column r when H_ij is the transpose
+      const bool diag = src[m] < 0, tr = (src[m] & 1) != 0;
+      const T *base = diag ? hd + (size_t)j[m] * 21 : ho + (size_t)(src[m] >> 1) * 36;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) h[m][c] = base[diag ? up6(r, c) : (tr ? c * 6 + r : r * 6 + c)];
+      const float4 *pp = reinterpret_cast<const float4 *>(pd + (size_t)j[m] * 12);
+      float4 *pq = reinterpret_cast<float4 *>(p[m]);
+#pragma unroll
+      for (int x = 0; x < NP4; ++x) pq[x] = pp[x];
+    }
+#pragma unroll
+    for (int m = 0; m < U; ++m) {   // branch-free, so that no load sinks into a branch
+      const bool live = mb + m < m1;
+      double hv[6], dd[3], S[9];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) hv[c] = live ? double(h[m][c]) : 0.0;
+#pragma unroll
+      for (int x = 0; x < 3; ++x) dd[x] = double(p[m][x]);
+#pragma unroll
+      for (int x = 0; x < 9; ++x) S[x] = double(p[m][3 + x]);
+      acc[0] += hv[0];
+      acc[1] += hv[1];
+      acc[2] += hv[2];
+      acc[3] += (dd[1] * hv[2] - dd[2] * hv[1]) + S[0] * hv[3] + S[3] * hv[4] + S[6] * hv[5];
+      acc[4] += (dd[2] * hv[0] - dd[0] * hv[2]) + S[1] * hv[3] + S[4] * hv[4] + S[7] * hv[5];
+      acc[5] += (dd[0] * hv[1] - dd[1] * hv[0]) + S[2] * hv[3] + S[5] * hv[4] + S[8] * hv[5];
+    }
+  }
+  T *o = reinterpret_cast<T *>(a.hp_val) + (size_t)k * 36 + r * 6;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o[c] = T(acc[c]);
+}
+
+// six values of an array the cycle reads once, with non-temporal loads.
+// The cycle's last kernel reads all its operands this way: measured on the
+// 219K plate, the PCG's product that follows then finds more of the Hessian
+// in the Infinity Cache (67.8 against 72.3 us with ordinary loads).
+__device__ __forceinline__ void ld6_stream(const float *p, float (&v)[6]) {
+  typedef float v2f __attribute__((ext_vector_type(2)));
+  const v2f *q = reinterpret_cast<const v2f *>(p);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const v2f x = __builtin_nontemporal_load(q + k);
+    v[2 * k] = x.x;
+    v[2 * k + 1] = x.y;
+  }
+}
+__device__ __forceinline__ void ld6_stream(const double *p, double (&v)[6]) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  const v2d *q = reinterpret_cast<const v2d *>(p);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const v2d x = __builtin_nontemporal_load(q + k);
+    v[2 * k] = x.x;
+    v[2 * k + 1] = x.y;
+  }
+}
+
+// The cycle's result u = t + omega D^-1 (r - H t) for t = t0 + P e_1, with
+// H t = H t0 + (H P) e_1 (r0 holds H t0, the cycle's fine product), written
+// to the PCG's u, and the (r, u) and (r, r) partials of each SPMV_ROWS-row
+// block for the scalars step.  The block's coupling entries are one
+// contiguous range: phase 1 gives each lane a row of an entry (six
+// consecutive values, so that a wavefront reads one contiguous stretch) and
+// e_1 of the entry's aggregate, FINAL_U rows in flight, and writes the
+// product to LDS; phase 2 is thread (row, component), which adds its row's
+// products in entry order after H t0.
+constexpr int FINAL_U = 3;
+constexpr int FINAL_CAP = FINAL_U * SPMV_ROWS;   // entries per pass: FINAL_U per row on average
+template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) void k_amg_final(DevPtrs d, AmgDev a) {
+  constexpr int NT = 6 * SPMV_ROWS;
+  static_assert(6 * FINAL_CAP == NT * FINAL_U, "one round of every lane's rows per pass");
+  __shared__ double prod[FINAL_CAP * 6];
+  __shared__ double ys[NT];
+  const int lb = blockIdx.x, r0 = lb * SPMV_ROWS;
+  if (!d.ctl[d.psid[r0]].cg_active) return;   // uniform over the workgroup
+  const int t = threadIdx.x, rl = t / 6, c = t - (t / 6) * 6, row = r0 + rl;
+  const size_t o = (size_t)row * 6 + c;
+  const double *e1 = a.lv[1].e;
+  // the row thread's own operands (non-temporal), issued before the
+  // entries' loads: its r, t0 and H t0, the Jacobi inverse's row, and
+  // component c of P_row e_p (zero unless the row is an unknown of an
+  // aggregate)
+  const double rc = __builtin_nontemporal_load(d.cr + o);
+  double tc = __builtin_nontemporal_load(a.t0 + o), hc = __builtin_nontemporal_load(a.r0 + o);
+  const int kr0 = a.hp_ptr[row], kr1 = a.hp_ptr[row + 1];
+  T di[6];
+  {
+    const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)row * 21;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) di[k] = __builtin_nontemporal_load(Di + up6(c, k));
+    const int p = a.parent0[row];
+    const bool use = p >= 0 && d.flags[row] == 0;
+    double dd[3], S[9];
+    {
+      const T *pp = reinterpret_cast<const T *>(a.pd0) + (size_t)row * 12;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) dd[m] = double(__builtin_nontemporal_load(pp + m));
+#pragma unroll
+      for (int m = 0; m < 9; ++m) S[m] = double(__builtin_nontemporal_load(pp + 3 + m));
+    }
+    double e[6], y[6];
+    ld6(e1 + (size_t)max(p, 0) * 6, e);
+    p_apply(dd, S, e, y);   // all six, then this thread's: no load under a branch
+    double pe = y[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) pe = (c == k) ? y[k] : pe;
+    tc += use ? pe : 0.0;
+  }
+  const int eb = a.hp_ptr[r0], ee = a.hp_ptr[r0 + SPMV_ROWS];
+  const T *hv = reinterpret_cast<const T *>(a.hp_val);
+  for (int cb = eb; cb < ee; cb += FINAL_CAP) {
+    const int nw = 6 * min(FINAL_CAP, ee - cb);   // (entry, row) items of the pass
+    T h[FINAL_U][6];
+    double ev[FINAL_U][6];
+#pragma unroll
+    for (int m = 0; m < FINAL_U; ++m) {   // lanes past the pass repeat its last item
+      const int q = min(m * NT + t, nw - 1);
+      const int k = cb + q / 6;
+      ld6_stream(hv + (size_t)k * 36 + (q - (q / 6) * 6) * 6, h[m]);
+      const double *e = e1 + (size_t)a.hp_agg[k] * 6;
+#pragma unroll
+      for (int x = 0; x < 6; ++x) ev[m][x] = e[x];
+    }
+#pragma unroll
+    for (int m = 0; m < FINAL_U; ++m) {
+      double y = 0.0;
+#pragma unroll
+      for (int x = 0; x < 6; ++x) y += double(h[m][x]) * ev[m][x];
+      if (m * NT + t < nw) prod[m * NT + t] = y;
     }
     __syncthreads();
-    tail_prolong<T>(d, a, l, nb, ne, res);
+    const int lo = max(kr0, cb), hi = min(kr1, cb + nw / 6);
+    for (int k = lo; k < hi; ++k) hc += prod[(k - cb) * 6 + c];
+    __syncthreads();
+  }
+  ys[t] = rc - hc;
+  __syncthreads();
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v += double(di[k]) * ys[rl * 6 + k];
+  const double un = tc + AMG_OMEGA * v;
+  d.cs[o] = un;
+  KSum ru = {0.0, 0.0}, none = {0.0, 0.0}, rr = {0.0, 0.0};
+  kadd(ru, rc * un);
+  kadd(rr, rc * rc);
+  block_ksum3(ru, none, rr);
+  if (t == 0) {
+    d.part_a[lb] = make_double2(ru.s, ru.c);
+    d.part_c[lb] = make_double2(rr.s, rr.c);
   }
 }
 
@@ -747,33 +924,35 @@ static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n
 template <typename T>
 static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
                      int spmv_variant, bool t0_ready, bool rev, hipStream_t s, SpmvMark mark) {
-  auto spmv = [&](const DevPtrs &dd, int mode, bool r) {
-    if (mark.fn) mark.fn(mark.arg, true);
-    launch_spmv(dd, mixed, spmv_variant, s, mode, r);
-    if (mark.fn) mark.fn(mark.arg, false);
-  };
-  // the fine products H t0 run through the PCG's own SpMV kernel, without
-  // its dots
+  // the fine product H t0 runs through the PCG's own SpMV kernel, without
+  // its dots, into r0
   DevPtrs dt = d;
   dt.cs = a.t0;
   dt.cAp = a.r0;
   if (!t0_ready) k_amg_fine_pre<T><<<d.n_pad / TILE, TILE, 0, s>>>(d, a);
-  spmv(dt, SPMV_DOTS_NONE, rev);
+  if (mark.fn) mark.fn(mark.arg, true);
+  launch_spmv(dt, mixed, spmv_variant, s, SPMV_DOTS_NONE, rev);
+  if (mark.fn) mark.fn(mark.arg, false);
   // each restriction also pre-smooths the level it fills (not the coarsest)
   k_amg_restrict1<T><<<nblk(hl[1].n * R1_LANES, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
   for (int l = 1; l < a.Lt; ++l) {
     k_amg_resid<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
     k_amg_restrict<T><<<nblk(hl[l + 1].n * RC_LANES, 256), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
   }
-  // levels Lt..L in one launch; it prolongs into level Lt - 1 (or t0)
+  // levels Lt..L in one launch; it prolongs into level Lt - 1 (or keeps e_1)
   k_amg_tail<T><<<n_scenes, AMG_TAIL_THREADS, 0, s>>>(d, a);
-  // each level's kernel also prolongs its correction one level down
-  for (int l = a.Lt - 1; l >= 1; --l) k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(d, a, l);
-  // the post-smoothing u = t0 + omega D^-1 (r - H t0) and the PCG's r dots,
-  // in the epilogue of the product H t0
-  DevPtrs df = dt;
-  df.cAp = d.cs;
-  spmv(df, SPMV_AMG_FINAL, !rev);
+  // each level's kernel also prolongs its correction one level down (level
+  // 1 keeps e_1)
+  for (int l = a.Lt - 1; l >= 1; --l) k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
+  // t = t0 + P e_1 and the post-smoothing u = t + omega D^-1 (r - H t),
+  // H t from H t0 and the fine coupling, with the PCG's r dots
+  k_amg_final<T><<<d.n_pad / SPMV_ROWS, 6 * SPMV_ROWS, 0, s>>>(d, a);
+}
+
+void launch_amg_couple(const DevPtrs &d, const AmgDev &a, bool mixed, hipStream_t s) {
+  if (a.nhp == 0) return;
+  if (mixed) k_amg_hp<float><<<nblk(6 * a.nhp, 256), 256, 0, s>>>(d, a);
+  else k_amg_hp<double><<<nblk(6 * a.nhp, 256), 256, 0, s>>>(d, a);
 }
 
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,

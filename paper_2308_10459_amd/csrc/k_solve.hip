@@ -183,11 +183,8 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // workgroup of a scene merges them for the scalars step: wavefront 0 takes
 // the partials of its own block and the next DOT_GROUP - 1 (one butterfly
 // tree per group, whatever the launch shape).  The merging workgroups are
-// spread over the scene, and so over all XCDs.  SPMV_DOTS_NONE (the first
-// product inside the multigrid cycle) writes w and nothing else;
-// SPMV_AMG_FINAL (the cycle's second product, u holding its iterate t)
-// writes the cycle's result t + omega D^-1 (r - H t) in place of w, with the
-// (r, .) partials of that result for the PCG's scalars.
+// spread over the scene, and so over all XCDs.  SPMV_DOTS_NONE (the product
+// inside the multigrid cycle) writes w and nothing else.
 template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spmv(DevPtrs d, int rdots, int rev) {
   static_assert(NT >= 6 * SPMV_ROWS, "one thread per (row, component)");
   constexpr int NQ = 36 * (int)sizeof(T) / 16;       // 16-byte pieces per block
@@ -223,7 +220,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   if (rowthr) {
     rbeg = d.row_ptr[row];
     rend = d.row_ptr[row + 1];
-    if (rdots == SPMV_DOTS_ALL || rdots == SPMV_AMG_FINAL) rc = d.cr[(size_t)row * 6 + c_out];
+    if (rdots == SPMV_DOTS_ALL) rc = d.cr[(size_t)row * 6 + c_out];
   }
   // the diagonal block times u_row, added before any slot product
   auto add_diag = [&]() {
@@ -329,30 +326,6 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
       for (int k = lo; k < hi; ++k) acc += prod[(k - cb) * 6 + c_out];
     }
     __syncthreads();
-  }
-  if (rdots == SPMV_AMG_FINAL) {   // uniform over the launch
-    // u = t0 + omega D^-1 (r - H t0) into cAp (u above holds t0); the row's
-    // r - H t0 shared through LDS; then the (r, u) and (r, r) partials
-    __shared__ double ys[6 * SPMV_ROWS];
-    if (rowthr) ys[t] = rc - acc;
-    __syncthreads();
-    KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
-    if (rowthr) {
-      const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)row * 21;
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) v += double(Di[up6(c_out, k)]) * ys[rl * 6 + k];
-      const double un = uc + AMG_OMEGA * v;
-      d.cAp[(size_t)row * 6 + c_out] = un;
-      kadd(ru, rc * un);
-      kadd(rr, rc * rc);
-    }
-    block_ksum3(ru, wu, rr);
-    if (t == 0) {
-      d.part_a[lb] = make_double2(ru.s, ru.c);
-      d.part_c[lb] = make_double2(rr.s, rr.c);
-    }
-    return;
   }
   if (rowthr) d.cAp[(size_t)row * 6 + c_out] = acc;
   if (rdots == SPMV_DOTS_NONE) return;   // uniform over the launch

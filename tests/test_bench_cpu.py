@@ -29,8 +29,6 @@ def test_spmv_algorithmic_bytes_per_unit():
         assert bench.spmv_algorithmic_bytes(1, 0, elt) == 21 * elt + 96
     # the 219,024-particle plate after its impact step (1,336,336 alive bonds)
     assert bench.spmv_algorithmic_bytes(219024, 1336336, 4) == 242547392
-    # with multigrid: one launch in three also reads r and the Jacobi inverse
-    assert bench.spmv_algorithmic_bytes(3, 0, 4, multigrid=True) == bench.spmv_algorithmic_bytes(3, 0, 4) + 48 + 84
 
 
 def test_bond_algorithmic_bytes_per_unit():
