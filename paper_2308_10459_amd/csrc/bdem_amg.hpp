@@ -56,7 +56,7 @@ struct AmgLevel {
   double *cen = nullptr;            // 3 per node
   double *pd = nullptr;             // 3 per node: x_node - c_parent (towards the next level)
   int *parent = nullptr;            // node of the next level
-  double *b = nullptr, *t = nullptr, *r = nullptr, *e = nullptr;   // 6 per node
+  double *b = nullptr, *t = nullptr, *e = nullptr;   // 6 per node
 };
 
 // device view of the whole hierarchy

@@ -393,7 +393,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
     addi(&V.parent, h.n);
     addd(&V.cen, 3 * (size_t)h.n);
     addd(&V.pd, 3 * (size_t)h.n);
-    for (double **v : {&V.b, &V.t, &V.r, &V.e}) addd(v, 6 * (size_t)h.n);
+    for (double **v : {&V.b, &V.t, &V.e}) addd(v, 6 * (size_t)h.n);
   }
   addi(&a.cbeg, NS + 1);
   addi(&a.tbeg, H.tbeg.size());
@@ -429,7 +429,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
     upi(V.row_ptr, h.row_ptr); upi(V.col, h.col); upi(V.slot_row, h.slot_row); upi(V.dslot, h.dslot);
     upi(V.gptr, h.gptr); upi(V.gsrc, h.gsrc); upi(V.mbeg, h.mbeg); upi(V.mlist, h.mlist);
     upi(V.active, h.active); upi(V.scene, h.scene); upi(V.parent, h.parent);
-    for (double *v : {V.b, V.t, V.r, V.e, V.cen, V.pd}) chk(hipMemsetAsync(v, 0, std::max<size_t>(6 * (size_t)h.n, 1) * sizeof(double) / (v == V.cen || v == V.pd ? 2 : 1), st));
+    for (double *v : {V.b, V.t, V.e, V.cen, V.pd}) chk(hipMemsetAsync(v, 0, std::max<size_t>(6 * (size_t)h.n, 1) * sizeof(double) / (v == V.cen || v == V.pd ? 2 : 1), st));
   }
   upi(a.cbeg, H.cbeg);
   upi(a.tbeg, H.tbeg);

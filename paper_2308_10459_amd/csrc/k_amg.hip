@@ -386,7 +386,6 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_pre(Dev
 // k + R1_LANES, ...; the lanes' sums then meet in a fixed butterfly, and six
 // of them write b and t.
 constexpr int R1_LANES = 64;   // a cell of side 8 r_max holds 60-90 close-packed particles
-constexpr int RC_LANES = 8;    // a coarser cell holds at most 8 cells
 
 template <int G> __device__ __forceinline__ void lanes_sum6(double (&v)[6]) {
 #pragma unroll
@@ -478,36 +477,93 @@ __device__ __forceinline__ double wave_row_apply(const AmgLevel &L, int A, const
   return y;
 }
 
-template <typename T> __global__ __launch_bounds__(256) void k_amg_resid(AmgDev a, int l) {
-  const AmgLevel &L = a.lv[l];
-  const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (A >= L.n) return;   // uniform over the wavefront
-  const double y = wave_row_apply<T>(L, A, L.t, lane);
-  if (lane < 6) L.r[(size_t)A * 6 + lane] = L.b[(size_t)A * 6 + lane] - y;
-}
-
-// b_{l+1} = P^T r_l (S = I above the particles) and, with `smooth` (level
-// l + 1 is not the coarsest), its pre-smoothing; RC_LANES lanes per node
+// Residual and restriction in one launch: for each node of level l + 1,
+// r_A = b_A - (A_l t_l)_A on each of its children A (at most 8, a cell of
+// twice the side), then b = sum over the active children of P_A^T r_A
+// (S = I above the particles) and, with `smooth` (level l + 1 is not the
+// coarsest), its pre-smoothing.  RR_THREADS threads per node: thread
+// (g, h) takes child g and its row's slots h, h + 16, ..., all six
+// components of each slot's product, with every load of a row of up to
+// 16 RR_U slots issued at once; the sixteen lanes of a child meet in a
+// fixed butterfly, the eight children in LDS in child order.
+constexpr int RR_THREADS = 128;
 template <typename T>
-__global__ __launch_bounds__(256) void k_amg_restrict(AmgDev a, int l, int smooth) {
+__global__ __launch_bounds__(256) void k_amg_resid_restrict(AmgDev a, int l, int smooth) {
+  constexpr int U = sizeof(T) == 4 ? 2 : 1;      // slots in flight per thread (registers)
+  constexpr int NQ = 36 * (int)sizeof(T) / 16;   // 16-byte pieces per block
+  constexpr int NPB = 256 / RR_THREADS;           // nodes per workgroup
+  __shared__ double zs[NPB][8][6];
   const AmgLevel &C = a.lv[l + 1], &F = a.lv[l];
-  const int A = (blockIdx.x * 256 + (int)threadIdx.x) / RC_LANES, k0 = threadIdx.x % RC_LANES;
-  const bool live = A < C.n;
-  double acc[6] = {0, 0, 0, 0, 0, 0}, S[9];
-  ident3(S);
-  if (live)
-    for (int k = C.mbeg[A] + k0; k < C.mbeg[A + 1]; k += RC_LANES) {
-      const int i = C.mlist[k];
-      if (!F.active[i]) continue;
-      const double dd[3] = {F.pd[3 * i], F.pd[3 * i + 1], F.pd[3 * i + 2]};
-      double x[6], y[6];
-      ld6(F.r + (size_t)i * 6, x);
-      pt_apply(dd, S, x, y);
+  const int nl = threadIdx.x / RR_THREADS, tid = threadIdx.x % RR_THREADS;
+  const int node = blockIdx.x * NPB + nl;
+  const bool live = node < C.n;
+  const int g = tid >> 4, h = tid & 15;
+  double z[6] = {0, 0, 0, 0, 0, 0};
+  if (live) {   // uniform over each wavefront (two per node)
+    const int mb = C.mbeg[node], me = C.mbeg[node + 1];
+    const bool has = mb + g < me;
+    const int A = C.mlist[has ? mb + g : mb];   // threads without a child repeat the first (dropped below)
+    const bool act = has && F.active[A] != 0;
+    const double dd[3] = {F.pd[3 * A], F.pd[3 * A + 1], F.pd[3 * A + 2]};
+    double bA[6];
+    ld6(F.b + (size_t)A * 6, bA);
+    const int s0 = F.row_ptr[A], s1 = F.row_ptr[A + 1];
+    const float4 *V4 = reinterpret_cast<const float4 *>(F.val);
+    double y[6] = {0, 0, 0, 0, 0, 0};
+    for (int sb = s0 + h; sb < s1; sb += 16 * U) {
+      int sl[U];
+      float4 bq[U][NQ];
+      double xv[U][6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) acc[m] += y[m];
+      for (int m = 0; m < U; ++m) sl[m] = (sb + 16 * m < s1) ? sb + 16 * m : sb;
+#pragma unroll
+      for (int m = 0; m < U; ++m) {
+        const float4 *b4 = V4 + (size_t)sl[m] * NQ;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) bq[m][q] = b4[q];
+        ld6(F.t + (size_t)F.col[sl[m]] * 6, xv[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < U; ++m) {   // branch-free, so that no load sinks into a branch
+        const T *bv = reinterpret_cast<const T *>(bq[m]);
+        const bool in = sb + 16 * m < s1;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int e = 0; e < 6; ++e) acc += double(bv[c * 6 + e]) * xv[m][e];
+          y[c] += in ? acc : 0.0;
+        }
+      }
     }
-  lanes_sum6<RC_LANES>(acc);
-  if (live && k0 < 6) store_b_and_smooth<T>(C, A, k0, acc, smooth);
+    // the child's row sum over its sixteen lanes, r_A, and P_A^T r_A
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) y[c] += __shfl_xor(y[c], off, 64);
+    double r[6], S[9];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) r[c] = bA[c] - y[c];
+    ident3(S);
+    pt_apply(dd, S, r, z);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) z[c] = act ? z[c] : 0.0;
+  }
+  if (h == 0)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) zs[nl][g][c] = z[c];
+  __syncthreads();
+  if (live && tid < 6) {
+    double acc[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v += zs[nl][k][c];
+      acc[c] = v;
+    }
+    store_b_and_smooth<T>(C, node, tid, acc, smooth);
+  }
 }
 
 // t_f += P_f e for one member f of a level-l node, l >= 2 (a level l - 1
@@ -820,7 +876,7 @@ __device__ __forceinline__ void ld6_stream(const double *p, double (&v)[6]) {
 // products in entry order after H t0.
 constexpr int FINAL_U = 3;
 constexpr int FINAL_CAP = FINAL_U * SPMV_ROWS;   // entries per pass: FINAL_U per row on average
-template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) void k_amg_final(DevPtrs d, AmgDev a) {
+template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_amg_final(DevPtrs d, AmgDev a) {
   constexpr int NT = 6 * SPMV_ROWS;
   static_assert(6 * FINAL_CAP == NT * FINAL_U, "one round of every lane's rows per pass");
   __shared__ double prod[FINAL_CAP * 6];
@@ -830,36 +886,13 @@ template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) void k_amg_fin
   const int t = threadIdx.x, rl = t / 6, c = t - (t / 6) * 6, row = r0 + rl;
   const size_t o = (size_t)row * 6 + c;
   const double *e1 = a.lv[1].e;
-  // the row thread's own operands (non-temporal), issued before the
-  // entries' loads: its r, t0 and H t0, the Jacobi inverse's row, and
-  // component c of P_row e_p (zero unless the row is an unknown of an
-  // aggregate)
+  // the row thread's own operands (non-temporal): its r, t0 and H t0
+  // before the entries' loads; after them (fewer registers held across the
+  // entries) the Jacobi inverse's row and component c of P_row e_p (zero
+  // unless the row is an unknown of an aggregate)
   const double rc = __builtin_nontemporal_load(d.cr + o);
   double tc = __builtin_nontemporal_load(a.t0 + o), hc = __builtin_nontemporal_load(a.r0 + o);
   const int kr0 = a.hp_ptr[row], kr1 = a.hp_ptr[row + 1];
-  T di[6];
-  {
-    const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)row * 21;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) di[k] = __builtin_nontemporal_load(Di + up6(c, k));
-    const int p = a.parent0[row];
-    const bool use = p >= 0 && d.flags[row] == 0;
-    double dd[3], S[9];
-    {
-      const T *pp = reinterpret_cast<const T *>(a.pd0) + (size_t)row * 12;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) dd[m] = double(__builtin_nontemporal_load(pp + m));
-#pragma unroll
-      for (int m = 0; m < 9; ++m) S[m] = double(__builtin_nontemporal_load(pp + 3 + m));
-    }
-    double e[6], y[6];
-    ld6(e1 + (size_t)max(p, 0) * 6, e);
-    p_apply(dd, S, e, y);   // all six, then this thread's: no load under a branch
-    double pe = y[0];
-#pragma unroll
-    for (int k = 1; k < 6; ++k) pe = (c == k) ? y[k] : pe;
-    tc += use ? pe : 0.0;
-  }
   const int eb = a.hp_ptr[r0], ee = a.hp_ptr[r0 + SPMV_ROWS];
   const T *hv = reinterpret_cast<const T *>(a.hp_val);
   for (int cb = eb; cb < ee; cb += FINAL_CAP) {
@@ -886,6 +919,29 @@ template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) void k_amg_fin
     const int lo = max(kr0, cb), hi = min(kr1, cb + nw / 6);
     for (int k = lo; k < hi; ++k) hc += prod[(k - cb) * 6 + c];
     __syncthreads();
+  }
+  T di[6];
+  {
+    const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)row * 21;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) di[k] = __builtin_nontemporal_load(Di + up6(c, k));
+    const int p = a.parent0[row];
+    const bool use = p >= 0 && d.flags[row] == 0;
+    double dd[3], S[9];
+    {
+      const T *pp = reinterpret_cast<const T *>(a.pd0) + (size_t)row * 12;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) dd[m] = double(__builtin_nontemporal_load(pp + m));
+#pragma unroll
+      for (int m = 0; m < 9; ++m) S[m] = double(__builtin_nontemporal_load(pp + 3 + m));
+    }
+    double e[6], y[6];
+    ld6(e1 + (size_t)max(p, 0) * 6, e);
+    p_apply(dd, S, e, y);   // all six, then this thread's: no load under a branch
+    double pe = y[0];
+#pragma unroll
+    for (int k = 1; k < 6; ++k) pe = (c == k) ? y[k] : pe;
+    tc += use ? pe : 0.0;
   }
   ys[t] = rc - hc;
   __syncthreads();
@@ -935,10 +991,8 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   if (mark.fn) mark.fn(mark.arg, false);
   // each restriction also pre-smooths the level it fills (not the coarsest)
   k_amg_restrict1<T><<<nblk(hl[1].n * R1_LANES, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
-  for (int l = 1; l < a.Lt; ++l) {
-    k_amg_resid<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
-    k_amg_restrict<T><<<nblk(hl[l + 1].n * RC_LANES, 256), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
-  }
+  for (int l = 1; l < a.Lt; ++l)
+    k_amg_resid_restrict<T><<<nblk(hl[l + 1].n, 256 / RR_THREADS), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
   // levels Lt..L in one launch; it prolongs into level Lt - 1 (or keeps e_1)
   k_amg_tail<T><<<n_scenes, AMG_TAIL_THREADS, 0, s>>>(d, a);
   // each level's kernel also prolongs its correction one level down (level

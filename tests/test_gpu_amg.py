@@ -26,8 +26,11 @@ def B():
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-@pytest.mark.parametrize("dims", [(5, 4, 3), (11, 10, 9), (16, 16, 8)])
+@pytest.mark.parametrize("dims", [(5, 4, 3), (11, 10, 9), (16, 16, 8), (64, 64, 16)])
 def test_vcycle_matches_oracle(B, mixed, dims):
+    # up to 2,048 particles the coarse levels fit the one-workgroup tail;
+    # 65,536 particles give levels of 1,024, 128 and 16 aggregates, the
+    # first two too large for it, so the per-level kernels run as well
     log(f"[amg vcycle] dims={dims} mixed={mixed}")
     sc, st = _perturbed_block(*dims, ground=True)
     o = oracle_for(sc, st)
