@@ -345,6 +345,15 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   for (int l = 1; l <= H.L; ++l)
     for (int v : H.lv[l].dslot)
       if (v < 0) { ctx->err = "multigrid: a coarse row without a diagonal block"; return BDEM_E_INVALID; }
+  {   // the level-1 restriction reads an aggregate's members as consecutive rows
+    const AmgHostLevel &l1 = H.lv[1];
+    for (int A = 0; A < l1.n; ++A)
+      for (int k = l1.mbeg[A]; k < l1.mbeg[A + 1]; ++k)
+        if (l1.mlist[k] != l1.mlist[l1.mbeg[A]] + (k - l1.mbeg[A])) {
+          ctx->err = "multigrid: the members of a first-level aggregate are not consecutive rows";
+          return BDEM_E_INVALID;
+        }
+  }
   // one allocation carved into the arrays
   Layout L;
   AmgDev &a = ctx->amg_d;

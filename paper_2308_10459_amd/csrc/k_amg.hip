@@ -411,28 +411,64 @@ __device__ __forceinline__ void store_b_and_smooth(const AmgLevel &L, int A, int
   L.t[(size_t)A * 6 + c] = AMG_OMEGA * y;
 }
 
+typedef double nt_v2d __attribute__((ext_vector_type(2)));
+typedef float nt_v4f __attribute__((ext_vector_type(4)));
+
+// The members of a level-1 aggregate are consecutive rows (the internal
+// order sorts particles by their aggregation cell; checked at create), so
+// a wavefront stages its members' r, H t0 and prolongator records through
+// LDS as contiguous 16-byte pieces, read non-temporally (they are not read
+// again in the cycle; the matrix the PCG's product reads next stays in the
+// Infinity Cache), then lane k takes member k, k + 64, ... as before.
 template <typename T>
 __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int smooth) {
+  static_assert(R1_LANES == 64, "one wavefront per aggregate");
+  constexpr int RW = 3;                            // 16-byte pieces of six doubles
+  constexpr int PW = 12 * (int)sizeof(T) / 16;     // of a prolongator record
+  __shared__ nt_v2d sr[4][64 * RW], sh[4][64 * RW];
+  __shared__ nt_v4f sp[4][64 * PW];
   const AmgLevel &L = a.lv[1];
-  const int A = (blockIdx.x * 256 + (int)threadIdx.x) / R1_LANES, k0 = threadIdx.x % R1_LANES;
-  const bool live = A < L.n;   // the same for the whole group
+  const int w = threadIdx.x >> 6, k0 = threadIdx.x & 63;
+  const int A = blockIdx.x * 4 + w;
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  if (live)
-    for (int k = L.mbeg[A] + k0; k < L.mbeg[A + 1]; k += R1_LANES) {
-      const int i = L.mlist[k];
-      if (d.flags[i] != 0) continue;
-      double dd[3], S[9], x[6], h[6], y[6];
-      load_pd0<T>(a, i, dd, S);
-      ld6(d.cr + (size_t)i * 6, x);
-      ld6(a.r0 + (size_t)i * 6, h);
+  if (A < L.n) {   // uniform over the wavefront
+    const int mb = L.mbeg[A], nm = L.mbeg[A + 1] - mb;
+    const int row0 = L.mlist[mb];
+    const nt_v2d *R2 = reinterpret_cast<const nt_v2d *>(d.cr + (size_t)row0 * 6);
+    const nt_v2d *H2 = reinterpret_cast<const nt_v2d *>(a.r0 + (size_t)row0 * 6);
+    const nt_v4f *P4 = reinterpret_cast<const nt_v4f *>(reinterpret_cast<const T *>(a.pd0) + (size_t)row0 * 12);
+    for (int c0 = 0; c0 < nm; c0 += 64) {
+      const int cnt = min(64, nm - c0);
+      for (int q = k0; q < cnt * RW; q += 64) {
+        sr[w][q] = __builtin_nontemporal_load(R2 + c0 * RW + q);
+        sh[w][q] = __builtin_nontemporal_load(H2 + c0 * RW + q);
+      }
+      for (int q = k0; q < cnt * PW; q += 64) sp[w][q] = __builtin_nontemporal_load(P4 + c0 * PW + q);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (k0 < cnt && d.flags[row0 + c0 + k0] == 0) {
+        const double *xs = reinterpret_cast<const double *>(&sr[w][k0 * RW]);
+        const double *hs = reinterpret_cast<const double *>(&sh[w][k0 * RW]);
+        const T *ps = reinterpret_cast<const T *>(&sp[w][k0 * PW]);
+        double dd[3], S[9], x[6], y[6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) x[m] -= h[m];
-      pt_apply(dd, S, x, y);
+        for (int m = 0; m < 3; ++m) dd[m] = double(ps[m]);
 #pragma unroll
-      for (int m = 0; m < 6; ++m) acc[m] += y[m];
+        for (int m = 0; m < 9; ++m) S[m] = double(ps[3 + m]);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) x[m] = xs[m] - hs[m];
+        pt_apply(dd, S, x, y);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) acc[m] += y[m];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();   // every lane has read before the next pieces land
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+  }
   lanes_sum6<R1_LANES>(acc);
-  if (live && k0 < 6) store_b_and_smooth<T>(L, A, k0, acc, smooth);
+  if (A < L.n && k0 < 6) store_b_and_smooth<T>(L, A, k0, acc, smooth);
 }
 
 // r = b - A t on a level above the tail, one wavefront per row
@@ -990,7 +1026,7 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   launch_spmv(dt, mixed, spmv_variant, s, SPMV_DOTS_NONE, rev);
   if (mark.fn) mark.fn(mark.arg, false);
   // each restriction also pre-smooths the level it fills (not the coarsest)
-  k_amg_restrict1<T><<<nblk(hl[1].n * R1_LANES, 256), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
+  k_amg_restrict1<T><<<nblk(hl[1].n, 4), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
   for (int l = 1; l < a.Lt; ++l)
     k_amg_resid_restrict<T><<<nblk(hl[l + 1].n, 256 / RR_THREADS), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
   // levels Lt..L in one launch; it prolongs into level Lt - 1 (or keeps e_1)

@@ -327,8 +327,13 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
     }
     __syncthreads();
   }
+  if (rdots == SPMV_DOTS_NONE) {   // uniform over the launch
+    // the cycle's product, read twice more in the same cycle: streamed out
+    // so that it does not take the matrix's place in the Infinity Cache
+    if (rowthr) __builtin_nontemporal_store(acc, d.cAp + (size_t)row * 6 + c_out);
+    return;
+  }
   if (rowthr) d.cAp[(size_t)row * 6 + c_out] = acc;
-  if (rdots == SPMV_DOTS_NONE) return;   // uniform over the launch
   KSum ru = {0.0, 0.0}, wu = {0.0, 0.0}, rr = {0.0, 0.0};
   if (rowthr) {
     kadd(ru, rc * uc);
