@@ -912,24 +912,45 @@ __device__ __forceinline__ void ld6_stream(const double *p, double (&v)[6]) {
 // products in entry order after H t0.
 constexpr int FINAL_U = 3;
 constexpr int FINAL_CAP = FINAL_U * SPMV_ROWS;   // entries per pass: FINAL_U per row on average
-template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_amg_final(DevPtrs d, AmgDev a) {
+template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 4))) void k_amg_final(DevPtrs d, AmgDev a) {
   constexpr int NT = 6 * SPMV_ROWS;
   static_assert(6 * FINAL_CAP == NT * FINAL_U, "one round of every lane's rows per pass");
+  // the block's Jacobi inverses and prolongator records: contiguous 16-byte
+  // pieces loaded (non-temporally) with the row operands, held over the
+  // entries' pass and read back through LDS by the row threads
+  constexpr int NSD = SPMV_ROWS * 21 * (int)sizeof(T) / 16, NSP = SPMV_ROWS * 12 * (int)sizeof(T) / 16;
+  constexpr int NSTG = (NSD + NSP + NT - 1) / NT;
+  static_assert(SPMV_ROWS * 21 * sizeof(T) % 16 == 0 && SPMV_ROWS * 12 * sizeof(T) % 16 == 0, "16-byte pieces");
   __shared__ double prod[FINAL_CAP * 6];
   __shared__ double ys[NT];
+  __shared__ nt_v4f stg[NSD + NSP];
   const int lb = blockIdx.x, r0 = lb * SPMV_ROWS;
   if (!d.ctl[d.psid[r0]].cg_active) return;   // uniform over the workgroup
   const int t = threadIdx.x, rl = t / 6, c = t - (t / 6) * 6, row = r0 + rl;
   const size_t o = (size_t)row * 6 + c;
   const double *e1 = a.lv[1].e;
-  // the row thread's own operands (non-temporal): its r, t0 and H t0
-  // before the entries' loads; after them (fewer registers held across the
-  // entries) the Jacobi inverse's row and component c of P_row e_p (zero
-  // unless the row is an unknown of an aggregate)
+  // the row thread's own operands (non-temporal): its r, t0 and H t0; its
+  // aggregate (component c of P_row e_p is added when the row is an unknown
+  // of one), and the staged pieces
   const double rc = __builtin_nontemporal_load(d.cr + o);
   double tc = __builtin_nontemporal_load(a.t0 + o), hc = __builtin_nontemporal_load(a.r0 + o);
   const int kr0 = a.hp_ptr[row], kr1 = a.hp_ptr[row + 1];
   const int eb = a.hp_ptr[r0], ee = a.hp_ptr[r0 + SPMV_ROWS];
+  const int p = a.parent0[row];
+  const bool use = p >= 0 && d.flags[row] == 0;
+  nt_v4f sv[NSTG];
+  {
+    const nt_v4f *gd = reinterpret_cast<const nt_v4f *>(reinterpret_cast<const T *>(d.dinv) + (size_t)r0 * 21);
+    const nt_v4f *gp = reinterpret_cast<const nt_v4f *>(reinterpret_cast<const T *>(a.pd0) + (size_t)r0 * 12);
+#pragma unroll
+    for (int m = 0; m < NSTG; ++m) {
+      const int q = m * NT + t;
+      if (q < NSD) sv[m] = __builtin_nontemporal_load(gd + q);
+      else if (q < NSD + NSP) sv[m] = __builtin_nontemporal_load(gp + (q - NSD));
+    }
+  }
+  double ep[6];
+  ld6(e1 + (size_t)max(p, 0) * 6, ep);
   const T *hv = reinterpret_cast<const T *>(a.hp_val);
   for (int cb = eb; cb < ee; cb += FINAL_CAP) {
     const int nw = 6 * min(FINAL_CAP, ee - cb);   // (entry, row) items of the pass
@@ -956,34 +977,28 @@ template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) __attribute__(
     for (int k = lo; k < hi; ++k) hc += prod[(k - cb) * 6 + c];
     __syncthreads();
   }
-  T di[6];
-  {
-    const T *Di = reinterpret_cast<const T *>(d.dinv) + (size_t)row * 21;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) di[k] = __builtin_nontemporal_load(Di + up6(c, k));
-    const int p = a.parent0[row];
-    const bool use = p >= 0 && d.flags[row] == 0;
-    double dd[3], S[9];
-    {
-      const T *pp = reinterpret_cast<const T *>(a.pd0) + (size_t)row * 12;
+  for (int m = 0; m < NSTG; ++m)
+    if (m * NT + t < NSD + NSP) stg[m * NT + t] = sv[m];
+  ys[t] = rc - hc;
+  __syncthreads();
+  const T *Di = reinterpret_cast<const T *>(stg) + rl * 21;
+  const T *pp = reinterpret_cast<const T *>(stg + NSD) + rl * 12;
+  {   // component c of P_row e_p
+    double dd[3], S[9], y[6];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) dd[m] = double(__builtin_nontemporal_load(pp + m));
+    for (int m = 0; m < 3; ++m) dd[m] = double(pp[m]);
 #pragma unroll
-      for (int m = 0; m < 9; ++m) S[m] = double(__builtin_nontemporal_load(pp + 3 + m));
-    }
-    double e[6], y[6];
-    ld6(e1 + (size_t)max(p, 0) * 6, e);
-    p_apply(dd, S, e, y);   // all six, then this thread's: no load under a branch
+    for (int m = 0; m < 9; ++m) S[m] = double(pp[3 + m]);
+    p_apply(dd, S, ep, y);
     double pe = y[0];
 #pragma unroll
     for (int k = 1; k < 6; ++k) pe = (c == k) ? y[k] : pe;
     tc += use ? pe : 0.0;
   }
-  ys[t] = rc - hc;
-  __syncthreads();
   double v = 0.0;
 #pragma unroll
-  for (int k = 0; k < 6; ++k) v += double(di[k]) * ys[rl * 6 + k];
+  for (int k = 0; k < 6; ++k) v += double(Di[up6(c, k)]) * ys[rl * 6 + k];
   const double un = tc + AMG_OMEGA * v;
   d.cs[o] = un;
   KSum ru = {0.0, 0.0}, none = {0.0, 0.0}, rr = {0.0, 0.0};
