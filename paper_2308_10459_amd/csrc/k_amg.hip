@@ -394,20 +394,29 @@ template <int G> __device__ __forceinline__ void lanes_sum6(double (&v)[6]) {
     for (int m = 0; m < 6; ++m) v[m] += __shfl_xor(v[m], off, 64);
 }
 
+// row c (c < 6; clamped, so that every lane may load one) of node A's
+// block-Jacobi inverse, loaded at a kernel's start, ahead of the sums it
+// multiplies
+template <typename T>
+__device__ __forceinline__ void load_dinv_row(const AmgLevel &L, int A, int c, T (&di)[6]) {
+  const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + min(c, 5) * 6;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) di[m] = Di[m];
+}
 // lane c < 6 of a node's group: b_c, and with `smooth` t_c = omega (D^-1 b)_c
+// (di: row c of the node's inverse)
 template <typename T>
 __device__ __forceinline__ void store_b_and_smooth(const AmgLevel &L, int A, int c, const double (&acc)[6],
-                                                   int smooth) {
+                                                   int smooth, const T (&di)[6]) {
   double bc = 0.0;
 #pragma unroll
   for (int m = 0; m < 6; ++m)
     if (m == c) bc = acc[m];
   L.b[(size_t)A * 6 + c] = bc;
   if (!smooth) return;
-  const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + c * 6;
   double y = 0.0;
 #pragma unroll
-  for (int m = 0; m < 6; ++m) y += double(Di[m]) * acc[m];
+  for (int m = 0; m < 6; ++m) y += double(di[m]) * acc[m];
   L.t[(size_t)A * 6 + c] = AMG_OMEGA * y;
 }
 
@@ -431,7 +440,9 @@ __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int 
   const int w = threadIdx.x >> 6, k0 = threadIdx.x & 63;
   const int A = blockIdx.x * 4 + w;
   double acc[6] = {0, 0, 0, 0, 0, 0};
+  T di[6];
   if (A < L.n) {   // uniform over the wavefront
+    load_dinv_row<T>(L, A, k0, di);
     const int mb = L.mbeg[A], nm = L.mbeg[A + 1] - mb;
     const int row0 = L.mlist[mb];
     const nt_v2d *R2 = reinterpret_cast<const nt_v2d *>(d.cr + (size_t)row0 * 6);
@@ -468,7 +479,7 @@ __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int 
     }
   }
   lanes_sum6<R1_LANES>(acc);
-  if (A < L.n && k0 < 6) store_b_and_smooth<T>(L, A, k0, acc, smooth);
+  if (A < L.n && k0 < 6) store_b_and_smooth<T>(L, A, k0, acc, smooth, di);
 }
 
 // r = b - A t on a level above the tail, one wavefront per row
@@ -535,7 +546,9 @@ __global__ __launch_bounds__(256) void k_amg_resid_restrict(AmgDev a, int l, int
   const bool live = node < C.n;
   const int g = tid >> 4, h = tid & 15;
   double z[6] = {0, 0, 0, 0, 0, 0};
+  T di[6];
   if (live) {   // uniform over each wavefront (two per node)
+    load_dinv_row<T>(C, node, tid, di);
     const int mb = C.mbeg[node], me = C.mbeg[node + 1];
     const bool has = mb + g < me;
     const int A = C.mlist[has ? mb + g : mb];   // threads without a child repeat the first (dropped below)
@@ -598,7 +611,7 @@ __global__ __launch_bounds__(256) void k_amg_resid_restrict(AmgDev a, int l, int
       for (int k = 0; k < 8; ++k) v += zs[nl][k][c];
       acc[c] = v;
     }
-    store_b_and_smooth<T>(C, node, tid, acc, smooth);
+    store_b_and_smooth<T>(C, node, tid, acc, smooth, di);
   }
 }
 
@@ -625,18 +638,22 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_post(AmgDev a
   const AmgLevel &L = a.lv[l];
   const int A = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (A >= L.n) return;   // uniform over the wavefront
+  // the row's b, t and inverse, loaded ahead of the row's product
+  const int c6 = min(lane, 5);
+  const double bl = L.b[(size_t)A * 6 + c6], tl = L.t[(size_t)A * 6 + c6];
+  T di[6];
+  load_dinv_row<T>(L, A, lane, di);
   const double y = wave_row_apply<T>(L, A, L.t, lane);
-  const double rb = (lane < 6) ? L.b[(size_t)A * 6 + lane] - y : 0.0;
+  const double rb = (lane < 6) ? bl - y : 0.0;
   double rv[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) rv[k] = __shfl(rb, k, 64);
   double ev = 0.0;
   if (lane < 6) {
-    const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + lane * 6;
     double u = 0.0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) u += double(Di[k]) * rv[k];
-    ev = L.t[(size_t)A * 6 + lane] + AMG_OMEGA * u;
+    for (int k = 0; k < 6; ++k) u += double(di[k]) * rv[k];
+    ev = tl + AMG_OMEGA * u;
     if (l == 1) L.e[(size_t)A * 6 + lane] = ev;
   }
   if (l == 1) return;   // uniform over the launch
