@@ -425,17 +425,20 @@ typedef float nt_v4f __attribute__((ext_vector_type(4)));
 
 // The members of a level-1 aggregate are consecutive rows (the internal
 // order sorts particles by their aggregation cell; checked at create), so
-// a wavefront stages its members' r, H t0 and prolongator records through
-// LDS as contiguous 16-byte pieces, read non-temporally (they are not read
-// again in the cycle; the matrix the PCG's product reads next stays in the
-// Infinity Cache), then lane k takes member k, k + 64, ... as before.
+// a wavefront stages its members' r - H t0 and prolongator records through
+// LDS, R1_CHUNK members at a time: contiguous 16-byte pieces, every load of
+// a chunk issued before the first store, read non-temporally (they are not
+// read again in the cycle; the matrix the PCG's product reads next stays in
+// the Infinity Cache).  Lane k then takes members k, k + 64, ... as before.
+constexpr int R1_CHUNK = 128;   // an interior cell of 8 r_max holds ~90 close-packed particles
 template <typename T>
 __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int smooth) {
   static_assert(R1_LANES == 64, "one wavefront per aggregate");
   constexpr int RW = 3;                            // 16-byte pieces of six doubles
   constexpr int PW = 12 * (int)sizeof(T) / 16;     // of a prolongator record
-  __shared__ nt_v2d sr[4][64 * RW], sh[4][64 * RW];
-  __shared__ nt_v4f sp[4][64 * PW];
+  constexpr int NX = R1_CHUNK * RW / 64, NPC = R1_CHUNK * PW / 64;   // pieces per lane
+  __shared__ nt_v2d sx[4][R1_CHUNK * RW];
+  __shared__ nt_v4f sp[4][R1_CHUNK * PW];
   const AmgLevel &L = a.lv[1];
   const int w = threadIdx.x >> 6, k0 = threadIdx.x & 63;
   const int A = blockIdx.x * 4 + w;
@@ -448,27 +451,38 @@ __global__ __launch_bounds__(256) void k_amg_restrict1(DevPtrs d, AmgDev a, int 
     const nt_v2d *R2 = reinterpret_cast<const nt_v2d *>(d.cr + (size_t)row0 * 6);
     const nt_v2d *H2 = reinterpret_cast<const nt_v2d *>(a.r0 + (size_t)row0 * 6);
     const nt_v4f *P4 = reinterpret_cast<const nt_v4f *>(reinterpret_cast<const T *>(a.pd0) + (size_t)row0 * 12);
-    for (int c0 = 0; c0 < nm; c0 += 64) {
-      const int cnt = min(64, nm - c0);
-      for (int q = k0; q < cnt * RW; q += 64) {
-        sr[w][q] = __builtin_nontemporal_load(R2 + c0 * RW + q);
-        sh[w][q] = __builtin_nontemporal_load(H2 + c0 * RW + q);
+    for (int c0 = 0; c0 < nm; c0 += R1_CHUNK) {
+      const int cnt = min(R1_CHUNK, nm - c0), nx = cnt * RW, np = cnt * PW;
+      nt_v2d rv[NX], hv[NX];
+      nt_v4f pv[NPC];
+#pragma unroll
+      for (int m = 0; m < NX; ++m) {   // pieces past the chunk repeat its last one
+        const int q = min(k0 + 64 * m, nx - 1);
+        rv[m] = __builtin_nontemporal_load(R2 + c0 * RW + q);
+        hv[m] = __builtin_nontemporal_load(H2 + c0 * RW + q);
       }
-      for (int q = k0; q < cnt * PW; q += 64) sp[w][q] = __builtin_nontemporal_load(P4 + c0 * PW + q);
+#pragma unroll
+      for (int m = 0; m < NPC; ++m) pv[m] = __builtin_nontemporal_load(P4 + c0 * PW + min(k0 + 64 * m, np - 1));
+#pragma unroll
+      for (int m = 0; m < NX; ++m)
+        if (k0 + 64 * m < nx) sx[w][k0 + 64 * m] = rv[m] - hv[m];
+#pragma unroll
+      for (int m = 0; m < NPC; ++m)
+        if (k0 + 64 * m < np) sp[w][k0 + 64 * m] = pv[m];
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (k0 < cnt && d.flags[row0 + c0 + k0] == 0) {
-        const double *xs = reinterpret_cast<const double *>(&sr[w][k0 * RW]);
-        const double *hs = reinterpret_cast<const double *>(&sh[w][k0 * RW]);
-        const T *ps = reinterpret_cast<const T *>(&sp[w][k0 * PW]);
+      for (int k = k0; k < cnt; k += 64) {
+        if (d.flags[row0 + c0 + k] != 0) continue;
+        const double *xs = reinterpret_cast<const double *>(&sx[w][k * RW]);
+        const T *ps = reinterpret_cast<const T *>(&sp[w][k * PW]);
         double dd[3], S[9], x[6], y[6];
 #pragma unroll
         for (int m = 0; m < 3; ++m) dd[m] = double(ps[m]);
 #pragma unroll
         for (int m = 0; m < 9; ++m) S[m] = double(ps[3 + m]);
 #pragma unroll
-        for (int m = 0; m < 6; ++m) x[m] = xs[m] - hs[m];
+        for (int m = 0; m < 6; ++m) x[m] = xs[m];
         pt_apply(dd, S, x, y);
 #pragma unroll
         for (int m = 0; m < 6; ++m) acc[m] += y[m];
