@@ -190,25 +190,27 @@ void amg_build(int n_pad, int n_scenes, const std::vector<double> &pos4,
   H.cbeg.assign(n_scenes + 1, 0);
   for (int a = 0; a < C.n; ++a) H.cbeg[C.scene[a] + 1]++;
   for (int s = 0; s < n_scenes; ++s) H.cbeg[s + 1] += H.cbeg[s];
-  // the tail: the coarsest levels whose every scene fits one workgroup's LDS
+  // the tail: the first level at which every scene has at most
+  // AMG_DENSE_MAX nodes (so are all coarser ones)
   H.Lt = H.L;
-  auto fits = [&](int l) {
-    const AmgHostLevel &V = H.lv[l];
-    std::vector<int> nodes(n_scenes, 0), slots(n_scenes, 0);
-    for (int a = 0; a < V.n; ++a) {
-      nodes[V.scene[a]]++;
-      slots[V.scene[a]] += V.row_ptr[a + 1] - V.row_ptr[a];
-    }
-    for (int s = 0; s < n_scenes; ++s)
-      if (nodes[s] > AMG_TAIL_ROWS || slots[s] > AMG_TAIL_SLOTS) return false;
-    return true;
+  auto most = [&](int l) {
+    std::vector<int> nodes(n_scenes, 0);
+    for (int a = 0; a < H.lv[l].n; ++a) nodes[H.lv[l].scene[a]]++;
+    return *std::max_element(nodes.begin(), nodes.end());
   };
-  while (H.Lt > 1 && fits(H.Lt - 1)) --H.Lt;
+  while (H.Lt > 1 && most(H.Lt - 1) <= AMG_DENSE_MAX) --H.Lt;
   H.tbeg.assign((size_t)(H.L - H.Lt + 1) * (n_scenes + 1), 0);
+  H.tmax.assign(H.L + 1, 0);
   for (int l = H.Lt; l <= H.L; ++l) {
     int *tb = H.tbeg.data() + (size_t)(l - H.Lt) * (n_scenes + 1);
     for (int a = 0; a < H.lv[l].n; ++a) tb[H.lv[l].scene[a] + 1]++;
     for (int s = 0; s < n_scenes; ++s) tb[s + 1] += tb[s];
+    H.tmax[l] = most(l);
+  }
+  H.noff.assign(n_scenes + 1, 0);
+  for (int s = 0; s < n_scenes; ++s) {
+    const int64_t m = 6 * (int64_t)(H.tbeg[s + 1] - H.tbeg[s]);
+    H.noff[s + 1] = H.noff[s] + m * m;
   }
   H.coff.assign(n_scenes, 0);
   int64_t off = 0;

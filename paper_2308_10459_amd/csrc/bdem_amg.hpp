@@ -37,12 +37,15 @@ namespace bdem {
 constexpr double AMG_CELL = 8.0;
 constexpr int AMG_COARSE_MAX = 16;
 constexpr double AMG_OMEGA = 0.9;
-// levels whose every scene has at most AMG_TAIL_ROWS nodes and
-// AMG_TAIL_SLOTS blocks (and all coarser ones) are cycled by one workgroup
-// per scene in a single launch, their products held in LDS
-constexpr int AMG_TAIL_ROWS = 256;
-constexpr int AMG_TAIL_SLOTS = 1024;
-constexpr int AMG_TAIL_THREADS = 1024;
+// the tail: the first level Lt at which every scene has at most
+// AMG_DENSE_MAX nodes.  Everything the cycle does from that level's b on
+// (its pre- and post-smoothing, the coarser levels, the dense solve) is
+// linear in b: one symmetric matrix N per scene, formed at setup from
+// N_L = A_L^-1 and N_l = S + (I - S A)(S + P N_{l+1} P^T (I - A S)),
+// S = omega D^-1 of level l.  Per PCG iteration the tail is e = N b,
+// AMG_DENSE_NODES tail nodes per workgroup, prolonged one level down.
+constexpr int AMG_DENSE_MAX = 64;
+constexpr int AMG_DENSE_NODES = 2;
 
 // device view of one coarse level (level >= 1)
 struct AmgLevel {
@@ -62,9 +65,14 @@ struct AmgLevel {
 // device view of the whole hierarchy
 struct AmgDev {
   int L = 0;                        // coarse levels (>= 1)
-  int Lt = 0;                       // first level of the single-launch tail (1 <= Lt <= L)
+  int Lt = 0;                       // the tail's level (1 <= Lt <= L)
+  int tmax[16] = {};                // most nodes of a scene on each tail level Lt..L
   int *tbeg = nullptr;              // (L - Lt + 1) x (n_scenes + 1): node range per scene on the
                                     // tail levels, level l at (l - Lt) * (n_scenes + 1)
+  int64_t *noff = nullptr;          // n_scenes + 1: offset of the scene's (6 n_Lt)^2 tail matrix
+  void *nmat = nullptr;             // the tail matrices N (T)
+  double *nwork = nullptr;          // 4 x the tail matrices' size: setup work (FP64), per scene
+                                    // four slots of (6 n_Lt)^2 at 4 noff[s]
   // fine level (particles, internal order)
   int *slot_row0 = nullptr;         // row of each fine off-diagonal slot
   int *parent0 = nullptr;           // level-1 node of each particle (-1: padding)
@@ -103,6 +111,8 @@ struct AmgHost {
   std::vector<int> cbeg;
   std::vector<int64_t> coff;
   int64_t cdense = 0;               // total doubles of the dense blocks
+  std::vector<int> tmax;            // per level (Lt..L at index l): most nodes of a scene
+  std::vector<int64_t> noff;        // n_scenes + 1 (tail matrices)
 };
 
 // Morton (Z-order) key of an aggregation cell (x, y, z >= 0): the order of

@@ -409,6 +409,10 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   L.add(reinterpret_cast<void **>(&a.coff), NS * sizeof(int64_t));
   addd(&a.cmat, (size_t)H.cdense);
   addd(&a.cwork, (size_t)H.cdense);
+  for (int l = H.Lt; l <= H.L; ++l) a.tmax[l] = H.tmax[l];
+  L.add(reinterpret_cast<void **>(&a.noff), (NS + 1) * sizeof(int64_t));
+  L.add(&a.nmat, std::max<size_t>((size_t)H.noff[NS], 1) * T);
+  addd(&a.nwork, 4 * std::max<size_t>((size_t)H.noff[NS], 1));
   AmgLevel *lvdev = nullptr;
   L.add(reinterpret_cast<void **>(&lvdev), (H.L + 1) * sizeof(AmgLevel));
   if (hipMalloc(&ctx->amg_mem, L.total + ALIGN) != hipSuccess) {
@@ -443,6 +447,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   upi(a.cbeg, H.cbeg);
   upi(a.tbeg, H.tbeg);
   chk(hipMemcpyAsync(a.coff, H.coff.data(), NS * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  chk(hipMemcpyAsync(a.noff, H.noff.data(), (NS + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
   chk(hipMemcpyAsync(lvdev, ctx->amg_hl.data(), (H.L + 1) * sizeof(AmgLevel), hipMemcpyHostToDevice, st));
   chk(hipMemsetAsync(a.pd0, 0, 12 * (size_t)NP * T, st));
   for (double *v : {a.t0, a.r0}) chk(hipMemsetAsync(v, 0, 6 * (size_t)NP * sizeof(double), st));

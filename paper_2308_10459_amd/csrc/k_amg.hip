@@ -5,6 +5,8 @@
 // definitions are described in bdem_amg.hpp.  All sums run in a fixed order
 // (contribution and child lists are sorted at create), so results are
 // reproducible run to run.
+#include <algorithm>
+
 #include "bdem_amg.hpp"
 #include "bdem_math.hpp"
 
@@ -678,166 +680,211 @@ template <typename T> __global__ __launch_bounds__(256) void k_amg_post(AmgDev a
 }
 
 // ---------------------------------------------------------------------------
-// The tail: levels Lt..L of one scene in one workgroup, in LDS.  The same
-// cycle as the per-level kernels: going down, r_l = b_l - A t_l and the
-// restriction into l + 1 with its pre-smoothing; the dense solve of the last
-// level; going up, e_l = t_l + omega D^-1 (b_l - A t_l) prolonged into the
-// level below (the last of them into level Lt - 1, which the next launch
-// reads; level 1's e_1 is kept for the cycle's last kernel).  A product A x takes one thread per block (its six
-// components into LDS), then one thread per (row, component) adds its row's
-// blocks in slot order.
+// The tail (levels Lt..L): one symmetric matrix N per scene (bdem_amg.hpp),
+// formed at setup in FP64 from the coarsest level up, in four work slots
+// per scene of (6 n_Lt)^2: slot 0 holds N of the level above, slot 1
+// W = I - A S, slot 2 Q = P N P^T, slot 3 T = S + Q W; then N = S + W^T T
+// goes to slot 0.  S = omega D^-1 of the level; P = [[I, -[d]x], [0, I]]
+// for an active node (d its offset from its parent's centroid), zero for
+// an inactive one.
 // ---------------------------------------------------------------------------
 
-// res[(A - nb) * 6 + c] = (b - A t)_c for the scene's rows [nb, ne) of level L
-template <typename T>
-__device__ __forceinline__ void tail_residual(const AmgLevel &L, int nb, int ne, double *prod, double *res) {
-  const T *val = reinterpret_cast<const T *>(L.val);
-  const int s0 = L.row_ptr[nb], s1 = L.row_ptr[ne];
-  for (int s = s0 + (int)threadIdx.x; s < s1; s += blockDim.x) {
-    const T *blk = val + (size_t)s * 36;
-    double x[6];
-    ld6(L.t + (size_t)L.col[s] * 6, x);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      double acc = 0.0;
-#pragma unroll
-      for (int e = 0; e < 6; ++e) acc += double(blk[c * 6 + e]) * x[e];
-      prod[(s - s0) * 6 + c] = acc;
-    }
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x) {
-    const int A = nb + q / 6, c = q - (q / 6) * 6;
-    double y = 0.0;
-    for (int s = L.row_ptr[A]; s < L.row_ptr[A + 1]; ++s) y += prod[(s - s0) * 6 + c];
-    res[q] = L.b[(size_t)A * 6 + c] - y;
-  }
-  __syncthreads();
+__device__ __forceinline__ void tail_range(const AmgDev &a, int l, int sc, int &nb, int &ne) {
+  const int *tb = a.tbeg + (size_t)(l - a.Lt) * (gridDim.y + 1);
+  nb = tb[sc];
+  ne = tb[sc + 1];
+}
+__device__ __forceinline__ double *tail_slot(const AmgDev &a, int sc, int k) {
+  return a.nwork + 4 * a.noff[sc] + (size_t)k * (size_t)(a.noff[sc + 1] - a.noff[sc]);
 }
 
-// e of the rows [nb, ne) (6 values per row in ev) prolonged into their
-// members one level down; on level 1 stored for the cycle's last kernel
-__device__ __forceinline__ void tail_prolong(const AmgDev &a, int l, int nb, int ne, const double *ev) {
+// slot 0 = the coarsest level's dense inverse
+__global__ __launch_bounds__(256) void k_tail_init(AmgDev a) {
+  const int sc = blockIdx.y;
+  const int64_t m = 6 * (int64_t)(a.cbeg[sc + 1] - a.cbeg[sc]);
+  const double *X = a.cwork + a.coff[sc];
+  double *o = tail_slot(a, sc, 0);
+  for (int64_t q = blockIdx.x * 256 + threadIdx.x; q < m * m; q += (int64_t)gridDim.x * 256) o[q] = X[q];
+}
+
+// slot 1 = W = I - A S of level l (dense, the scene's nodes): zeros first
+// (node pairs without a block), then every block of the level's pattern
+// (the diagonal ones included) from its slot
+__global__ __launch_bounds__(256) void k_tail_zero_w(AmgDev a, int l) {
+  const int sc = blockIdx.y;
+  int nb, ne;
+  tail_range(a, l, sc, nb, ne);
+  const int N6 = 6 * (ne - nb);
+  double *W = tail_slot(a, sc, 1);
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < N6 * N6; q += gridDim.x * 256) W[q] = 0.0;
+}
+template <typename T> __global__ __launch_bounds__(256) void k_tail_fill_w(AmgDev a, int l) {
+  const int sc = blockIdx.y;
   const AmgLevel &L = a.lv[l];
-  if (l == 1) {
-    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x) L.e[(size_t)nb * 6 + q] = ev[q];
-  } else {
-    const int *parent = a.lv[l - 1].parent;
-    for (int k = L.mbeg[nb] + (int)threadIdx.x; k < L.mbeg[ne]; k += blockDim.x) {
-      const int i = L.mlist[k];
-      const double *ep = ev + (parent[i] - nb) * 6;
-      const double e[6] = {ep[0], ep[1], ep[2], ep[3], ep[4], ep[5]};
-      prolong_one(a, l, i, e);
-    }
+  int nb, ne;
+  tail_range(a, l, sc, nb, ne);
+  const int N6 = 6 * (ne - nb);
+  double *W = tail_slot(a, sc, 1);
+  const T *val = reinterpret_cast<const T *>(L.val), *dinv = reinterpret_cast<const T *>(L.dinv);
+  const int s0 = L.row_ptr[nb], s1 = L.row_ptr[ne];
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < 36 * (s1 - s0); q += gridDim.x * 256) {
+    const int sl = s0 + q / 36, e = q - (q / 36) * 36, r = e / 6, c = e - (e / 6) * 6;
+    const int i = L.slot_row[sl], j = L.col[sl];
+    const T *Ab = val + (size_t)sl * 36 + r * 6, *Sj = dinv + (size_t)j * 36 + c;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v += double(Ab[k]) * double(Sj[k * 6]);
+    W[(size_t)(6 * (i - nb) + r) * N6 + 6 * (j - nb) + c] = (i == j && r == c ? 1.0 : 0.0) - AMG_OMEGA * v;
   }
-  __syncthreads();
 }
 
-template <typename T> __global__ __launch_bounds__(AMG_TAIL_THREADS) void k_amg_tail(DevPtrs d, AmgDev a) {
-  __shared__ double prod[AMG_TAIL_SLOTS * 6];
-  __shared__ double res[AMG_TAIL_ROWS * 6];
-  const int sc = blockIdx.x, NS = gridDim.x;
+// slot 2 = Q = P N P^T of level l, N (slot 0) of level l + 1
+__device__ __forceinline__ void tail_p(const AmgLevel &L, int i, double (&Pm)[36]) {
+#pragma unroll
+  for (int k = 0; k < 36; ++k) Pm[k] = (k % 7 == 0) ? 1.0 : 0.0;
+  if (!L.active[i]) {
+#pragma unroll
+    for (int k = 0; k < 36; ++k) Pm[k] = 0.0;
+    return;
+  }
+  const double d0 = L.pd[3 * i], d1 = L.pd[3 * i + 1], d2 = L.pd[3 * i + 2];
+  // -[d]x in rows 0-2, columns 3-5
+  Pm[0 * 6 + 4] = d2;  Pm[0 * 6 + 5] = -d1;
+  Pm[1 * 6 + 3] = -d2; Pm[1 * 6 + 5] = d0;
+  Pm[2 * 6 + 3] = d1;  Pm[2 * 6 + 4] = -d0;
+}
+__global__ __launch_bounds__(256) void k_tail_form_q(AmgDev a, int l) {
+  const int sc = blockIdx.y;
+  const AmgLevel &L = a.lv[l];
+  int nb, ne, cb, ce;
+  tail_range(a, l, sc, nb, ne);
+  tail_range(a, l + 1, sc, cb, ce);
+  const int n = ne - nb, N6 = 6 * n, M6 = 6 * (ce - cb);
+  const double *Nc = tail_slot(a, sc, 0);
+  double *Q = tail_slot(a, sc, 2);
+  for (int q = blockIdx.x * 256 + threadIdx.x; q < n * n; q += gridDim.x * 256) {   // one 6x6 block each
+    const int i = nb + q / n, j = nb + q % n;
+    double Pi[36], Pj[36];
+    tail_p(L, i, Pi);
+    tail_p(L, j, Pj);
+    const int pi = L.parent[i] - cb, pj = L.parent[j] - cb;
+    double B[36];   // N_{pi pj} P_j^T
+#pragma unroll
+    for (int x = 0; x < 6; ++x)
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int y = 0; y < 6; ++y) v += Nc[(size_t)(6 * pi + x) * M6 + 6 * pj + y] * Pj[b * 6 + y];
+        B[x * 6 + b] = v;
+      }
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        double v = 0.0;
+#pragma unroll
+        for (int x = 0; x < 6; ++x) v += Pi[r * 6 + x] * B[x * 6 + b];
+        Q[(size_t)(6 * (i - nb) + r) * N6 + 6 * (j - nb) + b] = v;
+      }
+  }
+}
+
+// MODE 0: slot 3 = S + Q W (slots 2, 1); MODE 1: slot 0 = S + W^T T (slots
+// 1, 3).  32 x 32 output tiles, the k range in 32-wide steps through LDS;
+// thread (ty, tx) forms outputs (ty + 16 u, tx + 16 v).
+template <typename T, int MODE> __global__ __launch_bounds__(256) void k_tail_gemm(AmgDev a, int l) {
+  __shared__ double As[32][33], Bs[32][33];
+  const int sc = blockIdx.y;
+  const AmgLevel &L = a.lv[l];
+  int nb, ne;
+  tail_range(a, l, sc, nb, ne);
+  const int N6 = 6 * (ne - nb), nt = (N6 + 31) / 32;
+  if ((int)blockIdx.x >= nt * nt) return;   // uniform over the workgroup
+  const int R0 = 32 * (blockIdx.x / nt), C0 = 32 * (blockIdx.x % nt);
+  const double *Am = tail_slot(a, sc, MODE == 0 ? 2 : 1), *Bm = tail_slot(a, sc, MODE == 0 ? 1 : 3);
+  double *Cm = tail_slot(a, sc, MODE == 0 ? 3 : 0);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int k0 = 0; k0 < N6; k0 += 32) {
+    for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+      const int r = e >> 5, c = e & 31;
+      const int gr = R0 + r, gk = k0 + c;   // As[r][c] = A(gr, gk)
+      double av = 0.0;
+      if (gr < N6 && gk < N6) av = MODE == 0 ? Am[(size_t)gr * N6 + gk] : Am[(size_t)gk * N6 + gr];
+      As[r][c] = av;
+      const int bk = k0 + r, bc = C0 + c;   // Bs[r][c] = B(bk, bc)
+      Bs[r][c] = (bk < N6 && bc < N6) ? Bm[(size_t)bk * N6 + bc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] += As[ty + 16 * u][k] * Bs[k][tx + 16 * v];
+    __syncthreads();
+  }
+  const T *dinv = reinterpret_cast<const T *>(L.dinv);
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int r = R0 + ty + 16 * u, c = C0 + tx + 16 * v;
+      if (r >= N6 || c >= N6) continue;
+      double o = acc[u][v];
+      if (r / 6 == c / 6) o += AMG_OMEGA * double(dinv[(size_t)(nb + r / 6) * 36 + (r % 6) * 6 + c % 6]);
+      Cm[(size_t)r * N6 + c] = o;
+    }
+}
+
+// N of the tail level (slot 0) into the cycle's matrix (T)
+template <typename T> __global__ __launch_bounds__(256) void k_tail_store(AmgDev a) {
+  const int sc = blockIdx.y;
+  const int64_t m = a.noff[sc + 1] - a.noff[sc];
+  const double *src = tail_slot(a, sc, 0);
+  T *o = reinterpret_cast<T *>(a.nmat) + a.noff[sc];
+  for (int64_t q = blockIdx.x * 256 + threadIdx.x; q < m; q += (int64_t)gridDim.x * 256) o[q] = T(src[q]);
+}
+
+// Per PCG iteration: e = N b on AMG_DENSE_NODES tail nodes of one scene
+// (each row by 16 lanes in a fixed butterfly, b staged in LDS), prolonged
+// into their members one level down (on level 1 kept for the cycle's last
+// kernel).
+constexpr int TAIL_THREADS = 6 * AMG_DENSE_NODES * 16;
+template <typename T> __global__ __launch_bounds__(TAIL_THREADS) void k_amg_tail(DevPtrs d, AmgDev a) {
+  __shared__ double bs[6 * AMG_DENSE_MAX];
+  __shared__ double ev[6 * AMG_DENSE_NODES];
+  const int sc = blockIdx.y;
   if (!d.ctl[sc].cg_active) return;   // uniform over the workgroup
-  auto range = [&](int l, int &nb, int &ne) {
-    const int *tb = a.tbeg + (size_t)(l - a.Lt) * (NS + 1);
-    nb = tb[sc];
-    ne = tb[sc + 1];
-  };
-  // going down
-  for (int l = a.Lt; l < a.L; ++l) {
-    int nb, ne, cb, ce;
-    range(l, nb, ne);
-    range(l + 1, cb, ce);
-    const AmgLevel &F = a.lv[l], &C = a.lv[l + 1];
-    tail_residual<T>(F, nb, ne, prod, res);
-    // b_{l+1} = P^T r_l, one thread per (node, component), members in order
-    for (int q = threadIdx.x; q < 6 * (ce - cb); q += blockDim.x) {
-      const int A = cb + q / 6, c = q - (q / 6) * 6;
-      double acc = 0.0;
-      for (int k = C.mbeg[A]; k < C.mbeg[A + 1]; ++k) {
-        const int i = C.mlist[k];
-        if (!F.active[i]) continue;
-        const double *x = res + (i - nb) * 6;
-        if (c < 3) {
-          acc += x[c];
-        } else {   // (d x x_p + x_y)_{c-3}, d = x_i - c_A
-          const double *dd = F.pd + 3 * (size_t)i;
-          const int u = (c - 2) % 3, v = (c - 1) % 3;
-          acc += (dd[u] * x[v] - dd[v] * x[u]) + x[c];
-        }
-      }
-      prod[q] = acc;
-      C.b[(size_t)A * 6 + c] = acc;
-    }
-    __syncthreads();
-    if (l + 1 < a.L)   // pre-smoothing from zero
-      for (int q = threadIdx.x; q < 6 * (ce - cb); q += blockDim.x) {
-        const int A = cb + q / 6, c = q - (q / 6) * 6;
-        const T *Di = reinterpret_cast<const T *>(C.dinv) + (size_t)A * 36 + c * 6;
-        double y = 0.0;
-#pragma unroll
-        for (int m = 0; m < 6; ++m) y += double(Di[m]) * prod[(A - cb) * 6 + m];
-        C.t[(size_t)A * 6 + c] = AMG_OMEGA * y;
-      }
-    __syncthreads();
-  }
-  // the last level: e = A^-1 b (dense), prolonged one level down.  b is in
-  // prod (the last restriction left it there; loaded when the tail is the
-  // last level alone); thread (row, chunk) forms its part of a row, every
-  // load of the dense inverse issued at once, and the parts are added in
-  // chunk order
-  {
-    int nb, ne;
-    range(a.L, nb, ne);
-    const AmgLevel &L = a.lv[a.L];
-    const int N = 6 * (ne - nb);
-    if (a.Lt == a.L) {
-      for (int q = threadIdx.x; q < N; q += blockDim.x) prod[q] = L.b[(size_t)6 * nb + q];
-      __syncthreads();
-    }
-    const double *X = a.cwork + a.coff[sc];
-    const int nch = AMG_TAIL_THREADS / N, len = (N + nch - 1) / nch;   // N <= 6 AMG_COARSE_MAX < threads
-    double *part = prod + N;   // nch x N partial sums
-    {
-      const int r = threadIdx.x % N, ch = threadIdx.x / N;
-      if (ch < nch) {
-        const int c0 = ch * len, c1 = min(N, c0 + len);
-        double acc = 0.0;
+  int nb, ne;
+  tail_range(a, a.Lt, sc, nb, ne);
+  const int node0 = nb + AMG_DENSE_NODES * (int)blockIdx.x;
+  if (node0 >= ne) return;   // uniform over the workgroup
+  const int nn = min(AMG_DENSE_NODES, ne - node0), N6 = 6 * (ne - nb);
+  const AmgLevel &L = a.lv[a.Lt];
+  for (int q = threadIdx.x; q < N6; q += TAIL_THREADS) bs[q] = L.b[(size_t)6 * nb + q];
+  __syncthreads();
+  const int r = threadIdx.x >> 4, h = threadIdx.x & 15;   // row of the chunk, its lane
+  const int rr = min(r, 6 * nn - 1);
+  const T *Nr = reinterpret_cast<const T *>(a.nmat) + a.noff[sc] + (size_t)(6 * (node0 - nb) + rr) * N6;
+  double acc = 0.0;
 #pragma unroll 4
-        for (int c = c0; c < c1; ++c) acc += X[(size_t)r * N + c] * prod[c];
-        part[ch * N + r] = acc;
-      }
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < N; r += blockDim.x) {
-      double acc = 0.0;
-      for (int ch = 0; ch < nch; ++ch) acc += part[ch * N + r];
-      res[r] = acc;
-    }
-    __syncthreads();
-    tail_prolong(a, a.L, nb, ne, res);
-  }
-  // going up
-  for (int l = a.L - 1; l >= a.Lt; --l) {
-    int nb, ne;
-    range(l, nb, ne);
-    const AmgLevel &L = a.lv[l];
-    tail_residual<T>(L, nb, ne, prod, res);
-    double ev[(6 * AMG_TAIL_ROWS + AMG_TAIL_THREADS - 1) / AMG_TAIL_THREADS];
-    int m = 0;
-    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x, ++m) {
-      const int A = nb + q / 6, c = q - (q / 6) * 6;
-      const T *Di = reinterpret_cast<const T *>(L.dinv) + (size_t)A * 36 + c * 6;
-      double u = 0.0;
+  for (int k = h; k < N6; k += 16) acc += double(Nr[k]) * bs[k];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) u += double(Di[k]) * res[(A - nb) * 6 + k];
-      ev[m] = L.t[(size_t)A * 6 + c] + AMG_OMEGA * u;
+  for (int off = 1; off < 16; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (h == 0 && r < 6 * nn) ev[r] = acc;
+  __syncthreads();
+  if (a.Lt == 1) {
+    for (int q = threadIdx.x; q < 6 * nn; q += TAIL_THREADS) L.e[(size_t)6 * node0 + q] = ev[q];
+  } else {
+    const int *parent = a.lv[a.Lt - 1].parent;
+    for (int k = L.mbeg[node0] + (int)threadIdx.x; k < L.mbeg[node0 + nn]; k += TAIL_THREADS) {
+      const int i = L.mlist[k];
+      const double *ep = ev + (parent[i] - node0) * 6;
+      const double e[6] = {ep[0], ep[1], ep[2], ep[3], ep[4], ep[5]};
+      prolong_one(a, a.Lt, i, e);
     }
-    __syncthreads();   // every thread has read res
-    m = 0;
-    for (int q = threadIdx.x; q < 6 * (ne - nb); q += blockDim.x, ++m) res[q] = ev[m];
-    __syncthreads();
-    tail_prolong(a, l, nb, ne, res);
   }
 }
 
@@ -1057,6 +1104,20 @@ static void setup_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n
     k_amg_dinv<T><<<nblk(hl[l].n, 128), 128, 0, s>>>(a, l);
   }
   k_amg_coarse_inverse<T><<<n_scenes, 1024, 0, s>>>(a);
+  // the tail matrices, from the coarsest level up to Lt
+  auto grid = [&](int64_t work) { return dim3((unsigned)std::min<int64_t>(std::max<int64_t>((work + 255) / 256, 1), 256), n_scenes); };
+  const int64_t mL = 6 * (int64_t)a.tmax[a.L];
+  k_tail_init<<<grid(mL * mL), 256, 0, s>>>(a);
+  for (int l = a.L - 1; l >= a.Lt; --l) {
+    const int64_t n6 = 6 * (int64_t)a.tmax[l], nt = (n6 + 31) / 32;
+    k_tail_zero_w<<<grid(n6 * n6), 256, 0, s>>>(a, l);
+    k_tail_fill_w<T><<<grid(n6 * n6), 256, 0, s>>>(a, l);
+    k_tail_form_q<<<grid(n6 * n6 / 36), 256, 0, s>>>(a, l);
+    k_tail_gemm<T, 0><<<dim3((unsigned)(nt * nt), n_scenes), 256, 0, s>>>(a, l);
+    k_tail_gemm<T, 1><<<dim3((unsigned)(nt * nt), n_scenes), 256, 0, s>>>(a, l);
+  }
+  const int64_t mt = 6 * (int64_t)a.tmax[a.Lt];
+  k_tail_store<T><<<grid(mt * mt), 256, 0, s>>>(a);
 }
 
 template <typename T>
@@ -1071,12 +1132,12 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
   if (mark.fn) mark.fn(mark.arg, true);
   launch_spmv(dt, mixed, spmv_variant, s, SPMV_DOTS_NONE, rev);
   if (mark.fn) mark.fn(mark.arg, false);
-  // each restriction also pre-smooths the level it fills (not the coarsest)
-  k_amg_restrict1<T><<<nblk(hl[1].n, 4), 256, 0, s>>>(d, a, a.L > 1 ? 1 : 0);
+  // each restriction also pre-smooths the level it fills, above the tail
+  k_amg_restrict1<T><<<nblk(hl[1].n, 4), 256, 0, s>>>(d, a, a.Lt > 1 ? 1 : 0);
   for (int l = 1; l < a.Lt; ++l)
-    k_amg_resid_restrict<T><<<nblk(hl[l + 1].n, 256 / RR_THREADS), 256, 0, s>>>(a, l, l + 1 < a.L ? 1 : 0);
-  // levels Lt..L in one launch; it prolongs into level Lt - 1 (or keeps e_1)
-  k_amg_tail<T><<<n_scenes, AMG_TAIL_THREADS, 0, s>>>(d, a);
+    k_amg_resid_restrict<T><<<nblk(hl[l + 1].n, 256 / RR_THREADS), 256, 0, s>>>(a, l, l + 1 < a.Lt ? 1 : 0);
+  // the tail: e = N b on level Lt, prolonged into level Lt - 1 (or kept as e_1)
+  k_amg_tail<T><<<dim3(nblk(a.tmax[a.Lt], AMG_DENSE_NODES), n_scenes), TAIL_THREADS, 0, s>>>(d, a);
   // each level's kernel also prolongs its correction one level down (level
   // 1 keeps e_1)
   for (int l = a.Lt - 1; l >= 1; --l) k_amg_post<T><<<nblk(hl[l].n, 4), 256, 0, s>>>(a, l);
