@@ -26,7 +26,7 @@ namespace bdem {
 
 constexpr int TILE = 256;       // particles / bonds per scene-aligned tile
 constexpr int SPMV_ROWS = 32;     // block rows per SpMV workgroup
-constexpr int SPMV_CAP = 384;     // slot products held in LDS per pass of an SpMV workgroup
+constexpr int SPMV_CAP = 512;     // slot products held in LDS per pass of an SpMV workgroup (~400 per 32 rows of a close-packed solid)
 constexpr int DOT_GROUP = 64;     // SpMV blocks whose (r, u), (r, r) partials one SpMV wavefront merges
 constexpr int CMAXC = 32;         // element-repulsion candidates per particle
 constexpr int ROWS_RT = 64;       // block rows per workgroup of the row-parallel evaluation

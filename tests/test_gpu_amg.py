@@ -26,11 +26,15 @@ def B():
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-@pytest.mark.parametrize("dims", [(5, 4, 3), (11, 10, 9), (16, 16, 8), (64, 64, 16)])
+@pytest.mark.parametrize("dims", [(5, 4, 3), (11, 10, 9), (16, 16, 8), (64, 64, 16), (64, 64, 32)])
 def test_vcycle_matches_oracle(B, mixed, dims):
-    # up to 2,048 particles the coarse levels fit the one-workgroup tail;
-    # 65,536 particles give levels of 1,024, 128 and 16 aggregates, the
-    # first two too large for it, so the per-level kernels run as well
+    # The dense tail starts at the first level with at most 64 aggregates.
+    # 60 particles: one level, the tail is the coarsest inverse; 990 and
+    # 2,048: the tail starts at level 1, its matrix formed from the level-2
+    # inverse; 65,536: levels of 1,024, 128 and 16 aggregates, two per-level
+    # levels above a tail that is the coarsest inverse; 131,072: levels of
+    # 2,048, 256, 32 and 4, a tail formed over two levels and prolonged into
+    # level 2
     log(f"[amg vcycle] dims={dims} mixed={mixed}")
     sc, st = _perturbed_block(*dims, ground=True)
     o = oracle_for(sc, st)
