@@ -119,22 +119,26 @@ void amg_build(int n_pad, int n_scenes, const std::vector<double> &pos4,
   H.parent0 = g.parent;
   // fine coupling H P: the distinct aggregates of each row's diagonal and
   // off-diagonal columns that are unknowns (P is zero elsewhere), ascending;
-  // the sources of an entry in slot order, the diagonal first
+  // the off-diagonal sources of an entry in slot order, and per row the
+  // entry its diagonal block adds to first (-1: none)
   H.hp_ptr.assign(n_pad + 1, 0);
   H.hp_gptr.assign(1, 0);
+  H.hp_self.assign(n_pad, -1);
   {
-    std::vector<std::pair<int, int>> src;   // (aggregate, source)
+    std::vector<std::pair<int, int>> src;   // (aggregate, slot; -1: the diagonal)
     for (int r = 0; r < n_pad; ++r) {
       src.clear();
-      if (g.parent[r] >= 0 && factive[r]) src.push_back({g.parent[r], -1 - r});
+      if (g.parent[r] >= 0 && factive[r]) src.push_back({g.parent[r], -1});
       for (int k = row_ptr[r]; k < row_ptr[r + 1]; ++k)
         if (g.parent[col[k]] >= 0 && factive[col[k]]) src.push_back({g.parent[col[k]], k});
       std::stable_sort(src.begin(), src.end(),
                        [](const std::pair<int, int> &x, const std::pair<int, int> &y) { return x.first < y.first; });
       for (size_t k = 0; k < src.size(); ++k) {
-        if (k > 0 && src[k].first != src[k - 1].first) H.hp_gptr.push_back((int)H.hp_gsrc.size());
-        if (k == 0 || src[k].first != src[k - 1].first) H.hp_agg.push_back(src[k].first);
-        H.hp_gsrc.push_back(src[k].second);
+        const bool fresh = k == 0 || src[k].first != src[k - 1].first;
+        if (fresh && k > 0) H.hp_gptr.push_back((int)H.hp_gsrc.size());
+        if (fresh) H.hp_agg.push_back(src[k].first);
+        if (src[k].second < 0) H.hp_self[r] = (int)H.hp_agg.size() - 1;
+        else H.hp_gsrc.push_back(src[k].second);
       }
       if (!src.empty()) H.hp_gptr.push_back((int)H.hp_gsrc.size());
       H.hp_ptr[r + 1] = (int)H.hp_agg.size();

@@ -80,12 +80,14 @@ struct AmgDev {
   double *t0 = nullptr, *r0 = nullptr;   // 6 per particle
   const AmgLevel *lv = nullptr;     // device array lv[0..L] (lv[0] unused)
   // fine coupling H P: per fine row its level-1 aggregates in ascending order
-  // (hp_ptr over rows, hp_agg per entry, 36 T per entry, row-major), and per
-  // entry the fine blocks that sum into it, in slot order (hp_gptr; per
-  // source hp_src: the slot's block code, (bond block << 1) | transposed, or
-  // -1 for the row's diagonal block; hp_col: the block's column j)
+  // (hp_ptr over rows, hp_agg per entry, 36 T per entry, row-major); per
+  // row the entry its diagonal block adds to (hp_self, -1: none), first;
+  // per entry its off-diagonal blocks, in slot order (hp_gptr; per source
+  // hp_src: the slot's block code, (bond block << 1) | transposed; hp_col:
+  // the block's column j)
   int nhp = 0;
-  int *hp_ptr = nullptr, *hp_agg = nullptr, *hp_gptr = nullptr, *hp_src = nullptr, *hp_col = nullptr;
+  int *hp_ptr = nullptr, *hp_agg = nullptr, *hp_self = nullptr, *hp_gptr = nullptr, *hp_src = nullptr,
+      *hp_col = nullptr;
   void *hp_val = nullptr;
   // coarsest level: dense inverse per scene
   int *cbeg = nullptr;              // n_scenes + 1: node range per scene on level L
@@ -104,9 +106,8 @@ struct AmgHost {
   int Lt = 0;
   std::vector<int> tbeg;
   std::vector<int> parent0, slot_row0;
-  // fine coupling pattern (AmgDev); hp_gsrc per source: the slot, or
-  // -1 - row for the diagonal block
-  std::vector<int> hp_ptr, hp_agg, hp_gptr, hp_gsrc;
+  // fine coupling pattern (AmgDev); hp_gsrc per source: the slot
+  std::vector<int> hp_ptr, hp_agg, hp_self, hp_gptr, hp_gsrc;
   std::vector<AmgHostLevel> lv;     // lv[1..L]
   std::vector<int> cbeg;
   std::vector<int64_t> coff;

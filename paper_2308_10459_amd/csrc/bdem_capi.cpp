@@ -371,13 +371,13 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   // the coupling's sources as the kernel reads them: block code and column
   std::vector<int> hp_src(H.hp_gsrc.size()), hp_col(H.hp_gsrc.size());
   for (size_t m = 0; m < H.hp_gsrc.size(); ++m) {
-    const int g = H.hp_gsrc[m];
-    hp_src[m] = g < 0 ? -1 : sblk[g];
-    hp_col[m] = g < 0 ? -1 - g : col[g];
+    hp_src[m] = sblk[H.hp_gsrc[m]];
+    hp_col[m] = col[H.hp_gsrc[m]];
   }
   a.nhp = (int)H.hp_agg.size();
   addi(&a.hp_ptr, H.hp_ptr.size());
   addi(&a.hp_agg, H.hp_agg.size());
+  addi(&a.hp_self, H.hp_self.size());
   addi(&a.hp_gptr, H.hp_gptr.size());
   addi(&a.hp_src, hp_src.size());
   addi(&a.hp_col, hp_col.size());
@@ -433,6 +433,7 @@ static int amg_upload(bdem_ctx *ctx, const std::vector<double> &pos4, const std:
   upi(a.parent0, H.parent0);
   upi(a.hp_ptr, H.hp_ptr);
   upi(a.hp_agg, H.hp_agg);
+  upi(a.hp_self, H.hp_self);
   upi(a.hp_gptr, H.hp_gptr);
   upi(a.hp_src, hp_src);
   upi(a.hp_col, hp_col);

@@ -893,65 +893,117 @@ template <typename T> __global__ __launch_bounds__(TAIL_THREADS) void k_amg_tail
 // ---------------------------------------------------------------------------
 
 // fine coupling (H P)_{i,a} = sum of H_ij P_j over the blocks of row i whose
-// column j is an unknown of aggregate a.  Row r of H_ij P_j, with h = row r
-// of H_ij split into (h_t, h_w): columns 0-2 are h_t, columns 3-5 are
-// d_j x h_t + S_j^T h_w.  Thread (entry, r); its sources HP_U at a time,
-// every load of those issued before the first product, in the fixed order
-// of the pattern.
-constexpr int HP_U = 2;   // sources in flight per thread (about five per entry)
-template <typename T> __global__ __launch_bounds__(256) void k_amg_hp(DevPtrs d, AmgDev a) {
-  const int q = blockIdx.x * 256 + (int)threadIdx.x;
-  const int k = q / 6, r = q - (q / 6) * 6;
-  if (k >= a.nhp) return;
-  const T *hd = reinterpret_cast<const T *>(d.hdiag), *ho = reinterpret_cast<const T *>(d.hoff);
-  const T *pd = reinterpret_cast<const T *>(a.pd0);
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  const int m0 = a.hp_gptr[k], m1 = a.hp_gptr[k + 1];
-  constexpr int U = HP_U;
-  constexpr int NP4 = 12 * (int)sizeof(T) / 16;   // 16-byte pieces of a prolongator record
-  for (int mb = m0; mb < m1; mb += U) {
-    int src[U], j[U];
+// column j is an unknown of aggregate a, the diagonal block first, then the
+// off-diagonal ones in slot order.  Row r of H_ij P_j, with h = row r of H_ij
+// split into (h_t, h_w): columns 0-2 are h_t, columns 3-5 are
+// d_j x h_t + S_j^T h_w.  A workgroup takes HP_ROWS fine rows, whose
+// entries and sources are contiguous ranges: phase 1 gives each thread a
+// source (its whole block and the column's prolongator record, every load
+// issued at once) and writes the 36 values of its product to LDS, the rows'
+// diagonal products too; phase 2 gives each thread entry values (entry,
+// element), summed from LDS in the fixed order.  Sources beyond HP_CAP are
+// taken in further passes, their sums added to the entry's values.
+constexpr int HP_ROWS = 8, HP_THREADS = 128, HP_CAP = 128;   // ~100 off-diagonal sources per 8 rows
+template <typename T>
+__device__ __forceinline__ void hp_product(const T (&H)[36], const T (&pr)[12], T *out) {
+  const double dd[3] = {double(pr[0]), double(pr[1]), double(pr[2])};
 #pragma unroll
-    for (int m = 0; m < U; ++m) {   // past the entry: its last source again
-      const int mm = min(mb + m, m1 - 1);
-      src[m] = a.hp_src[mm];
-      j[m] = a.hp_col[mm];
-    }
-    T h[U][6], p[U][12];
+  for (int r = 0; r < 6; ++r) {
+    const double h0 = double(H[r * 6]), h1 = double(H[r * 6 + 1]), h2 = double(H[r * 6 + 2]);
+    const double h3 = double(H[r * 6 + 3]), h4 = double(H[r * 6 + 4]), h5 = double(H[r * 6 + 5]);
+    out[r * 6] = T(h0);
+    out[r * 6 + 1] = T(h1);
+    out[r * 6 + 2] = T(h2);
 #pragma unroll
-    for (int m = 0; m < U; ++m) {
-      // diagonal: packed upper triangle of row j; off-diagonal: row r of the
-      // stored block, or its column r when H_ij is the transpose
-      const bool diag = src[m] < 0, tr = (src[m] & 1) != 0;
-      const T *base = diag ? hd + (size_t)j[m] * 21 : ho + (size_t)(src[m] >> 1) * 36;
-#pragma unroll
-      for (int c = 0; c < 6; ++c) h[m][c] = base[diag ? up6(r, c) : (tr ? c * 6 + r : r * 6 + c)];
-      const float4 *pp = reinterpret_cast<const float4 *>(pd + (size_t)j[m] * 12);
-      float4 *pq = reinterpret_cast<float4 *>(p[m]);
-#pragma unroll
-      for (int x = 0; x < NP4; ++x) pq[x] = pp[x];
-    }
-#pragma unroll
-    for (int m = 0; m < U; ++m) {   // branch-free, so that no load sinks into a branch
-      const bool live = mb + m < m1;
-      double hv[6], dd[3], S[9];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) hv[c] = live ? double(h[m][c]) : 0.0;
-#pragma unroll
-      for (int x = 0; x < 3; ++x) dd[x] = double(p[m][x]);
-#pragma unroll
-      for (int x = 0; x < 9; ++x) S[x] = double(p[m][3 + x]);
-      acc[0] += hv[0];
-      acc[1] += hv[1];
-      acc[2] += hv[2];
-      acc[3] += (dd[1] * hv[2] - dd[2] * hv[1]) + S[0] * hv[3] + S[3] * hv[4] + S[6] * hv[5];
-      acc[4] += (dd[2] * hv[0] - dd[0] * hv[2]) + S[1] * hv[3] + S[4] * hv[4] + S[7] * hv[5];
-      acc[5] += (dd[0] * hv[1] - dd[1] * hv[0]) + S[2] * hv[3] + S[5] * hv[4] + S[8] * hv[5];
+    for (int m = 0; m < 3; ++m) {
+      const double cr = m == 0 ? dd[1] * h2 - dd[2] * h1 : (m == 1 ? dd[2] * h0 - dd[0] * h2 : dd[0] * h1 - dd[1] * h0);
+      out[r * 6 + 3 + m] = T(cr + double(pr[3 + m]) * h3 + double(pr[6 + m]) * h4 + double(pr[9 + m]) * h5);
     }
   }
-  T *o = reinterpret_cast<T *>(a.hp_val) + (size_t)k * 36 + r * 6;
+}
+template <typename T> __global__ __launch_bounds__(HP_THREADS) void k_amg_hp(DevPtrs d, AmgDev a) {
+  constexpr int NQ = 36 * (int)sizeof(T) / 16, NP4 = 12 * (int)sizeof(T) / 16;   // 16-byte pieces
+  constexpr int U = (HP_CAP + HP_THREADS - 1) / HP_THREADS;
+  __shared__ T prod[HP_CAP * 36];
+  __shared__ T dprod[HP_ROWS * 36];
+  __shared__ int sh_ptr[HP_ROWS + 1], sh_self[HP_ROWS];
+  const int r0 = blockIdx.x * HP_ROWS, t = threadIdx.x;
+  if (t <= HP_ROWS) sh_ptr[t] = a.hp_ptr[r0 + t];
+  if (t < HP_ROWS) sh_self[t] = a.hp_self[r0 + t];
+  const T *hd = reinterpret_cast<const T *>(d.hdiag);
+  const float4 *HO = reinterpret_cast<const float4 *>(d.hoff);
+  const float4 *PD = reinterpret_cast<const float4 *>(a.pd0);
+  // the rows' diagonal products (rows without a self entry skip theirs)
+  if (t < HP_ROWS) {
+    const int i = r0 + t;
+    T H[36], pr[12];
+    const T *D = hd + (size_t)i * 21;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) o[c] = T(acc[c]);
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) H[r * 6 + c] = D[up6(r, c)];
+    float4 *pp = reinterpret_cast<float4 *>(pr);
+#pragma unroll
+    for (int x = 0; x < NP4; ++x) pp[x] = PD[(size_t)i * NP4 + x];
+    hp_product<T>(H, pr, dprod + t * 36);
+  }
+  __syncthreads();
+  const int e0 = sh_ptr[0], e1 = sh_ptr[HP_ROWS];
+  if (e0 == e1) return;   // uniform over the workgroup
+  const int g0 = a.hp_gptr[e0], g1 = a.hp_gptr[e1];
+  T *hv = reinterpret_cast<T *>(a.hp_val);
+  const int nitems = 36 * (e1 - e0);
+  for (int pb = g0; pb == g0 || pb < g1; pb += HP_CAP) {   // at least once: the diagonal-only entries
+    const int ns = max(0, min(HP_CAP, g1 - pb));
+    {
+      int src[U], j[U];
+#pragma unroll
+      for (int m = 0; m < U; ++m) {   // threads past the pass repeat its last source
+        const int q = pb + min(m * HP_THREADS + t, max(ns - 1, 0));
+        src[m] = ns > 0 ? a.hp_src[q] : 0;
+        j[m] = ns > 0 ? a.hp_col[q] : r0;
+      }
+      float4 bq[U][NQ], pq[U][NP4];
+#pragma unroll
+      for (int m = 0; m < U; ++m) {
+        if (ns > 0) {
+#pragma unroll
+          for (int x = 0; x < NQ; ++x) bq[m][x] = HO[(size_t)(src[m] >> 1) * NQ + x];
+        }
+#pragma unroll
+        for (int x = 0; x < NP4; ++x) pq[m][x] = PD[(size_t)j[m] * NP4 + x];
+      }
+#pragma unroll
+      for (int m = 0; m < U; ++m) {
+        const int q = m * HP_THREADS + t;
+        if (q >= ns) continue;
+        const T *b = reinterpret_cast<const T *>(bq[m]);
+        const bool tr = (src[m] & 1) != 0;   // H_ij is the transpose of the stored block
+        T H[36];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int c = 0; c < 6; ++c) H[r * 6 + c] = tr ? b[c * 6 + r] : b[r * 6 + c];
+        hp_product<T>(H, reinterpret_cast<const T(&)[12]>(pq[m]), prod + q * 36);
+      }
+    }
+    __syncthreads();
+    for (int it = t; it < nitems; it += HP_THREADS) {
+      const int k = e0 + it / 36, q = it - (it / 36) * 36;
+      int rl = 0;
+      while (rl + 1 < HP_ROWS && sh_ptr[rl + 1] <= k) ++rl;
+      const int s0 = a.hp_gptr[k], s1 = a.hp_gptr[k + 1];
+      const int lo = max(s0, pb), hi = min(s1, pb + ns);
+      const bool first = pb == g0 || s0 >= pb;   // no value written for this entry yet
+      if (!first && lo >= hi) continue;
+      double acc = first ? 0.0 : double(hv[(size_t)k * 36 + q]);
+      if (first && sh_self[rl] == k) acc += double(dprod[rl * 36 + q]);
+      for (int m = lo; m < hi; ++m) acc += double(prod[(m - pb) * 36 + q]);
+      hv[(size_t)k * 36 + q] = T(acc);
+    }
+    __syncthreads();
+    if (pb >= g1 - HP_CAP) break;   // uniform: the last pass
+  }
 }
 
 // six values of an array the cycle reads once, with non-temporal loads.
@@ -1148,8 +1200,9 @@ static void vcycle_t(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int 
 
 void launch_amg_couple(const DevPtrs &d, const AmgDev &a, bool mixed, hipStream_t s) {
   if (a.nhp == 0) return;
-  if (mixed) k_amg_hp<float><<<nblk(6 * a.nhp, 256), 256, 0, s>>>(d, a);
-  else k_amg_hp<double><<<nblk(6 * a.nhp, 256), 256, 0, s>>>(d, a);
+  static_assert(TILE % HP_ROWS == 0, "coupling row blocks nest in the tiles");
+  if (mixed) k_amg_hp<float><<<d.n_pad / HP_ROWS, HP_THREADS, 0, s>>>(d, a);
+  else k_amg_hp<double><<<d.n_pad / HP_ROWS, HP_THREADS, 0, s>>>(d, a);
 }
 
 void launch_amg_setup(const DevPtrs &d, const AmgDev &a, const AmgLevel *hl, int n_scenes, bool mixed,
