@@ -192,3 +192,50 @@ def test_amg_with_repulsion_and_midpoint(B, mixed):
         _compare_states(sc, got, ref, prev, tol, f"step {k} newton {sg['newton_iters']} cg {sg['cg_iters']}")
         prev = ref
     sim.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_vcycle_of_batched_scenes_matches_each_scene_alone(B, mixed):
+    """Two blocks of the same hierarchy depth in one context (65,536 and
+    36,864 particles: levels of 1,024 / 128 / 16 and 576 / 72 / 9
+    aggregates), so each scene's V-cycle is the one the oracle applies to
+    that scene alone: per-level kernels over both scenes' nodes, and a dense
+    tail per scene (16 and 9 aggregates) in one launch.  FP64 1e-9 and
+    mixed 1e-3 of each scene's largest entry, as for one scene."""
+    from tests.test_gpu_parity import _perturbed_block
+    dt = 1e-3
+    parts = []
+    for s, dims in enumerate([(64, 64, 16), (48, 48, 16)]):
+        sc, st = _perturbed_block(*dims, ground=True)
+        sc.pos[:, 0] += 10.0 * s
+        st["pos"][:, 0] += 10.0 * s
+        ev_pos, ev_quat, _, _ = S.perturb_state(sc, 5 + s, 1e-4, 0.01)
+        ev_pos[sc.flags != 0], ev_quat[sc.flags != 0] = st["pos"][sc.flags != 0], st["quat"][sc.flags != 0]
+        b = np.random.default_rng(11 + s).normal(size=(sc.n, 6))
+        b[sc.flags != 0] = 0.0
+        o = oracle_for(sc, st)
+        _, _, hd, ho = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=True)
+        x_o, L = o.amg_apply(ev_pos, ev_quat, hd, ho, b)
+        log(f"  scene {s}: {sc.n} particles, {L} coarse levels")
+        assert L == 3
+        parts.append((sc, st, ev_pos, ev_quat, b, x_o))
+    cat = lambda key: np.concatenate([p[0].__dict__[key] for p in parts])
+    sid = np.concatenate([np.full(p[0].n, s, dtype=np.int32) for s, p in enumerate(parts)])
+    offs = np.cumsum([0] + [p[0].n for p in parts])
+    ij = np.concatenate([p[0].ij + offs[s] for s, p in enumerate(parts)])
+    batch = S.Scene(name="two_blocks", pos=cat("pos"), quat=cat("quat"), vel=cat("vel"), qvel=cat("qvel"),
+                    radius=cat("radius"), pmat=sid.copy(), flags=cat("flags"), ij=ij,
+                    materials=[p[0].materials[0] for p in parts], k_contact=parts[0][0].k_contact,
+                    ground_offset=parts[0][0].ground_offset, scene_id=sid,
+                    dt_per_scene=np.full(len(parts), dt))
+    log(f"[amg vcycle batch] n={batch.n} mixed={mixed}")
+    sim = make_sim(batch, mixed=mixed, preconditioner=B.BDEM_PRECOND_AMG, hessian=B.BDEM_HESS_EIGEN_CLAMP)
+    sim.set_state(**{k: np.concatenate([p[1][k] for p in parts]) for k in ("pos", "quat", "vel", "qvel")})
+    x = sim.precond_apply(dt, np.concatenate([p[4] for p in parts]), np.concatenate([p[2] for p in parts]),
+                          np.concatenate([p[3] for p in parts]))
+    for s, p in enumerate(parts):
+        xs = x[offs[s]:offs[s + 1]]
+        err = np.abs(xs - p[5]).max() / np.abs(p[5]).max()
+        log(f"  scene {s}: max rel err {err:.2e}")
+        assert err <= (1e-3 if mixed else 1e-9), s
+    sim.close()
