@@ -1,10 +1,11 @@
 // Aggregation multigrid preconditioner: numeric setup at the first Newton
 // iteration of a step, or at every one (rigid-body-mode prolongation,
 // Galerkin coarse operators, block-Jacobi inverses, dense inverse of the
-// last level per scene) and the V-cycle applied to the PCG residual.  The symbolic hierarchy and its
-// definitions are described in bdem_amg.hpp.  All sums run in a fixed order
-// (contribution and child lists are sorted at create), so results are
-// reproducible run to run.
+// last level and the tail matrix per scene), the fine coupling H P after
+// every Hessian evaluation, and the V-cycle applied to the PCG residual.
+// The symbolic hierarchy and its definitions are described in
+// bdem_amg.hpp.  All sums run in a fixed order (contribution and child
+// lists are sorted at create), so results are reproducible run to run.
 #include <algorithm>
 
 #include "bdem_amg.hpp"
