@@ -745,6 +745,7 @@ static int create_impl(const bdem_particles *p, const bdem_bonds *b, const bdem_
   DevPtrs &d = ctx->d;
   d.n_pad = NP;
   d.nb_pad = NB;
+  d.one_scene = NS == 1 ? 1 : 0;
   d.n_slots = S.n_slots;
   d.n_bucket = S.n_bucket;
   // ---- params ----

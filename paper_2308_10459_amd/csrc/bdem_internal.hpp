@@ -68,6 +68,7 @@ struct Params {
 
 struct DevPtrs {
   int n_pad, nb_pad, n_slots;
+  int one_scene;                     // 1: every row is scene 0 (no scene lookup needed)
   // particles
   double4 *pn, *qn, *vn, *wn;        // state x_n and rates
   double4 *ph, *qh;                  // prediction
@@ -121,6 +122,10 @@ struct DevPtrs {
   int *cand_over;                     // particles with more than CMAXC candidates
   double2 *part_d;                    // per-tile partial of the repulsion's w.u in PCG
 };
+
+// the scene of a row (of a tile: every row of a tile is one scene's); with
+// one scene, no load
+__device__ __forceinline__ int row_scene(const DevPtrs &d, int row) { return d.one_scene ? 0 : d.psid[row]; }
 
 // ----- launchers (kernels in the .hip files) -----
 // bond kernels

@@ -374,7 +374,7 @@ template <typename T> __global__ __launch_bounds__(1024) void k_amg_coarse_inver
 // fine pre-smoothing from zero: t0 = omega D^-1 r
 template <typename T> __global__ __launch_bounds__(TILE) void k_amg_fine_pre(DevPtrs d, AmgDev a) {
   const int r = blockIdx.x * TILE + threadIdx.x;
-  if (!d.ctl[d.psid[blockIdx.x * TILE]].cg_active) return;
+  if (!d.ctl[row_scene(d, blockIdx.x * TILE)].cg_active) return;
   double x[6], y[6];
   ld6(d.cr + (size_t)r * 6, x);
   sym21_apply(reinterpret_cast<const T *>(d.dinv) + (size_t)r * 21, x, y);
@@ -1056,7 +1056,7 @@ template <typename T> __global__ __launch_bounds__(6 * SPMV_ROWS) __attribute__(
   __shared__ double ys[NT];
   __shared__ nt_v4f stg[NSD + NSP];
   const int lb = blockIdx.x, r0 = lb * SPMV_ROWS;
-  if (!d.ctl[d.psid[r0]].cg_active) return;   // uniform over the workgroup
+  if (!d.ctl[row_scene(d, r0)].cg_active) return;   // uniform over the workgroup
   const int t = threadIdx.x, rl = t / 6, c = t - (t / 6) * 6, row = r0 + rl;
   const size_t o = (size_t)row * 6 + c;
   const double *e1 = a.lv[1].e;

@@ -143,7 +143,7 @@ __device__ __forceinline__ void store6(double *p, const double (&v)[6]) {
 // r = -z, x = 0, u = M^-1 r, p = q = 0
 template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs d) {
   const int r = blockIdx.x * TILE + threadIdx.x;
-  const int scene = d.psid[blockIdx.x * TILE];
+  const int scene = row_scene(d, blockIdx.x * TILE);
   if (!d.ctl[scene].cg_active) return;
   double z[6], rv[6], uv[6];
   load6(d.z + (size_t)r * 6, z);
@@ -192,7 +192,7 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
   const double *prod = reinterpret_cast<const double *>(prod2);
   const int lb = rev ? xcd_block_rev(blockIdx.x, gridDim.x) : xcd_block(blockIdx.x, gridDim.x);
   const int r0 = lb * SPMV_ROWS;
-  const int scene = d.psid[r0];
+  const int scene = row_scene(d, r0);
   if (!d.ctl[scene].cg_active) return;
   const int t = threadIdx.x;
   const int s0 = d.row_ptr[r0], s1 = d.row_ptr[r0 + SPMV_ROWS];
@@ -481,7 +481,7 @@ template <typename T, int ROWS> __global__ __launch_bounds__(6 * ROWS) void k_cg
   static_assert(ROWS % SPMV_ROWS == 0 && 6 * SPMV_ROWS == 192, "dot blocks of three wavefronts");
   __shared__ double rs[6 * ROWS];
   const int r0 = blockIdx.x * ROWS;
-  const int scene = d.psid[r0];
+  const int scene = row_scene(d, r0);
   const SceneCtl &c = d.ctl[scene];
   if (!c.cg_active) return;
   const double a = c.alpha, b = c.beta;
