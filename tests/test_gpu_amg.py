@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2308_10459_amd import scenes as S
-from tests.gpu_helpers import log, make_sim, oracle_for, sampled_oracle_egh
+from tests.gpu_helpers import log, make_sim, oracle_for, row_scale, sampled_oracle_egh
 from tests.test_gpu_parity import TIGHT, _compare_states, _perturbed_block
 
 pytestmark = pytest.mark.gpu
@@ -66,6 +66,47 @@ def test_vcycle_matches_oracle(B, mixed, dims):
         ref = np.einsum("nij,nj->ni", np.linalg.inv(hd), b)
         np.testing.assert_allclose(xj, ref, rtol=0, atol=1e-9 * np.abs(ref).max())
         sj.close()
+    sim.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_densely_bonded_block_takes_several_passes(B, mixed):
+    """A 24x24x12 simple-cubic block bonded to every particle within 2.3
+    spacings (167,876 bonds, 16 to 56 per particle, 48.6 on average): each
+    row-blocked kernel needs several LDS passes per workgroup (the bond rows'
+    evaluation, the SpMV's 32-row blocks, the fine coupling H P's 8-row blocks
+    and the cycle's last kernel), which the close-packed workloads rarely
+    reach.  The Hessian and one V-cycle against the oracle at the tolerances
+    above."""
+    log(f"[dense bonds] mixed={mixed}")
+    sc, st = _perturbed_block(24, 24, 12, ground=True)
+    sc.ij = S.bonds_cutoff(sc.pos, 0.02 * 2.3)
+    deg = np.bincount(sc.ij.ravel(), minlength=sc.n)
+    log(f"  n={sc.n} bonds={sc.nb} degree {deg.min()}..{deg.max()}")
+    assert 8 * deg.mean() > 3 * 128
+    o = oracle_for(sc, st)
+    dt = 1e-3
+    ev_pos, ev_quat, _, _ = S.perturb_state(sc, 5, 1e-4, 0.01)
+    ev_pos[sc.flags != 0], ev_quat[sc.flags != 0] = st["pos"][sc.flags != 0], st["quat"][sc.flags != 0]
+    _, z_o, hd_o, ho_o = o.energy_grad_hess(dt, ev_pos, ev_quat, psd=True)
+    sim = make_sim(sc, mixed=mixed, preconditioner=B.BDEM_PRECOND_AMG, hessian=B.BDEM_HESS_EIGEN_CLAMP)
+    sim.set_state(**st)
+    _, z, hd, ho = sim.energy_grad_hess(dt, B.BDEM_EGH_G | B.BDEM_EGH_H | B.BDEM_EGH_PSD, ev_pos, ev_quat)
+    assert np.abs(z - z_o).max() <= 1e-11 * np.abs(z_o).max()
+    scale = row_scale(hd_o, ho_o, sc.ij, sc.n)
+    ed = np.linalg.norm((hd - hd_o).reshape(sc.n, -1), axis=1) / scale
+    eo = np.linalg.norm((ho - ho_o).reshape(sc.nb, -1), axis=1) / np.minimum(
+        scale[sc.ij[:, 0]], scale[sc.ij[:, 1]])
+    log(f"  Hessian: max diag err {ed.max():.2e}  max off err {eo.max():.2e}")
+    tol = 1e-4 if mixed else 1e-10
+    assert ed.max() <= tol and eo.max() <= tol
+    b = np.random.default_rng(1).normal(size=(sc.n, 6))
+    b[sc.flags != 0] = 0.0
+    x_o, L = o.amg_apply(ev_pos, ev_quat, hd_o, ho_o, b)
+    x = sim.precond_apply(dt, b, ev_pos, ev_quat)
+    err = np.abs(x - x_o).max() / np.abs(x_o).max()
+    log(f"  coarse levels {L}; V-cycle max rel err {err:.2e}")
+    assert err <= (1e-3 if mixed else 1e-9)
     sim.close()
 
 
