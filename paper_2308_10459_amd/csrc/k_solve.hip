@@ -170,9 +170,13 @@ template <typename T> __global__ __launch_bounds__(TILE) void k_cg_init(DevPtrs 
 // pieces) and u_j, U slots in flight, and writes the six components of
 // H_slot u_j to LDS; waves take 64-slot chunks and load the next chunks'
 // indices while the current blocks are in flight.  FP64 blocks (twice the
-// registers per block): lane (slot, c) reads line c of the block (row c as
-// stored, or column c for the transpose) and u_j, U lines in flight, and
-// writes component c.
+// registers per block): two adjacent lanes per slot, lane h loading rows
+// 3h .. 3h + 2 as stored (nine 16-byte pieces) and u_j, U slot halves in
+// flight.  For the block as stored each lane forms components 3h .. 3h + 2;
+// for the transpose each forms, over its three rows, partial sums of all
+// six components and takes its partner's for its own three, so that every
+// component is the sum over rows 0-2 plus the sum over rows 3-5 in both
+// lanes.
 // Phase 2: thread (row, c) adds the diagonal block times u_row and its row's
 // slot products in slot order, so the sum order is fixed and the launch
 // shape (NT, U) does not change a bit: threads past 6 * SPMV_ROWS add zeros
@@ -292,30 +296,57 @@ template <typename T, int NT, int U> __global__ __launch_bounds__(NT) void k_spm
         }
       }
     } else {
-      const T *Hb = reinterpret_cast<const T *>(d.hoff);
+      const double2 *H2 = reinterpret_cast<const double2 *>(d.hoff);
       double *prodw = reinterpret_cast<double *>(prod2);
-      const int nl = ns * 6;
-      for (int base = 0; base < nl; base += NT * U) {
-        double hv[U][6], uj[U][6];
-        int id[U];
+      const int ni = ns * 2;   // (slot, half) items; a pair of adjacent lanes per slot
+      for (int base = 0; base < ni; base += NT * U) {
+        double2 hq[U][9];
+        double uj[U][6];
+        int id[U], tr[U];
 #pragma unroll
-        for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last line
-          id[m] = min(base + m * NT + t, nl - 1);
-          const int sl = id[m] / 6, c = id[m] - (id[m] / 6) * 6;
+        for (int m = 0; m < U; ++m) {   // lanes past the pass repeat its last item
+          id[m] = min(base + m * NT + t, ni - 1);
+          const int sl = id[m] >> 1;
           const int sb = d.sblk[cb + sl];
           const int jj = d.col[cb + sl];
-          const T *h = Hb + (size_t)(sb >> 1) * 36 + ((sb & 1) ? c : c * 6);
-          const int st = (sb & 1) ? 6 : 1;
+          tr[m] = sb & 1;
+          const double2 *b = H2 + (size_t)(sb >> 1) * 18 + (id[m] & 1) * 9;
 #pragma unroll
-          for (int e = 0; e < 6; ++e) hv[m][e] = double(h[e * st]);
+          for (int q = 0; q < 9; ++q) hq[m][q] = b[q];
           load6(u + (size_t)jj * 6, uj[m]);
         }
 #pragma unroll
         for (int m = 0; m < U; ++m) {
-          double a = 0.0;
+          const bool h = (id[m] & 1) != 0;
+          const double *hr = reinterpret_cast<const double *>(hq[m]);   // rows 3h .. 3h + 2 as stored
+          double own[3], give[3];
 #pragma unroll
-          for (int e = 0; e < 6; ++e) a += hv[m][e] * uj[m][e];
-          if (base + m * NT + t < nl) prodw[id[m]] = a;
+          for (int k = 0; k < 3; ++k) {
+            double a = 0.0, g = 0.0;
+            if (!tr[m]) {
+#pragma unroll
+              for (int e = 0; e < 6; ++e) a += hr[k * 6 + e] * uj[m][e];
+            } else {
+#pragma unroll
+              for (int e = 0; e < 3; ++e) {
+                const double ue = h ? uj[m][3 + e] : uj[m][e];
+                a += (h ? hr[e * 6 + 3 + k] : hr[e * 6 + k]) * ue;
+                g += (h ? hr[e * 6 + k] : hr[e * 6 + 3 + k]) * ue;
+              }
+            }
+            own[k] = a;
+            give[k] = g;
+          }
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const double rx = __shfl_xor(give[k], 1);
+            if (tr[m]) own[k] += rx;
+          }
+          if (base + m * NT + t < ni) {
+            double *pw = prodw + (id[m] >> 1) * 6 + (h ? 3 : 0);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pw[k] = own[k];
+          }
         }
       }
     }
