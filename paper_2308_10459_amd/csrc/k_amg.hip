@@ -980,11 +980,19 @@ template <typename T> __global__ __launch_bounds__(HP_THREADS) void k_amg_hp(Dev
         if (q >= ns) continue;
         const T *b = reinterpret_cast<const T *>(bq[m]);
         const bool tr = (src[m] & 1) != 0;   // H_ij is the transpose of the stored block
+        // the transpose as register swaps at fixed indices: a select between
+        // b[c * 6 + r] and b[r * 6 + c] became an indexed private array (scratch) in FP64
         T H[36];
+#pragma unroll
+        for (int k = 0; k < 36; ++k) H[k] = b[k];
 #pragma unroll
         for (int r = 0; r < 6; ++r)
 #pragma unroll
-          for (int c = 0; c < 6; ++c) H[r * 6 + c] = tr ? b[c * 6 + r] : b[r * 6 + c];
+          for (int c = r + 1; c < 6; ++c) {
+            const T x = H[r * 6 + c], y = H[c * 6 + r];
+            H[r * 6 + c] = tr ? y : x;
+            H[c * 6 + r] = tr ? x : y;
+          }
         hp_product<T>(H, reinterpret_cast<const T(&)[12]>(pq[m]), prod + q * 36);
       }
     }
