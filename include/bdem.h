@@ -187,7 +187,7 @@ typedef struct {
  * computes the same bits). */
 typedef struct {
   int32_t spmv_threads;    /* SpMV workgroup size; 32 block rows per workgroup (192, 256, 384, 512) */
-  int32_t spmv_trips;      /* slots (FP32 blocks) or block lines (FP64) in flight per SpMV thread (1, 2) */
+  int32_t spmv_trips;      /* slots (FP32 blocks) or slot halves (FP64) in flight per SpMV thread (1, 2) */
   int32_t update_rows;     /* block rows per CG-update workgroup (32, 64, 128) */
   int32_t cg_chunk;        /* PCG iterations issued per host poll */
   int32_t use_graph;       /* 1: those iterations replay a captured HIP graph */
